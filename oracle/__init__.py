@@ -1,0 +1,184 @@
+"""FP64 CPU oracle for entropic OT on SE(2) -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  The product library never loads it and shares no code with it.
+
+`se2_oracle.c` holds the arithmetic (FP64, log domain, OpenMP over output
+pixels); this module builds it with gcc and wraps it with ctypes.  `dense.py`
+holds an independent dense-matrix checker for tiny grids.
+
+Paper references (arXiv 2402.15322): group law Section 2.3; rho_b Section 4.3;
+group convolution Section 4.2; Sinkhorn Section 4.1; IBP barycenter Appendix A.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "se2_oracle.c")
+_LIB = os.path.join(_HERE, "libse2oracle.so")
+_lib = None
+
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        i, d = ctypes.c_int, ctypes.c_double
+        L.oc_rho2.restype = d
+        L.oc_rho2.argtypes = [d, d, d, d, d, d]
+        L.oc_half_angle.restype = None
+        L.oc_half_angle.argtypes = [d, d, d, _D]
+        L.oc_kernel_table.restype = None
+        L.oc_kernel_table.argtypes = [i, i, d, d, d, d, i, _D, _D]
+        for fn in (L.oc_conv_log, L.oc_conv_linear):
+            fn.restype = None
+            fn.argtypes = [i, i, i, i, _D, _D, _D]
+        L.oc_sinkhorn.restype = i
+        L.oc_sinkhorn.argtypes = [i, i, i, i, _D, _D, _D, _D, i, d, _D, _D, _D, _D]
+        L.oc_ibp.restype = i
+        L.oc_ibp.argtypes = [i, i, i, i, _D, i, _D, _D, i, d, _D, _D, _D]
+        L.oc_plan_stats.restype = None
+        L.oc_plan_stats.argtypes = [i, i, i, i, _D, _D, _D, _D, _D, _D, _D, _D]
+        L.oc_plan_l1.restype = d
+        L.oc_plan_l1.argtypes = [i, i, i, i, _D, _D, _D, _D, _D]
+        L.oc_num_threads.restype = i
+        L.oc_num_threads.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_D)
+
+
+def num_threads() -> int:
+    return int(lib().oc_num_threads())
+
+
+def rho2(x: float, y: float, theta: float, w: Sequence[float]) -> float:
+    """rho_b(g)^2 for g = (x, y, theta) (Section 4.3)."""
+    return float(lib().oc_rho2(x, y, theta, *w))
+
+
+def half_angle(x: float, y: float, theta: float) -> np.ndarray:
+    b = np.zeros(3)
+    lib().oc_half_angle(x, y, theta, _p(b))
+    return b
+
+
+def kernel_table(nt: int, axial: bool, w: Sequence[float], eps: float, R: int) -> Tuple[np.ndarray, np.ndarray]:
+    """(logk, cost) over the window, shape [2R+1][2R+1][nt][nt], (dx,dy) = out - in."""
+    W = 2 * R + 1
+    logk = np.zeros((W, W, nt, nt))
+    cost = np.zeros((W, W, nt, nt))
+    lib().oc_kernel_table(nt, int(axial), w[0], w[1], w[2], eps, R, _p(logk), _p(cost))
+    return logk, cost
+
+
+def conv_log(logk: np.ndarray, login: np.ndarray) -> np.ndarray:
+    """log of (K * exp(login)) on the grid [ny][nx][nt]."""
+    ny, nx, nt = login.shape
+    R = (logk.shape[0] - 1) // 2
+    out = np.empty_like(login)
+    lib().oc_conv_log(nx, ny, nt, R, _p(np.ascontiguousarray(logk)), _p(np.ascontiguousarray(login)), _p(out))
+    return out
+
+
+def conv_linear(logk: np.ndarray, x: np.ndarray) -> np.ndarray:
+    ny, nx, nt = x.shape
+    R = (logk.shape[0] - 1) // 2
+    out = np.empty_like(x)
+    lib().oc_conv_linear(nx, ny, nt, R, _p(np.ascontiguousarray(logk)), _p(np.ascontiguousarray(x)), _p(out))
+    return out
+
+
+def safe_log(m: np.ndarray) -> np.ndarray:
+    with np.errstate(divide="ignore"):
+        return np.log(m)
+
+
+def sinkhorn(logk: np.ndarray, mu: np.ndarray, nu: np.ndarray, max_iter: int, tol: float,
+             psi_init: Optional[np.ndarray] = None):
+    """Log-domain Sinkhorn.  Returns (phi, psi, iters, err, err_hist) with phi = f/eps, psi = g/eps."""
+    ny, nx, nt = mu.shape
+    R = (logk.shape[0] - 1) // 2
+    lmu, lnu = safe_log(mu), safe_log(nu)
+    phi = np.empty_like(mu)
+    psi = np.empty_like(mu)
+    hist = np.zeros(max(max_iter, 1))
+    err = ctypes.c_double(0.0)
+    it = lib().oc_sinkhorn(nx, ny, nt, R, _p(np.ascontiguousarray(logk)), _p(lmu), _p(lnu),
+                           _p(psi_init), max_iter, tol, _p(phi), _p(psi), _p(hist), ctypes.byref(err))
+    if it < 0:
+        raise MemoryError("oracle sinkhorn failed")
+    return phi, psi, it, err.value, hist[:it]
+
+
+def ibp(logk: np.ndarray, mus: Sequence[np.ndarray], lambdas: Sequence[float], max_iter: int, tol: float):
+    """Log-domain IBP barycenter.  Returns (bary, iters, err, err_hist)."""
+    ny, nx, nt = mus[0].shape
+    R = (logk.shape[0] - 1) // 2
+    lm = np.ascontiguousarray(np.stack([safe_log(m) for m in mus]))
+    lam = np.ascontiguousarray(np.asarray(lambdas, dtype=np.float64))
+    logbar = np.zeros_like(mus[0])
+    hist = np.zeros(max(max_iter, 1))
+    err = ctypes.c_double(0.0)
+    it = lib().oc_ibp(nx, ny, nt, R, _p(np.ascontiguousarray(logk)), len(mus), _p(lm), _p(lam),
+                      max_iter, tol, _p(logbar), _p(hist), ctypes.byref(err))
+    if it < 0:
+        raise ValueError("oracle ibp failed")
+    return np.exp(logbar), it, err.value, hist[:it]
+
+
+def plan_stats(logk: np.ndarray, cost_tab: np.ndarray, phi: np.ndarray, psi: np.ndarray):
+    """(cost, mass, marg1, marg2) of pi = exp(phi + logk + psi) (Section 4.1)."""
+    ny, nx, nt = phi.shape
+    R = (logk.shape[0] - 1) // 2
+    m1 = np.empty_like(phi)
+    m2 = np.empty_like(phi)
+    c = ctypes.c_double(0.0)
+    m = ctypes.c_double(0.0)
+    lib().oc_plan_stats(nx, ny, nt, R, _p(np.ascontiguousarray(logk)), _p(np.ascontiguousarray(cost_tab)),
+                        _p(np.ascontiguousarray(phi)), _p(np.ascontiguousarray(psi)),
+                        ctypes.byref(c), ctypes.byref(m), _p(m1), _p(m2))
+    return c.value, m.value, m1, m2
+
+
+def plan_l1(logk, phi_a, psi_a, phi_b, psi_b) -> float:
+    ny, nx, nt = phi_a.shape
+    R = (logk.shape[0] - 1) // 2
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (logk, phi_a, psi_a, phi_b, psi_b)]
+    return float(lib().oc_plan_l1(nx, ny, nt, R, *[_p(v) for v in a]))
+
+
+def marginal_errors(logk, cost_tab, phi, psi, mu, nu):
+    """(L1 error of marginal 1, of marginal 2, cost, mass) of the plan from (phi, psi)."""
+    cost, mass, m1, m2 = plan_stats(logk, cost_tab, phi, psi)
+    return float(np.abs(m1 - mu).sum()), float(np.abs(m2 - nu).sum()), cost, mass
+
+
+PI = math.pi

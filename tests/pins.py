@@ -1,0 +1,348 @@
+"""Checks that pin the FP64 oracle to facts the paper and the mathematics fix.
+
+Each function raises AssertionError when the oracle disagrees.  They are
+collected by `test_oracle_pins.py` and re-run by `test_oracle_mutants.py`
+against deliberately broken copies of the oracle, to show that a plausible
+mistake (dropped term, wrong sign, transposed operand) fails at least one pin.
+
+Paper references (arXiv 2402.15322): group law Section 2.3; half-angle distance
+Section 4.3 eqs. (rhob), (logcomp); group convolution and K = K^T Section 4.2;
+Sinkhorn Section 4.1; equivariance Lemma (equivariance) and Corollary
+(equivariance-sinkhorn); the SO(2) counterexample Lemma in Section 3;
+barycenter algorithm Appendix A.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.optimize import linprog
+
+import oracle
+from oracle import dense
+
+PI = math.pi
+
+
+def _rand_measure(rng, shape, zero_frac=0.0):
+    m = rng.uniform(0.1, 1.0, shape)
+    if zero_frac > 0:
+        m[rng.uniform(size=shape) < zero_frac] = 0.0
+    return m / m.sum()
+
+
+# --------------------------------------------------------------------------
+# P1: closed-form values of rho_b at hand-checkable points, K(e) = 1,
+#     rho_b(g^-1) = rho_b(g), and rho_b(., ., pi) = rho_b(., ., -pi)
+# --------------------------------------------------------------------------
+
+def pin_rho_closed_forms():
+    # g = (1, 0, pi/2): b = (cos pi/4, -sin pi/4, pi/2)
+    assert abs(oracle.rho2(1, 0, PI / 2, (1, 2, 1)) - (0.5 + 4 * 0.5 + PI ** 2 / 4)) < 1e-12
+    # g = (0, 1, pi/2): b = (sin pi/4, cos pi/4, pi/2)
+    assert abs(oracle.rho2(0, 1, PI / 2, (1, 2, 1)) - (0.5 + 4 * 0.5 + PI ** 2 / 4)) < 1e-12
+    # g = (1, 1, 0): b = (1, 1, 0)
+    assert abs(oracle.rho2(1, 1, 0.0, (1, 3, 1)) - 10.0) < 1e-12
+    # g = (3, 4, pi) is represented with theta = -pi: b = (-4, 3, -pi)
+    assert abs(oracle.rho2(3, 4, PI, (1, 2, 1)) - (16 + 4 * 9 + PI ** 2)) < 1e-12
+    assert abs(oracle.rho2(3, 4, -PI, (1, 2, 1)) - (16 + 4 * 9 + PI ** 2)) < 1e-12
+    # pure rotation: rho_b = w3 |theta|
+    assert abs(oracle.rho2(0, 0, 0.7, (2, 5, 3)) - 9 * 0.49) < 1e-12
+    # pure translation along the frame axes: rho_b = w1 |x|, w2 |y|
+    assert abs(oracle.rho2(2.5, 0, 0.0, (3, 5, 7)) - 9 * 6.25) < 1e-12
+    assert abs(oracle.rho2(0, -1.5, 0.0, (3, 5, 7)) - 25 * 2.25) < 1e-12
+    # half-angle coordinates: half turn maps (x, y) to (y, -x)/...; theta = pi/3
+    b = oracle.half_angle(2.0, 0.0, PI / 3)
+    assert np.allclose(b, [2 * math.cos(PI / 6), -2 * math.sin(PI / 6), PI / 3], atol=1e-14)
+
+
+def pin_rho_inverse_symmetry():
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        x, y = rng.uniform(-5, 5, 2)
+        th = rng.uniform(-PI, PI)
+        w = rng.uniform(0.3, 4.0, 3)
+        g = dense.se2_matrix(x, y, th)
+        xi, yi, ti = dense.coords(np.linalg.inv(g))
+        a = oracle.rho2(x, y, th, w)
+        b = oracle.rho2(xi, yi, ti, w)
+        assert abs(a - b) <= 1e-10 * max(1.0, a)
+
+
+def pin_table_identity_and_symmetry():
+    for nt, axial in ((8, False), (16, False), (8, True)):
+        R = 3
+        logk, cost = oracle.kernel_table(nt, axial, (1.0, 2.5, 1.3), 0.3, R)
+        for k in range(nt):
+            assert logk[R, R, k, k] == 0.0          # K(e) = 1
+        # M = M^T  <=>  T[d, ko, ki] = T[-d, ki, ko]   (Section 4.2: K = K^T)
+        flipped = logk[::-1, ::-1].transpose(0, 1, 3, 2)
+        assert np.max(np.abs(logk - flipped)) <= 1e-12 * np.max(np.abs(logk))
+        assert np.all(cost >= 0.0)
+        assert np.allclose(logk, -cost / 0.3, rtol=1e-15, atol=0)
+
+
+# --------------------------------------------------------------------------
+# P2 / P3: the window convolution equals the explicit matrix built from
+#          homogeneous SE(2) matrices; that matrix is symmetric
+# --------------------------------------------------------------------------
+
+def pin_conv_equals_dense_matrix():
+    rng = np.random.default_rng(5)
+    for (nx, ny, nt, axial, R, w, eps) in ((6, 5, 4, False, 2, (1.0, 2.0, 1.0), 0.7),
+                                           (5, 5, 4, True, 2, (1.0, 3.0, 0.8), 0.9),
+                                           (4, 6, 6, False, 1, (1.5, 1.0, 2.0), 2.0)):
+        LM = dense.dense_logk(nx, ny, nt, axial, w, eps, R)
+        logk, _ = oracle.kernel_table(nt, axial, w, eps, R)
+        v = rng.uniform(0.0, 1.0, (ny, nx, nt))
+        lin = oracle.conv_linear(logk, v)
+        ref = (np.exp(LM) @ v.reshape(-1)).reshape(v.shape)
+        assert np.max(np.abs(lin - ref)) <= 1e-13 * np.max(np.abs(ref))
+        lv = rng.normal(0.0, 5.0, (ny, nx, nt))
+        lv[0, 0, :2] = -np.inf
+        got = oracle.conv_log(logk, lv)
+        want = dense.conv_log(LM, lv)
+        assert np.max(np.abs(got - want)) <= 1e-12 * max(1.0, np.max(np.abs(want)))
+        # symmetry of the operator
+        finite = np.isfinite(LM)
+        assert np.array_equal(finite, finite.T)
+        assert np.max(np.abs(np.where(finite, LM - LM.T, 0.0))) <= 1e-12 * np.max(np.abs(LM[finite]))
+
+
+# --------------------------------------------------------------------------
+# P4: one orientation -> separable anisotropic Gaussian (two 1-D passes)
+# P5: one pixel -> circulant theta convolution (FFT)
+# --------------------------------------------------------------------------
+
+def pin_single_orientation_is_separable_gaussian():
+    rng = np.random.default_rng(7)
+    nx, ny, R, w, eps = 13, 9, 3, (1.2, 2.0, 5.0), 0.8
+    logk, _ = oracle.kernel_table(1, False, w, eps, R)
+    v = rng.uniform(0, 1, (ny, nx, 1))
+    d = np.arange(-R, R + 1)
+    gx = np.exp(-(w[0] * d) ** 2 / eps)
+    gy = np.exp(-(w[1] * d) ** 2 / eps)
+    tmp = np.stack([np.convolve(v[iy, :, 0], gx, mode="same") for iy in range(ny)])
+    ref = np.stack([np.convolve(tmp[:, ix], gy, mode="same") for ix in range(nx)], axis=1)
+    got = oracle.conv_linear(logk, v)[:, :, 0]
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(ref)
+
+
+def pin_single_pixel_is_circulant():
+    rng = np.random.default_rng(8)
+    for nt, axial in ((16, False), (12, False), (8, True)):
+        w3, eps = 1.3, 0.6
+        period = PI if axial else 2 * PI
+        logk, _ = oracle.kernel_table(nt, axial, (1.0, 1.0, w3), eps, 0)
+        phi = period * np.arange(nt) / nt
+        d = np.mod(phi + PI, 2 * PI) - PI
+        if axial:
+            d = np.minimum(np.abs(d), np.abs(np.mod(phi + 2 * PI, 2 * PI) - PI))
+        k = np.exp(-(w3 * d) ** 2 / eps)
+        v = rng.uniform(0, 1, nt)
+        ref = np.real(np.fft.ifft(np.fft.fft(k) * np.fft.fft(v)))
+        got = oracle.conv_linear(logk, v.reshape(1, 1, nt)).reshape(-1)
+        assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(ref)
+
+
+# --------------------------------------------------------------------------
+# P6 / P11: exact grid symmetries (90-degree rotation with a quarter-turn
+# shift of theta, mirror with theta -> -theta); equivariance of conv,
+# Sinkhorn plans and barycenters, invariance and symmetry of the cost
+# --------------------------------------------------------------------------
+
+def rot90(a: np.ndarray, axial: bool = False) -> np.ndarray:
+    """(ix, iy, k) -> (N-1-iy, ix, k + nt/4), nt/2 for axial grids (left translation by a quarter turn)."""
+    ny, nx, nt = a.shape
+    shift = nt // 2 if axial else nt // 4
+    out = np.empty_like(a)
+    for iy in range(ny):
+        for ix in range(nx):
+            out[ix, nx - 1 - iy] = np.roll(a[iy, ix], shift)
+    return out
+
+
+def mirror(a: np.ndarray) -> np.ndarray:
+    """(ix, iy, k) -> (ix, N-1-iy, -k)."""
+    out = a[::-1, :, :]
+    idx = (-np.arange(a.shape[2])) % a.shape[2]
+    return np.ascontiguousarray(out[:, :, idx])
+
+
+def pin_conv_equivariance():
+    rng = np.random.default_rng(9)
+    for nt, axial in ((8, False), (8, True)):
+        logk, _ = oracle.kernel_table(nt, axial, (1.0, 2.0, 1.0), 0.5, 2)
+        v = rng.normal(0, 3, (7, 7, nt))
+        c = oracle.conv_log(logk, v)
+        assert np.max(np.abs(oracle.conv_log(logk, rot90(v, axial)) - rot90(c, axial))) < 1e-12
+        assert np.max(np.abs(oracle.conv_log(logk, mirror(v)) - mirror(c))) < 1e-12
+
+
+def pin_sinkhorn_equivariance_and_cost_symmetry():
+    rng = np.random.default_rng(10)
+    nt = 8
+    logk, cost = oracle.kernel_table(nt, False, (1.0, 2.0, 1.0), 0.5, 2)
+    mu = _rand_measure(rng, (6, 6, nt))
+    nu = _rand_measure(rng, (6, 6, nt))
+    phi, psi, it, err, _ = oracle.sinkhorn(logk, mu, nu, 60, -1.0)
+    pr, sr, _, _, _ = oracle.sinkhorn(logk, rot90(mu), rot90(nu), 60, -1.0)
+    assert np.max(np.abs(pr - rot90(phi))) < 1e-10 and np.max(np.abs(sr - rot90(psi))) < 1e-10
+    pm, sm, _, _, _ = oracle.sinkhorn(logk, mirror(mu), mirror(nu), 60, -1.0)
+    assert np.max(np.abs(pm - mirror(phi))) < 1e-10
+    c0 = oracle.plan_stats(logk, cost, phi, psi)[0]
+    c1 = oracle.plan_stats(logk, cost, pr, sr)[0]
+    assert abs(c0 - c1) < 1e-12 * c0
+    # symmetric in (mu, nu) at convergence: K = K^T makes the swapped plan the transpose
+    phi, psi, it, err, _ = oracle.sinkhorn(logk, mu, nu, 3000, 1e-12)
+    q, r, it2, err2, _ = oracle.sinkhorn(logk, nu, mu, 3000, 1e-12)
+    assert err < 1e-12 and err2 < 1e-12
+    ca = oracle.plan_stats(logk, cost, phi, psi)[0]
+    cb = oracle.plan_stats(logk, cost, q, r)[0]
+    assert ca > 0 and abs(ca - cb) < 1e-9 * ca
+
+
+def pin_barycenter_equivariance():
+    rng = np.random.default_rng(12)
+    nt = 8
+    logk, _ = oracle.kernel_table(nt, False, (1.0, 2.0, 1.0), 0.6, 2)
+    mus = [_rand_measure(rng, (6, 6, nt)) for _ in range(3)]
+    lam = [0.2, 0.5, 0.3]
+    b, _, _, _ = oracle.ibp(logk, mus, lam, 40, -1.0)
+    br, _, _, _ = oracle.ibp(logk, [rot90(m) for m in mus], lam, 40, -1.0)
+    assert np.max(np.abs(br - rot90(b))) < 1e-12 * np.max(b) * 100
+
+
+# --------------------------------------------------------------------------
+# P7: marginals at convergence; the second marginal is exact after a b-update
+# --------------------------------------------------------------------------
+
+def pin_sinkhorn_marginals():
+    rng = np.random.default_rng(13)
+    nt = 8
+    logk, cost = oracle.kernel_table(nt, False, (1.0, 2.0, 1.0), 0.8, 2)
+    mu = _rand_measure(rng, (5, 6, nt))
+    nu = _rand_measure(rng, (5, 6, nt))
+    phi, psi, it, err, hist = oracle.sinkhorn(logk, mu, nu, 5000, 1e-11)
+    assert err <= 1e-11 and it < 5000
+    e1, e2, c, mass = oracle.marginal_errors(logk, cost, phi, psi, mu, nu)
+    assert e1 <= 2e-11          # the reported error is the plan's first-marginal error
+    assert abs(e1 - err) <= 1e-12
+    assert e2 <= 1e-13          # exact after the b-update
+    assert abs(mass - 1.0) <= 1e-11
+    # an unconverged iterate: the reported error still equals the plan's
+    phi, psi, it, err, hist = oracle.sinkhorn(logk, mu, nu, 3, -1.0)
+    e1, e2, _, _ = oracle.marginal_errors(logk, cost, phi, psi, mu, nu)
+    assert it == 3 and abs(e1 - err) <= 1e-12 * max(1.0, err) and e2 <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# P8: the paper's SO(2) counterexample (Lemma in Section 3): two Diracs at
+#     +-pi/4 against their half-turn; the optimal cost tends to (pi - 2 pi/4)^2,
+#     not pi^2, as eps -> 0.  Needs zero-mass handling.
+# --------------------------------------------------------------------------
+
+def pin_so2_counterexample():
+    nt = 16
+    mu = np.zeros((1, 1, nt)); nu = np.zeros((1, 1, nt))
+    mu[0, 0, 2] = mu[0, 0, 14] = 0.5       # +pi/4, -pi/4
+    nu[0, 0, 10] = nu[0, 0, 6] = 0.5       # +pi/4 + pi, -pi/4 + pi
+    for eps in (0.05, 0.02):
+        logk, cost = oracle.kernel_table(nt, False, (1.0, 1.0, 1.0), eps, 0)
+        phi, psi, it, err, _ = oracle.sinkhorn(logk, mu, nu, 200, 1e-13)
+        c = oracle.plan_stats(logk, cost, phi, psi)[0]
+        assert abs(c - (PI - 2 * PI / 4) ** 2) < 1e-8, c
+        assert abs(c - PI ** 2) > 1.0
+
+
+# --------------------------------------------------------------------------
+# P9: barycenter closed forms (Appendix A with lambda = e_k, or identical inputs):
+#     v stays 1 and bar = K*(mu_k / K*1) from the first iteration on
+# --------------------------------------------------------------------------
+
+def pin_barycenter_closed_form():
+    rng = np.random.default_rng(14)
+    nx, ny, nt, R, w, eps = 5, 4, 6, 2, (1.0, 2.0, 1.0), 0.7
+    LM = dense.dense_logk(nx, ny, nt, False, w, eps, R)
+    K = np.exp(LM)
+    logk, _ = oracle.kernel_table(nt, False, w, eps, R)
+    m0 = _rand_measure(rng, (ny, nx, nt))
+    m1 = _rand_measure(rng, (ny, nx, nt))
+    want0 = (K @ (m0.reshape(-1) / (K @ np.ones(m0.size)))).reshape(m0.shape)
+    want1 = (K @ (m1.reshape(-1) / (K @ np.ones(m1.size)))).reshape(m1.shape)
+    b, it, err, _ = oracle.ibp(logk, [m0, m1], [1.0, 0.0], 7, -1.0)
+    assert np.max(np.abs(b - want0)) < 1e-13 * np.max(want0)
+    b, it, err, _ = oracle.ibp(logk, [m0, m1], [0.0, 1.0], 3, -1.0)
+    assert np.max(np.abs(b - want1)) < 1e-13 * np.max(want1)
+    b, it, err, _ = oracle.ibp(logk, [m0, m0], [0.3, 0.7], 5, -1.0)
+    assert np.max(np.abs(b - want0)) < 1e-12 * np.max(want0)
+    assert err < 1e-12  # the w-side marginal is met at the fixed point
+
+
+# --------------------------------------------------------------------------
+# P10: brute force -- dense-matrix Sinkhorn / IBP, and an exact LP as eps -> 0
+# --------------------------------------------------------------------------
+
+def pin_dense_sinkhorn_and_ibp():
+    rng = np.random.default_rng(15)
+    nx, ny, nt, R, w, eps = 4, 5, 4, 2, (1.0, 2.0, 1.5), 0.4
+    LM = dense.dense_logk(nx, ny, nt, False, w, eps, R)
+    logk, _ = oracle.kernel_table(nt, False, w, eps, R)
+    mu = _rand_measure(rng, (ny, nx, nt), zero_frac=0.1)
+    nu = _rand_measure(rng, (ny, nx, nt))
+    phi, psi, it, err, _ = oracle.sinkhorn(logk, mu, nu, 25, -1.0)
+    dphi, dpsi = dense.sinkhorn(LM, mu, nu, 25)
+    pa = dense.plan(LM, phi, psi)
+    pb = dense.plan(LM, dphi, dpsi)
+    assert np.sum(np.abs(pa - pb)) < 1e-12
+    l1 = oracle.plan_l1(logk, phi, psi, dphi, dpsi)
+    assert l1 < 1e-12
+    mus = [_rand_measure(rng, (ny, nx, nt)) for _ in range(3)]
+    lam = [0.5, 0.25, 0.25]
+    b, _, _, _ = oracle.ibp(logk, mus, lam, 15, -1.0)
+    bd = dense.ibp(LM, mus, lam, 15)
+    assert np.max(np.abs(b - bd)) < 1e-12 * np.max(bd)
+
+
+def pin_small_eps_matches_linear_program():
+    rng = np.random.default_rng(16)
+    nx, ny, nt, R, w = 3, 3, 4, 2, (1.0, 2.0, 1.0)
+    mu = _rand_measure(rng, (ny, nx, nt))
+    nu = _rand_measure(rng, (ny, nx, nt))
+    _, cost_tab = oracle.kernel_table(nt, False, w, 1.0, R)
+    LM = dense.dense_logk(nx, ny, nt, False, w, 1.0, R)     # = -rho^2 (eps = 1)
+    C = -LM
+    n = mu.size
+    # exact LP over the full 3x3 grid (R = 2 covers every pair)
+    A = np.zeros((2 * n, n * n))
+    for i in range(n):
+        A[i, i * n:(i + 1) * n] = 1.0
+        A[n + i, i::n] = 1.0
+    res = linprog(C.reshape(-1), A_eq=A, b_eq=np.concatenate([mu.reshape(-1), nu.reshape(-1)]),
+                  bounds=(0, None), method="highs")
+    assert res.status == 0
+    for eps in (0.05, 0.02):
+        logk, cost = oracle.kernel_table(nt, False, w, eps, R)
+        phi, psi, it, err, _ = oracle.sinkhorn(logk, mu, nu, 20000, 1e-10)
+        c = oracle.plan_stats(logk, cost, phi, psi)[0]
+        # feasible plan => cost >= LP optimum; entropic gap <= eps * 2 log n
+        assert c >= res.fun - 1e-8
+        assert c - res.fun <= eps * 2 * math.log(n)
+
+
+ALL_PINS = [
+    pin_rho_closed_forms,
+    pin_rho_inverse_symmetry,
+    pin_table_identity_and_symmetry,
+    pin_conv_equals_dense_matrix,
+    pin_single_orientation_is_separable_gaussian,
+    pin_single_pixel_is_circulant,
+    pin_conv_equivariance,
+    pin_sinkhorn_equivariance_and_cost_symmetry,
+    pin_barycenter_equivariance,
+    pin_sinkhorn_marginals,
+    pin_so2_counterexample,
+    pin_barycenter_closed_form,
+    pin_dense_sinkhorn_and_ibp,
+    pin_small_eps_matches_linear_program,
+]
