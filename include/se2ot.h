@@ -1,0 +1,226 @@
+/*
+ * se2ot.h -- C ABI of the MI355X (gfx950) library for entropic optimal transport
+ * on the roto-translation group SE(2) = R^2 x| SO(2).
+ *
+ * The operations follow "Optimal Transport on the Lie Group of Roto-translations"
+ * (Bon, Pai, Bellaard, Mula, Duits; arXiv 2402.15322):
+ *
+ *   se2_kernel_build  Gibbs kernel K(g) = exp(-rho_b(g)^2 / eps) on a window of
+ *                     grid offsets; rho_b is the half-angle distance approximation
+ *                     of Section 4.3, eqs. (rhob) and (logcomp), with the
+ *                     left-invariant metric diag(w1^2, w2^2, w3^2) of Section 2.3.
+ *   se2_conv          the group convolution (K * f)(g) = sum_h K(h^-1 g) f(h) of
+ *                     Section 4.2 (the operator K b of the scaling iterations).
+ *   se2_conv_log      the same operator on log-values: log(K * exp(f)).
+ *   se2_sinkhorn      entropic OT between two measures, the Sinkhorn iterations
+ *                     a = mu / K b, b = nu / K^T a of Section 4.1 (in log form).
+ *   se2_barycenter    the iterative Bregman projections of Appendix A.
+ *   se2_solve_queue_* a serving queue that admits OT and barycenter solves by an
+ *                     HBM budget and advances all admitted solves together.
+ *
+ * Discretisation: pixel (ix, iy) sits at (x, y) = (ix, iy) (unit spacing);
+ * theta_k = k * Theta / ntheta with Theta = 2*pi, or pi when theta_axial = 1
+ * (orientations without direction; the distance on the quotient by the half
+ * turn is the smaller of its two lifts).  The kernel is truncated to a square
+ * (2r+1)^2 window of grid offsets x_out - x_in with full theta support; the
+ * spatial boundary is zero (no wrap) and theta is periodic.  The Haar cell
+ * volume is dropped (a constant that the scalings absorb).
+ *
+ * Layout of every grid array: [batch][iy][ix][k], theta innermost, dense.
+ *
+ * Pointers: unless stated otherwise, array arguments are HIP DEVICE pointers
+ * owned by the caller; the library never frees them and keeps no reference
+ * after the call returns (queue requests excepted, see below).
+ *
+ * Errors: functions return 0 (SE2_OK) or a negative code; se2_strerror() names
+ * it.  Invalid arguments are detected before any device work is queued.
+ * Non-convergence is not an error: it is reported in se2_report_t.status.
+ */
+#ifndef SE2OT_H
+#define SE2OT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SE2_OK 0
+#define SE2_EINVAL (-1)   /* bad argument or input measure (NaN, negative, not normalised) */
+#define SE2_ENOMEM (-2)   /* device or host allocation failed, or request exceeds the queue budget */
+#define SE2_EHIP (-3)     /* a HIP runtime call failed */
+#define SE2_ENUMERIC (-4) /* non-finite value produced (e.g. mass with no partner in the window) */
+#define SE2_PENDING 1     /* queue ticket not finished yet */
+
+/* Solve status in se2_report_t.status */
+#define SE2_CONVERGED 0
+#define SE2_MAX_ITER 1
+
+typedef struct {
+    int32_t nx, ny;      /* pixels, >= 1 */
+    int32_t ntheta;      /* orientations: 8, 16 or 32 */
+    int32_t theta_axial; /* 0: theta in [0, 2 pi); 1: theta in [0, pi) */
+} se2_grid_t;
+
+typedef struct {
+    double w1, w2, w3; /* metric weights, > 0 (Section 2.3, eq. (metric_SE2)) */
+    double eps;        /* entropic regularisation, > 0 (Section 4.1) */
+    int32_t radius;    /* window half-width r: offsets |dx|, |dy| <= r, 0 <= r <= 12 */
+} se2_metric_t;
+
+/* Arithmetic of a convolution.
+ *  SE2_BF16: se2_conv only -- input rounded to bfloat16 (RNE), kernel in bfloat16,
+ *            products accumulated in FP32 on the matrix cores (MFMA); float in/out.
+ *  SE2_F32 : FP32 kernel and accumulation (se2_conv: float in/out); for the
+ *            log-domain paths: exponent arguments formed in FP64, FP32 exp2 and
+ *            FP32 partial sums combined in FP64.
+ *  SE2_F64 : FP64 throughout (se2_conv: double in/out).                      */
+typedef enum { SE2_BF16 = 0, SE2_F32 = 1, SE2_F64 = 2 } se2_prec_t;
+
+typedef struct {
+    double tol_marg_l1;   /* stop when the marginal L1 error <= tol; tol < 0 runs exactly max_iter */
+    int32_t max_iter;     /* >= 1 */
+    int32_t check_every;  /* iterations between convergence checks (>= 1) */
+    se2_prec_t prec;      /* SE2_F32 (default engine) or SE2_F64 (FP64 exp, slow) */
+    int32_t final_check;  /* 1: recompute the final marginal error with an FP64 convolution */
+    int32_t prune;        /* 1: certified pruning of negligible window entries (results equal the dense
+                             sum to 2^-48 relative per skipped entry); 0: every entry, every time */
+    const double *init_g; /* device, may be NULL: warm start g/eps-scaled potential, natural log units */
+} se2_opts_t;
+
+typedef struct {
+    int32_t status;     /* SE2_CONVERGED, SE2_MAX_ITER */
+    int32_t iters;      /* iterations done by the returned iterate */
+    double marg_l1;     /* L1 error of the non-exact marginal(s) of the returned iterate */
+    double marg_l1_f64; /* same, from an FP64 convolution (final_check = 1), else -1 */
+    double cost;        /* sum pi * rho_b^2 (OT) or sum_i lambda_i <pi_i, rho_b^2> (barycenter) */
+    double mass;        /* total mass of the plan (OT) or of the barycenter */
+    double dual;        /* <f, mu> + <g, nu> (OT only, diagnostic) */
+    double seconds;     /* wall time of the solve on the host clock */
+    double terms_dense;  /* in-grid window terms evaluated by dense convolution visits */
+    double terms_sparse; /* list entries evaluated by certified sparse visits (per output) */
+    int32_t convs;      /* group convolutions applied */
+    int32_t reserved;
+} se2_report_t;
+
+typedef struct se2_kernel_s *se2_kernel_t; /* library-owned, immutable, usable from any thread */
+typedef struct se2_queue_s *se2_queue_t;
+typedef void *se2_stream_t;                /* a hipStream_t; NULL = the default stream */
+
+/* Library version and device check.  Returns 0 if a gfx950 device is current. */
+int se2_init(void);
+const char *se2_strerror(int code);
+
+/*
+ * se2_kernel_build -- tabulate the Gibbs kernel on the window (Sections 4.2, 4.3).
+ * For each offset d = (dx, dy), |dx|,|dy| <= r, and orientation pair (ko, ki):
+ *     logK[d][ko][ki] = -rho_b(h^-1 g)^2 / eps,   h = (x, theta_ki), g = (x + d, theta_ko),
+ *     h^-1 g = (R_{-theta_ki} d, theta_ko - theta_ki)    (group law of Section 2.3).
+ * Tables are built on the host in FP64 and uploaded once (FP64 log-kernel, FP64
+ * cost rho_b^2, FP32 and bfloat16 kernels for se2_conv).  The handle is
+ * immutable and may be shared by concurrent solves.  Uses the current device.
+ */
+int se2_kernel_build(const se2_grid_t *grid, const se2_metric_t *metric, se2_kernel_t *out);
+int se2_kernel_destroy(se2_kernel_t k);
+
+/* Copy the FP64 tables to HOST memory, layout [dy+r][dx+r][ko][ki], natural log
+ * units: host_logk = -rho_b^2/eps, host_cost = rho_b^2 (either may be NULL).
+ * Each must hold (2r+1)^2 * ntheta^2 doubles. */
+int se2_kernel_table(se2_kernel_t k, double *host_logk, double *host_cost);
+
+/* Grid and window of a kernel (any pointer may be NULL). */
+int se2_kernel_info(se2_kernel_t k, se2_grid_t *grid, se2_metric_t *metric, int32_t *window_nonzero_bf16);
+
+/*
+ * se2_conv -- out[b] = K * in[b] for b < batch (Section 4.2), stream-ordered,
+ * no host synchronisation.  SE2_BF16 and SE2_F32 read/write float arrays,
+ * SE2_F64 double arrays; each is batch * nx * ny * ntheta elements.
+ * in and out must not overlap.
+ */
+int se2_conv(se2_kernel_t k, se2_prec_t prec, const void *in, void *out, int32_t batch, se2_stream_t stream);
+
+/*
+ * se2_conv_log -- out[b] = log(K * exp(in[b])) in natural-log units, FP64 in and
+ * out (-inf allowed: zero mass), the log form of the operator applied in every
+ * Sinkhorn half-step.  prec SE2_F32: FP64 exponent arguments, FP32 exp2 and
+ * partial sums, FP64 combination; SE2_F64: FP64 throughout.  Stream-ordered.
+ */
+int se2_conv_log(se2_kernel_t k, se2_prec_t prec, const double *in, double *out, int32_t batch,
+                 se2_stream_t stream);
+
+/*
+ * se2_sinkhorn -- entropic OT between mu and nu (Section 4.1), log form:
+ *     f/eps <- log mu - log K exp(g/eps),   g/eps <- log nu - log K exp(f/eps),
+ * starting from g = init_g (0 if NULL); K^T = K because rho_b(g^-1) = rho_b(g).
+ * mu, nu: device FP64 probability vectors (finite, >= 0, |sum - 1| <= 1e-9).
+ * f_out, g_out: device FP64 (may be NULL) receive f = eps log a, g = eps log b
+ * of the returned iterate (-inf where the mass is zero).  The plan is
+ * pi(x, y) = exp((f(x) + g(y) - rho_b^2(x, y)) / eps) on the window; it is never
+ * materialised.  Blocks the calling thread until the solve is done (the work is
+ * queued on `stream`).  report may be NULL.
+ */
+int se2_sinkhorn(se2_kernel_t k, const double *mu, const double *nu, const se2_opts_t *opts,
+                 double *f_out, double *g_out, se2_report_t *report, se2_stream_t stream);
+
+/*
+ * se2_barycenter -- entropic Wasserstein barycenter of n measures with weights
+ * lambda (Appendix A, iterative Bregman projections), log form.
+ * mus: HOST array of n device pointers to FP64 probability vectors;
+ * lambdas: HOST array of n weights on the simplex (>= 0, |sum - 1| <= 1e-12);
+ * bary_out: device FP64 grid array receiving the barycenter.  Measures with
+ * lambda_i = 0 do not enter the barycenter and are skipped.  Blocking.
+ */
+int se2_barycenter(se2_kernel_t k, int32_t n, const double *const *mus, const double *lambdas,
+                   const se2_opts_t *opts, double *bary_out, se2_report_t *report, se2_stream_t stream);
+
+/*
+ * Serving queue.  A worker thread owns one stream on the current device.  Requests
+ * are admitted in arrival order while the HBM budget and the slot count allow;
+ * every admitted solve keeps its potentials resident and all admitted solves
+ * advance together, one batched launch per half-step for each (ntheta) class.
+ * A solve's arithmetic (tiling, reduction order) does not depend on what else is
+ * admitted, so its result is bitwise the same alone or in a mix.
+ */
+#define SE2_REQ_OT 0
+#define SE2_REQ_BARYCENTER 1
+
+typedef struct {
+    int32_t kind;               /* SE2_REQ_OT or SE2_REQ_BARYCENTER */
+    int32_t n;                  /* barycenter: number of measures (<= 16) */
+    se2_kernel_t kernel;        /* must outlive the request */
+    const double *mu, *nu;      /* OT: device inputs, copied into slot memory at admission */
+    const double *const *mus;   /* barycenter: host array of n device pointers, copied at admission */
+    const double *lambdas;      /* barycenter: host weights, copied at submit */
+    se2_opts_t opts;            /* init_g ignored */
+    double *f_out, *g_out;      /* OT outputs (device, may be NULL); must stay valid until done */
+    double *bary_out;           /* barycenter output (device) */
+} se2_request_t;
+
+/* Device bytes a request occupies in the queue while it is resident (inputs, potentials,
+ * pruning state); a request with more bytes than the budget is rejected at submit. */
+int se2_request_bytes(const se2_request_t *req, size_t *bytes);
+int se2_solve_queue_create(size_t hbm_budget_bytes, int32_t max_slots, se2_queue_t *out);
+/* Non-blocking.  SE2_ENOMEM if the request alone exceeds the budget. */
+int se2_solve_queue_submit(se2_queue_t q, const se2_request_t *req, uint64_t *ticket);
+/* SE2_PENDING while running; 0 and the report once done; a negative code if the solve failed. */
+int se2_solve_queue_poll(se2_queue_t q, uint64_t ticket, se2_report_t *report);
+int se2_solve_queue_wait(se2_queue_t q, uint64_t ticket, se2_report_t *report);
+/* Timestamps (host steady clock, seconds) of submit, admission and completion. */
+int se2_solve_queue_times(se2_queue_t q, uint64_t ticket, double *t_submit, double *t_admit, double *t_done);
+/* Counters: admitted, completed, rejected, peak slots in use, batched steps run. */
+int se2_solve_queue_stats(se2_queue_t q, int64_t *out5);
+/* Kernel timing of the queue's log-domain convolutions, measured with HIP events on
+ * the queue's own stream (diagnostics for benchmarks).  enable = 1 starts
+ * recording (and zeroes the totals); out4 receives [seconds inside convolution
+ * launches, algorithmic LSE terms (window entries inside the grid), launches,
+ * output elements]. */
+int se2_solve_queue_profile(se2_queue_t q, int32_t enable);
+int se2_solve_queue_kernel_time(se2_queue_t q, double *out4);
+/* Waits for all submitted work, then frees the queue. */
+int se2_solve_queue_destroy(se2_queue_t q);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SE2OT_H */

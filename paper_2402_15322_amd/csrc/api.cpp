@@ -1,0 +1,332 @@
+// C ABI of the SE(2) entropic-OT library: argument checks, kernel handles,
+// stream-ordered convolutions and the blocking Sinkhorn / barycenter drivers.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "solver.h"
+
+namespace se2 {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_last_hip_error(hipError_t e, const char *what, const char *file, int line) {
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+    g_last_error = buf;
+}
+
+namespace {
+
+bool valid_grid(const se2_grid_t *g) {
+    return g && g->nx >= 1 && g->ny >= 1 && (g->ntheta == 8 || g->ntheta == 16 || g->ntheta == 32) &&
+           (g->theta_axial == 0 || g->theta_axial == 1) &&
+           static_cast<long long>(g->nx) * g->ny * g->ntheta <= (1LL << 31);
+}
+
+bool valid_metric(const se2_metric_t *m) {
+    return m && std::isfinite(m->w1) && std::isfinite(m->w2) && std::isfinite(m->w3) && std::isfinite(m->eps) &&
+           m->w1 > 0 && m->w2 > 0 && m->w3 > 0 && m->eps > 0 && m->radius >= 0 && m->radius <= kMaxRadius;
+}
+
+bool valid_opts(const se2_opts_t *o) {
+    return o && o->max_iter >= 1 && o->check_every >= 1 && (o->prec == SE2_F32 || o->prec == SE2_F64) &&
+           !std::isnan(o->tol_marg_l1);
+}
+
+}  // namespace
+
+// Device-side FP64 validation of a probability vector: finite, >= 0, |sum - 1| <= tol.
+int validate_measure(const double *m, size_t n, double tol, hipStream_t st) {
+    double *stats = nullptr;
+    SE2_HIP(hipMallocAsync(reinterpret_cast<void **>(&stats), (2 + 2 * 256) * sizeof(double), st));
+    int rc = launch_validate(m, n, stats, st);
+    double h[2] = {0, 0};
+    if (rc == SE2_OK) {
+        SE2_HIP(hipMemcpyAsync(h, stats, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        SE2_HIP(hipStreamSynchronize(st));
+    }
+    SE2_HIP(hipFreeAsync(stats, st));
+    if (rc) return rc;
+    if (h[1] != 0.0 || !(std::fabs(h[0] - 1.0) <= tol)) {
+        g_last_error = "input measure is not a probability vector (negative, non-finite or |sum-1| > tol)";
+        return SE2_EINVAL;
+    }
+    return SE2_OK;
+}
+
+namespace {
+
+struct DeviceBlock {
+    void *p = nullptr;
+    hipStream_t st = nullptr;
+    ~DeviceBlock() {
+        if (p) (void)hipFreeAsync(p, st);
+    }
+};
+
+}  // namespace
+}  // namespace se2
+
+using namespace se2;
+
+extern "C" {
+
+int se2_init(void) {
+    int dev = 0;
+    SE2_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    SE2_HIP(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        g_last_error = std::string("device is ") + prop.gcnArchName + ", library built for gfx950";
+        return SE2_EINVAL;
+    }
+    return SE2_OK;
+}
+
+const char *se2_strerror(int code) {
+    switch (code) {
+        case SE2_OK: return "ok";
+        case SE2_EINVAL: return g_last_error.empty() ? "invalid argument" : g_last_error.c_str();
+        case SE2_ENOMEM: return "out of memory or over the queue budget";
+        case SE2_EHIP: return g_last_error.empty() ? "HIP runtime error" : g_last_error.c_str();
+        case SE2_ENUMERIC: return "non-finite value (mass without a partner inside the window?)";
+        case SE2_PENDING: return "pending";
+        default: return "unknown error";
+    }
+}
+
+int se2_kernel_build(const se2_grid_t *grid, const se2_metric_t *metric, se2_kernel_t *out) {
+    if (!out || !valid_grid(grid) || !valid_metric(metric)) return SE2_EINVAL;
+    Kernel *k = new (std::nothrow) Kernel();
+    if (!k) return SE2_ENOMEM;
+    k->grid = *grid;
+    k->metric = *metric;
+    SE2_HIP(hipGetDevice(&k->device));
+    int rc = build_tables(*k);
+    if (rc) {
+        se2_kernel_destroy(reinterpret_cast<se2_kernel_t>(k));
+        return rc;
+    }
+    *out = reinterpret_cast<se2_kernel_t>(k);
+    return SE2_OK;
+}
+
+int se2_kernel_destroy(se2_kernel_t h) {
+    Kernel *k = reinterpret_cast<Kernel *>(h);
+    if (!k) return SE2_EINVAL;
+    (void)hipFree(k->d_L64);
+    (void)hipFree(k->d_L32);
+    (void)hipFree(k->d_cost);
+    (void)hipFree(k->d_K32);
+    (void)hipFree(k->d_Kbf16);
+    (void)hipFree(k->d_K64);
+    (void)hipFree(k->d_Bpack);
+    delete k;
+    return SE2_OK;
+}
+
+int se2_kernel_table(se2_kernel_t h, double *host_logk, double *host_cost) {
+    const Kernel *k = reinterpret_cast<const Kernel *>(h);
+    if (!k) return SE2_EINVAL;
+    if (host_logk) std::memcpy(host_logk, k->logk.data(), k->entries * sizeof(double));
+    if (host_cost) std::memcpy(host_cost, k->cost.data(), k->entries * sizeof(double));
+    return SE2_OK;
+}
+
+int se2_kernel_info(se2_kernel_t h, se2_grid_t *grid, se2_metric_t *metric, int32_t *nz) {
+    const Kernel *k = reinterpret_cast<const Kernel *>(h);
+    if (!k) return SE2_EINVAL;
+    if (grid) *grid = k->grid;
+    if (metric) *metric = k->metric;
+    if (nz) *nz = k->nonzero_bf16;
+    return SE2_OK;
+}
+
+int se2_conv(se2_kernel_t h, se2_prec_t prec, const void *in, void *out, int32_t batch, se2_stream_t stream) {
+    const Kernel *k = reinterpret_cast<const Kernel *>(h);
+    if (!k || !in || !out || batch < 0 || in == out) return SE2_EINVAL;
+    if (batch == 0) return SE2_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    switch (prec) {
+        case SE2_BF16:
+            return launch_conv_bf16(*k, static_cast<const float *>(in), static_cast<float *>(out), batch, st);
+        case SE2_F32:
+            return launch_conv_f32(*k, static_cast<const float *>(in), static_cast<float *>(out), batch, st);
+        case SE2_F64:
+            return launch_conv_f64(*k, static_cast<const double *>(in), static_cast<double *>(out), batch, st);
+        default:
+            return SE2_EINVAL;
+    }
+}
+
+int se2_conv_log(se2_kernel_t h, se2_prec_t prec, const double *in, double *out, int32_t batch,
+                 se2_stream_t stream) {
+    const Kernel *k = reinterpret_cast<const Kernel *>(h);
+    if (!k || !in || !out || batch < 0 || in == out || (prec != SE2_F32 && prec != SE2_F64)) return SE2_EINVAL;
+    if (batch == 0) return SE2_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const size_t E = static_cast<size_t>(k->grid.nx) * k->grid.ny * k->grid.ntheta;
+    const int tiles = tiles_of(k->grid.nx) * tiles_of(k->grid.ny);
+    // natural -> base-2 log units on a scratch copy; results scaled back in place
+    double *tmp = nullptr;
+    SE2_HIP(hipMallocAsync(reinterpret_cast<void **>(&tmp), E * batch * sizeof(double), st));
+    int rc = launch_scale(in, tmp, E * batch, kLog2e, st);
+    std::vector<ConvJob> jobs(batch);
+    for (int b = 0; b < batch && rc == SE2_OK; ++b) {
+        ConvJob &j = jobs[b];
+        j = ConvJob{};
+        j.in = tmp + E * b;
+        j.out = out + E * b;
+        j.L64 = k->d_L64;
+        j.L32 = k->d_L32;
+        j.nx = k->grid.nx;
+        j.ny = k->grid.ny;
+        j.R = k->metric.radius;
+        j.epi = EPI_RAW;
+        j.tiles_x = tiles_of(k->grid.nx);
+        j.tiles = tiles;
+        j.first_block = b * tiles;
+    }
+    ConvJob *dj = nullptr;
+    int32_t *dm = nullptr;
+    std::vector<int32_t> map(static_cast<size_t>(tiles) * batch);
+    for (int b = 0; b < batch; ++b)
+        for (int t = 0; t < tiles; ++t) map[static_cast<size_t>(b) * tiles + t] = b;
+    if (rc == SE2_OK) {
+        SE2_HIP(hipMallocAsync(reinterpret_cast<void **>(&dj), batch * sizeof(ConvJob), st));
+        SE2_HIP(hipMallocAsync(reinterpret_cast<void **>(&dm), map.size() * sizeof(int32_t), st));
+        SE2_HIP(hipMemcpyAsync(dj, jobs.data(), batch * sizeof(ConvJob), hipMemcpyHostToDevice, st));
+        SE2_HIP(hipMemcpyAsync(dm, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        rc = launch_conv_lse(dj, batch, tiles * batch, dm, k->grid.ntheta, k->metric.radius, prec == SE2_F64, false,
+                             st);
+    }
+    if (rc == SE2_OK) rc = launch_scale(out, out, E * batch, kLn2, st);
+    // host vectors are read by the async copies: wait before they go out of scope
+    SE2_HIP(hipStreamSynchronize(st));
+    if (dj) SE2_HIP(hipFreeAsync(dj, st));
+    if (dm) SE2_HIP(hipFreeAsync(dm, st));
+    SE2_HIP(hipFreeAsync(tmp, st));
+    return rc;
+}
+
+int se2_sinkhorn(se2_kernel_t h, const double *mu, const double *nu, const se2_opts_t *opts, double *f_out,
+                 double *g_out, se2_report_t *report, se2_stream_t stream) {
+    const Kernel *k = reinterpret_cast<const Kernel *>(h);
+    if (!k || !mu || !nu || !valid_opts(opts)) return SE2_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const double t0 = now_seconds();
+    const size_t E = static_cast<size_t>(k->grid.nx) * k->grid.ny * k->grid.ntheta;
+    int rc = validate_measure(mu, E, 1e-9, st);
+    if (rc) return rc;
+    if ((rc = validate_measure(nu, E, 1e-9, st))) return rc;
+    Solve s;
+    s.kind = SE2_REQ_OT;
+    s.k = k;
+    s.opts = *opts;
+    s.n = 1;
+    s.t_start = t0;
+    DeviceBlock mem;
+    mem.st = st;
+    const size_t bytes = solve_bytes(SE2_REQ_OT, *k, 1, opts->prune != 0);
+    SE2_HIP(hipMallocAsync(&mem.p, bytes, st));
+    solve_bind(s, mem.p);
+    if ((rc = solve_setup_ot(s, mu, nu, opts->init_g, st))) return rc;
+    Engine eng;
+    std::vector<Solve *> one = {&s};
+    if ((rc = eng.init_first_halfstep(one, st))) return rc;
+    s.convs = 1;
+    std::vector<double> errs;
+    while (!s.done) {
+        const bool last = s.iter + 1 >= opts->max_iter;
+        const bool check = last || ((s.iter + 1) % opts->check_every == 0);
+        if ((rc = eng.step(one, check, st))) return rc;
+        if (check) {
+            if ((rc = eng.read_errors(one, errs, st))) return rc;
+            s.last_err = errs[0];
+            if (!std::isfinite(errs[0])) {
+                g_last_error = "non-finite marginal error";
+                return SE2_ENUMERIC;
+            }
+            if (opts->tol_marg_l1 >= 0 && errs[0] <= opts->tol_marg_l1) {
+                s.done = true;
+                s.status = SE2_CONVERGED;
+            } else if (last) {
+                s.done = true;
+                s.status = SE2_MAX_ITER;
+            } else {
+                s.cur ^= 1;
+            }
+        }
+    }
+    return solve_finish_ot(s, f_out, g_out, report, st);
+}
+
+int se2_barycenter(se2_kernel_t h, int32_t n, const double *const *mus, const double *lambdas,
+                   const se2_opts_t *opts, double *bary_out, se2_report_t *report, se2_stream_t stream) {
+    const Kernel *k = reinterpret_cast<const Kernel *>(h);
+    if (!k || n < 1 || n > 16 || !mus || !lambdas || !bary_out || !valid_opts(opts)) return SE2_EINVAL;
+    double lsum = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (!(lambdas[i] >= 0.0) || !std::isfinite(lambdas[i]) || !mus[i]) return SE2_EINVAL;
+        lsum += lambdas[i];
+    }
+    if (!(std::fabs(lsum - 1.0) <= 1e-12)) return SE2_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const double t0 = now_seconds();
+    const size_t E = static_cast<size_t>(k->grid.nx) * k->grid.ny * k->grid.ntheta;
+    std::vector<const double *> act;
+    std::vector<double> lam;
+    int rc;
+    for (int i = 0; i < n; ++i) {
+        if ((rc = validate_measure(mus[i], E, 1e-9, st))) return rc;
+        if (lambdas[i] > 0.0) {
+            act.push_back(mus[i]);
+            lam.push_back(lambdas[i]);
+        }
+    }
+    Solve s;
+    s.kind = SE2_REQ_BARYCENTER;
+    s.k = k;
+    s.opts = *opts;
+    s.n = static_cast<int>(act.size());
+    s.lam = lam;
+    s.t_start = t0;
+    DeviceBlock mem;
+    mem.st = st;
+    SE2_HIP(hipMallocAsync(&mem.p, solve_bytes(SE2_REQ_BARYCENTER, *k, s.n, opts->prune != 0), st));
+    solve_bind(s, mem.p);
+    if ((rc = solve_setup_bary(s, act, st))) return rc;
+    Engine eng;
+    std::vector<Solve *> one = {&s};
+    if ((rc = eng.init_first_halfstep(one, st))) return rc;
+    s.convs = s.n;
+    std::vector<double> errs;
+    while (!s.done) {
+        const bool last = s.iter + 1 >= opts->max_iter;
+        const bool check = last || ((s.iter + 1) % opts->check_every == 0);
+        if ((rc = eng.step(one, check, st))) return rc;
+        if (check) {
+            if ((rc = eng.read_errors(one, errs, st))) return rc;
+            s.last_err = errs[0];
+            if (!std::isfinite(errs[0])) {
+                g_last_error = "non-finite marginal error";
+                return SE2_ENUMERIC;
+            }
+            if (opts->tol_marg_l1 >= 0 && errs[0] <= opts->tol_marg_l1) {
+                s.done = true;
+                s.status = SE2_CONVERGED;
+            } else if (last) {
+                s.done = true;
+                s.status = SE2_MAX_ITER;
+            }
+        }
+    }
+    return solve_finish_bary(s, bary_out, report, st);
+}
+
+}  // extern "C"

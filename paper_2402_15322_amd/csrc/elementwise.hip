@@ -1,0 +1,310 @@
+// Elementwise and reduction kernels around the convolutions (gfx950).
+//
+// Every reduction is two-level with a fixed order (per-block tree, then one
+// block over the partials in index order), so a result depends only on the data
+// and the array length, never on timing or on what else runs on the device.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "se2_internal.h"
+
+namespace se2 {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ double block_tree_sum(double v, double *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (static_cast<int>(threadIdx.x) < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scale(const double *__restrict__ in, double *__restrict__ out, size_t n,
+                                                    double mul) {
+    for (size_t i = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<size_t>(gridDim.x) * kThreads)
+        out[i] = in[i] * mul;
+}
+
+__global__ __launch_bounds__(kThreads) void k_log2m(const double *__restrict__ m, double *__restrict__ out, size_t n) {
+    for (size_t i = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<size_t>(gridDim.x) * kThreads) {
+        const double v = m[i];
+        out[i] = (v > 0.0) ? log2(v) : -INFINITY;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_exp2(const double *__restrict__ in, double *__restrict__ out, size_t n) {
+    for (size_t i = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<size_t>(gridDim.x) * kThreads)
+        out[i] = exp2(in[i]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill(double *__restrict__ p, size_t n, double v) {
+    for (size_t i = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<size_t>(gridDim.x) * kThreads)
+        p[i] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill_i32(int32_t *__restrict__ p, size_t n, int32_t v) {
+    for (size_t i = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<size_t>(gridDim.x) * kThreads)
+        p[i] = v;
+}
+
+// Per block: [sum m, count of bad entries (non-finite or negative)], over a
+// fixed contiguous chunk of the array per block.
+__global__ __launch_bounds__(kThreads) void k_validate_partial(const double *__restrict__ m, size_t n, size_t chunk,
+                                                               double *__restrict__ part) {
+    __shared__ double sh[kThreads];
+    const size_t b0 = blockIdx.x * chunk;
+    const size_t b1 = (b0 + chunk < n) ? b0 + chunk : n;
+    double s = 0.0, bad = 0.0;
+    for (size_t i = b0 + threadIdx.x; i < b1; i += kThreads) {
+        const double v = m[i];
+        if (!(v >= 0.0) || !isfinite(v)) bad += 1.0;
+        else s += v;
+    }
+    s = block_tree_sum(s, sh);
+    bad = block_tree_sum(bad, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s;
+        part[2 * blockIdx.x + 1] = bad;
+    }
+}
+
+// out[c] = sum over p < count of part[p * stride + c], c < stride, in index order.
+__global__ __launch_bounds__(kThreads) void k_reduce_fixed(const double *__restrict__ part, int count, int stride,
+                                                           double *__restrict__ out) {
+    __shared__ double sh[kThreads];
+    for (int c = 0; c < stride; ++c) {
+        double s = 0.0;
+        for (int p = threadIdx.x; p < count; p += kThreads) s += part[static_cast<size_t>(p) * stride + c];
+        s = block_tree_sum(s, sh);
+        if (threadIdx.x == 0) out[c] = s;
+    }
+}
+
+// One block per job: out[j] = sum of partials[offsets[j] .. offsets[j+1]).
+__global__ __launch_bounds__(kThreads) void k_sum_partials(const double *__restrict__ part,
+                                                           const int32_t *__restrict__ offsets,
+                                                           double *__restrict__ out) {
+    __shared__ double sh[kThreads];
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int p = offsets[j] + threadIdx.x; p < offsets[j + 1]; p += kThreads) s += part[p];
+    s = block_tree_sum(s, sh);
+    if (threadIdx.x == 0) out[j] = s;
+}
+
+struct CombineArgs {
+    double *lv[16];
+    const double *ld[16];
+    double lam[16];
+};
+
+// IBP combine (Appendix A): log bar = sum_i lambda_i log d_i (fixed i order),
+// then log v_i += log bar - log d_i (log v_i = -inf where the barycenter is 0).
+__global__ __launch_bounds__(kThreads) void k_ibp_combine(CombineArgs a, int n, size_t len,
+                                                          double *__restrict__ logbar) {
+    for (size_t x = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x; x < len;
+         x += static_cast<size_t>(gridDim.x) * kThreads) {
+        double bar = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double d = a.ld[i][x];
+            bar = (d == -INFINITY || bar == -INFINITY) ? -INFINITY : bar + a.lam[i] * d;
+        }
+        logbar[x] = bar;
+        for (int i = 0; i < n; ++i) {
+            const double v = a.lv[i][x];
+            a.lv[i][x] = (bar == -INFINITY || v == -INFINITY) ? -INFINITY : v + (bar - a.ld[i][x]);
+        }
+    }
+}
+
+// Plan statistics of pi(x, y) = 2^(phi2(x) + L2(x - y) + psi2(y)) over the window:
+// per block [sum pi * rho^2, sum pi].  One thread per output element (x, ko).
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_plan_cost(const double *__restrict__ phi2,
+                                                        const double *__restrict__ psi2,
+                                                        const double *__restrict__ L64,
+                                                        const double *__restrict__ cost, int nx, int ny, int R,
+                                                        double *__restrict__ part) {
+    __shared__ double sh[kThreads];
+    const size_t n = static_cast<size_t>(nx) * ny * NT;
+    const size_t i = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x;
+    const int W = 2 * R + 1;
+    double c = 0.0, m = 0.0;
+    if (i < n) {
+        const int ko = static_cast<int>(i % NT);
+        const size_t pix = i / NT;
+        const int ix = static_cast<int>(pix % nx), iy = static_cast<int>(pix / nx);
+        const double f = phi2[i];
+        if (f != -INFINITY) {
+            for (int dy = -R; dy <= R; ++dy) {
+                const int jy = iy - dy;
+                if (jy < 0 || jy >= ny) continue;
+                for (int dx = -R; dx <= R; ++dx) {
+                    const int jx = ix - dx;
+                    if (jx < 0 || jx >= nx) continue;
+                    const size_t kb = (static_cast<size_t>((dy + R) * W + (dx + R)) * NT + ko) * NT;
+                    const double *g = psi2 + (static_cast<size_t>(jy) * nx + jx) * NT;
+                    float rs = 0.0f, rc = 0.0f;
+                    for (int ki = 0; ki < NT; ++ki) {
+                        const double u = (f + L64[kb + ki]) + g[ki];
+                        const float p = __builtin_amdgcn_exp2f(static_cast<float>(u));
+                        rs += p;
+                        rc += p * static_cast<float>(cost[kb + ki]);
+                    }
+                    m += rs;
+                    c += rc;
+                }
+            }
+        }
+    }
+    c = block_tree_sum(c, sh);
+    m = block_tree_sum(m, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = c;
+        part[2 * blockIdx.x + 1] = m;
+    }
+}
+
+// Per block: sum over entries with m > 0 of f2 * m.
+__global__ __launch_bounds__(kThreads) void k_dot_pos(const double *__restrict__ f2, const double *__restrict__ m,
+                                                      size_t n, size_t chunk, double *__restrict__ part) {
+    __shared__ double sh[kThreads];
+    const size_t b0 = blockIdx.x * chunk;
+    const size_t b1 = (b0 + chunk < n) ? b0 + chunk : n;
+    double s = 0.0;
+    for (size_t i = b0 + threadIdx.x; i < b1; i += kThreads) {
+        const double w = m[i];
+        if (w > 0.0) s += f2[i] * w;
+    }
+    s = block_tree_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+int grid_for(size_t n) {
+    size_t b = (n + kThreads - 1) / kThreads;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return static_cast<int>(b);
+}
+
+}  // namespace
+
+int launch_scale(const double *in, double *out, size_t n, double mul, hipStream_t s) {
+    if (n == 0) return SE2_OK;
+    hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(kThreads), 0, s, in, out, n, mul);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+int launch_log2_measure(const double *m, double *logm, size_t n, hipStream_t s) {
+    if (n == 0) return SE2_OK;
+    hipLaunchKernelGGL(k_log2m, dim3(grid_for(n)), dim3(kThreads), 0, s, m, logm, n);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+int launch_exp2_out(const double *in2, double *out, size_t n, hipStream_t s) {
+    if (n == 0) return SE2_OK;
+    hipLaunchKernelGGL(k_exp2, dim3(grid_for(n)), dim3(kThreads), 0, s, in2, out, n);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+int launch_fill(double *p, size_t n, double v, hipStream_t s) {
+    if (n == 0) return SE2_OK;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kThreads), 0, s, p, n, v);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+int launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t s) {
+    if (n == 0) return SE2_OK;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(kThreads), 0, s, p, n, v);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+// d_stats receives [sum, bad]; needs a scratch of 2 * 256 doubles after the first 2.
+int launch_validate(const double *m, size_t n, double *d_stats, hipStream_t s) {
+    const int nb = 256;
+    const size_t chunk = (n + nb - 1) / nb;
+    double *part = d_stats + 2;
+    hipLaunchKernelGGL(k_validate_partial, dim3(nb), dim3(kThreads), 0, s, m, n, chunk == 0 ? 1 : chunk, part);
+    SE2_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce_fixed, dim3(1), dim3(kThreads), 0, s, part, nb, 2, d_stats);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+int launch_reduce_fixed(const double *partials, int count, int stride, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_fixed, dim3(1), dim3(kThreads), 0, s, partials, count, stride, out);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+int launch_sum_partials(const double *partials, const int32_t *offsets, int njobs, double *out, hipStream_t s) {
+    if (njobs <= 0) return SE2_OK;
+    hipLaunchKernelGGL(k_sum_partials, dim3(njobs), dim3(kThreads), 0, s, partials, offsets, out);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+int launch_ibp_combine(double *const *lv, const double *const *ld, const double *lambdas, int n, size_t len,
+                       double *logbar, hipStream_t s) {
+    if (n < 1 || n > 16) return SE2_EINVAL;
+    CombineArgs a{};
+    for (int i = 0; i < n; ++i) {
+        a.lv[i] = lv[i];
+        a.ld[i] = ld[i];
+        a.lam[i] = lambdas[i];
+    }
+    hipLaunchKernelGGL(k_ibp_combine, dim3(grid_for(len)), dim3(kThreads), 0, s, a, n, len, logbar);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+// partials must hold 2 * ceil(E / 256) doubles; returns the block count through `tiles`-independent math.
+int launch_plan_cost(const Kernel &k, const double *phi2, const double *psi2, double *partials, int nblocks,
+                     hipStream_t s) {
+    const int nx = k.grid.nx, ny = k.grid.ny, R = k.metric.radius;
+    switch (k.grid.ntheta) {
+        case 8:
+            hipLaunchKernelGGL(k_plan_cost<8>, dim3(nblocks), dim3(kThreads), 0, s, phi2, psi2, k.d_L64, k.d_cost,
+                               nx, ny, R, partials);
+            break;
+        case 16:
+            hipLaunchKernelGGL(k_plan_cost<16>, dim3(nblocks), dim3(kThreads), 0, s, phi2, psi2, k.d_L64,
+                               k.d_cost, nx, ny, R, partials);
+            break;
+        case 32:
+            hipLaunchKernelGGL(k_plan_cost<32>, dim3(nblocks), dim3(kThreads), 0, s, phi2, psi2, k.d_L64,
+                               k.d_cost, nx, ny, R, partials);
+            break;
+        default:
+            return SE2_EINVAL;
+    }
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+int launch_dot_exp(const double *f2, const double *m, size_t n, double *partials, int nblocks, hipStream_t s) {
+    const size_t chunk = (n + nblocks - 1) / nblocks;
+    hipLaunchKernelGGL(k_dot_pos, dim3(nblocks), dim3(kThreads), 0, s, f2, m, n, chunk == 0 ? 1 : chunk, partials);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+}  // namespace se2

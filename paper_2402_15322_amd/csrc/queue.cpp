@@ -1,0 +1,480 @@
+// Serving queue: admission by HBM budget, continuous batching of resident solves.
+//
+// A worker thread owns one HIP stream and one device arena of the budget size.
+// Each request is admitted in arrival order once a slot and enough arena memory
+// are free; its inputs are copied into its slot, its potentials stay resident,
+// and every admitted solve advances one iteration per engine step (one batched
+// launch per half-step and ntheta class covering all of them).  A solve only
+// decides to stop at its own check iterations (multiples of its check_every, or
+// its max_iter), and its tiles and reductions never mix with other solves', so
+// its result is bitwise the same alone or admitted next to others.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+
+#include "solver.h"
+
+namespace se2 {
+namespace {
+
+// First-fit allocator over one device block (offsets in bytes, 256-byte granules).
+class Arena {
+public:
+    bool init(size_t bytes) {
+        size_ = (bytes / 256) * 256;
+        if (size_ == 0) return true;
+        if (hipMalloc(&base_, size_) != hipSuccess) return false;
+        free_[0] = size_;
+        return true;
+    }
+    ~Arena() {
+        if (base_) (void)hipFree(base_);
+    }
+    void *alloc(size_t bytes) {
+        bytes = (bytes + 255) / 256 * 256;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const size_t off = it->first, sz = it->second;
+                free_.erase(it);
+                if (sz > bytes) free_[off + bytes] = sz - bytes;
+                used_[off] = bytes;
+                in_use_ += bytes;
+                return static_cast<char *>(base_) + off;
+            }
+        }
+        return nullptr;
+    }
+    void release(void *p) {
+        const size_t off = static_cast<size_t>(static_cast<char *>(p) - static_cast<char *>(base_));
+        auto u = used_.find(off);
+        if (u == used_.end()) return;
+        size_t sz = u->second;
+        used_.erase(u);
+        in_use_ -= sz;
+        size_t o = off;
+        auto nx = free_.lower_bound(o);
+        if (nx != free_.end() && nx->first == o + sz) {
+            sz += nx->second;
+            free_.erase(nx);
+        }
+        auto pv = free_.lower_bound(o);
+        if (pv != free_.begin()) {
+            --pv;
+            if (pv->first + pv->second == o) {
+                o = pv->first;
+                sz += pv->second;
+                free_.erase(pv);
+            }
+        }
+        free_[o] = sz;
+    }
+    size_t size() const { return size_; }
+
+private:
+    void *base_ = nullptr;
+    size_t size_ = 0, in_use_ = 0;
+    std::map<size_t, size_t> free_, used_;
+};
+
+enum ReqState { WAITING = 0, ACTIVE = 1, DONE = 2 };
+
+struct Req {
+    uint64_t ticket = 0;
+    se2_request_t r{};
+    std::vector<double> lambdas_all;
+    std::vector<const double *> mus_all;
+    Solve s;
+    int state = WAITING;
+    int rc = SE2_OK;
+    se2_report_t rep{};
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    size_t bytes = 0;
+    void *mem = nullptr;
+    std::vector<double *> inputs;  // copies in slot memory
+};
+
+}  // namespace
+}  // namespace se2
+
+struct se2_queue_s {
+    std::mutex mu;
+    std::condition_variable cv, done_cv;
+    std::thread worker;
+    hipStream_t st = nullptr;
+    int device = 0;
+    size_t budget = 0;
+    int max_slots = 1;
+    se2::Arena arena;
+    std::deque<se2::Req *> waiting;
+    std::vector<se2::Req *> active;
+    std::map<uint64_t, std::unique_ptr<se2::Req>> all;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    int64_t admitted = 0, completed = 0, rejected = 0, peak = 0, steps = 0;
+    int prof_request = 0;
+    bool prof_reset = false;
+    double prof_snapshot[4] = {0, 0, 0, 0};
+    se2::Engine eng;
+};
+
+namespace se2 {
+namespace {
+
+size_t request_bytes(const Req &q) {
+    const Kernel &k = *reinterpret_cast<const Kernel *>(q.r.kernel);
+    const size_t E = static_cast<size_t>(k.grid.nx) * k.grid.ny * k.grid.ntheta;
+    const bool prune = q.r.opts.prune != 0;
+    if (q.r.kind == SE2_REQ_OT)
+        return solve_bytes(SE2_REQ_OT, k, 1, prune) + 2 * ((E * sizeof(double) + 255) / 256 * 256);
+    const int n = static_cast<int>(q.mus_all.size());
+    int npos = 0;
+    for (double l : q.lambdas_all) npos += l > 0.0;
+    return solve_bytes(SE2_REQ_BARYCENTER, k, npos, prune) + n * ((E * sizeof(double) + 255) / 256 * 256);
+}
+
+// Bind slot memory, copy inputs, validate, initialise.  Worker thread, queue stream.
+int admit_one(se2_queue_s *Q, Req *q) {
+    const Kernel *k = reinterpret_cast<const Kernel *>(q->r.kernel);
+    const size_t E = static_cast<size_t>(k->grid.nx) * k->grid.ny * k->grid.ntheta;
+    const size_t in_bytes = (E * sizeof(double) + 255) / 256 * 256;
+    Solve &s = q->s;
+    s.kind = q->r.kind;
+    s.k = k;
+    s.opts = q->r.opts;
+    s.opts.init_g = nullptr;
+    s.t_start = now_seconds();
+    char *p = static_cast<char *>(q->mem);
+    const int nin = q->r.kind == SE2_REQ_OT ? 2 : static_cast<int>(q->mus_all.size());
+    for (int i = 0; i < nin; ++i) {
+        double *dst = reinterpret_cast<double *>(p + static_cast<size_t>(i) * in_bytes);
+        const double *src = q->r.kind == SE2_REQ_OT ? (i == 0 ? q->r.mu : q->r.nu) : q->mus_all[i];
+        SE2_HIP(hipMemcpyAsync(dst, src, E * sizeof(double), hipMemcpyDeviceToDevice, Q->st));
+        q->inputs.push_back(dst);
+    }
+    char *solve_mem = p + static_cast<size_t>(nin) * in_bytes;
+    int rc;
+    for (int i = 0; i < nin; ++i)
+        if ((rc = validate_measure(q->inputs[i], E, 1e-9, Q->st))) return rc;
+    if (q->r.kind == SE2_REQ_OT) {
+        s.n = 1;
+        solve_bind(s, solve_mem);
+        return solve_setup_ot(s, q->inputs[0], q->inputs[1], nullptr, Q->st);
+    }
+    std::vector<const double *> act;
+    s.lam.clear();
+    for (size_t i = 0; i < q->mus_all.size(); ++i) {
+        if (q->lambdas_all[i] > 0.0) {
+            act.push_back(q->inputs[i]);
+            s.lam.push_back(q->lambdas_all[i]);
+        }
+    }
+    s.n = static_cast<int>(act.size());
+    solve_bind(s, solve_mem);
+    rc = solve_setup_bary(s, act, Q->st);
+    return rc;
+}
+
+void finish_one(se2_queue_s *Q, Req *q) {
+    if (q->rc == SE2_OK) {
+        if (q->r.kind == SE2_REQ_OT)
+            q->rc = solve_finish_ot(q->s, q->r.f_out, q->r.g_out, &q->rep, Q->st);
+        else
+            q->rc = solve_finish_bary(q->s, q->r.bary_out, &q->rep, Q->st);
+    }
+    (void)hipStreamSynchronize(Q->st);
+    std::lock_guard<std::mutex> lk(Q->mu);
+    Q->arena.release(q->mem);
+    q->mem = nullptr;
+    q->t_done = now_seconds();
+    q->rep.seconds = q->t_done - q->t_submit;
+    q->state = DONE;
+    Q->completed += 1;
+}
+
+void worker_main(se2_queue_s *Q) {
+    (void)hipSetDevice(Q->device);
+    std::vector<double> errs;
+    for (;;) {
+        std::vector<Req *> fresh;
+        {
+            std::unique_lock<std::mutex> lk(Q->mu);
+            Q->cv.wait(lk, [&] { return Q->stop || !Q->waiting.empty() || !Q->active.empty(); });
+            if (Q->prof_reset) {
+                Q->prof_reset = false;
+                (void)Q->eng.collect_profile();
+                Q->eng.set_profiling(Q->prof_request != 0);
+                for (double &v : Q->prof_snapshot) v = 0.0;
+            }
+            if (Q->stop && Q->waiting.empty() && Q->active.empty()) return;
+            // admission in arrival order: stop at the first request that does not fit
+            while (!Q->waiting.empty() && static_cast<int>(Q->active.size() + fresh.size()) < Q->max_slots) {
+                Req *q = Q->waiting.front();
+                void *m = Q->arena.alloc(q->bytes);
+                if (!m) break;
+                q->mem = m;
+                Q->waiting.pop_front();
+                fresh.push_back(q);
+            }
+        }
+        std::vector<Solve *> init;
+        for (Req *q : fresh) {
+            q->t_admit = now_seconds();
+            q->state = ACTIVE;
+            q->rc = admit_one(Q, q);
+            if (q->rc == SE2_OK) init.push_back(&q->s);
+        }
+        if (!init.empty()) {
+            const int rc = Q->eng.init_first_halfstep(init, Q->st);
+            for (Solve *s : init) s->convs = (s->kind == SE2_REQ_OT) ? 1 : s->n;
+            if (rc)
+                for (Req *q : fresh) q->rc = rc;
+        }
+        {
+            std::lock_guard<std::mutex> lk(Q->mu);
+            for (Req *q : fresh) {
+                Q->active.push_back(q);
+                Q->admitted += 1;
+            }
+            if (static_cast<int64_t>(Q->active.size()) > Q->peak) Q->peak = static_cast<int64_t>(Q->active.size());
+        }
+        // failed admissions finish immediately
+        std::vector<Req *> run;
+        for (Req *q : Q->active) {
+            if (q->rc != SE2_OK) finish_one(Q, q);
+            else run.push_back(q);
+        }
+        if (run.empty()) {
+            std::lock_guard<std::mutex> lk(Q->mu);
+            Q->active.clear();
+            Q->done_cv.notify_all();
+            continue;
+        }
+        // one iteration for every running solve
+        std::vector<Solve *> solves;
+        bool check = false;
+        for (Req *q : run) {
+            Solve &s = q->s;
+            solves.push_back(&s);
+            const int next = s.iter + 1;
+            if (next % s.opts.check_every == 0 || next >= s.opts.max_iter) check = true;
+        }
+        int rc = Q->eng.step(solves, check, Q->st);
+        Q->steps += 1;
+        std::vector<Req *> finished;
+        if (rc == SE2_OK && check) rc = Q->eng.read_errors(solves, errs, Q->st);
+        for (size_t i = 0; i < run.size(); ++i) {
+            Req *q = run[i];
+            Solve &s = q->s;
+            if (rc != SE2_OK) {
+                q->rc = rc;
+                finished.push_back(q);
+                continue;
+            }
+            if (!check) continue;
+            const bool own_check = (s.iter % s.opts.check_every == 0) || s.iter >= s.opts.max_iter;
+            if (!own_check) {
+                if (s.kind == SE2_REQ_OT) s.cur ^= 1;
+                continue;
+            }
+            s.last_err = errs[i];
+            if (!std::isfinite(errs[i])) {
+                q->rc = SE2_ENUMERIC;
+                finished.push_back(q);
+            } else if (s.opts.tol_marg_l1 >= 0 && errs[i] <= s.opts.tol_marg_l1) {
+                s.status = SE2_CONVERGED;
+                finished.push_back(q);
+            } else if (s.iter >= s.opts.max_iter) {
+                s.status = SE2_MAX_ITER;
+                finished.push_back(q);
+            } else if (s.kind == SE2_REQ_OT) {
+                s.cur ^= 1;
+            }
+        }
+        if (check) {
+            std::lock_guard<std::mutex> lk(Q->mu);
+            Q->prof_snapshot[0] = Q->eng.prof_seconds;
+            Q->prof_snapshot[1] = Q->eng.prof_terms;
+            Q->prof_snapshot[2] = static_cast<double>(Q->eng.prof_launches);
+            Q->prof_snapshot[3] = Q->eng.prof_outputs;
+        }
+        for (Req *q : finished) finish_one(Q, q);
+        if (!finished.empty()) {
+            std::lock_guard<std::mutex> lk(Q->mu);
+            Q->active.erase(std::remove_if(Q->active.begin(), Q->active.end(),
+                                           [](Req *q) { return q->state == DONE; }),
+                            Q->active.end());
+            Q->done_cv.notify_all();
+        }
+    }
+}
+
+}  // namespace
+}  // namespace se2
+
+using namespace se2;
+
+extern "C" {
+
+int se2_solve_queue_create(size_t hbm_budget_bytes, int32_t max_slots, se2_queue_t *out) {
+    if (!out || max_slots < 1) return SE2_EINVAL;
+    auto *Q = new (std::nothrow) se2_queue_s();
+    if (!Q) return SE2_ENOMEM;
+    Q->budget = hbm_budget_bytes;
+    Q->max_slots = max_slots;
+    if (hipGetDevice(&Q->device) != hipSuccess || hipStreamCreateWithFlags(&Q->st, hipStreamNonBlocking) != hipSuccess) {
+        delete Q;
+        return SE2_EHIP;
+    }
+    if (!Q->arena.init(hbm_budget_bytes)) {
+        (void)hipStreamDestroy(Q->st);
+        delete Q;
+        return SE2_ENOMEM;
+    }
+    Q->worker = std::thread(worker_main, Q);
+    *out = Q;
+    return SE2_OK;
+}
+
+int se2_request_bytes(const se2_request_t *req, size_t *bytes) {
+    if (!req || !bytes || !req->kernel) return SE2_EINVAL;
+    Req q;
+    q.r = *req;
+    if (req->kind == SE2_REQ_BARYCENTER) {
+        if (req->n < 1 || req->n > 16 || !req->lambdas) return SE2_EINVAL;
+        for (int i = 0; i < req->n; ++i) {
+            q.mus_all.push_back(nullptr);
+            q.lambdas_all.push_back(req->lambdas[i]);
+        }
+    } else if (req->kind != SE2_REQ_OT) {
+        return SE2_EINVAL;
+    }
+    *bytes = request_bytes(q);
+    return SE2_OK;
+}
+
+int se2_solve_queue_submit(se2_queue_t Q, const se2_request_t *req, uint64_t *ticket) {
+    if (!Q || !req || !ticket || !req->kernel) return SE2_EINVAL;
+    const se2_opts_t &o = req->opts;
+    if (o.max_iter < 1 || o.check_every < 1 || std::isnan(o.tol_marg_l1)) return SE2_EINVAL;
+    auto q = std::make_unique<Req>();
+    q->r = *req;
+    q->r.opts.init_g = nullptr;
+    if (req->kind == SE2_REQ_OT) {
+        if (!req->mu || !req->nu) return SE2_EINVAL;
+    } else if (req->kind == SE2_REQ_BARYCENTER) {
+        if (req->n < 1 || req->n > 16 || !req->mus || !req->lambdas || !req->bary_out) return SE2_EINVAL;
+        double lsum = 0.0;
+        int npos = 0;
+        for (int i = 0; i < req->n; ++i) {
+            if (!req->mus[i] || !(req->lambdas[i] >= 0.0) || !std::isfinite(req->lambdas[i])) return SE2_EINVAL;
+            lsum += req->lambdas[i];
+            npos += req->lambdas[i] > 0.0;
+            q->mus_all.push_back(req->mus[i]);
+            q->lambdas_all.push_back(req->lambdas[i]);
+        }
+        if (!(std::fabs(lsum - 1.0) <= 1e-12) || npos == 0) return SE2_EINVAL;
+        q->r.mus = nullptr;
+        q->r.lambdas = nullptr;
+    } else {
+        return SE2_EINVAL;
+    }
+    q->bytes = request_bytes(*q);
+    q->t_submit = now_seconds();
+    std::lock_guard<std::mutex> lk(Q->mu);
+    if (q->bytes > Q->arena.size()) {
+        Q->rejected += 1;
+        return SE2_ENOMEM;
+    }
+    q->ticket = Q->next_ticket++;
+    *ticket = q->ticket;
+    Q->waiting.push_back(q.get());
+    Q->all[q->ticket] = std::move(q);
+    Q->cv.notify_all();
+    return SE2_OK;
+}
+
+int se2_solve_queue_poll(se2_queue_t Q, uint64_t ticket, se2_report_t *report) {
+    if (!Q) return SE2_EINVAL;
+    std::lock_guard<std::mutex> lk(Q->mu);
+    auto it = Q->all.find(ticket);
+    if (it == Q->all.end()) return SE2_EINVAL;
+    Req *q = it->second.get();
+    if (q->state != DONE) return SE2_PENDING;
+    if (report) *report = q->rep;
+    return q->rc;
+}
+
+int se2_solve_queue_wait(se2_queue_t Q, uint64_t ticket, se2_report_t *report) {
+    if (!Q) return SE2_EINVAL;
+    std::unique_lock<std::mutex> lk(Q->mu);
+    auto it = Q->all.find(ticket);
+    if (it == Q->all.end()) return SE2_EINVAL;
+    Req *q = it->second.get();
+    Q->done_cv.wait(lk, [&] { return q->state == DONE; });
+    if (report) *report = q->rep;
+    return q->rc;
+}
+
+int se2_solve_queue_times(se2_queue_t Q, uint64_t ticket, double *t_submit, double *t_admit, double *t_done) {
+    if (!Q) return SE2_EINVAL;
+    std::lock_guard<std::mutex> lk(Q->mu);
+    auto it = Q->all.find(ticket);
+    if (it == Q->all.end()) return SE2_EINVAL;
+    Req *q = it->second.get();
+    if (t_submit) *t_submit = q->t_submit;
+    if (t_admit) *t_admit = q->t_admit;
+    if (t_done) *t_done = q->t_done;
+    return q->state == DONE ? SE2_OK : SE2_PENDING;
+}
+
+int se2_solve_queue_stats(se2_queue_t Q, int64_t *out5) {
+    if (!Q || !out5) return SE2_EINVAL;
+    std::lock_guard<std::mutex> lk(Q->mu);
+    out5[0] = Q->admitted;
+    out5[1] = Q->completed;
+    out5[2] = Q->rejected;
+    out5[3] = Q->peak;
+    out5[4] = Q->steps;
+    return SE2_OK;
+}
+
+int se2_solve_queue_profile(se2_queue_t Q, int32_t enable) {
+    if (!Q) return SE2_EINVAL;
+    std::lock_guard<std::mutex> lk(Q->mu);
+    Q->prof_request = enable ? 1 : 0;
+    Q->prof_reset = true;
+    return SE2_OK;
+}
+
+int se2_solve_queue_kernel_time(se2_queue_t Q, double *out4) {
+    if (!Q || !out4) return SE2_EINVAL;
+    std::lock_guard<std::mutex> lk(Q->mu);
+    out4[0] = Q->prof_snapshot[0];
+    out4[1] = Q->prof_snapshot[1];
+    out4[2] = Q->prof_snapshot[2];
+    out4[3] = Q->prof_snapshot[3];
+    return SE2_OK;
+}
+
+int se2_solve_queue_destroy(se2_queue_t Q) {
+    if (!Q) return SE2_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(Q->mu);
+        Q->stop = true;
+        Q->cv.notify_all();
+    }
+    if (Q->worker.joinable()) Q->worker.join();
+    (void)hipStreamSynchronize(Q->st);
+    (void)hipStreamDestroy(Q->st);
+    delete Q;
+    return SE2_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,143 @@
+// Internal declarations of the SE(2) entropic-OT library (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/se2ot.h"
+
+namespace se2 {
+
+// Everything on the device works in base-2 log units: a log-scaling phi2 =
+// f / (eps ln 2) and a log-kernel L2 = -rho^2 / (eps ln 2), so every exponential
+// is a native exp2.  The C ABI speaks natural logs and converts at the edges.
+constexpr double kLn2 = 0.693147180559945309417232121458176568;
+constexpr double kLog2e = 1.442695040888963407359924681001892137;
+
+constexpr int kTile = 8;          // output tile of the log-domain kernels: 8 x 8 pixels
+constexpr int kConvThreads = 256; // 4 waves of 64
+constexpr int kMaxRadius = 12;
+
+// Certified pruning of the log-domain convolution (base-2 units): entries within
+// kListCut of an output's maximum are listed; a list stays in use while the drift
+// of the input from the halo it was built on spreads over at most kDriftSpread, so
+// every skipped entry is below 2^-(kListCut - kDriftSpread) = 2^-48 of the
+// result's largest term.
+constexpr double kListCut = 64.0;
+constexpr float kDriftSpread = 16.0f;
+constexpr int kListMax = 512;               // entries per (tile, ko); longer lists fall back to dense
+constexpr int kListLds = 2048;              // entries per tile staged in LDS; more fall back to dense
+constexpr size_t kSparseLdsMax = 98304;     // the sparse path keeps the full FP64 halo in LDS
+
+struct ListEntry {
+    double L;     // log2 kernel value of the entry
+    int32_t off;  // LDS offset of the input relative to the output pixel: ki*npix + (R-dy)*HW + (R-dx)
+    int32_t pad;
+};
+
+#define SE2_HIP(call)                                                  \
+    do {                                                               \
+        hipError_t e_ = (call);                                        \
+        if (e_ != hipSuccess) {                                        \
+            se2::set_last_hip_error(e_, #call, __FILE__, __LINE__);    \
+            return SE2_EHIP;                                           \
+        }                                                              \
+    } while (0)
+
+void set_last_hip_error(hipError_t e, const char *what, const char *file, int line);
+
+// Device-side description of one log-domain convolution applied to one grid array.
+enum Epilogue : int32_t {
+    EPI_RAW = 0,   // out = LSE
+    EPI_SCALE = 1, // out = logm - LSE  (Sinkhorn half-step / IBP w-update), error partial vs old
+    EPI_ADD = 2,   // out = base + LSE   (IBP d-update: log d = log v + log K*w)
+};
+
+struct ConvJob {
+    const double *in;   // log2 input [ny][nx][nt]
+    double *out;        // log2 output
+    const double *aux;  // EPI_SCALE: log2 marginal; EPI_ADD: base array
+    const double *old;  // EPI_SCALE: previous output for the marginal error (may be null)
+    double *partial;    // EPI_SCALE: one FP64 error partial per tile (may be null)
+    const double *L64;  // log2 kernel [W][W][nt][nt], FP64
+    const float *L32;   // the same in FP32 (max pass only)
+    // certified pruning state of this (solve, direction); lists == nullptr: dense only
+    ListEntry *lists;   // [tiles][nt][lmax]
+    double *ref;        // [tiles][nt * npix] input halo the lists were built on
+    int32_t *len;       // [tiles][nt], -1 = none
+    float *mref;        // [E] per-output maximum exponent at build time
+    int32_t *dense_flag; // [tiles] dense visits (diagnostics), may be null
+    double *work;       // [tiles][2] in-grid LSE terms evaluated on the dense / sparse path, may be null
+    int32_t nx, ny, R, epi;
+    int32_t tiles_x, tiles, first_block, lmax;
+};
+
+// Pruning state of one convolution direction of one solve.
+struct ListSet {
+    ListEntry *lists = nullptr;
+    double *ref = nullptr;
+    int32_t *len = nullptr;
+    float *mref = nullptr;
+    int32_t *dense_flag = nullptr;
+    double *work = nullptr;
+};
+
+struct Kernel {
+    se2_grid_t grid;
+    se2_metric_t metric;
+    int W = 0;                  // 2R+1
+    size_t entries = 0;         // W*W*nt*nt
+    std::vector<double> logk;   // natural-log kernel (host copy)
+    std::vector<double> cost;   // rho^2 (host copy)
+    double *d_L64 = nullptr;    // log2 kernel, FP64
+    float *d_L32 = nullptr;     // log2 kernel, FP32
+    double *d_cost = nullptr;   // rho^2, FP64
+    float *d_K32 = nullptr;     // exp(logk) in FP32 (zero below the FP32 range)
+    uint16_t *d_Kbf16 = nullptr; // exp(logk) in bfloat16 (RNE), table layout
+    double *d_K64 = nullptr;    // exp(logk) in FP64
+    uint16_t *d_Bpack = nullptr; // bfloat16 kernel packed in MFMA B-operand order
+    int nonzero_bf16 = 0;       // window offsets with any nonzero bfloat16 entry
+    int device = 0;
+};
+
+// kernel_table.cpp
+int build_tables(Kernel &k);
+
+// launchers (conv_lse.hip)
+int launch_conv_lse(const ConvJob *d_jobs, int njobs, int nblocks, const int32_t *d_block_job, int nt, int R_max,
+                    bool f64exp, bool sparse, hipStream_t s);
+bool conv_lse_sparse_fits(int nt, int R);
+
+// launchers (conv_linear.hip)
+std::vector<uint16_t> pack_bf16_operand(const std::vector<uint16_t> &Kb, int nt, int R);
+size_t conv_bf16_lds_bytes(int nt, int R);
+int launch_conv_bf16(const Kernel &k, const float *in, float *out, int batch, hipStream_t s);
+int launch_conv_f32(const Kernel &k, const float *in, float *out, int batch, hipStream_t s);
+int launch_conv_f64(const Kernel &k, const double *in, double *out, int batch, hipStream_t s);
+
+// elementwise.hip
+int launch_scale(const double *in, double *out, size_t n, double mul, hipStream_t s);
+int launch_log2_measure(const double *m, double *logm, size_t n, hipStream_t s);
+int launch_validate(const double *m, size_t n, double *d_stats /* 3 doubles */, hipStream_t s);
+int launch_fill(double *p, size_t n, double v, hipStream_t s);
+int launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t s);
+int launch_sum_partials(const double *partials, const int32_t *offsets, int njobs, double *out, hipStream_t s);
+int launch_ibp_combine(double *const *lv, const double *const *ld, const double *lambdas, int n, size_t len,
+                       double *logbar, hipStream_t s);
+int launch_plan_cost(const Kernel &k, const double *phi2, const double *psi2, double *partials /* per tile x 3 */,
+                     int tiles, hipStream_t s);
+int launch_reduce_fixed(const double *partials, int count, int stride, double *out, hipStream_t s);
+int launch_exp2_out(const double *in2, double *out, size_t n, hipStream_t s);
+int launch_dot_exp(const double *f2, const double *m, size_t n, double *partials, int nblocks, hipStream_t s);
+
+// api.cpp: device-side FP64 check of a probability vector (finite, >= 0, |sum - 1| <= tol); syncs `st`.
+int validate_measure(const double *m, size_t n, double tol, hipStream_t st);
+
+// helpers
+inline int tiles_of(int n) { return (n + kTile - 1) / kTile; }
+
+}  // namespace se2

@@ -1,0 +1,627 @@
+// Sinkhorn and IBP state machines on the device, and the batched stepping engine.
+//
+// Sinkhorn (Section 4.1), log form with phi = log a, psi = log b in base-2 units:
+//     phi_{l+1} = log mu - LSE(L + psi_l),   psi_{l+1} = log nu - LSE(L + phi_{l+1}),
+// psi_0 = 0 (or a warm start), K^T = K.  Iteration l = b-update then a-update; the
+// a-update of iteration l+1 also yields the first-marginal L1 error of (phi_l, psi_l),
+//     e_l = sum_x mu(x) |2^(phi_l(x) - phi_{l+1}(x)) - 1|,
+// whose second marginal is exact.  phi is double-buffered so that the iterate
+// whose error was measured is the one returned.
+//
+// IBP barycenter (Appendix A), log form, measures with lambda_i > 0 only:
+//     w-update  lw_i = log mu_i - LSE(L + lv_i)
+//     d-update  ld_i = lv_i + LSE(L + lw_i)
+//     combine   log bar = sum_i lambda_i ld_i,  lv_i += log bar - ld_i
+// The w-update of iteration j+1 yields max_i sum mu_i |2^(lw_i^(j) - lw_i^(j+1)) - 1|,
+// the mu_i-side marginal error of iterate j (its barycenter side is exact).
+#include "solver.h"
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+namespace se2 {
+
+double now_seconds() {
+    using clk = std::chrono::steady_clock;
+    return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
+}
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+
+struct Carver {
+    char *p;
+    size_t used = 0;
+    template <typename T>
+    T *take(size_t count) {
+        T *r = p ? reinterpret_cast<T *>(p + used) : nullptr;
+        used += up(count * sizeof(T));
+        return r;
+    }
+};
+
+int cost_blocks(size_t E) { return static_cast<int>((E + 255) / 256); }
+
+ListSet carve_lists(Carver &c, const Kernel &k, size_t E, int tiles, bool prune) {
+    const int nt = k.grid.ntheta, HW = kTile + 2 * k.metric.radius;
+    ListSet l;
+    if (prune) {
+        l.lists = c.take<ListEntry>(static_cast<size_t>(tiles) * nt * kListMax);
+        l.ref = c.take<double>(static_cast<size_t>(tiles) * nt * HW * HW);
+        l.len = c.take<int32_t>(static_cast<size_t>(tiles) * nt);
+        l.mref = c.take<float>(E);
+    }
+    l.dense_flag = c.take<int32_t>(static_cast<size_t>(tiles));
+    l.work = c.take<double>(2 * static_cast<size_t>(tiles));
+    return l;
+}
+
+// Lays out every buffer of a solve; with mem == nullptr it only measures.
+size_t carve(Solve &s, int kind, const Kernel &k, int n, bool prune, void *mem) {
+    const size_t E = static_cast<size_t>(k.grid.nx) * k.grid.ny * k.grid.ntheta;
+    const int tiles = tiles_of(k.grid.nx) * tiles_of(k.grid.ny);
+    prune = prune && conv_lse_sparse_fits(k.grid.ntheta, k.metric.radius);
+    const int nj = kind == SE2_REQ_OT ? 1 : n;
+    const size_t npart = static_cast<size_t>(tiles) * nj;
+    const size_t ncost = 2 * static_cast<size_t>(cost_blocks(E)) * nj + 512;
+    Carver c{static_cast<char *>(mem)};
+    if (kind == SE2_REQ_OT) {
+        s.lmu = c.take<double>(E);
+        s.lnu = c.take<double>(E);
+        s.phi[0] = c.take<double>(E);
+        s.phi[1] = c.take<double>(E);
+        s.psi = c.take<double>(E);
+        s.ls_phi = carve_lists(c, k, E, tiles, prune);
+        s.ls_psi = carve_lists(c, k, E, tiles, prune);
+    } else {
+        s.lm.assign(n, nullptr);
+        s.lv.assign(n, nullptr);
+        s.lw.assign(n, nullptr);
+        s.ld.assign(n, nullptr);
+        for (int i = 0; i < n; ++i) {
+            s.lm[i] = c.take<double>(E);
+            s.lv[i] = c.take<double>(E);
+            s.lw[i] = c.take<double>(E);
+            s.ld[i] = c.take<double>(E);
+        }
+        s.logbar = c.take<double>(E);
+        s.phi[0] = c.take<double>(E);  // scratch for the FP64 check
+        s.ls_v.assign(n, ListSet());
+        s.ls_w.assign(n, ListSet());
+        for (int i = 0; i < n; ++i) {
+            s.ls_v[i] = carve_lists(c, k, E, tiles, prune);
+            s.ls_w[i] = carve_lists(c, k, E, tiles, prune);
+        }
+    }
+    s.partial = c.take<double>(npart > ncost ? npart : ncost);
+    s.err = c.take<double>(static_cast<size_t>(nj) + 8);
+    s.offsets = c.take<int32_t>(static_cast<size_t>(nj) + 1);
+    return c.used;
+}
+
+}  // namespace
+
+double conv_terms(const Kernel &k) {
+    const int R = k.metric.radius, nt = k.grid.ntheta;
+    double sx = 0.0, sy = 0.0;
+    for (int d = -R; d <= R; ++d) {
+        sx += (k.grid.nx - std::abs(d)) > 0 ? (k.grid.nx - std::abs(d)) : 0;
+        sy += (k.grid.ny - std::abs(d)) > 0 ? (k.grid.ny - std::abs(d)) : 0;
+    }
+    return sx * sy * nt * nt;
+}
+
+size_t solve_bytes(int kind, const Kernel &k, int n_active, bool prune) {
+    Solve tmp;
+    return carve(tmp, kind, k, n_active, prune, nullptr);
+}
+
+bool prune_enabled(const Solve &s) {
+    return s.opts.prune != 0 && conv_lse_sparse_fits(s.k->grid.ntheta, s.k->metric.radius);
+}
+
+void solve_bind(Solve &s, void *mem) {
+    s.E = static_cast<size_t>(s.k->grid.nx) * s.k->grid.ny * s.k->grid.ntheta;
+    s.tiles = tiles_of(s.k->grid.nx) * tiles_of(s.k->grid.ny);
+    s.bytes = carve(s, s.kind, *s.k, s.n, s.opts.prune != 0, mem);
+    s.block = mem;
+}
+
+namespace {
+int reset_list(const ListSet &l, const Solve &s, hipStream_t st) {
+    const size_t nt = s.k->grid.ntheta;
+    int rc = SE2_OK;
+    if (l.len) rc = launch_fill_i32(l.len, static_cast<size_t>(s.tiles) * nt, -1, st);
+    if (rc == SE2_OK && l.dense_flag) rc = launch_fill_i32(l.dense_flag, static_cast<size_t>(s.tiles), 0, st);
+    if (rc == SE2_OK && l.work) rc = launch_fill(l.work, 2 * static_cast<size_t>(s.tiles), 0.0, st);
+    return rc;
+}
+}  // namespace
+
+int solve_reset_lists(Solve &s, hipStream_t st) {
+    int rc = SE2_OK;
+    if (s.kind == SE2_REQ_OT) {
+        if ((rc = reset_list(s.ls_phi, s, st))) return rc;
+        return reset_list(s.ls_psi, s, st);
+    }
+    for (int i = 0; i < s.n; ++i) {
+        if ((rc = reset_list(s.ls_v[i], s, st))) return rc;
+        if ((rc = reset_list(s.ls_w[i], s, st))) return rc;
+    }
+    return rc;
+}
+
+int solve_setup_ot(Solve &s, const double *mu, const double *nu, const double *init_g, hipStream_t st) {
+    s.mu_lin = mu;
+    s.nu_lin = nu;
+    int rc;
+    if ((rc = launch_log2_measure(mu, s.lmu, s.E, st))) return rc;
+    if ((rc = launch_log2_measure(nu, s.lnu, s.E, st))) return rc;
+    // g/eps (natural) -> base-2 units: multiply by log2(e)
+    if (init_g) {
+        if ((rc = launch_scale(init_g, s.psi, s.E, kLog2e, st))) return rc;
+    } else if ((rc = launch_fill(s.psi, s.E, 0.0, st))) {
+        return rc;
+    }
+    if ((rc = solve_reset_lists(s, st))) return rc;
+    std::vector<int32_t> off = {0, s.tiles};
+    SE2_HIP(hipMemcpyAsync(s.offsets, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    SE2_HIP(hipStreamSynchronize(st));  // `off` is a host temporary
+    s.cur = 0;
+    s.iter = 0;
+    s.done = false;
+    return SE2_OK;
+}
+
+int solve_setup_bary(Solve &s, const std::vector<const double *> &mus, hipStream_t st) {
+    int rc;
+    s.m_lin = mus;
+    for (int i = 0; i < s.n; ++i) {
+        if ((rc = launch_log2_measure(mus[i], s.lm[i], s.E, st))) return rc;
+        if ((rc = launch_fill(s.lv[i], s.E, 0.0, st))) return rc;
+    }
+    if ((rc = solve_reset_lists(s, st))) return rc;
+    std::vector<int32_t> off(s.n + 1);
+    for (int i = 0; i <= s.n; ++i) off[i] = i * s.tiles;
+    SE2_HIP(hipMemcpyAsync(s.offsets, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    SE2_HIP(hipStreamSynchronize(st));
+    s.iter = 0;
+    s.done = false;
+    return SE2_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Engine
+// ---------------------------------------------------------------------------
+
+Engine::Engine() {}
+
+void Engine::set_profiling(bool on) {
+    prof_ = on;
+    prof_seconds = prof_terms = prof_outputs = 0.0;
+    prof_launches = 0;
+}
+
+int Engine::collect_profile() {
+    for (Pending &p : pending_) {
+        float ms = 0.0f;
+        SE2_HIP(hipEventSynchronize(p.b));
+        SE2_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+        prof_seconds += 1e-3 * ms;
+        prof_terms += p.terms;
+        prof_outputs += p.outputs;
+        prof_launches += 1;
+        spare_.push_back(p.a);
+        spare_.push_back(p.b);
+    }
+    pending_.clear();
+    return SE2_OK;
+}
+
+Engine::~Engine() {
+    for (Pending &p : pending_) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (hipEvent_t e : spare_) (void)hipEventDestroy(e);
+    if (d_jobs_) (void)hipFree(d_jobs_);
+    if (d_map_) (void)hipFree(d_map_);
+    if (h_jobs_) (void)hipHostFree(h_jobs_);
+    if (h_map_) (void)hipHostFree(h_map_);
+    if (h_err_) (void)hipHostFree(h_err_);
+    for (auto &e : staged_)
+        if (e) (void)hipEventDestroy(e);
+}
+
+int Engine::ensure(size_t njobs, size_t nblocks) {
+    if (!staged_[0]) {
+        SE2_HIP(hipEventCreateWithFlags(&staged_[0], hipEventDisableTiming));
+        SE2_HIP(hipEventCreateWithFlags(&staged_[1], hipEventDisableTiming));
+    }
+    if (njobs > cap_jobs_ || nblocks > cap_blocks_) {
+        // wait until both staging halves are free before reallocating
+        SE2_HIP(hipEventSynchronize(staged_[0]));
+        SE2_HIP(hipEventSynchronize(staged_[1]));
+        size_t nj = njobs > cap_jobs_ ? njobs * 2 : cap_jobs_;
+        size_t nb = nblocks > cap_blocks_ ? nblocks * 2 : cap_blocks_;
+        if (d_jobs_) SE2_HIP(hipFree(d_jobs_));
+        if (d_map_) SE2_HIP(hipFree(d_map_));
+        if (h_jobs_) SE2_HIP(hipHostFree(h_jobs_));
+        if (h_map_) SE2_HIP(hipHostFree(h_map_));
+        // device side: 2 halves as well, so an in-flight launch never sees its table rewritten
+        SE2_HIP(hipMalloc(&d_jobs_, 2 * nj * sizeof(ConvJob)));
+        SE2_HIP(hipMalloc(&d_map_, 2 * nb * sizeof(int32_t)));
+        SE2_HIP(hipHostMalloc(&h_jobs_, 2 * nj * sizeof(ConvJob), hipHostMallocDefault));
+        SE2_HIP(hipHostMalloc(&h_map_, 2 * nb * sizeof(int32_t), hipHostMallocDefault));
+        cap_jobs_ = nj;
+        cap_blocks_ = nb;
+    }
+    return SE2_OK;
+}
+
+int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool with_err, hipStream_t st) {
+    // group jobs by ntheta (the kernel is specialised on it)
+    static const int kClasses[3] = {8, 16, 32};
+    for (int nt : kClasses) {
+        std::vector<ConvJob> jobs;
+        int R_max = 0;
+        int nblocks = 0;
+        bool any_lists = false;
+        for (Solve *s : solves) {
+            if (s->k->grid.ntheta != nt) continue;
+            const Kernel &k = *s->k;
+            ConvJob base{};
+            base.L64 = k.d_L64;
+            base.L32 = k.d_L32;
+            base.nx = k.grid.nx;
+            base.ny = k.grid.ny;
+            base.R = k.metric.radius;
+            base.tiles_x = tiles_of(k.grid.nx);
+            base.tiles = s->tiles;
+            base.lmax = kListMax;
+            if (base.R > R_max) R_max = base.R;
+            auto attach = [&](ConvJob &j, const ListSet &l) {
+                j.lists = l.lists;
+                j.ref = l.ref;
+                j.len = l.len;
+                j.mref = l.mref;
+                j.dense_flag = l.dense_flag;
+                j.work = l.work;
+                if (l.lists) any_lists = true;
+            };
+            if (s->kind == SE2_REQ_OT) {
+                ConvJob j = base;
+                if (stage == 0) {  // b-update: psi = log nu - LSE(L + phi[cur])
+                    j.in = s->phi[s->cur];
+                    j.out = s->psi;
+                    j.aux = s->lnu;
+                    j.epi = EPI_SCALE;
+                    attach(j, s->ls_phi);
+                } else {  // a-update: phi[1-cur] = log mu - LSE(L + psi)
+                    j.in = s->psi;
+                    j.out = s->phi[1 - s->cur];
+                    j.aux = s->lmu;
+                    j.epi = EPI_SCALE;
+                    attach(j, s->ls_psi);
+                    if (with_err) {
+                        j.old = s->phi[s->cur];
+                        j.partial = s->partial;
+                    }
+                }
+                j.first_block = nblocks;
+                nblocks += j.tiles;
+                jobs.push_back(j);
+            } else {
+                for (int i = 0; i < s->n; ++i) {
+                    ConvJob j = base;
+                    if (stage == 0) {  // d-update: ld_i = lv_i + LSE(L + lw_i)
+                        j.in = s->lw[i];
+                        j.out = s->ld[i];
+                        j.aux = s->lv[i];
+                        j.epi = EPI_ADD;
+                        attach(j, s->ls_w[i]);
+                    } else {  // w-update: lw_i = log mu_i - LSE(L + lv_i)
+                        j.in = s->lv[i];
+                        j.out = s->lw[i];
+                        j.aux = s->lm[i];
+                        j.epi = EPI_SCALE;
+                        attach(j, s->ls_v[i]);
+                        if (with_err) {
+                            j.old = s->lw[i];
+                            j.partial = s->partial + static_cast<size_t>(i) * s->tiles;
+                        }
+                    }
+                    j.first_block = nblocks;
+                    nblocks += j.tiles;
+                    jobs.push_back(j);
+                }
+            }
+        }
+        if (jobs.empty()) continue;
+        int rc = ensure(jobs.size(), nblocks);
+        if (rc) return rc;
+        const int h = flip_;
+        flip_ ^= 1;
+        SE2_HIP(hipEventSynchronize(staged_[h]));  // the copy that last read this half is done
+        ConvJob *hj = h_jobs_ + h * cap_jobs_;
+        int32_t *hm = h_map_ + h * cap_blocks_;
+        ConvJob *dj = d_jobs_ + h * cap_jobs_;
+        int32_t *dm = d_map_ + h * cap_blocks_;
+        std::memcpy(hj, jobs.data(), jobs.size() * sizeof(ConvJob));
+        for (size_t q = 0; q < jobs.size(); ++q)
+            for (int b = 0; b < jobs[q].tiles; ++b) hm[jobs[q].first_block + b] = static_cast<int32_t>(q);
+        SE2_HIP(hipMemcpyAsync(dj, hj, jobs.size() * sizeof(ConvJob), hipMemcpyHostToDevice, st));
+        SE2_HIP(hipMemcpyAsync(dm, hm, static_cast<size_t>(nblocks) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        SE2_HIP(hipEventRecord(staged_[h], st));
+        const bool f64 = false;
+        Pending pe{};
+        if (prof_) {
+            for (int q = 0; q < 2; ++q) {
+                hipEvent_t e = nullptr;
+                if (!spare_.empty()) {
+                    e = spare_.back();
+                    spare_.pop_back();
+                } else {
+                    SE2_HIP(hipEventCreate(&e));
+                }
+                (q == 0 ? pe.a : pe.b) = e;
+            }
+            for (Solve *s : solves) {
+                if (s->k->grid.ntheta != nt) continue;
+                const double c = (s->kind == SE2_REQ_OT) ? 1.0 : s->n;
+                pe.terms += c * conv_terms(*s->k);
+                pe.outputs += c * static_cast<double>(s->E);
+            }
+            SE2_HIP(hipEventRecord(pe.a, st));
+        }
+        rc = launch_conv_lse(dj, static_cast<int>(jobs.size()), nblocks, dm, nt, R_max, f64, any_lists, st);
+        if (rc) return rc;
+        if (prof_) {
+            SE2_HIP(hipEventRecord(pe.b, st));
+            pending_.push_back(pe);
+        }
+        // The device tables of half h are only rewritten after staged_[h] completes a second
+        // time, i.e. after this launch (stream order) has consumed them.
+        for (Solve *s : solves) s->convs += (s->k->grid.ntheta == nt) ? (s->kind == SE2_REQ_OT ? 1 : s->n) : 0;
+    }
+    return SE2_OK;
+}
+
+int Engine::init_first_halfstep(const std::vector<Solve *> &solves, hipStream_t st) {
+    const int rc = launch_stage(solves, 1, false, st);
+    if (rc) return rc;
+    // the first a-update wrote phi[1 - cur]: that is the current a-potential now
+    for (Solve *s : solves)
+        if (s->kind == SE2_REQ_OT) s->cur ^= 1;
+    return SE2_OK;
+}
+
+int Engine::step(const std::vector<Solve *> &solves, bool check, hipStream_t st) {
+    int rc = launch_stage(solves, 0, false, st);
+    if (rc) return rc;
+    for (Solve *s : solves) {
+        if (s->kind != SE2_REQ_BARYCENTER) continue;
+        std::vector<const double *> ld(s->ld.begin(), s->ld.end());
+        rc = launch_ibp_combine(s->lv.data(), ld.data(), s->lam.data(), s->n, s->E, s->logbar, st);
+        if (rc) return rc;
+    }
+    rc = launch_stage(solves, 1, check, st);
+    if (rc) return rc;
+    for (Solve *s : solves) {
+        s->iter += 1;
+        if (check) {
+            rc = launch_sum_partials(s->partial, s->offsets, s->kind == SE2_REQ_OT ? 1 : s->n, s->err, st);
+            if (rc) return rc;
+        } else if (s->kind == SE2_REQ_OT) {
+            s->cur ^= 1;  // the new a-potential becomes current; nobody needs the old one
+        }
+    }
+    return SE2_OK;
+}
+
+int Engine::read_errors(const std::vector<Solve *> &solves, std::vector<double> &max_err, hipStream_t st) {
+    size_t total = 0;
+    for (Solve *s : solves) total += (s->kind == SE2_REQ_OT) ? 1 : s->n;
+    if (total > cap_err_) {
+        if (h_err_) SE2_HIP(hipHostFree(h_err_));
+        SE2_HIP(hipHostMalloc(&h_err_, total * 2 * sizeof(double), hipHostMallocDefault));
+        cap_err_ = total * 2;
+    }
+    size_t off = 0;
+    for (Solve *s : solves) {
+        const size_t c = (s->kind == SE2_REQ_OT) ? 1 : s->n;
+        SE2_HIP(hipMemcpyAsync(h_err_ + off, s->err, c * sizeof(double), hipMemcpyDeviceToHost, st));
+        off += c;
+    }
+    SE2_HIP(hipStreamSynchronize(st));
+    if (prof_) {
+        int rc = collect_profile();
+        if (rc) return rc;
+    }
+    max_err.assign(solves.size(), 0.0);
+    off = 0;
+    for (size_t q = 0; q < solves.size(); ++q) {
+        const size_t c = (solves[q]->kind == SE2_REQ_OT) ? 1 : solves[q]->n;
+        double m = 0.0;
+        for (size_t i = 0; i < c; ++i) {
+            const double e = h_err_[off + i];
+            if (!(e <= m)) m = e;  // NaN propagates
+        }
+        max_err[q] = m;
+        off += c;
+    }
+    return SE2_OK;
+}
+
+// ---------------------------------------------------------------------------
+// finishing
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// FP64 re-check of the marginal error: out = aux - LSE_f64(L + in) vs old.
+int f64_check(const Kernel &k, const double *in, const double *aux, const double *old, double *scratch_out,
+              double *partial, double *err_out, const int32_t *offsets, int tiles, hipStream_t st) {
+    ConvJob j{};
+    j.in = in;
+    j.out = scratch_out;
+    j.aux = aux;
+    j.old = old;
+    j.partial = partial;
+    j.L64 = k.d_L64;
+    j.L32 = k.d_L32;
+    j.nx = k.grid.nx;
+    j.ny = k.grid.ny;
+    j.R = k.metric.radius;
+    j.epi = EPI_SCALE;
+    j.tiles_x = tiles_of(k.grid.nx);
+    j.tiles = tiles;
+    j.first_block = 0;
+    ConvJob *dj = nullptr;
+    int32_t *dm = nullptr;
+    SE2_HIP(hipMallocAsync(reinterpret_cast<void **>(&dj), sizeof(ConvJob), st));
+    SE2_HIP(hipMallocAsync(reinterpret_cast<void **>(&dm), tiles * sizeof(int32_t), st));
+    SE2_HIP(hipMemcpyAsync(dj, &j, sizeof(ConvJob), hipMemcpyHostToDevice, st));
+    SE2_HIP(hipMemsetAsync(dm, 0, tiles * sizeof(int32_t), st));
+    int rc = launch_conv_lse(dj, 1, tiles, dm, k.grid.ntheta, k.metric.radius, true, false, st);
+    if (rc) return rc;
+    rc = launch_sum_partials(partial, offsets, 1, err_out, st);
+    if (rc) return rc;
+    SE2_HIP(hipStreamSynchronize(st));  // `j` lives on this frame
+    SE2_HIP(hipFreeAsync(dj, st));
+    SE2_HIP(hipFreeAsync(dm, st));
+    return SE2_OK;
+}
+
+int read_scalar(const double *d, double *h, hipStream_t st) {
+    SE2_HIP(hipMemcpyAsync(h, d, sizeof(double), hipMemcpyDeviceToHost, st));
+    SE2_HIP(hipStreamSynchronize(st));
+    return SE2_OK;
+}
+
+}  // namespace
+
+namespace {
+// Sum of the dense and sparse term counters of a list set (host copy; syncs `st`).
+int read_work(const ListSet &l, int tiles, double *dense, double *sparse, hipStream_t st) {
+    if (!l.work) return SE2_OK;
+    std::vector<double> h(2 * static_cast<size_t>(tiles));
+    SE2_HIP(hipMemcpyAsync(h.data(), l.work, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    SE2_HIP(hipStreamSynchronize(st));
+    for (int t = 0; t < tiles; ++t) {
+        *dense += h[2 * t];
+        *sparse += h[2 * t + 1];
+    }
+    return SE2_OK;
+}
+}  // namespace
+
+int solve_finish_ot(Solve &s, double *f_out, double *g_out, se2_report_t *rep, hipStream_t st) {
+    const Kernel &k = *s.k;
+    const double scale = k.metric.eps * kLn2;  // base-2 log-scaling -> eps * natural log
+    const double *phi = s.phi[s.cur];
+    int rc;
+    if (f_out && (rc = launch_scale(phi, f_out, s.E, scale, st))) return rc;
+    if (g_out && (rc = launch_scale(s.psi, g_out, s.E, scale, st))) return rc;
+    se2_report_t r{};
+    r.status = s.status;
+    r.iters = s.iter;
+    r.marg_l1 = s.last_err;
+    r.marg_l1_f64 = -1.0;
+    r.convs = s.convs;
+    // plan cost and mass
+    const int nb = cost_blocks(s.E);
+    double *part = s.partial;  // large enough: >= 2 * nb + 512
+    if ((rc = launch_plan_cost(k, phi, s.psi, part, nb, st))) return rc;
+    if ((rc = launch_reduce_fixed(part, nb, 2, s.err + 2, st))) return rc;
+    double cm[2] = {0, 0};
+    SE2_HIP(hipMemcpyAsync(cm, s.err + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    // dual <f, mu> + <g, nu>
+    const int dnb = 256;
+    if ((rc = launch_dot_exp(phi, s.mu_lin, s.E, part, dnb, st))) return rc;
+    if ((rc = launch_reduce_fixed(part, dnb, 1, s.err + 4, st))) return rc;
+    if ((rc = launch_dot_exp(s.psi, s.nu_lin, s.E, part, dnb, st))) return rc;
+    if ((rc = launch_reduce_fixed(part, dnb, 1, s.err + 5, st))) return rc;
+    double dd[2] = {0, 0};
+    SE2_HIP(hipMemcpyAsync(dd, s.err + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    SE2_HIP(hipStreamSynchronize(st));
+    r.cost = cm[0];
+    r.mass = cm[1];
+    r.dual = scale * (dd[0] + dd[1]);
+    if (s.opts.final_check) {
+        // first marginal: a-update from psi in FP64 vs phi; second: b-update from phi vs psi
+        double e1 = 0, e2 = 0;
+        double *scratch = s.phi[1 - s.cur];
+        if ((rc = f64_check(k, s.psi, s.lmu, phi, scratch, s.partial, s.err + 6, s.offsets, s.tiles, st))) return rc;
+        if ((rc = read_scalar(s.err + 6, &e1, st))) return rc;
+        if ((rc = f64_check(k, phi, s.lnu, s.psi, scratch, s.partial, s.err + 6, s.offsets, s.tiles, st))) return rc;
+        if ((rc = read_scalar(s.err + 6, &e2, st))) return rc;
+        r.marg_l1_f64 = e1 + e2;
+    }
+    if ((rc = read_work(s.ls_phi, s.tiles, &r.terms_dense, &r.terms_sparse, st))) return rc;
+    if ((rc = read_work(s.ls_psi, s.tiles, &r.terms_dense, &r.terms_sparse, st))) return rc;
+    r.seconds = now_seconds() - s.t_start;
+    if (!std::isfinite(r.cost) || !std::isfinite(r.marg_l1)) rc = SE2_ENUMERIC;
+    else rc = SE2_OK;
+    if (rep) *rep = r;
+    return rc;
+}
+
+int solve_finish_bary(Solve &s, double *bary_out, se2_report_t *rep, hipStream_t st) {
+    const Kernel &k = *s.k;
+    int rc;
+    if ((rc = launch_exp2_out(s.logbar, bary_out, s.E, st))) return rc;
+    se2_report_t r{};
+    r.status = s.status;
+    r.iters = s.iter;
+    r.marg_l1 = s.last_err;
+    r.marg_l1_f64 = -1.0;
+    r.convs = s.convs;
+    // sum_i lambda_i <pi_i, rho^2> with pi_i = diag(w_i) K diag(v_i) (first marginal exact)
+    const int nb = cost_blocks(s.E);
+    double cost = 0.0;
+    for (int i = 0; i < s.n; ++i) {
+        if ((rc = launch_plan_cost(k, s.lw[i], s.lv[i], s.partial, nb, st))) return rc;
+        if ((rc = launch_reduce_fixed(s.partial, nb, 2, s.err + 2, st))) return rc;
+        double cm[2];
+        SE2_HIP(hipMemcpyAsync(cm, s.err + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        SE2_HIP(hipStreamSynchronize(st));
+        cost += s.lam[i] * cm[0];
+    }
+    // barycenter mass (FP64 fixed-order sum of bary_out, reusing the validation reduction)
+    double *stats = s.partial;
+    if ((rc = launch_validate(bary_out, s.E, stats, st))) return rc;
+    double mass = 0.0;
+    if ((rc = read_scalar(stats, &mass, st))) return rc;
+    r.cost = cost;
+    r.mass = mass;
+    r.dual = 0.0;
+    if (s.opts.final_check) {
+        // barycenter side of pi_i = diag(w_i) K diag(v_i) in FP64: sum bar |v_i (K*w_i) / bar - 1|
+        // (its mu_i side is exact by construction of the last w-update)
+        double worst = 0.0;
+        for (int i = 0; i < s.n; ++i) {
+            double e = 0.0;
+            if ((rc = f64_check(k, s.lw[i], s.logbar, s.lv[i], s.phi[0], s.partial, s.err + 6, s.offsets, s.tiles,
+                                st)))
+                return rc;
+            if ((rc = read_scalar(s.err + 6, &e, st))) return rc;
+            if (!(e <= worst)) worst = e;
+        }
+        r.marg_l1_f64 = worst;
+    }
+    for (int i = 0; i < s.n; ++i) {
+        if ((rc = read_work(s.ls_v[i], s.tiles, &r.terms_dense, &r.terms_sparse, st))) return rc;
+        if ((rc = read_work(s.ls_w[i], s.tiles, &r.terms_dense, &r.terms_sparse, st))) return rc;
+    }
+    r.seconds = now_seconds() - s.t_start;
+    rc = (std::isfinite(r.cost) && std::isfinite(r.marg_l1)) ? SE2_OK : SE2_ENUMERIC;
+    if (rep) *rep = r;
+    return rc;
+}
+
+}  // namespace se2

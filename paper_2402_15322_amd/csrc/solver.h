@@ -1,0 +1,117 @@
+// Solver state machines for Sinkhorn (Section 4.1) and IBP barycenters (Appendix A),
+// and the engine that advances any set of them together with batched launches.
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "se2_internal.h"
+
+namespace se2 {
+
+// Stream-ordered device allocation with an optional arena (the serving queue's budget).
+class DeviceArena;
+
+struct DevBuf {
+    double *p = nullptr;
+    size_t n = 0;
+};
+
+// One solve, resident on the device.  All potentials are base-2 log-scalings.
+struct Solve {
+    int kind = SE2_REQ_OT;           // SE2_REQ_OT or SE2_REQ_BARYCENTER
+    const Kernel *k = nullptr;
+    size_t E = 0;                    // elements per grid array
+    int tiles = 0;                   // 8x8 output tiles per grid array
+    se2_opts_t opts{};
+    // OT
+    double *lmu = nullptr, *lnu = nullptr, *phi[2] = {nullptr, nullptr}, *psi = nullptr;
+    ListSet ls_phi, ls_psi;          // pruning state of the b-update (input phi) and a-update (input psi)
+    const double *mu_lin = nullptr, *nu_lin = nullptr;  // FP64 inputs (dual, final checks)
+    int cur = 0;
+    // barycenter: only measures with lambda > 0
+    int n = 0;
+    std::vector<double> lam;
+    std::vector<double *> lm, lv, lw, ld;
+    std::vector<ListSet> ls_v, ls_w;  // pruning state of the w-update (input lv_i) and d-update (input lw_i)
+    std::vector<const double *> m_lin;
+    double *logbar = nullptr;
+    // common
+    double *partial = nullptr;       // tiles * max(1, n) error partials
+    double *err = nullptr;           // max(1, n) reduced errors (device)
+    int32_t *offsets = nullptr;      // per-job partial offsets (device), max(1, n) + 1
+    int iter = 0;                    // completed iterations
+    bool done = false;
+    int status = SE2_MAX_ITER;
+    double last_err = -1.0;
+    int convs = 0;
+    double t_start = 0.0;
+    // memory
+    void *block = nullptr;           // single allocation holding every buffer
+    size_t bytes = 0;
+};
+
+// Window entries inside the grid summed over all outputs: the algorithmic LSE
+// terms of one convolution of a grid array with this kernel.
+double conv_terms(const Kernel &k);
+
+// Bytes one solve needs on the device (for admission against a budget).
+size_t solve_bytes(int kind, const Kernel &k, int n_active, bool prune);
+bool prune_enabled(const Solve &s);
+
+// Carve the buffers of `s` out of `mem` (size solve_bytes()).
+void solve_bind(Solve &s, void *mem);
+
+// Upload inputs and initialise: log-marginals, potentials, the first half-step.
+// mus/lams: for barycenters the active measures only.  Stream-ordered.
+int solve_reset_lists(Solve &s, hipStream_t st);
+int solve_setup_ot(Solve &s, const double *mu, const double *nu, const double *init_g_natural, hipStream_t st);
+int solve_setup_bary(Solve &s, const std::vector<const double *> &mus, hipStream_t st);
+
+// Advances a set of solves (same ntheta or not) by one iteration each, with batched
+// launches: one launch per (stage, ntheta class).  If `check` is true, also reduces
+// each solve's marginal error into its device `err` slot.
+class Engine {
+public:
+    Engine();
+    ~Engine();
+    int init_first_halfstep(const std::vector<Solve *> &solves, hipStream_t st);
+    int step(const std::vector<Solve *> &solves, bool check, hipStream_t st);
+    // Copies err slots of the given solves to host (synchronises the stream).
+    int read_errors(const std::vector<Solve *> &solves, std::vector<double> &max_err, hipStream_t st);
+    // Optional event timing of every log-domain convolution launch.
+    void set_profiling(bool on);
+    int collect_profile();  // folds finished event pairs into the totals (after a sync)
+    double prof_seconds = 0.0, prof_terms = 0.0, prof_outputs = 0.0;
+    int64_t prof_launches = 0;
+
+private:
+    int launch_stage(const std::vector<Solve *> &solves, int stage, bool with_err, hipStream_t st);
+    int ensure(size_t njobs, size_t nblocks);
+    ConvJob *d_jobs_ = nullptr;
+    int32_t *d_map_ = nullptr;
+    ConvJob *h_jobs_ = nullptr;      // pinned staging (double-buffered)
+    int32_t *h_map_ = nullptr;
+    size_t cap_jobs_ = 0, cap_blocks_ = 0;
+    int flip_ = 0;
+    hipEvent_t staged_[2] = {nullptr, nullptr};
+    double *h_err_ = nullptr;
+    size_t cap_err_ = 0;
+    bool prof_ = false;
+    struct Pending {
+        hipEvent_t a, b;
+        double terms, outputs;
+    };
+    std::vector<Pending> pending_;
+    std::vector<hipEvent_t> spare_;
+    std::vector<double *> d_err_gather_;
+};
+
+// Final report pieces: potentials out (natural units), plan cost, mass, dual,
+// optional FP64 re-check of the marginal error.  Blocking on `st`.
+int solve_finish_ot(Solve &s, double *f_out, double *g_out, se2_report_t *rep, hipStream_t st);
+int solve_finish_bary(Solve &s, double *bary_out, se2_report_t *rep, hipStream_t st);
+
+double now_seconds();
+
+}  // namespace se2
