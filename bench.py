@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--plain", type=int, default=2, help="solves run one at a time beside the queue")
     ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations for the CPU baseline (0: auto)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-prune", action="store_true", help="dense convolutions only (no certified pruning)")
     return ap.parse_args()
 
 
@@ -78,7 +79,8 @@ def main():
     fs = [torch.empty_like(m) for m in mus]
     gs = [torch.empty_like(m) for m in mus]
     torch.cuda.synchronize()
-    o = native.opts(tol=a.tol, max_iter=a.max_iter, check_every=a.check_every, final_check=True)
+    o = native.opts(tol=a.tol, max_iter=a.max_iter, check_every=a.check_every, final_check=True,
+                    prune=not a.no_prune)
     # the budget admits the whole batch (each solve keeps its potentials and pruning state resident)
     q = native.SolveQueue(hbm_budget_bytes=native.ot_request_bytes(k, o) * a.batch + (64 << 20), max_slots=a.batch)
 
@@ -162,7 +164,7 @@ def main():
         "speedup_vs_plain": (value / plain_rate) if plain_rate else None,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS, "traffic": None,
-                     "kernel": "k_conv_lse", "avg_launch_us": avg_launch * 1e6,
+                     "kernel": "log-domain convolution (k_sparse + k_rebuild)", "avg_launch_us": avg_launch * 1e6,
                      "dense_terms_per_launch": td / launches, "sparse_terms_per_launch": ts / launches,
                      "window_terms_per_launch": kt["terms"] / launches,
                      "slots_per_term": {"dense": SLOTS_DENSE, "sparse": SLOTS_SPARSE}},

@@ -6,31 +6,36 @@
 // (Section 4.1) written as the group convolution of Section 4.2, evaluated term
 // by term in the log domain.
 //
-// Dense path (exact): every window entry is visited.  A first pass finds the
-// per-output maximum M of the exponents in FP32; the second forms each exponent
-// u = L2 + in - M in FP64 (the two addends are O(10^3) and nearly cancel for the
-// terms that matter), rounds u to FP32 and takes a native exp2.  Partial sums
-// over one window row are FP32 and are combined in FP64.  F64EXP uses an FP64
-// exp2 and FP64 sums throughout (the checking path).
+// Dense evaluation (exact): every window entry is visited.  A first pass finds
+// the per-output maximum M of the exponents in FP32; the second forms each
+// exponent u = L2 + in - M in FP64 (the two addends are O(10^3) and nearly cancel
+// for the terms that matter), rounds u to FP32 and takes a native exp2.  Partial
+// sums over one window row are FP32 and are combined in FP64.  F64EXP uses an
+// FP64 exp2 and FP64 sums throughout (the checking path).
 //
-// Certified sparse path (SPARSE kernels, jobs that carry term lists): a dense
-// visit of a tile also records, for each output orientation ko, the union over
-// the tile's 64 pixels of the window entries (d, ki) whose exponent is within
-// kListCut of that output's maximum, the maximum itself (mref) and the input
-// halo it saw (ref).  A later visit measures the drift delta = in - ref over the
-// halo, lo <= delta <= hi.  Every skipped entry had u <= -kListCut at reference
-// time; its exponent grew by at most hi and the maximum fell by at most -lo, so
-// now u <= -kListCut + (hi - lo).  While the spread hi - lo <= kDriftSpread the
-// skipped entries sum to less than n 2^-(kListCut - kDriftSpread) = n 2^-48 of
-// the result and the tile only visits its list, shifting exponents by
-// mref + (lo + hi)/2 (within 2^+-spread/2 of the true maximum).  Otherwise the
-// tile takes the dense path and rebuilds its list.  The decision is per tile, so results stay independent of
-// any other job in the launch.
+// Certified pruning (jobs that carry term lists).  A dense visit of a tile records,
+// for each output orientation ko, the union over the tile's 64 pixels of the window
+// terms (d, ki) whose exponent is within kListCut of that output's maximum, the
+// maximum itself (mref) and the input halo it saw (ref).  A later visit measures
+// the drift delta = in - ref over the halo, lo <= delta <= hi.  Every unlisted term
+// had u <= -kListCut at reference time; its exponent grew by at most hi and the
+// maximum fell by at most -lo, so now u <= -kListCut + (hi - lo).  While the spread
+// hi - lo <= kDriftSpread the unlisted terms are each below 2^-(kListCut -
+// kDriftSpread) = 2^-48 of the largest term and the tile evaluates its lists only,
+// shifting exponents by mref + (lo + hi)/2 (within 2^+-spread/2 of the true
+// maximum).  Otherwise the tile is rebuilt densely.  Every decision is per tile and
+// depends only on that job's data, so results are independent of the other jobs in
+// a launch.
 //
-// Work layout: one workgroup = one 8 x 8 output tile of one job, all ntheta
-// outputs; lane = pixel of the tile, wave w owns ko = w, w+4, ... .  The input
-// halo (8+2R)^2 is staged in LDS as FP64, theta-major so that the 64 lanes of a
-// wave read neighbouring addresses.  Kernel values and list entries are
+// Kernels.  k_conv_lse evaluates jobs without lists densely, one 8 x 8 output tile
+// (all ko) per workgroup: lane = pixel of the tile, wave w owns ko = w, w+4, ... .
+// Pruned jobs run k_sparse (certificate, then list evaluation; min(nt, 16) waves
+// per tile) followed by k_rebuild, which takes the tiles whose certificate failed and
+// spreads each over ntheta workgroups (one per ko, the window rows split over the
+// four waves), so that a few rebuilds never hold a launch on one compute unit.
+//
+// The input halo (8+2R)^2 is staged in LDS as FP64, theta-major so that the 64 lanes
+// of a wave read neighbouring addresses.  Kernel values of the dense visits are
 // wave-uniform and read through the scalar cache.
 #include <hip/hip_runtime.h>
 
@@ -44,34 +49,71 @@ namespace {
 
 typedef const __attribute__((address_space(4))) double *cdptr;
 typedef const __attribute__((address_space(4))) float *cfptr;
-typedef const __attribute__((address_space(4))) int32_t *ciptr;
 
+// Stage the input halo (8+2R)^2 x KC orientations (from k0) in LDS as [kc][hy][hx],
+// -inf outside the grid.  Loads are unconditional (clamped address, then a select) and
+// unrolled so that many are in flight; hy = p / HW via a float reciprocal (exact for
+// p < 2^20: the +0.5 keeps the rounding error far below the gap to an integer).
 template <int KC>
 __device__ __forceinline__ void load_halo(double *lds, const double *__restrict__ in, int nt, int k0, int x0, int y0,
                                           int R, int HW, int nx, int ny) {
     const int npix = HW * HW;
     const int total = npix * KC;
+    const float inv = 1.0f / static_cast<float>(HW);
+#pragma unroll 8
     for (int e = threadIdx.x; e < total; e += kConvThreads) {
         const int p = e / KC;
         const int kc = e - p * KC;
-        const int hy = p / HW;
+        const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv);
         const int hx = p - hy * HW;
         const int gy = y0 - R + hy, gx = x0 - R + hx;
-        double v = -INFINITY;
-        if (gy >= 0 && gy < ny && gx >= 0 && gx < nx) v = in[(static_cast<size_t>(gy) * nx + gx) * nt + k0 + kc];
-        lds[kc * npix + p] = v;
+        const bool inside = gy >= 0 && gy < ny && gx >= 0 && gx < nx;
+        const int cy = min(max(gy, 0), ny - 1), cx = min(max(gx, 0), nx - 1);
+        const double v = in[(static_cast<size_t>(cy) * nx + cx) * nt + k0 + kc];
+        lds[kc * npix + p] = inside ? v : -INFINITY;
     }
 }
 
-__device__ __forceinline__ double block_sum_fixed(double v, double *scratch) {
-    // Fixed-order tree over the 256 threads: the result does not depend on timing.
-    scratch[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = kConvThreads / 2; s > 0; s >>= 1) {
-        if (static_cast<int>(threadIdx.x) < s) scratch[threadIdx.x] += scratch[threadIdx.x + s];
-        __syncthreads();
+// The same for all orientations, also folding the drift against the reference halo
+// into [lo, hi] (bad: a finite value met a -inf one).
+template <int NT>
+__device__ __forceinline__ void load_halo_drift(double *lds, const double *__restrict__ in,
+                                                const double *__restrict__ ref, int x0, int y0, int R, int HW, int nx,
+                                                int ny, float &lo, float &hi, bool &bad) {
+    const int npix = HW * HW;
+    const int total = npix * NT;
+    const float inv = 1.0f / static_cast<float>(HW);
+#pragma unroll 8
+    for (int e = threadIdx.x; e < total; e += kConvThreads) {
+        const int p = e / NT;
+        const int kc = e - p * NT;
+        const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv);
+        const int hx = p - hy * HW;
+        const int gy = y0 - R + hy, gx = x0 - R + hx;
+        const bool inside = gy >= 0 && gy < ny && gx >= 0 && gx < nx;
+        const int cy = min(max(gy, 0), ny - 1), cx = min(max(gx, 0), nx - 1);
+        const double v = in[(static_cast<size_t>(cy) * nx + cx) * NT + kc];
+        const int li = kc * npix + p;
+        const double b = ref[li];
+        const double a = inside ? v : -INFINITY;
+        lds[li] = a;
+        const bool both = (a == -INFINITY) && (b == -INFINITY);
+        const double de = both ? 0.0 : a - b;  // +-inf or NaN when only one side is -inf
+        bad = bad || !(fabs(de) < 1e30);
+        const float df = static_cast<float>(de);
+        lo = both ? lo : fminf(lo, df);
+        hi = both ? hi : fmaxf(hi, df);
     }
-    return scratch[0];
+}
+
+// Sum over the 256 threads: butterflies within each wave, then the four wave sums in
+// wave order (fixed order, independent of timing).  `scratch` holds 4 doubles.
+__device__ __forceinline__ double block_sum_waves(double v, double *scratch) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return ((scratch[0] + scratch[1]) + scratch[2]) + scratch[3];
 }
 
 __device__ __forceinline__ float wave_max(float v) {
@@ -79,15 +121,41 @@ __device__ __forceinline__ float wave_max(float v) {
     return v;
 }
 
-template <int NT, int KC, bool F64EXP, bool SPARSE>
+__device__ __forceinline__ double wave_sum(double v) {
+    // butterfly in a fixed lane pattern: deterministic
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Scaling epilogue of one output element; returns its contribution to the marginal error.
+__device__ __forceinline__ double epilogue(const ConvJob &job, size_t idx, double lse) {
+    double o, err = 0.0;
+    if (job.epi == EPI_RAW) {
+        o = lse;
+    } else if (job.epi == EPI_SCALE) {
+        const double lm = job.aux[idx];
+        o = (lm == -INFINITY) ? -INFINITY : lm - lse;
+        if (job.old != nullptr && lm != -INFINITY) err = exp2(lm) * fabs(expm1((job.old[idx] - o) * kLn2));
+    } else {
+        const double bse = job.aux[idx];
+        o = (bse == -INFINITY || lse == -INFINITY) ? -INFINITY : bse + lse;
+    }
+    job.out[idx] = o;
+    return err;
+}
+
+// LDS offset of list term j relative to the output pixel: ki*npix + (R-dy)*HW + (R-dx).
+__device__ __forceinline__ int term_offset(uint32_t term, int nt, int R, int W, int HW, int npix) {
+    const int kc = static_cast<int>(term) % nt, r = static_cast<int>(term) / nt;
+    const int dyi = r / W, dxi = r - dyi * W;
+    return kc * npix + (2 * R - dyi) * HW + (2 * R - dxi);
+}
+
+template <int NT, int KC, bool F64EXP>
 __global__ __launch_bounds__(kConvThreads) void k_conv_lse(const ConvJob *__restrict__ jobs,
                                                            const int32_t *__restrict__ block_job) {
     extern __shared__ double lds[];
-    __shared__ float s_red[kConvThreads / 64];
-    __shared__ float s_red2[kConvThreads / 64];
-    __shared__ int s_flag;
-    __shared__ int s_list_off[NT + 1];
-    static_assert(!SPARSE || KC == NT, "the sparse path keeps the whole halo in LDS");
+    __shared__ double s_sum[8];
     constexpr int NJ = NT / 4;
     const int j = block_job[blockIdx.x];
     const ConvJob job = jobs[j];
@@ -105,117 +173,17 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_lse(const ConvJob *__rest
     const size_t obase = (static_cast<size_t>(gy) * nx + gx) * NT;
     const cdptr L64 = (cdptr)(job.L64);
     const cfptr L32 = (cfptr)(job.L32);
-    const bool lists = SPARSE && job.lists != nullptr;
 
     double lse[NJ];
-    float mx[NJ];
-
-    // ---------------- certified sparse path ----------------
-    bool dense = true;
-    float spread = 0.0f, shift = 0.0f;
-    if constexpr (SPARSE) {
-        if (lists) {
-            load_halo<NT>(lds, job.in, NT, 0, x0, y0, R, HW, nx, ny);
-            if (threadIdx.x == 0) {
-                // list offsets of the tile's orientations; missing/overflowed lists or a total
-                // beyond the LDS staging capacity force the dense path
-                int acc = 0, ok = 1;
-                for (int k = 0; k < NT; ++k) {
-                    const int n = job.len[static_cast<size_t>(tile) * NT + k];
-                    s_list_off[k] = acc;
-                    if (n < 0) ok = 0;
-                    else acc += n;
-                }
-                s_list_off[NT] = acc;
-                s_flag = (ok && acc <= kListLds) ? 1 : 0;
-            }
-            __syncthreads();
-            const double *ref = job.ref + static_cast<size_t>(tile) * NT * npix;
-            // drift delta = in - ref over the halo; only its spread matters: a common shift of the
-            // inputs moves every exponent and the maximum alike
-            float dlo = INFINITY, dhi = -INFINITY;
-            bool bad = false;
-            for (int e = threadIdx.x; e < NT * npix; e += kConvThreads) {
-                const double a = lds[e], b = ref[e];
-                if (a == -INFINITY && b == -INFINITY) continue;
-                const double de = a - b;  // +-inf or NaN when only one side is -inf
-                if (!(fabs(de) < 1e30)) {
-                    bad = true;
-                    continue;
-                }
-                dlo = fminf(dlo, static_cast<float>(de));
-                dhi = fmaxf(dhi, static_cast<float>(de));
-            }
-            if (bad) s_flag = 0;
-            dlo = -wave_max(-dlo);
-            dhi = wave_max(dhi);
-            if (lane == 0) {
-                s_red[wave] = dlo;
-                s_red2[wave] = dhi;
-            }
-            __syncthreads();
-            const float lo = fminf(fminf(s_red[0], s_red[1]), fminf(s_red[2], s_red[3]));
-            const float hi = fmaxf(fmaxf(s_red2[0], s_red2[1]), fmaxf(s_red2[2], s_red2[3]));
-            // all entries -inf on both sides: no spread at all
-            spread = (hi >= lo) ? hi - lo : 0.0f;
-            shift = (hi >= lo) ? 0.5f * (hi + lo) : 0.0f;
-            // 1 ulp of the FP32 differences per unit of magnitude is far below kDriftSpread's slack
-            dense = !(s_flag != 0 && spread <= kDriftSpread);
-        }
-    }
-    int listed = 0;  // list entries visited by this wave (sparse path)
-    if (!dense) {
-        // Stage the tile's lists in LDS (one bulk copy), then lane = pixel, one ko at a time,
-        // with the entries read as wave-wide broadcasts, 8 per step.
-        ListEntry *lst_lds = reinterpret_cast<ListEntry *>(lds + static_cast<size_t>(NT) * npix);
-        const int total = s_list_off[NT];
-        const ListEntry *src = job.lists;
-        for (int e = threadIdx.x; e < total; e += kConvThreads) {
-            int ko = 0;
-            while (e >= s_list_off[ko + 1]) ++ko;
-            lst_lds[e] = src[(static_cast<size_t>(tile) * NT + ko) * job.lmax + (e - s_list_off[ko])];
-        }
-        __syncthreads();
-        const int base = py * HW + px;
-#pragma unroll
-        for (int q = 0; q < NJ; ++q) {
-            const int ko = wave + 4 * q;
-            const int e0 = s_list_off[ko], n = s_list_off[ko + 1] - e0;
-            listed += n;
-            const float mr = valid ? job.mref[obase + ko] : -INFINITY;
-            // the reference maximum moved with the inputs by shift +- spread/2
-            const double M = (mr == -INFINITY) ? 0.0 : static_cast<double>(mr) + static_cast<double>(shift);
-            const ListEntry *L = lst_lds + e0;
-            double S = 0.0;
-            int e = 0;
-            for (; e + 8 <= n; e += 8) {
-                double v[8];
-                double lv[8];
-#pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    lv[t] = L[e + t].L;
-                    v[t] = lds[L[e + t].off + base];
-                }
-                float s8 = 0.0f;
-#pragma unroll
-                for (int t = 0; t < 8; ++t) s8 += __builtin_amdgcn_exp2f(static_cast<float>((lv[t] + v[t]) - M));
-                S += static_cast<double>(s8);
-            }
-            float st = 0.0f;
-            for (; e < n; ++e) st += __builtin_amdgcn_exp2f(static_cast<float>((L[e].L + lds[L[e].off + base]) - M));
-            S += static_cast<double>(st);
-            lse[q] = (mr == -INFINITY || !(S > 0.0)) ? -INFINITY : M + log2(S);
-        }
-    } else {
-        // ---------------- dense path ----------------
+    {
+        // ---------------- dense evaluation ----------------
+        float mx[NJ];
 #pragma unroll
         for (int q = 0; q < NJ; ++q) mx[q] = -INFINITY;
         for (int k0 = 0; k0 < NT; k0 += KC) {
-            if (!(SPARSE && lists)) {
-                if (k0 > 0) __syncthreads();
-                load_halo<KC>(lds, job.in, NT, k0, x0, y0, R, HW, nx, ny);
-                __syncthreads();
-            }
+            if (k0 > 0) __syncthreads();
+            load_halo<KC>(lds, job.in, NT, k0, x0, y0, R, HW, nx, ny);
+            __syncthreads();
             for (int dy = -R; dy <= R; ++dy) {
                 for (int dx = -R; dx <= R; ++dx) {
                     const int hb = (py + R - dy) * HW + (px + R - dx);
@@ -230,12 +198,10 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_lse(const ConvJob *__rest
             }
         }
         double M[NJ], S[NJ];
-        int cnt[NJ];
 #pragma unroll
         for (int q = 0; q < NJ; ++q) {
             M[q] = (mx[q] == -INFINITY) ? 0.0 : static_cast<double>(mx[q]);
             S[q] = 0.0;
-            cnt[q] = 0;
         }
         for (int k0 = 0; k0 < NT; k0 += KC) {
             if (NT > KC) {
@@ -266,29 +232,9 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_lse(const ConvJob *__rest
                         for (int kc = 0; kc < KC; ++kc) {
                             const double v = lds[kc * npix + hb];
 #pragma unroll
-                            for (int q = 0; q < NJ; ++q) {
-                                const double Lv = Lr[(wave + 4 * q) * NT + kc];
-                                const double u = (v + Lv) - M[q];
-                                srow[q] += __builtin_amdgcn_exp2f(static_cast<float>(u));
-                                if constexpr (SPARSE) {
-                                    if (lists) {
-                                        // union over the tile's pixels of the entries within the list cut
-                                        const bool keep = valid && u >= -kListCut;
-                                        if (__ballot(keep) != 0) {
-                                            if (cnt[q] < job.lmax && lane == 0) {
-                                                ListEntry *dst = job.lists +
-                                                                 (static_cast<size_t>(tile) * NT + wave + 4 * q) *
-                                                                     job.lmax +
-                                                                 cnt[q];
-                                                dst->L = Lv;
-                                                dst->off = kc * npix + (R - dy) * HW + (R - dx);
-                                                dst->pad = 0;
-                                            }
-                                            cnt[q] += 1;
-                                        }
-                                    }
-                                }
-                            }
+                            for (int q = 0; q < NJ; ++q)
+                                srow[q] += __builtin_amdgcn_exp2f(
+                                    static_cast<float>((v + Lr[(wave + 4 * q) * NT + kc]) - M[q]));
                         }
                     }
 #pragma unroll
@@ -298,80 +244,383 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_lse(const ConvJob *__rest
         }
 #pragma unroll
         for (int q = 0; q < NJ; ++q) lse[q] = (S[q] > 0.0) ? M[q] + log2(S[q]) : -INFINITY;
-        if constexpr (SPARSE) {
-            if (lists) {
-                // publish the rebuilt lists, the reference maxima and the reference halo
-#pragma unroll
-                for (int q = 0; q < NJ; ++q) {
-                    if (lane == 0) job.len[static_cast<size_t>(tile) * NT + wave + 4 * q] =
-                        (cnt[q] <= job.lmax) ? cnt[q] : -1;
-                    if (valid) job.mref[obase + wave + 4 * q] = mx[q];
-                }
-                double *ref = job.ref + static_cast<size_t>(tile) * NT * npix;
-                for (int e = threadIdx.x; e < NT * npix; e += kConvThreads) ref[e] = lds[e];
-                if (job.dense_flag != nullptr && threadIdx.x == 0) job.dense_flag[tile] += 1;
-            }
-        }
     }
 
     // ---------------- work counters (diagnostics) ----------------
     if (job.work != nullptr) {
-        // in-grid terms of this lane's outputs (dense) or the visited list entries (sparse)
+        // in-grid terms of this lane's outputs
         double w = 0.0;
         if (valid) {
-            if (dense) {
-                const int cx = min(R, gx) + min(R, nx - 1 - gx) + 1;
-                const int cy = min(R, gy) + min(R, ny - 1 - gy) + 1;
-                w = static_cast<double>(cx) * cy * NT * NJ;
-            } else {
-                w = static_cast<double>(listed);
-            }
+            const int cx = min(R, gx) + min(R, nx - 1 - gx) + 1;
+            const int cy = min(R, gy) + min(R, ny - 1 - gy) + 1;
+            w = static_cast<double>(cx) * cy * NT * NJ;
         }
-        __syncthreads();
-        const double t = block_sum_fixed(w, lds);
-        if (threadIdx.x == 0) job.work[2 * tile + (dense ? 0 : 1)] += t;
-        __syncthreads();
+        const double t = block_sum_waves(w, s_sum);
+        if (threadIdx.x == 0) job.work[2 * tile] += t;
     }
 
     // ---------------- epilogue ----------------
     double err = 0.0;
     if (valid) {
 #pragma unroll
-        for (int q = 0; q < NJ; ++q) {
-            const size_t idx = obase + wave + 4 * q;
-            double o;
-            if (job.epi == EPI_RAW) {
-                o = lse[q];
-            } else if (job.epi == EPI_SCALE) {
-                const double lm = job.aux[idx];
-                o = (lm == -INFINITY) ? -INFINITY : lm - lse[q];
-                if (job.old != nullptr && lm != -INFINITY)
-                    err += exp2(lm) * fabs(expm1((job.old[idx] - o) * kLn2));
-            } else {
-                const double bse = job.aux[idx];
-                o = (bse == -INFINITY || lse[q] == -INFINITY) ? -INFINITY : bse + lse[q];
-            }
-            job.out[idx] = o;
-        }
+        for (int q = 0; q < NJ; ++q) err += epilogue(job, obase + wave + 4 * q, lse[q]);
     }
     if (job.epi == EPI_SCALE && job.partial != nullptr) {
-        __syncthreads();
-        const double t = block_sum_fixed(err, lds);
-        if (threadIdx.x == 0) job.partial[tile] = t;
+        // partials are laid out [tile][nt]; a tile evaluated here fills slot 0
+        const double t = block_sum_waves(err, s_sum + 4);
+        if (static_cast<int>(threadIdx.x) < NT)
+            job.partial[static_cast<size_t>(tile) * NT + threadIdx.x] = (threadIdx.x == 0) ? t : 0.0;
     }
 }
 
-template <int NT, int KC, bool F64EXP, bool SPARSE>
-int launch_t(const ConvJob *d_jobs, int nblocks, const int32_t *d_block_job, int R_max, hipStream_t s) {
+// Certified sparse evaluation of pruned jobs: one workgroup per 8 x 8 tile with
+// min(nt, 16) waves sharing the halo and the staged lists (wave w owns ko = w, w+NW,
+// ...); lane = pixel.  A tile whose certificate fails is appended to the rebuild list
+// and left to k_rebuild.
+template <int NT>
+__global__ __launch_bounds__(64 * (NT < 16 ? NT : 16)) void k_sparse(const ConvJob *__restrict__ jobs,
+                                                                     const int32_t *__restrict__ block_job,
+                                                                     int2 *__restrict__ rebuild,
+                                                                     int *__restrict__ rebuild_count) {
+    constexpr int NW = NT < 16 ? NT : 16;  // waves
+    constexpr int NTH = 64 * NW;
+    constexpr int NJ = NT / NW;             // orientations per wave
+    extern __shared__ double lds[];
+    __shared__ float s_lo[NW], s_hi[NW];
+    __shared__ double s_err[NW], s_work[NW];
+    __shared__ int s_flag;
+    __shared__ int s_list_off[NT + 1];
+    const int j = block_job[blockIdx.x];
+    const ConvJob job = jobs[j];
+    const int tile = static_cast<int>(blockIdx.x) - job.first_block;
+    const int ty = tile / job.tiles_x;
+    const int tx = tile - ty * job.tiles_x;
+    const int x0 = tx * kTile, y0 = ty * kTile;
+    const int R = job.R, W = 2 * R + 1, HW = kTile + 2 * R, npix = HW * HW;
+    const int nx = job.nx, ny = job.ny;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int px = lane & 7, py = lane >> 3;
+    const int gx = x0 + px, gy = y0 + py;
+    const bool valid = gx < nx && gy < ny;
+    const size_t obase = (static_cast<size_t>(gy) * nx + gx) * NT;
+
+    // ---------------- certificate ----------------
+    // drift delta = in - ref over the halo; only its spread matters: a common shift of the
+    // inputs moves every exponent and the maximum alike
+    const double *ref = job.ref + static_cast<size_t>(tile) * NT * npix;
+    float dlo = INFINITY, dhi = -INFINITY;
+    bool bad = false;
+    {
+        const float inv = 1.0f / static_cast<float>(HW);
+#pragma unroll 4
+        for (int e = threadIdx.x; e < npix * NT; e += NTH) {
+            const int p = e / NT;
+            const int kc = e - p * NT;
+            const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv);
+            const int hx = p - hy * HW;
+            const int qy = y0 - R + hy, qx = x0 - R + hx;
+            const bool inside = qy >= 0 && qy < ny && qx >= 0 && qx < nx;
+            const int cy = min(max(qy, 0), ny - 1), cx = min(max(qx, 0), nx - 1);
+            const double v = job.in[(static_cast<size_t>(cy) * nx + cx) * NT + kc];
+            const int li = kc * npix + p;
+            const double b = ref[li];
+            const double a = inside ? v : -INFINITY;
+            lds[li] = a;
+            const bool both = (a == -INFINITY) && (b == -INFINITY);
+            const double de = both ? 0.0 : a - b;  // +-inf or NaN when only one side is -inf
+            bad = bad || !(fabs(de) < 1e30);
+            const float df = static_cast<float>(de);
+            dlo = both ? dlo : fminf(dlo, df);
+            dhi = both ? dhi : fmaxf(dhi, df);
+        }
+    }
+    if (threadIdx.x == 0) {
+        // list offsets of the tile's orientations; a missing/overflowed list or a total
+        // beyond the LDS staging capacity needs a rebuild
+        int acc = 0, ok = 1;
+        for (int k = 0; k < NT; ++k) {
+            const int n = job.len[static_cast<size_t>(tile) * NT + k];
+            s_list_off[k] = acc;
+            if (n < 0) ok = 0;
+            else acc += n;
+        }
+        s_list_off[NT] = acc;
+        s_flag = (ok && acc <= kListLds) ? 1 : 0;
+    }
+    __syncthreads();
+    if (bad) s_flag = 0;
+    dlo = -wave_max(-dlo);
+    dhi = wave_max(dhi);
+    if (lane == 0) {
+        s_lo[wave] = dlo;
+        s_hi[wave] = dhi;
+    }
+    __syncthreads();
+    float lo = s_lo[0], hi = s_hi[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+        lo = fminf(lo, s_lo[w]);
+        hi = fmaxf(hi, s_hi[w]);
+    }
+    // all entries -inf on both sides: no spread at all
+    const float spread = (hi >= lo) ? hi - lo : 0.0f;
+    const float shift = (hi >= lo) ? 0.5f * (hi + lo) : 0.0f;
+    if (!(s_flag != 0 && spread <= kDriftSpread)) {
+        // left to the rebuild kernel (block-uniform exit, nothing written here)
+        if (threadIdx.x == 0) {
+            const int slot = atomicAdd(rebuild_count, 1);
+            rebuild[slot] = make_int2(j, tile);
+        }
+        return;
+    }
+
+    // ---------------- certified sparse evaluation ----------------
+    // Each wave stages the packed list entries of its own orientations (kernel value with
+    // the LDS offset in its low mantissa bits) and reads them back as wave-wide
+    // broadcasts, 8 per step; LDS operations of one wave complete in order, so no
+    // barrier is needed between its copy and its reads.
+    double *lst_lds = lds + static_cast<size_t>(NT) * npix;
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) {
+        const int ko = wave + NW * q;
+        const int e0 = s_list_off[ko], n = s_list_off[ko + 1] - e0;
+        const ListEntry *src = job.lists + (static_cast<size_t>(tile) * NT + ko) * job.lmax;
+        for (int e = lane; e < n; e += 64) lst_lds[e0 + e] = src[e];
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int base = py * HW + px;
+    double err = 0.0, work = 0.0;
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) {
+        const int ko = wave + NW * q;
+        const int e0 = s_list_off[ko], n = s_list_off[ko + 1] - e0;
+        const float mr = valid ? job.mref[obase + ko] : -INFINITY;
+        // the reference maximum moved with the inputs by shift +- spread/2
+        const double M = (mr == -INFINITY) ? 0.0 : static_cast<double>(mr) + static_cast<double>(shift);
+        const double *Lp = lst_lds + e0;
+        double S = 0.0;
+        int e = 0;
+        for (; e + 8 <= n; e += 8) {
+            double v[8], lv[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const double pk = Lp[e + t];
+                const unsigned int lo32 = static_cast<unsigned int>(__double2loint(pk));
+                lv[t] = __hiloint2double(__double2hiint(pk), static_cast<int>(lo32 & ~((1u << kOffBits) - 1u)));
+                v[t] = lds[(lo32 & ((1u << kOffBits) - 1u)) + base];
+            }
+            float s8 = 0.0f;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) s8 += __builtin_amdgcn_exp2f(static_cast<float>((lv[t] + v[t]) - M));
+            S += static_cast<double>(s8);
+        }
+        float st = 0.0f;
+        for (; e < n; ++e) {
+            const double pk = Lp[e];
+            const unsigned int lo32 = static_cast<unsigned int>(__double2loint(pk));
+            const double lv =
+                __hiloint2double(__double2hiint(pk), static_cast<int>(lo32 & ~((1u << kOffBits) - 1u)));
+            st += __builtin_amdgcn_exp2f(static_cast<float>((lv + lds[(lo32 & ((1u << kOffBits) - 1u)) + base]) - M));
+        }
+        S += static_cast<double>(st);
+        const double lse = (mr == -INFINITY || !(S > 0.0)) ? -INFINITY : M + log2(S);
+        if (valid) {
+            err += epilogue(job, obase + ko, lse);
+            work += static_cast<double>(n);
+        }
+    }
+    // error partial of the tile (slot 0 of [tile][nt]) and the work counter, in wave order
+    err = wave_sum(err);
+    work = wave_sum(work);
+    if (lane == 0) {
+        s_err[wave] = err;
+        s_work[wave] = work;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double te = 0.0, tw = 0.0;
+        for (int w = 0; w < NW; ++w) {
+            te += s_err[w];
+            tw += s_work[w];
+        }
+        if (job.epi == EPI_SCALE && job.partial != nullptr) job.partial[static_cast<size_t>(tile) * NT] = te;
+        if (job.work != nullptr) job.work[2 * tile + 1] += tw;
+    }
+    if (job.epi == EPI_SCALE && job.partial != nullptr && threadIdx.x > 0 && static_cast<int>(threadIdx.x) < NT)
+        job.partial[static_cast<size_t>(tile) * NT + threadIdx.x] = 0.0;
+}
+
+// Dense rebuild of the tiles listed by k_sparse: one workgroup per (tile, ko); the
+// window rows dy = -R + w, -R + w + 4, ... belong to wave w, whose partial maxima and
+// sums are combined in LDS in wave order; lane = pixel of the tile.  Each wave also
+// records, per window offset of its rows, a ballot mask of the orientations ki whose
+// term is within kListCut of the maximum for some pixel; the masks are compacted
+// into the (tile, ko) list and the packed entries stored.
+template <int NT>
+__global__ __launch_bounds__(kConvThreads) void k_rebuild(const ConvJob *__restrict__ jobs,
+                                                          const int2 *__restrict__ rebuild,
+                                                          const int *__restrict__ rebuild_count) {
+    extern __shared__ double lds[];
+    __shared__ float s_mx[kConvThreads / 64][64];
+    __shared__ double s_S[kConvThreads / 64][64];
+    __shared__ int s_cnt;
+    static_assert(NT <= 32, "masks hold up to 32 input orientations");
+    const int nitems = *rebuild_count * NT;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int px = lane & 7, py = lane >> 3;
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int2 it = rebuild[item / NT];
+        const int ko = item % NT;
+        const ConvJob job = jobs[it.x];
+        const int tile = it.y;
+        const int ty = tile / job.tiles_x;
+        const int tx = tile - ty * job.tiles_x;
+        const int x0 = tx * kTile, y0 = ty * kTile;
+        const int R = job.R, W = 2 * R + 1, HW = kTile + 2 * R, npix = HW * HW;
+        const int nx = job.nx, ny = job.ny;
+        const int gx = x0 + px, gy = y0 + py;
+        const bool valid = gx < nx && gy < ny;
+        const size_t idx = (static_cast<size_t>(gy) * nx + gx) * NT + ko;
+        const cdptr L64 = (cdptr)(job.L64);
+        const cfptr L32 = (cfptr)(job.L32);
+        // LDS: halo, then W*W masks (one per window offset), then up to lmax term indices
+        uint32_t *masks = reinterpret_cast<uint32_t *>(lds + static_cast<size_t>(NT) * npix);
+        uint32_t *terms = masks + W * W;
+
+        __syncthreads();  // LDS of the previous item is free
+        load_halo<NT>(lds, job.in, NT, 0, x0, y0, R, HW, nx, ny);
+        __syncthreads();
+
+        // pass 1: maximum over this wave's rows
+        float mx = -INFINITY;
+        for (int dy = -R + wave; dy <= R; dy += 4) {
+            for (int dx = -R; dx <= R; ++dx) {
+                const int hb = (py + R - dy) * HW + (px + R - dx);
+                const cfptr Lr = L32 + (static_cast<size_t>((dy + R) * W + (dx + R)) * NT + ko) * NT;
+#pragma unroll
+                for (int kc = 0; kc < NT; ++kc) mx = fmaxf(mx, static_cast<float>(lds[kc * npix + hb]) + Lr[kc]);
+            }
+        }
+        s_mx[wave][lane] = mx;
+        __syncthreads();
+        mx = fmaxf(fmaxf(s_mx[0][lane], s_mx[1][lane]), fmaxf(s_mx[2][lane], s_mx[3][lane]));
+        const double M = (mx == -INFINITY) ? 0.0 : static_cast<double>(mx);
+
+        // pass 2: sum and membership masks of this wave's rows
+        double S = 0.0;
+        for (int dy = -R + wave; dy <= R; dy += 4) {
+            float srow = 0.0f;
+            for (int dx = -R; dx <= R; ++dx) {
+                const int hb = (py + R - dy) * HW + (px + R - dx);
+                const cdptr Lr = L64 + (static_cast<size_t>((dy + R) * W + (dx + R)) * NT + ko) * NT;
+                uint32_t m = 0u;
+#pragma unroll
+                for (int kc = 0; kc < NT; ++kc) {
+                    const double u = (lds[kc * npix + hb] + Lr[kc]) - M;
+                    srow += __builtin_amdgcn_exp2f(static_cast<float>(u));
+                    m |= (__ballot(valid && u >= -kListCut) != 0ull ? 1u : 0u) << kc;
+                }
+                if (lane == 0) masks[(dy + R) * W + (dx + R)] = m;
+            }
+            S += static_cast<double>(srow);
+        }
+        s_S[wave][lane] = S;
+        __syncthreads();
+        S = ((s_S[0][lane] + s_S[1][lane]) + s_S[2][lane]) + s_S[3][lane];
+        const double lse = (S > 0.0) ? M + log2(S) : -INFINITY;
+
+        if (wave == 0) {
+            // compaction: term index ((dy+R)*W + dx+R)*NT + ki for every set bit, in order
+            int cnt = 0;
+            for (int r = 0; r < W * W; ++r) {
+                uint32_t m = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(masks[r])));
+                while (m != 0u) {
+                    const int b = __builtin_ctz(m);
+                    m &= m - 1u;
+                    if (cnt < job.lmax && lane == 0) terms[cnt] = static_cast<uint32_t>(r * NT + b);
+                    ++cnt;
+                }
+            }
+            if (lane == 0) {
+                job.len[static_cast<size_t>(tile) * NT + ko] = (cnt <= job.lmax) ? cnt : -1;
+                s_cnt = cnt;
+            }
+            if (valid) job.mref[idx] = mx;
+            // epilogue of the 64 outputs (pixel, ko) and this item's error partial
+            const double err = valid ? epilogue(job, idx, lse) : 0.0;
+            const double es = wave_sum(err);
+            if (job.epi == EPI_SCALE && job.partial != nullptr && lane == 0)
+                job.partial[static_cast<size_t>(tile) * NT + ko] = es;
+            if (job.work != nullptr) {
+                double w = 0.0;
+                if (valid) {
+                    const int cx = min(R, gx) + min(R, nx - 1 - gx) + 1;
+                    const int cy = min(R, gy) + min(R, ny - 1 - gy) + 1;
+                    w = static_cast<double>(cx) * cy * NT;
+                }
+                const double ws = wave_sum(w);
+                if (lane == 0) atomicAdd(&job.work[2 * tile], ws);
+            }
+        }
+        __syncthreads();
+        {
+            // packed entries of (tile, ko), written by all threads
+            const int n = s_cnt <= job.lmax ? s_cnt : 0;
+            ListEntry *dst = job.lists + (static_cast<size_t>(tile) * NT + ko) * job.lmax;
+            for (int e = threadIdx.x; e < n; e += kConvThreads) {
+                const uint32_t term = terms[e];
+                const double Lv = job.L64[((term / NT) * NT + ko) * NT + term % NT];
+                const uint32_t off = static_cast<uint32_t>(term_offset(term, NT, R, W, HW, npix));
+                const unsigned long long b =
+                    (static_cast<unsigned long long>(__double_as_longlong(Lv)) & ~((1ull << kOffBits) - 1ull)) | off;
+                dst[e] = __longlong_as_double(static_cast<long long>(b));
+            }
+        }
+        if (ko == 0) {
+            double *ref = job.ref + static_cast<size_t>(tile) * NT * npix;
+            for (int e = threadIdx.x; e < NT * npix; e += kConvThreads) ref[e] = lds[e];
+            if (job.dense_flag != nullptr && threadIdx.x == 0) job.dense_flag[tile] += 1;
+        }
+    }
+}
+
+template <int NT, int KC, bool F64EXP>
+int launch_dense_t(const ConvJob *d_jobs, int nblocks, const int32_t *d_block_job, int R_max, hipStream_t s) {
     const int HW = kTile + 2 * R_max;
     size_t lds = static_cast<size_t>(HW) * HW * KC * sizeof(double);
-    if (SPARSE) lds += static_cast<size_t>(kListLds) * sizeof(ListEntry);  // staged lists of the sparse path
     if (lds < kConvThreads * sizeof(double)) lds = kConvThreads * sizeof(double);
     if (lds > 65536)
-        SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_conv_lse<NT, KC, F64EXP, SPARSE>),
+        SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_conv_lse<NT, KC, F64EXP>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-    hipLaunchKernelGGL((k_conv_lse<NT, KC, F64EXP, SPARSE>), dim3(nblocks), dim3(kConvThreads), lds, s, d_jobs,
+    hipLaunchKernelGGL((k_conv_lse<NT, KC, F64EXP>), dim3(nblocks), dim3(kConvThreads), lds, s, d_jobs,
                        d_block_job);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+template <int NT>
+int launch_sparse_t(const ConvJob *d_jobs, int nblocks, const int32_t *d_block_job, int R_max, int2 *rebuild,
+                    int *rebuild_count, hipStream_t s) {
+    constexpr int NW = NT < 16 ? NT : 16;
+    const int HW = kTile + 2 * R_max, W = 2 * R_max + 1;
+    const size_t lds = static_cast<size_t>(HW) * HW * NT * sizeof(double) + kListLds * sizeof(double);
+    if (lds > 65536)
+        SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sparse<NT>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+    int rc = launch_fill_i32(rebuild_count, 1, 0, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_sparse<NT>, dim3(nblocks), dim3(64 * NW), lds, s, d_jobs, d_block_job, rebuild,
+                       rebuild_count);
+    SE2_HIP(hipGetLastError());
+    const size_t lr = static_cast<size_t>(HW) * HW * NT * sizeof(double) +
+                      (static_cast<size_t>(W) * W + kListMax) * sizeof(uint32_t);
+    if (lr > 65536)
+        SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rebuild<NT>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lr)));
+    const int grid = nblocks * NT < kRebuildGrid ? nblocks * NT : kRebuildGrid;
+    hipLaunchKernelGGL(k_rebuild<NT>, dim3(grid), dim3(kConvThreads), lr, s, d_jobs, rebuild, rebuild_count);
     SE2_HIP(hipGetLastError());
     return SE2_OK;
 }
@@ -384,36 +633,38 @@ bool conv_lse_sparse_fits(int nt, int R) {
 }
 
 int launch_conv_lse(const ConvJob *d_jobs, int njobs, int nblocks, const int32_t *d_block_job, int nt, int R_max,
-                    bool f64exp, bool sparse, hipStream_t s) {
+                    bool f64exp, bool sparse, int2 *rebuild, int *rebuild_count, hipStream_t s) {
     (void)njobs;
     if (nblocks <= 0) return SE2_OK;
     if (R_max < 0 || R_max > kMaxRadius) return SE2_EINVAL;
     const int HW = kTile + 2 * R_max;
-    if (sparse && !f64exp && conv_lse_sparse_fits(nt, R_max)) {
+    if (sparse) {
+        // every job of a sparse launch carries lists (the engine groups them apart)
+        if (f64exp || !conv_lse_sparse_fits(nt, R_max) || !rebuild || !rebuild_count) return SE2_EINVAL;
         switch (nt) {
-            case 8: return launch_t<8, 8, false, true>(d_jobs, nblocks, d_block_job, R_max, s);
-            case 16: return launch_t<16, 16, false, true>(d_jobs, nblocks, d_block_job, R_max, s);
-            case 32: return launch_t<32, 32, false, true>(d_jobs, nblocks, d_block_job, R_max, s);
+            case 8: return launch_sparse_t<8>(d_jobs, nblocks, d_block_job, R_max, rebuild, rebuild_count, s);
+            case 16: return launch_sparse_t<16>(d_jobs, nblocks, d_block_job, R_max, rebuild, rebuild_count, s);
+            case 32: return launch_sparse_t<32>(d_jobs, nblocks, d_block_job, R_max, rebuild, rebuild_count, s);
             default: return SE2_EINVAL;
         }
     }
     const bool kc16 = HW * HW * 16 * 8 <= 65536;
     switch (nt) {
         case 8:
-            return f64exp ? launch_t<8, 8, true, false>(d_jobs, nblocks, d_block_job, R_max, s)
-                          : launch_t<8, 8, false, false>(d_jobs, nblocks, d_block_job, R_max, s);
+            return f64exp ? launch_dense_t<8, 8, true>(d_jobs, nblocks, d_block_job, R_max, s)
+                          : launch_dense_t<8, 8, false>(d_jobs, nblocks, d_block_job, R_max, s);
         case 16:
             if (kc16)
-                return f64exp ? launch_t<16, 16, true, false>(d_jobs, nblocks, d_block_job, R_max, s)
-                              : launch_t<16, 16, false, false>(d_jobs, nblocks, d_block_job, R_max, s);
-            return f64exp ? launch_t<16, 8, true, false>(d_jobs, nblocks, d_block_job, R_max, s)
-                          : launch_t<16, 8, false, false>(d_jobs, nblocks, d_block_job, R_max, s);
+                return f64exp ? launch_dense_t<16, 16, true>(d_jobs, nblocks, d_block_job, R_max, s)
+                              : launch_dense_t<16, 16, false>(d_jobs, nblocks, d_block_job, R_max, s);
+            return f64exp ? launch_dense_t<16, 8, true>(d_jobs, nblocks, d_block_job, R_max, s)
+                          : launch_dense_t<16, 8, false>(d_jobs, nblocks, d_block_job, R_max, s);
         case 32:
             if (kc16)
-                return f64exp ? launch_t<32, 16, true, false>(d_jobs, nblocks, d_block_job, R_max, s)
-                              : launch_t<32, 16, false, false>(d_jobs, nblocks, d_block_job, R_max, s);
-            return f64exp ? launch_t<32, 8, true, false>(d_jobs, nblocks, d_block_job, R_max, s)
-                          : launch_t<32, 8, false, false>(d_jobs, nblocks, d_block_job, R_max, s);
+                return f64exp ? launch_dense_t<32, 16, true>(d_jobs, nblocks, d_block_job, R_max, s)
+                              : launch_dense_t<32, 16, false>(d_jobs, nblocks, d_block_job, R_max, s);
+            return f64exp ? launch_dense_t<32, 8, true>(d_jobs, nblocks, d_block_job, R_max, s)
+                          : launch_dense_t<32, 8, false>(d_jobs, nblocks, d_block_job, R_max, s);
         default:
             return SE2_EINVAL;
     }

@@ -27,17 +27,20 @@ constexpr int kMaxRadius = 12;
 // of the input from the halo it was built on spreads over at most kDriftSpread, so
 // every skipped entry is below 2^-(kListCut - kDriftSpread) = 2^-48 of the
 // result's largest term.
-constexpr double kListCut = 64.0;
-constexpr float kDriftSpread = 16.0f;
+constexpr double kListCut = 80.0;
+constexpr float kDriftSpread = 32.0f;
 constexpr int kListMax = 512;               // entries per (tile, ko); longer lists fall back to dense
-constexpr int kListLds = 2048;              // entries per tile staged in LDS; more fall back to dense
+constexpr int kListLds = 4096;              // entries per tile staged in LDS; more fall back to dense
 constexpr size_t kSparseLdsMax = 98304;     // the sparse path keeps the full FP64 halo in LDS
 
-struct ListEntry {
-    double L;     // log2 kernel value of the entry
-    int32_t off;  // LDS offset of the input relative to the output pixel: ki*npix + (R-dy)*HW + (R-dx)
-    int32_t pad;
-};
+// A list entry is the FP64 log2 kernel value of a window term with its low kOffBits
+// mantissa bits replaced by the LDS offset of the term's input relative to the output
+// pixel, ki*npix + (R-dy)*HW + (R-dx) (< 2^15 whenever the halo fits kSparseLdsMax);
+// the kernel value changes by less than 2^-37 relative, far below the FP32 rounding
+// of the exponents it enters.
+typedef double ListEntry;
+constexpr uint32_t kOffBits = 15;
+constexpr int kRebuildGrid = 2048;          // workgroups of the wide rebuild kernel
 
 #define SE2_HIP(call)                                                  \
     do {                                                               \
@@ -66,7 +69,7 @@ struct ConvJob {
     const double *L64;  // log2 kernel [W][W][nt][nt], FP64
     const float *L32;   // the same in FP32 (max pass only)
     // certified pruning state of this (solve, direction); lists == nullptr: dense only
-    ListEntry *lists;   // [tiles][nt][lmax]
+    ListEntry *lists;   // [tiles][nt][lmax] packed entries
     double *ref;        // [tiles][nt * npix] input halo the lists were built on
     int32_t *len;       // [tiles][nt], -1 = none
     float *mref;        // [E] per-output maximum exponent at build time
@@ -108,8 +111,10 @@ struct Kernel {
 int build_tables(Kernel &k);
 
 // launchers (conv_lse.hip)
+// Error partials of EPI_SCALE jobs are laid out [tile][nt]; `rebuild` must hold one
+// int2 per block of the launch (sparse launches only).
 int launch_conv_lse(const ConvJob *d_jobs, int njobs, int nblocks, const int32_t *d_block_job, int nt, int R_max,
-                    bool f64exp, bool sparse, hipStream_t s);
+                    bool f64exp, bool sparse, int2 *rebuild, int *rebuild_count, hipStream_t s);
 bool conv_lse_sparse_fits(int nt, int R);
 
 // launchers (conv_linear.hip)

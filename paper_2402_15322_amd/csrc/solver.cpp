@@ -66,7 +66,7 @@ size_t carve(Solve &s, int kind, const Kernel &k, int n, bool prune, void *mem) 
     const int tiles = tiles_of(k.grid.nx) * tiles_of(k.grid.ny);
     prune = prune && conv_lse_sparse_fits(k.grid.ntheta, k.metric.radius);
     const int nj = kind == SE2_REQ_OT ? 1 : n;
-    const size_t npart = static_cast<size_t>(tiles) * nj;
+    const size_t npart = static_cast<size_t>(tiles) * k.grid.ntheta * nj;
     const size_t ncost = 2 * static_cast<size_t>(cost_blocks(E)) * nj + 512;
     Carver c{static_cast<char *>(mem)};
     if (kind == SE2_REQ_OT) {
@@ -168,7 +168,7 @@ int solve_setup_ot(Solve &s, const double *mu, const double *nu, const double *i
         return rc;
     }
     if ((rc = solve_reset_lists(s, st))) return rc;
-    std::vector<int32_t> off = {0, s.tiles};
+    std::vector<int32_t> off = {0, s.tiles * s.k->grid.ntheta};
     SE2_HIP(hipMemcpyAsync(s.offsets, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     SE2_HIP(hipStreamSynchronize(st));  // `off` is a host temporary
     s.cur = 0;
@@ -186,7 +186,7 @@ int solve_setup_bary(Solve &s, const std::vector<const double *> &mus, hipStream
     }
     if ((rc = solve_reset_lists(s, st))) return rc;
     std::vector<int32_t> off(s.n + 1);
-    for (int i = 0; i <= s.n; ++i) off[i] = i * s.tiles;
+    for (int i = 0; i <= s.n; ++i) off[i] = i * s.tiles * s.k->grid.ntheta;
     SE2_HIP(hipMemcpyAsync(s.offsets, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     SE2_HIP(hipStreamSynchronize(st));
     s.iter = 0;
@@ -223,6 +223,8 @@ int Engine::collect_profile() {
 }
 
 Engine::~Engine() {
+    if (d_rebuild_) (void)hipFree(d_rebuild_);
+    if (d_rebuild_count_) (void)hipFree(d_rebuild_count_);
     for (Pending &p : pending_) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
@@ -263,16 +265,49 @@ int Engine::ensure(size_t njobs, size_t nblocks) {
     return SE2_OK;
 }
 
+int Engine::stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, int R_max, bool sparse,
+                             hipStream_t st) {
+    int rc = ensure(jobs.size(), nblocks);
+    if (rc) return rc;
+    const int h = flip_;
+    flip_ ^= 1;
+    SE2_HIP(hipEventSynchronize(staged_[h]));  // the copy that last read this half is done
+    ConvJob *hj = h_jobs_ + h * cap_jobs_;
+    int32_t *hm = h_map_ + h * cap_blocks_;
+    ConvJob *dj = d_jobs_ + h * cap_jobs_;
+    int32_t *dm = d_map_ + h * cap_blocks_;
+    std::memcpy(hj, jobs.data(), jobs.size() * sizeof(ConvJob));
+    for (size_t q = 0; q < jobs.size(); ++q)
+        for (int b = 0; b < jobs[q].tiles; ++b) hm[jobs[q].first_block + b] = static_cast<int32_t>(q);
+    SE2_HIP(hipMemcpyAsync(dj, hj, jobs.size() * sizeof(ConvJob), hipMemcpyHostToDevice, st));
+    SE2_HIP(hipMemcpyAsync(dm, hm, static_cast<size_t>(nblocks) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    SE2_HIP(hipEventRecord(staged_[h], st));
+    if (sparse && static_cast<size_t>(nblocks) > cap_rebuild_) {
+        // stream order: earlier launches that used the old buffers finish before it is freed
+        SE2_HIP(hipStreamSynchronize(st));
+        if (d_rebuild_) SE2_HIP(hipFree(d_rebuild_));
+        if (!d_rebuild_count_) SE2_HIP(hipMalloc(&d_rebuild_count_, sizeof(int)));
+        cap_rebuild_ = static_cast<size_t>(nblocks) * 2;
+        SE2_HIP(hipMalloc(&d_rebuild_, cap_rebuild_ * sizeof(int2)));
+    }
+    // The device tables of half h are only rewritten after staged_[h] completes a second
+    // time, i.e. after this launch (stream order) has consumed them.
+    return launch_conv_lse(dj, static_cast<int>(jobs.size()), nblocks, dm, nt, R_max, false, sparse,
+                           sparse ? d_rebuild_ : nullptr, sparse ? d_rebuild_count_ : nullptr, st);
+}
+
 int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool with_err, hipStream_t st) {
-    // group jobs by ntheta (the kernel is specialised on it)
+    // group jobs by ntheta (the kernels are specialised on it) and by whether they carry
+    // term lists (pruned jobs run the certified sparse kernel and its rebuild)
     static const int kClasses[3] = {8, 16, 32};
     for (int nt : kClasses) {
-        std::vector<ConvJob> jobs;
+        std::vector<ConvJob> jobs[2];
+        int nblocks[2] = {0, 0};
         int R_max = 0;
-        int nblocks = 0;
-        bool any_lists = false;
+        bool present = false;
         for (Solve *s : solves) {
             if (s->k->grid.ntheta != nt) continue;
+            present = true;
             const Kernel &k = *s->k;
             ConvJob base{};
             base.L64 = k.d_L64;
@@ -291,7 +326,12 @@ int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool wit
                 j.mref = l.mref;
                 j.dense_flag = l.dense_flag;
                 j.work = l.work;
-                if (l.lists) any_lists = true;
+            };
+            auto push = [&](ConvJob &j) {
+                const int g = j.lists != nullptr ? 1 : 0;
+                j.first_block = nblocks[g];
+                nblocks[g] += j.tiles;
+                jobs[g].push_back(j);
             };
             if (s->kind == SE2_REQ_OT) {
                 ConvJob j = base;
@@ -312,9 +352,7 @@ int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool wit
                         j.partial = s->partial;
                     }
                 }
-                j.first_block = nblocks;
-                nblocks += j.tiles;
-                jobs.push_back(j);
+                push(j);
             } else {
                 for (int i = 0; i < s->n; ++i) {
                     ConvJob j = base;
@@ -332,32 +370,14 @@ int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool wit
                         attach(j, s->ls_v[i]);
                         if (with_err) {
                             j.old = s->lw[i];
-                            j.partial = s->partial + static_cast<size_t>(i) * s->tiles;
+                            j.partial = s->partial + static_cast<size_t>(i) * s->tiles * s->k->grid.ntheta;
                         }
                     }
-                    j.first_block = nblocks;
-                    nblocks += j.tiles;
-                    jobs.push_back(j);
+                    push(j);
                 }
             }
         }
-        if (jobs.empty()) continue;
-        int rc = ensure(jobs.size(), nblocks);
-        if (rc) return rc;
-        const int h = flip_;
-        flip_ ^= 1;
-        SE2_HIP(hipEventSynchronize(staged_[h]));  // the copy that last read this half is done
-        ConvJob *hj = h_jobs_ + h * cap_jobs_;
-        int32_t *hm = h_map_ + h * cap_blocks_;
-        ConvJob *dj = d_jobs_ + h * cap_jobs_;
-        int32_t *dm = d_map_ + h * cap_blocks_;
-        std::memcpy(hj, jobs.data(), jobs.size() * sizeof(ConvJob));
-        for (size_t q = 0; q < jobs.size(); ++q)
-            for (int b = 0; b < jobs[q].tiles; ++b) hm[jobs[q].first_block + b] = static_cast<int32_t>(q);
-        SE2_HIP(hipMemcpyAsync(dj, hj, jobs.size() * sizeof(ConvJob), hipMemcpyHostToDevice, st));
-        SE2_HIP(hipMemcpyAsync(dm, hm, static_cast<size_t>(nblocks) * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        SE2_HIP(hipEventRecord(staged_[h], st));
-        const bool f64 = false;
+        if (!present) continue;
         Pending pe{};
         if (prof_) {
             for (int q = 0; q < 2; ++q) {
@@ -378,14 +398,15 @@ int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool wit
             }
             SE2_HIP(hipEventRecord(pe.a, st));
         }
-        rc = launch_conv_lse(dj, static_cast<int>(jobs.size()), nblocks, dm, nt, R_max, f64, any_lists, st);
-        if (rc) return rc;
+        for (int g = 0; g < 2; ++g) {
+            if (jobs[g].empty()) continue;
+            const int rc = stage_and_launch(jobs[g], nblocks[g], nt, R_max, g == 1, st);
+            if (rc) return rc;
+        }
         if (prof_) {
             SE2_HIP(hipEventRecord(pe.b, st));
             pending_.push_back(pe);
         }
-        // The device tables of half h are only rewritten after staged_[h] completes a second
-        // time, i.e. after this launch (stream order) has consumed them.
         for (Solve *s : solves) s->convs += (s->k->grid.ntheta == nt) ? (s->kind == SE2_REQ_OT ? 1 : s->n) : 0;
     }
     return SE2_OK;
@@ -487,7 +508,7 @@ int f64_check(const Kernel &k, const double *in, const double *aux, const double
     SE2_HIP(hipMallocAsync(reinterpret_cast<void **>(&dm), tiles * sizeof(int32_t), st));
     SE2_HIP(hipMemcpyAsync(dj, &j, sizeof(ConvJob), hipMemcpyHostToDevice, st));
     SE2_HIP(hipMemsetAsync(dm, 0, tiles * sizeof(int32_t), st));
-    int rc = launch_conv_lse(dj, 1, tiles, dm, k.grid.ntheta, k.metric.radius, true, false, st);
+    int rc = launch_conv_lse(dj, 1, tiles, dm, k.grid.ntheta, k.metric.radius, true, false, nullptr, nullptr, st);
     if (rc) return rc;
     rc = launch_sum_partials(partial, offsets, 1, err_out, st);
     if (rc) return rc;

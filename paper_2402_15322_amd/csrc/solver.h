@@ -37,7 +37,7 @@ struct Solve {
     std::vector<const double *> m_lin;
     double *logbar = nullptr;
     // common
-    double *partial = nullptr;       // tiles * max(1, n) error partials
+    double *partial = nullptr;       // [job][tile][nt] error partials
     double *err = nullptr;           // max(1, n) reduced errors (device)
     int32_t *offsets = nullptr;      // per-job partial offsets (device), max(1, n) + 1
     int iter = 0;                    // completed iterations
@@ -87,9 +87,13 @@ public:
 
 private:
     int launch_stage(const std::vector<Solve *> &solves, int stage, bool with_err, hipStream_t st);
+    int stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, int R_max, bool sparse, hipStream_t st);
     int ensure(size_t njobs, size_t nblocks);
     ConvJob *d_jobs_ = nullptr;
     int32_t *d_map_ = nullptr;
+    int2 *d_rebuild_ = nullptr;      // tiles left to the wide rebuild kernel, one slot per block
+    int *d_rebuild_count_ = nullptr;
+    size_t cap_rebuild_ = 0;
     ConvJob *h_jobs_ = nullptr;      // pinned staging (double-buffered)
     int32_t *h_map_ = nullptr;
     size_t cap_jobs_ = 0, cap_blocks_ = 0;
