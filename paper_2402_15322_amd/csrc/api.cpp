@@ -232,7 +232,7 @@ int se2_sinkhorn(se2_kernel_t h, const double *mu, const double *nu, const se2_o
     s.t_start = t0;
     DeviceBlock mem;
     mem.st = st;
-    const size_t bytes = solve_bytes(SE2_REQ_OT, *k, 1, opts->prune != 0);
+    const size_t bytes = solve_bytes(SE2_REQ_OT, *k, 1, prune_wanted(*opts));
     SE2_HIP(hipMallocAsync(&mem.p, bytes, st));
     solve_bind(s, mem.p);
     if ((rc = solve_setup_ot(s, mu, nu, opts->init_g, st))) return rc;
@@ -298,7 +298,7 @@ int se2_barycenter(se2_kernel_t h, int32_t n, const double *const *mus, const do
     s.t_start = t0;
     DeviceBlock mem;
     mem.st = st;
-    SE2_HIP(hipMallocAsync(&mem.p, solve_bytes(SE2_REQ_BARYCENTER, *k, s.n, opts->prune != 0), st));
+    SE2_HIP(hipMallocAsync(&mem.p, solve_bytes(SE2_REQ_BARYCENTER, *k, s.n, prune_wanted(*opts)), st));
     solve_bind(s, mem.p);
     if ((rc = solve_setup_bary(s, act, st))) return rc;
     Engine eng;

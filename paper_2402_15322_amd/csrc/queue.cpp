@@ -130,7 +130,7 @@ namespace {
 size_t request_bytes(const Req &q) {
     const Kernel &k = *reinterpret_cast<const Kernel *>(q.r.kernel);
     const size_t E = static_cast<size_t>(k.grid.nx) * k.grid.ny * k.grid.ntheta;
-    const bool prune = q.r.opts.prune != 0;
+    const bool prune = prune_wanted(q.r.opts);
     if (q.r.kind == SE2_REQ_OT)
         return solve_bytes(SE2_REQ_OT, k, 1, prune) + 2 * ((E * sizeof(double) + 255) / 256 * 256);
     const int n = static_cast<int>(q.mus_all.size());

@@ -121,13 +121,13 @@ size_t solve_bytes(int kind, const Kernel &k, int n_active, bool prune) {
 }
 
 bool prune_enabled(const Solve &s) {
-    return s.opts.prune != 0 && conv_lse_sparse_fits(s.k->grid.ntheta, s.k->metric.radius);
+    return prune_wanted(s.opts) && conv_lse_sparse_fits(s.k->grid.ntheta, s.k->metric.radius);
 }
 
 void solve_bind(Solve &s, void *mem) {
     s.E = static_cast<size_t>(s.k->grid.nx) * s.k->grid.ny * s.k->grid.ntheta;
     s.tiles = tiles_of(s.k->grid.nx) * tiles_of(s.k->grid.ny);
-    s.bytes = carve(s, s.kind, *s.k, s.n, s.opts.prune != 0, mem);
+    s.bytes = carve(s, s.kind, *s.k, s.n, prune_wanted(s.opts), mem);
     s.block = mem;
 }
 
@@ -265,7 +265,7 @@ int Engine::ensure(size_t njobs, size_t nblocks) {
     return SE2_OK;
 }
 
-int Engine::stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, int R_max, bool sparse,
+int Engine::stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, int R_max, bool sparse, bool f64,
                              hipStream_t st) {
     int rc = ensure(jobs.size(), nblocks);
     if (rc) return rc;
@@ -292,17 +292,17 @@ int Engine::stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, in
     }
     // The device tables of half h are only rewritten after staged_[h] completes a second
     // time, i.e. after this launch (stream order) has consumed them.
-    return launch_conv_lse(dj, static_cast<int>(jobs.size()), nblocks, dm, nt, R_max, false, sparse,
+    return launch_conv_lse(dj, static_cast<int>(jobs.size()), nblocks, dm, nt, R_max, f64, sparse,
                            sparse ? d_rebuild_ : nullptr, sparse ? d_rebuild_count_ : nullptr, st);
 }
 
 int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool with_err, hipStream_t st) {
-    // group jobs by ntheta (the kernels are specialised on it) and by whether they carry
-    // term lists (pruned jobs run the certified sparse kernel and its rebuild)
+    // group jobs by ntheta (the kernels are specialised on it) and by engine: dense FP32,
+    // pruned (certified sparse kernel and its rebuild), dense FP64
     static const int kClasses[3] = {8, 16, 32};
     for (int nt : kClasses) {
-        std::vector<ConvJob> jobs[2];
-        int nblocks[2] = {0, 0};
+        std::vector<ConvJob> jobs[3];
+        int nblocks[3] = {0, 0, 0};
         int R_max = 0;
         bool present = false;
         for (Solve *s : solves) {
@@ -327,8 +327,9 @@ int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool wit
                 j.dense_flag = l.dense_flag;
                 j.work = l.work;
             };
+            const bool f64 = s->opts.prec == SE2_F64;
             auto push = [&](ConvJob &j) {
-                const int g = j.lists != nullptr ? 1 : 0;
+                const int g = f64 ? 2 : (j.lists != nullptr ? 1 : 0);
                 j.first_block = nblocks[g];
                 nblocks[g] += j.tiles;
                 jobs[g].push_back(j);
@@ -398,9 +399,9 @@ int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool wit
             }
             SE2_HIP(hipEventRecord(pe.a, st));
         }
-        for (int g = 0; g < 2; ++g) {
+        for (int g = 0; g < 3; ++g) {
             if (jobs[g].empty()) continue;
-            const int rc = stage_and_launch(jobs[g], nblocks[g], nt, R_max, g == 1, st);
+            const int rc = stage_and_launch(jobs[g], nblocks[g], nt, R_max, g == 1, g == 2, st);
             if (rc) return rc;
         }
         if (prof_) {

@@ -57,6 +57,8 @@ double conv_terms(const Kernel &k);
 
 // Bytes one solve needs on the device (for admission against a budget).
 size_t solve_bytes(int kind, const Kernel &k, int n_active, bool prune);
+// Pruning applies to the FP32 engine only (the FP64 engine always visits every term).
+inline bool prune_wanted(const se2_opts_t &o) { return o.prune != 0 && o.prec != SE2_F64; }
 bool prune_enabled(const Solve &s);
 
 // Carve the buffers of `s` out of `mem` (size solve_bytes()).
@@ -87,7 +89,8 @@ public:
 
 private:
     int launch_stage(const std::vector<Solve *> &solves, int stage, bool with_err, hipStream_t st);
-    int stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, int R_max, bool sparse, hipStream_t st);
+    int stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, int R_max, bool sparse, bool f64,
+                         hipStream_t st);
     int ensure(size_t njobs, size_t nblocks);
     ConvJob *d_jobs_ = nullptr;
     int32_t *d_map_ = nullptr;

@@ -157,6 +157,27 @@ def test_sinkhorn_tiny_200_iterations(nat):
     assert abs(rep["cost"] - c_o) <= 1e-5 * c_o
 
 
+def test_sinkhorn_f64_engine(nat):
+    """prec = F64 runs every convolution with FP64 exponentials and sums: the iterate
+    then agrees with the FP64 oracle to rounding (plan L1 1e-9 after 200 iterations)."""
+    torch = torch_dev()
+    inst = synth.tiny_ot(1)
+    g = inst.grid
+    k = _kernel(nat, g.nx, g.ny, g.nt, g.axial, inst.w, inst.eps, inst.radius)
+    logk, _ = oracle.kernel_table(g.nt, g.axial, inst.w, inst.eps, inst.radius)
+    mu, nu = to_dev(inst.mu), to_dev(inst.nu)
+    phi_o, psi_o, _, err_o, _ = oracle.sinkhorn(logk, inst.mu, inst.nu, 200, -1.0)
+    l1 = {}
+    for prec in (nat.SE2_F32, nat.SE2_F64):
+        f = torch.empty_like(mu)
+        gg = torch.empty_like(mu)
+        rep = nat.se2_sinkhorn(k, mu, nu, nat.opts(tol=-1, max_iter=200, check_every=50, prec=prec), f, gg)
+        l1[prec] = oracle.plan_l1(logk, to_host(f) / inst.eps, to_host(gg) / inst.eps, phi_o, psi_o)
+        assert abs(rep["marg_l1"] - err_o) <= 1e-6
+    assert l1[nat.SE2_F64] <= 1e-9, l1
+    assert l1[nat.SE2_F32] <= 1e-5, l1
+
+
 def test_sinkhorn_converges_to_tolerance(nat):
     """A smooth random pair at eps = 1 reaches 1e-6 in a few hundred iterations (478 in the oracle)."""
     rng = np.random.default_rng(31)
