@@ -3,12 +3,15 @@
 //   BF16: implicit GEMM on the matrix cores.  For a fixed window row dy and a group
 //         of window columns, the contraction over (dx, ki) is a 16 x 32 by 32 x 16
 //         product: rows = 16 output pixels of one image row, columns = 16 output
-//         orientations ko, K-dimension = (dx slot, ki).  One
-//         v_mfma_f32_16x16x32_bf16 per (output row segment, dy, dx group); FP32
-//         accumulation over the whole window.  The input halo tile is rounded to
-//         bfloat16 (RNE) once while it is staged in LDS; kernel fragments are
-//         pre-packed on the host in operand order (one coalesced 16-byte load per
-//         lane) and zero-padded where the dx group overhangs the window.
+//         orientations ko, K-dimension = (dx slot, ki); one
+//         v_mfma_f32_16x16x32_bf16 each, FP32 accumulation over the whole window.
+//         Reuse: a wave owns 8 output rows and holds the kernel fragments of 8
+//         window rows in registers, so every input-row fragment read from LDS feeds
+//         up to 8 MFMAs (output row oy and window row dy meet input row oy - dy).
+//         The input halo tile is rounded to bfloat16 (RNE) once while it is staged
+//         in LDS; kernel fragments are pre-packed on the host in operand order (one
+//         coalesced 16-byte load per lane) and zero-padded where a dx group
+//         overhangs the window or a dy chunk runs past it.
 //   F32 / F64: the same tiling on the vector ALUs with FP32 / FP64 FMAs.
 #include <hip/hip_runtime.h>
 
@@ -24,14 +27,24 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
 namespace {
 
 constexpr int kSeg = 16;   // output pixels per MFMA row block
-constexpr int kRowsPerWave = 4;
+constexpr int kRPW = 8;    // output rows per wave
 constexpr int kWaves = 4;
-constexpr int kRows = kRowsPerWave * kWaves;  // output rows per workgroup
+constexpr int kRows = kRPW * kWaves;  // output rows per workgroup
+constexpr int kDYCMax = 8;  // most window rows whose kernel fragments a wave holds at once
 
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return static_cast<uint16_t>(u >> 16);
+// dy chunking of a window of W rows: the fewest chunks of at most kDYCMax rows, all of
+// one size DYC >= 4 (rows past the window are zero fragments).
+__host__ __device__ constexpr int dy_chunk(int W) {
+    const int n = (W + kDYCMax - 1) / kDYCMax;
+    const int d = (W + n - 1) / n;
+    return d < 4 ? 4 : d;
+}
+
+__device__ __forceinline__ uint32_t f32x2_to_bf16x2_rne(float lo, float hi) {
+    uint32_t a = __float_as_uint(lo), b = __float_as_uint(hi);
+    a += 0x7fffu + ((a >> 16) & 1u);
+    b += 0x7fffu + ((b >> 16) & 1u);
+    return (a >> 16) | (b & 0xffff0000u);
 }
 
 // Geometry of the packing: SPM dx slots per MFMA K-dimension, NB column blocks of 16 ko.
@@ -42,7 +55,42 @@ struct Pack {
     static constexpr int NB = (NT > 16) ? NT / 16 : 1;
 };
 
-template <int NT>
+// MFMAs of one dy chunk for one dx group: t runs over the input rows that the wave's 8
+// output rows meet with the chunk's window rows; (r, c) with r - c = t - (DYC - 1) is
+// output row r and window row dy0 + c.  Rows past the window carry zero fragments; the
+// input row is clamped into the halo for them (the product is then 0).
+template <int NT, int DYC>
+__device__ __forceinline__ void mfma_chunk(f32x4_t (&acc)[kRPW][Pack<NT>::NB],
+                                           const bf16x8_t (&bfr)[DYC][Pack<NT>::NB], const uint16_t *lds16,
+                                           int hrow_t0, int HWX, int hx, int kio) {
+    using P = Pack<NT>;
+    constexpr int T = kRPW + DYC - 1;
+    const uint16_t *base = lds16 + hx * NT + kio;
+    const int rstride = HWX * NT;
+    auto read_a = [&](int t) {
+        return *reinterpret_cast<const bf16x8_t *>(base + max(hrow_t0 + t, 0) * rstride);
+    };
+    // the read of input row t+1 is issued before the MFMAs of row t
+    bf16x8_t a = read_a(0);
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        bf16x8_t an = a;
+        if (t + 1 < T) an = read_a(t + 1);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int r = 0; r < kRPW; ++r) {
+            const int c = r - t + DYC - 1;
+            if (c < 0 || c >= DYC) continue;
+#pragma unroll
+            for (int nb = 0; nb < P::NB; ++nb)
+                acc[r][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[c][nb], acc[r][nb], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        a = an;
+    }
+}
+
+template <int NT, int DYC>
 __global__ __launch_bounds__(256) void k_conv_bf16(const float *__restrict__ in, float *__restrict__ out,
                                                    const bf16x8_t *__restrict__ Bp, int nx, int ny, int R,
                                                    int tiles_x, int tiles_y) {
@@ -60,65 +108,102 @@ __global__ __launch_bounds__(256) void k_conv_bf16(const float *__restrict__ in,
     const float *img = in + static_cast<size_t>(b) * nx * ny * NT;
     float *dst = out + static_cast<size_t>(b) * nx * ny * NT;
 
-    // stage halo [hy][hx][ki] as bfloat16; hx = 0 is pixel x0 - R - (overhang)
+    // stage halo [hy][hx][ki] as bfloat16, four orientations per thread and element;
+    // hx = 0 is pixel x0 - R - (overhang).  Loads go out in batches of 8 per thread
+    // (clamped indices, no branches) before any of them is converted and stored.
     const int xl = x0 - R - (G * P::SPM - W);
-    const int total = HWY * HWX * NT;
-    for (int e = threadIdx.x; e < total; e += 256) {
-        const int k = e % NT;
-        const int p = e / NT;
-        const int hy = p / HWX, hx = p - hy * HWX;
-        const int gy = y0 - R + hy, gx = xl + hx;
-        float v = 0.0f;
-        if (gy >= 0 && gy < ny && gx >= 0 && gx < nx) v = img[(static_cast<size_t>(gy) * nx + gx) * NT + k];
-        lds16[e] = f32_to_bf16_rne(v);
+    {
+        constexpr int Q = NT / 4;
+        constexpr int NB8 = 8;
+        const int total = HWY * HWX * Q;
+        const float inv = 1.0f / static_cast<float>(HWX);
+        for (int e0 = 0; e0 < total; e0 += NB8 * 256) {
+            float4 v[NB8];
+            bool ok[NB8];
+#pragma unroll
+            for (int u = 0; u < NB8; ++u) {
+                const int e = min(e0 + u * 256 + static_cast<int>(threadIdx.x), total - 1);
+                const int p = e / Q, q = e - p * Q;
+                // p / HWX through a float reciprocal: exact for p < 2^20 (the +0.5 keeps
+                // the rounding error far from an integer boundary)
+                const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv), hx = p - hy * HWX;
+                const int gy = y0 - R + hy, gx = xl + hx;
+                ok[u] = gy >= 0 && gy < ny && gx >= 0 && gx < nx;
+                const int cy = min(max(gy, 0), ny - 1), cx = min(max(gx, 0), nx - 1);
+                v[u] = *reinterpret_cast<const float4 *>(&img[(static_cast<size_t>(cy) * nx + cx) * NT + 4 * q]);
+            }
+#pragma unroll
+            for (int u = 0; u < NB8; ++u) {
+                const int e = e0 + u * 256 + static_cast<int>(threadIdx.x);
+                if (e < total)
+                    *reinterpret_cast<uint2 *>(&lds16[4 * e]) =
+                        ok[u] ? make_uint2(f32x2_to_bf16x2_rne(v[u].x, v[u].y), f32x2_to_bf16x2_rne(v[u].z, v[u].w))
+                              : make_uint2(0u, 0u);
+            }
+        }
     }
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
     const int i = lane & 15;   // output pixel within the segment (A row)
     const int kb = lane >> 4;  // 8-wide K block of this lane
     const int slot = (kb * 8) / P::KI;
     const int kio = (kb * 8) % P::KI;
+    const int row0 = wave * kRPW;  // first output row of this wave within the tile
 
-    f32x4_t acc[kRowsPerWave][P::NB];
+    f32x4_t acc[kRPW][P::NB];
 #pragma unroll
-    for (int r = 0; r < kRowsPerWave; ++r)
+    for (int r = 0; r < kRPW; ++r)
 #pragma unroll
         for (int nb = 0; nb < P::NB; ++nb) acc[r][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
-    for (int dy = -R; dy <= R; ++dy) {
-        for (int g = 0; g < G; ++g) {
-            bf16x8_t bfr[P::NB];
+    // (g, chunk) steps; the kernel fragments of the next step are loaded while the
+    // current one runs on the matrix cores
+    const int nchunks = (W + DYC - 1) / DYC;
+    const int nsteps = G * nchunks;
+    bf16x8_t b0[DYC][P::NB], b1[DYC][P::NB];
+    auto load_b = [&](bf16x8_t(&dstb)[DYC][P::NB], int step) {
+        const int g = step / nchunks, ch = step - g * nchunks;
+        const bf16x8_t *src = Bp + (static_cast<size_t>(ch * DYC) * G + g) * P::NB * 64 + lane;
 #pragma unroll
-            for (int nb = 0; nb < P::NB; ++nb)
-                bfr[nb] = Bp[((static_cast<size_t>(dy + R) * G + g) * P::NB + nb) * 64 + lane];
-            // this lane's dx: slots of group g run dx = -R + g*SPM + slot
-            const int dxl = -R + g * P::SPM + slot;
-            // input pixel x0 + i - dx  ->  halo column (x0 + i - dx) - xl
-            const int hx = x0 + i - dxl - xl;
+        for (int c = 0; c < DYC; ++c)
 #pragma unroll
-            for (int r = 0; r < kRowsPerWave; ++r) {
-                const int oy = wave * kRowsPerWave + r;        // output row within the tile
-                const int hy = oy + R - dy;                    // input row y0 + oy - dy
-                const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(&lds16[(hy * HWX + hx) * NT + kio]);
+            for (int nb = 0; nb < P::NB; ++nb) dstb[c][nb] = src[(static_cast<size_t>(c) * G * P::NB + nb) * 64];
+    };
+    auto run = [&](const bf16x8_t(&bfr)[DYC][P::NB], int step) {
+        const int g = step / nchunks, ch = step - g * nchunks;
+        // this lane's dx: slots of group g run dx = -R + g*SPM + slot; input pixel
+        // x0 + i - dx sits at halo column (x0 + i - dx) - xl
+        const int hx = x0 + i - (-R + g * P::SPM + slot) - xl;
+        const int dy0 = -R + ch * DYC;
+        // halo row of (r, c): row0 + r - (dy0 + c) + R = hrow_t0 + t
+        mfma_chunk<NT, DYC>(acc, bfr, lds16, row0 + R - dy0 - (DYC - 1), HWX, hx, kio);
+    };
+    // the prefetch index is clamped (the last step reloads its own fragments) so the
+    // loop body has no branch and the loads' wait counts stay exact
+    load_b(b0, 0);
+    for (int step = 0; step < nsteps; ++step) {
+        load_b(b1, min(step + 1, nsteps - 1));
+        __builtin_amdgcn_sched_barrier(0);
+        run(b0, step);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int nb = 0; nb < P::NB; ++nb)
-                    acc[r][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[nb], acc[r][nb], 0, 0, 0);
-            }
-        }
+        for (int c = 0; c < DYC; ++c)
+#pragma unroll
+            for (int nb = 0; nb < P::NB; ++nb) b0[c][nb] = b1[c][nb];
     }
 
     // D: lane holds column j = lane % 16 (ko), rows 4*(lane/16) + q (pixels)
     const int j = lane & 15;
 #pragma unroll
-    for (int r = 0; r < kRowsPerWave; ++r) {
-        const int gy = y0 + wave * kRowsPerWave + r;
+    for (int r = 0; r < kRPW; ++r) {
+        const int gy = y0 + row0 + r;
         if (gy >= ny) continue;
 #pragma unroll
         for (int nb = 0; nb < P::NB; ++nb) {
             const int ko = nb * 16 + j;
-            if (ko >= NT) continue;
+            if (ko >= NT) continue;  // nt = 8: columns 8..15 are padding
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int gx = x0 + 4 * (lane >> 4) + q;
@@ -182,7 +267,7 @@ __global__ __launch_bounds__(256) void k_conv_valu(const T *__restrict__ in, T *
     }
 }
 
-template <int NT>
+template <int NT, int DYC>
 int launch_bf16_t(const Kernel &k, const float *in, float *out, int batch, hipStream_t s) {
     using P = Pack<NT>;
     const int nx = k.grid.nx, ny = k.grid.ny, R = k.metric.radius, W = 2 * R + 1;
@@ -191,12 +276,24 @@ int launch_bf16_t(const Kernel &k, const float *in, float *out, int batch, hipSt
     const size_t lds = static_cast<size_t>(HWX) * HWY * NT * sizeof(uint16_t);
     const int tx = (nx + kSeg - 1) / kSeg, ty = (ny + kRows - 1) / kRows;
     if (lds > 65536)
-        SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_conv_bf16<NT>),
+        SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_conv_bf16<NT, DYC>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-    hipLaunchKernelGGL(k_conv_bf16<NT>, dim3(tx * ty * batch), dim3(256), lds, s, in, out,
+    hipLaunchKernelGGL((k_conv_bf16<NT, DYC>), dim3(tx * ty * batch), dim3(256), lds, s, in, out,
                        reinterpret_cast<const bf16x8_t *>(k.d_Bpack), nx, ny, R, tx, ty);
     SE2_HIP(hipGetLastError());
     return SE2_OK;
+}
+
+template <int NT>
+int launch_bf16_nt(const Kernel &k, const float *in, float *out, int batch, hipStream_t s) {
+    switch (dy_chunk(2 * k.metric.radius + 1)) {
+        case 4: return launch_bf16_t<NT, 4>(k, in, out, batch, s);
+        case 5: return launch_bf16_t<NT, 5>(k, in, out, batch, s);
+        case 6: return launch_bf16_t<NT, 6>(k, in, out, batch, s);
+        case 7: return launch_bf16_t<NT, 7>(k, in, out, batch, s);
+        case 8: return launch_bf16_t<NT, 8>(k, in, out, batch, s);
+        default: return SE2_EINVAL;
+    }
 }
 
 template <typename T, int NT, int KC>
@@ -234,14 +331,17 @@ size_t conv_bf16_lds_bytes(int nt, int R) {
 
 // Host packing of the bfloat16 kernel into MFMA B-operand order:
 // Bp[dy][g][nb][lane][e] = K[dy][dx = -R + g*SPM + slot][ko = nb*16 + lane%16][ki], where
-// lane/16 = kb selects K-rows 8*kb .. 8*kb+7 = (slot, ki); zero outside the window or ko >= NT.
+// lane/16 = kb selects K-rows 8*kb .. 8*kb+7 = (slot, ki); zero outside the window or
+// ko >= NT.  The dy rows run on to a multiple of the dy chunk (zero rows).
 std::vector<uint16_t> pack_bf16_operand(const std::vector<uint16_t> &Kb, int nt, int R) {
     const int W = 2 * R + 1;
     const int spm = (nt >= 32) ? 1 : 32 / nt;
     const int kis = 32 / spm;
     const int NB = (nt > 16) ? nt / 16 : 1;
     const int G = (W + spm - 1) / spm;
-    std::vector<uint16_t> Bp(static_cast<size_t>(W) * G * NB * 64 * 8, 0);
+    const int DYC = dy_chunk(W);
+    const int WP = (W + DYC - 1) / DYC * DYC;
+    std::vector<uint16_t> Bp(static_cast<size_t>(WP) * G * NB * 64 * 8, 0);
     for (int dyi = 0; dyi < W; ++dyi)
         for (int g = 0; g < G; ++g)
             for (int nb = 0; nb < NB; ++nb)
@@ -261,9 +361,9 @@ std::vector<uint16_t> pack_bf16_operand(const std::vector<uint16_t> &Kb, int nt,
 
 int launch_conv_bf16(const Kernel &k, const float *in, float *out, int batch, hipStream_t s) {
     switch (k.grid.ntheta) {
-        case 8: return launch_bf16_t<8>(k, in, out, batch, s);
-        case 16: return launch_bf16_t<16>(k, in, out, batch, s);
-        case 32: return launch_bf16_t<32>(k, in, out, batch, s);
+        case 8: return launch_bf16_nt<8>(k, in, out, batch, s);
+        case 16: return launch_bf16_nt<16>(k, in, out, batch, s);
+        case 32: return launch_bf16_nt<32>(k, in, out, batch, s);
         default: return SE2_EINVAL;
     }
 }
