@@ -10,8 +10,9 @@ resident solve).  Inputs are on the device before the timed region starts.
 Printed JSON line: the whole-job Sinkhorn iteration rate, solves/s (completed
 and converged), p50/p99 solve latency, the roofline of the dominant kernel (the
 log-domain convolution, timed with HIP events on the queue's stream), the same
-solves run one at a time beside it, and the FP64 CPU oracle timed on a bounded
-sample on this host.
+solves run one at a time beside it, the FP64 CPU oracle timed on a bounded
+sample on this host, and the linear se2_conv (BF16 on the matrix cores, and
+FP32) at the workloads' grid shapes against the MFMA peak.
 """
 from __future__ import annotations
 
@@ -55,7 +56,58 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations for the CPU baseline (0: auto)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-prune", action="store_true", help="dense convolutions only (no certified pruning)")
+    ap.add_argument("--no-conv", action="store_true", help="skip the linear se2_conv measurements")
+    ap.add_argument("--conv-only", action="store_true", help="only the linear se2_conv measurements")
+    ap.add_argument("--conv-reps", type=int, default=20)
+    ap.add_argument("--copy-ref-mb", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (a known-size reference for HBM counters)")
     return ap.parse_args()
+
+
+# Linear group convolutions timed beside the solver: the three grid shapes of the
+# workloads, each at the batch one half-step of that workload applies (one convolution
+# per solve at 64x64x16 for the bench batch; 2 measures x 5 interpolation weights at
+# 128x128x16; 4 measures at 256x256x32 axial).
+CONV_SHAPES = (
+    # n, ntheta, radius, axial, w, eps, batch (None: the bench batch)
+    (64, 16, 5, False, (1.0, 3.0, 1.0), 0.1, None),
+    (128, 16, 7, False, (1.0, 3.0, 1.0), 0.05, 10),
+    (256, 32, 10, True, (1.0, 4.0, 1.0), 0.03, 4),
+)
+PEAK_BF16_TFLOPS = 2500.0  # dense MFMA, bf16
+PEAK_F32_TFLOPS = 157.3
+
+
+def conv_measurements(native, torch, batch: int, reps: int):
+    """se2_conv (BF16 MFMA and FP32) timed with HIP events on the current stream."""
+    out = []
+    for n, nt, R, axial, w, eps, b in CONV_SHAPES:
+        b = b or batch
+        k = native.Kernel(n, n, nt, axial, w, eps, R)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(7)
+        x = torch.rand((b, n, n, nt), device="cuda", generator=g)
+        y = torch.empty_like(x)
+        flops = 2.0 * b * n * n * nt * nt * (2 * R + 1) ** 2
+        rec = {"shape": f"{n}x{n}x{nt}{' axial' if axial else ''}, {2 * R + 1}x{2 * R + 1} window", "batch": b,
+               "flops_per_launch": flops}
+        for prec, tag, peak in ((native.SE2_BF16, "bf16", PEAK_BF16_TFLOPS), (native.SE2_F32, "f32", PEAK_F32_TFLOPS)):
+            native.se2_conv(k, prec, x, y)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                native.se2_conv(k, prec, x, y)
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) * 1e-3 / reps
+            rec[f"{tag}_us"] = t * 1e6
+            rec[f"{tag}_tflops"] = flops / t / 1e12
+            rec[f"{tag}_frac"] = flops / t / 1e12 / peak
+        out.append(rec)
+        del k
+    return out
 
 
 def main():
@@ -72,6 +124,15 @@ def main():
 
     torch.cuda.set_device(0)
     native.se2_init()
+    if a.copy_ref_mb > 0:
+        src = torch.ones(a.copy_ref_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if a.conv_only:
+        print(json.dumps({"se2_conv": conv_measurements(native, torch, a.batch, a.conv_reps)}), flush=True)
+        return
     k = native.Kernel(NX, NX, NT, False, W_METRIC, EPS, R)
     insts = [synth.lines64(i, paired=True) for i in range(a.batch)]
     mus = [torch.from_numpy(x.mu).cuda() for x in insts]
@@ -132,6 +193,8 @@ def main():
         plain_iters += rep["iters"]
     plain_rate = plain_iters / plain_wall if plain_wall > 0 else None
 
+    conv_meas = None if a.no_conv else conv_measurements(native, torch, a.batch, a.conv_reps)
+
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(insts[0], a.cpu_iters)
@@ -169,6 +232,8 @@ def main():
                      "window_terms_per_launch": kt["terms"] / launches,
                      "slots_per_term": {"dense": SLOTS_DENSE, "sparse": SLOTS_SPARSE}},
         "cpu_baseline": cpu,
+        "se2_conv": {"bound": "mfma", "peak_bf16_tflops": PEAK_BF16_TFLOPS, "peak_f32_tflops": PEAK_F32_TFLOPS,
+                     "flops": "2 * batch * nx * ny * ntheta^2 * window", "launches": conv_meas},
     }
     print(json.dumps(out), flush=True)
 

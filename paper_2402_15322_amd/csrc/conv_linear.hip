@@ -5,9 +5,10 @@
 //         product: rows = 16 output pixels of one image row, columns = 16 output
 //         orientations ko, K-dimension = (dx slot, ki); one
 //         v_mfma_f32_16x16x32_bf16 each, FP32 accumulation over the whole window.
-//         Reuse: a wave owns 8 output rows and holds the kernel fragments of 8
-//         window rows in registers, so every input-row fragment read from LDS feeds
-//         up to 8 MFMAs (output row oy and window row dy meet input row oy - dy).
+//         Reuse: a wave owns 8 (or 4) output rows and holds the kernel fragments of
+//         up to 8 window rows in registers, so every input-row fragment read from
+//         LDS feeds up to 8 MFMAs (output row oy and window row dy meet input row
+//         oy - dy).
 //         The input halo tile is rounded to bfloat16 (RNE) once while it is staged
 //         in LDS; kernel fragments are pre-packed on the host in operand order (one
 //         coalesced 16-byte load per lane) and zero-padded where a dx group
@@ -27,9 +28,8 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
 namespace {
 
 constexpr int kSeg = 16;   // output pixels per MFMA row block
-constexpr int kRPW = 8;    // output rows per wave
-constexpr int kWaves = 4;
-constexpr int kRows = kRPW * kWaves;  // output rows per workgroup
+constexpr int kWaves = 4;  // a workgroup is kWaves * RPW output rows of kSeg pixels
+constexpr int kNumCUs = 256;  // compute units of an MI355X
 constexpr int kDYCMax = 8;  // most window rows whose kernel fragments a wave holds at once
 
 // dy chunking of a window of W rows: the fewest chunks of at most kDYCMax rows, all of
@@ -55,16 +55,16 @@ struct Pack {
     static constexpr int NB = (NT > 16) ? NT / 16 : 1;
 };
 
-// MFMAs of one dy chunk for one dx group: t runs over the input rows that the wave's 8
+// MFMAs of one dy chunk for one dx group: t runs over the input rows that the wave's
 // output rows meet with the chunk's window rows; (r, c) with r - c = t - (DYC - 1) is
 // output row r and window row dy0 + c.  Rows past the window carry zero fragments; the
 // input row is clamped into the halo for them (the product is then 0).
-template <int NT, int DYC>
-__device__ __forceinline__ void mfma_chunk(f32x4_t (&acc)[kRPW][Pack<NT>::NB],
+template <int NT, int DYC, int RPW>
+__device__ __forceinline__ void mfma_chunk(f32x4_t (&acc)[RPW][Pack<NT>::NB],
                                            const bf16x8_t (&bfr)[DYC][Pack<NT>::NB], const uint16_t *lds16,
                                            int hrow_t0, int HWX, int hx, int kio) {
     using P = Pack<NT>;
-    constexpr int T = kRPW + DYC - 1;
+    constexpr int T = RPW + DYC - 1;
     const uint16_t *base = lds16 + hx * NT + kio;
     const int rstride = HWX * NT;
     auto read_a = [&](int t) {
@@ -78,7 +78,7 @@ __device__ __forceinline__ void mfma_chunk(f32x4_t (&acc)[kRPW][Pack<NT>::NB],
         if (t + 1 < T) an = read_a(t + 1);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int r = 0; r < kRPW; ++r) {
+        for (int r = 0; r < RPW; ++r) {
             const int c = r - t + DYC - 1;
             if (c < 0 || c >= DYC) continue;
 #pragma unroll
@@ -90,7 +90,7 @@ __device__ __forceinline__ void mfma_chunk(f32x4_t (&acc)[kRPW][Pack<NT>::NB],
     }
 }
 
-template <int NT, int DYC>
+template <int NT, int DYC, int RPW>
 __global__ __launch_bounds__(256) void k_conv_bf16(const float *__restrict__ in, float *__restrict__ out,
                                                    const bf16x8_t *__restrict__ Bp, int nx, int ny, int R,
                                                    int tiles_x, int tiles_y) {
@@ -99,6 +99,7 @@ __global__ __launch_bounds__(256) void k_conv_bf16(const float *__restrict__ in,
     const int W = 2 * R + 1;
     const int G = (W + P::SPM - 1) / P::SPM;
     const int HWX = kSeg + 2 * R + (G * P::SPM - W);  // halo width incl. overhang of the last dx group
+    constexpr int kRows = RPW * kWaves;
     const int HWY = kRows + 2 * R;
     const int tiles = tiles_x * tiles_y;
     const int b = blockIdx.x / tiles;
@@ -150,11 +151,11 @@ __global__ __launch_bounds__(256) void k_conv_bf16(const float *__restrict__ in,
     const int kb = lane >> 4;  // 8-wide K block of this lane
     const int slot = (kb * 8) / P::KI;
     const int kio = (kb * 8) % P::KI;
-    const int row0 = wave * kRPW;  // first output row of this wave within the tile
+    const int row0 = wave * RPW;  // first output row of this wave within the tile
 
-    f32x4_t acc[kRPW][P::NB];
+    f32x4_t acc[RPW][P::NB];
 #pragma unroll
-    for (int r = 0; r < kRPW; ++r)
+    for (int r = 0; r < RPW; ++r)
 #pragma unroll
         for (int nb = 0; nb < P::NB; ++nb) acc[r][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(256) void k_conv_bf16(const float *__restrict__ in,
         const int hx = x0 + i - (-R + g * P::SPM + slot) - xl;
         const int dy0 = -R + ch * DYC;
         // halo row of (r, c): row0 + r - (dy0 + c) + R = hrow_t0 + t
-        mfma_chunk<NT, DYC>(acc, bfr, lds16, row0 + R - dy0 - (DYC - 1), HWX, hx, kio);
+        mfma_chunk<NT, DYC, RPW>(acc, bfr, lds16, row0 + R - dy0 - (DYC - 1), HWX, hx, kio);
     };
     // the prefetch index is clamped (the last step reloads its own fragments) so the
     // loop body has no branch and the loads' wait counts stay exact
@@ -197,7 +198,7 @@ __global__ __launch_bounds__(256) void k_conv_bf16(const float *__restrict__ in,
     // D: lane holds column j = lane % 16 (ko), rows 4*(lane/16) + q (pixels)
     const int j = lane & 15;
 #pragma unroll
-    for (int r = 0; r < kRPW; ++r) {
+    for (int r = 0; r < RPW; ++r) {
         const int gy = y0 + row0 + r;
         if (gy >= ny) continue;
 #pragma unroll
@@ -267,31 +268,43 @@ __global__ __launch_bounds__(256) void k_conv_valu(const T *__restrict__ in, T *
     }
 }
 
-template <int NT, int DYC>
+template <int NT, int DYC, int RPW>
 int launch_bf16_t(const Kernel &k, const float *in, float *out, int batch, hipStream_t s) {
     using P = Pack<NT>;
     const int nx = k.grid.nx, ny = k.grid.ny, R = k.metric.radius, W = 2 * R + 1;
     const int G = (W + P::SPM - 1) / P::SPM;
-    const int HWX = kSeg + 2 * R + (G * P::SPM - W), HWY = kRows + 2 * R;
+    const int rows = RPW * kWaves;
+    const int HWX = kSeg + 2 * R + (G * P::SPM - W), HWY = rows + 2 * R;
     const size_t lds = static_cast<size_t>(HWX) * HWY * NT * sizeof(uint16_t);
-    const int tx = (nx + kSeg - 1) / kSeg, ty = (ny + kRows - 1) / kRows;
+    const int tx = (nx + kSeg - 1) / kSeg, ty = (ny + rows - 1) / rows;
     if (lds > 65536)
-        SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_conv_bf16<NT, DYC>),
+        SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_conv_bf16<NT, DYC, RPW>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-    hipLaunchKernelGGL((k_conv_bf16<NT, DYC>), dim3(tx * ty * batch), dim3(256), lds, s, in, out,
+    hipLaunchKernelGGL((k_conv_bf16<NT, DYC, RPW>), dim3(tx * ty * batch), dim3(256), lds, s, in, out,
                        reinterpret_cast<const bf16x8_t *>(k.d_Bpack), nx, ny, R, tx, ty);
     SE2_HIP(hipGetLastError());
     return SE2_OK;
 }
 
+// 8 output rows per wave, or 4 (twice the workgroups, less reuse per LDS read) when
+// 8 would leave fewer than 4 workgroups per compute unit.  nt = 32 keeps 8: its halo
+// limits it to one workgroup per compute unit either way (measured: 8 rows faster).
+template <int NT, int DYC>
+int launch_bf16_rpw(const Kernel &k, const float *in, float *out, int batch, hipStream_t s) {
+    const long tiles8 = static_cast<long>((k.grid.nx + kSeg - 1) / kSeg) * ((k.grid.ny + 8 * kWaves - 1) / (8 * kWaves));
+    if (NT >= 32 || tiles8 * batch >= 4L * kNumCUs) return launch_bf16_t<NT, DYC, 8>(k, in, out, batch, s);
+    if constexpr (NT < 32) return launch_bf16_t<NT, DYC, 4>(k, in, out, batch, s);
+    return SE2_EINVAL;
+}
+
 template <int NT>
 int launch_bf16_nt(const Kernel &k, const float *in, float *out, int batch, hipStream_t s) {
     switch (dy_chunk(2 * k.metric.radius + 1)) {
-        case 4: return launch_bf16_t<NT, 4>(k, in, out, batch, s);
-        case 5: return launch_bf16_t<NT, 5>(k, in, out, batch, s);
-        case 6: return launch_bf16_t<NT, 6>(k, in, out, batch, s);
-        case 7: return launch_bf16_t<NT, 7>(k, in, out, batch, s);
-        case 8: return launch_bf16_t<NT, 8>(k, in, out, batch, s);
+        case 4: return launch_bf16_rpw<NT, 4>(k, in, out, batch, s);
+        case 5: return launch_bf16_rpw<NT, 5>(k, in, out, batch, s);
+        case 6: return launch_bf16_rpw<NT, 6>(k, in, out, batch, s);
+        case 7: return launch_bf16_rpw<NT, 7>(k, in, out, batch, s);
+        case 8: return launch_bf16_rpw<NT, 8>(k, in, out, batch, s);
         default: return SE2_EINVAL;
     }
 }
@@ -326,7 +339,7 @@ size_t conv_bf16_lds_bytes(int nt, int R) {
     const int W = 2 * R + 1;
     const int spm = (nt >= 32) ? 1 : 32 / nt;
     const int G = (W + spm - 1) / spm;
-    return static_cast<size_t>(kSeg + 2 * R + (G * spm - W)) * (kRows + 2 * R) * nt * sizeof(uint16_t);
+    return static_cast<size_t>(kSeg + 2 * R + (G * spm - W)) * (8 * kWaves + 2 * R) * nt * sizeof(uint16_t);
 }
 
 // Host packing of the bfloat16 kernel into MFMA B-operand order:
