@@ -49,60 +49,51 @@ namespace {
 
 typedef const __attribute__((address_space(4))) double *cdptr;
 typedef const __attribute__((address_space(4))) float *cfptr;
+// Global-memory views of the job's pointers: global (not flat) loads wait on the
+// vector-memory counter only, so they do not serialise against LDS traffic.
+typedef const __attribute__((address_space(1))) double *gdptr;
+typedef const __attribute__((address_space(1))) float *gfptr;
+typedef const __attribute__((address_space(1))) int32_t *giptr;
+typedef __attribute__((address_space(1))) double *gdptr_w;
+typedef __attribute__((address_space(1))) float *gfptr_w;
+
+constexpr int kHaloBatch = 4;  // halo elements each thread loads before storing any
 
 // Stage the input halo (8+2R)^2 x KC orientations (from k0) in LDS as [kc][hy][hx],
-// -inf outside the grid.  Loads are unconditional (clamped address, then a select) and
-// unrolled so that many are in flight; hy = p / HW via a float reciprocal (exact for
-// p < 2^20: the +0.5 keeps the rounding error far below the gap to an integer).
+// -inf outside the grid.  Each thread issues kHaloBatch loads (clamped addresses, no
+// branches) before it stores any of them; hy = p / HW via a float reciprocal (exact
+// for p < 2^20: the +0.5 keeps the rounding error far below the gap to an integer).
 template <int KC>
-__device__ __forceinline__ void load_halo(double *lds, const double *__restrict__ in, int nt, int k0, int x0, int y0,
-                                          int R, int HW, int nx, int ny) {
+__device__ __forceinline__ void load_halo(double *lds, const double *in_, int nt, int k0, int x0, int y0, int R,
+                                          int HW, int nx, int ny) {
+    const gdptr in = (gdptr)in_;
     const int npix = HW * HW;
     const int total = npix * KC;
     const float inv = 1.0f / static_cast<float>(HW);
-#pragma unroll 8
-    for (int e = threadIdx.x; e < total; e += kConvThreads) {
-        const int p = e / KC;
-        const int kc = e - p * KC;
-        const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv);
-        const int hx = p - hy * HW;
-        const int gy = y0 - R + hy, gx = x0 - R + hx;
-        const bool inside = gy >= 0 && gy < ny && gx >= 0 && gx < nx;
-        const int cy = min(max(gy, 0), ny - 1), cx = min(max(gx, 0), nx - 1);
-        const double v = in[(static_cast<size_t>(cy) * nx + cx) * nt + k0 + kc];
-        lds[kc * npix + p] = inside ? v : -INFINITY;
-    }
-}
-
-// The same for all orientations, also folding the drift against the reference halo
-// into [lo, hi] (bad: a finite value met a -inf one).
-template <int NT>
-__device__ __forceinline__ void load_halo_drift(double *lds, const double *__restrict__ in,
-                                                const double *__restrict__ ref, int x0, int y0, int R, int HW, int nx,
-                                                int ny, float &lo, float &hi, bool &bad) {
-    const int npix = HW * HW;
-    const int total = npix * NT;
-    const float inv = 1.0f / static_cast<float>(HW);
-#pragma unroll 8
-    for (int e = threadIdx.x; e < total; e += kConvThreads) {
-        const int p = e / NT;
-        const int kc = e - p * NT;
-        const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv);
-        const int hx = p - hy * HW;
-        const int gy = y0 - R + hy, gx = x0 - R + hx;
-        const bool inside = gy >= 0 && gy < ny && gx >= 0 && gx < nx;
-        const int cy = min(max(gy, 0), ny - 1), cx = min(max(gx, 0), nx - 1);
-        const double v = in[(static_cast<size_t>(cy) * nx + cx) * NT + kc];
-        const int li = kc * npix + p;
-        const double b = ref[li];
-        const double a = inside ? v : -INFINITY;
-        lds[li] = a;
-        const bool both = (a == -INFINITY) && (b == -INFINITY);
-        const double de = both ? 0.0 : a - b;  // +-inf or NaN when only one side is -inf
-        bad = bad || !(fabs(de) < 1e30);
-        const float df = static_cast<float>(de);
-        lo = both ? lo : fminf(lo, df);
-        hi = both ? hi : fmaxf(hi, df);
+    for (int e0 = 0; e0 < total; e0 += kHaloBatch * kConvThreads) {
+        double v[kHaloBatch];
+        bool ok[kHaloBatch];
+#pragma unroll
+        for (int u = 0; u < kHaloBatch; ++u) {
+            const int e = min(e0 + u * kConvThreads + static_cast<int>(threadIdx.x), total - 1);
+            const int p = e / KC;
+            const int kc = e - p * KC;
+            const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv);
+            const int hx = p - hy * HW;
+            const int gy = y0 - R + hy, gx = x0 - R + hx;
+            ok[u] = gy >= 0 && gy < ny && gx >= 0 && gx < nx;
+            const int cy = min(max(gy, 0), ny - 1), cx = min(max(gx, 0), nx - 1);
+            v[u] = in[(static_cast<size_t>(cy) * nx + cx) * nt + k0 + kc];
+        }
+#pragma unroll
+        for (int u = 0; u < kHaloBatch; ++u) {
+            const int e = e0 + u * kConvThreads + static_cast<int>(threadIdx.x);
+            if (e < total) {
+                const int p = e / KC;
+                const int kc = e - p * KC;
+                lds[kc * npix + p] = ok[u] ? v[u] : -INFINITY;
+            }
+        }
     }
 }
 
@@ -133,14 +124,14 @@ __device__ __forceinline__ double epilogue(const ConvJob &job, size_t idx, doubl
     if (job.epi == EPI_RAW) {
         o = lse;
     } else if (job.epi == EPI_SCALE) {
-        const double lm = job.aux[idx];
+        const double lm = ((gdptr)job.aux)[idx];
         o = (lm == -INFINITY) ? -INFINITY : lm - lse;
-        if (job.old != nullptr && lm != -INFINITY) err = exp2(lm) * fabs(expm1((job.old[idx] - o) * kLn2));
+        if (job.old != nullptr && lm != -INFINITY) err = exp2(lm) * fabs(expm1((((gdptr)job.old)[idx] - o) * kLn2));
     } else {
-        const double bse = job.aux[idx];
+        const double bse = ((gdptr)job.aux)[idx];
         o = (bse == -INFINITY || lse == -INFINITY) ? -INFINITY : bse + lse;
     }
-    job.out[idx] = o;
+    ((gdptr_w)job.out)[idx] = o;
     return err;
 }
 
@@ -273,100 +264,151 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_lse(const ConvJob *__rest
     }
 }
 
+// Workgroup i is dispatched to XCD i % 8; logical blocks are handed out so that each
+// XCD gets a contiguous range (neighbouring tiles of a solve share that XCD's L2).
+// Returns -1 for the padding blocks of a grid of 8 * ceil(nblocks / 8).
+__device__ __forceinline__ int xcd_block(int nblocks) {
+    const int per = (nblocks + 7) >> 3;
+    const int i = static_cast<int>(blockIdx.x);
+    const int lb = (i & 7) * per + (i >> 3);
+    return lb < nblocks ? lb : -1;
+}
+
+__host__ __forceinline__ int xcd_grid(int nblocks) { return ((nblocks + 7) >> 3) << 3; }
+
+// Scaling epilogue with the per-output operands already loaded (aux, old).
+__device__ __forceinline__ double epilogue_pre(const ConvJob &job, size_t idx, double lse, double lm, double od) {
+    double o, err = 0.0;
+    if (job.epi == EPI_RAW) {
+        o = lse;
+    } else if (job.epi == EPI_SCALE) {
+        o = (lm == -INFINITY) ? -INFINITY : lm - lse;
+        if (job.old != nullptr && lm != -INFINITY) err = exp2(lm) * fabs(expm1((od - o) * kLn2));
+    } else {
+        o = (lm == -INFINITY || lse == -INFINITY) ? -INFINITY : lm + lse;
+    }
+    ((gdptr_w)job.out)[idx] = o;
+    return err;
+}
+
 // Certified sparse evaluation of pruned jobs: one workgroup per 8 x 8 tile with
-// min(nt, 16) waves sharing the halo and the staged lists (wave w owns ko = w, w+NW,
-// ...); lane = pixel.  A tile whose certificate fails is appended to the rebuild list
-// and left to k_rebuild.
+// NW = min(nt, 16) waves (wave w owns ko = w, w+NW, ...; lane = pixel).  Every global
+// load of the tile's lanes (list lengths, per-output operands, the input halo and its
+// reference) is issued before the certificate is decided.  A tile whose certificate
+// fails is appended to the rebuild list and left to k_rebuild.
 template <int NT>
 __global__ __launch_bounds__(64 * (NT < 16 ? NT : 16)) void k_sparse(const ConvJob *__restrict__ jobs,
                                                                      const int32_t *__restrict__ block_job,
-                                                                     int2 *__restrict__ rebuild,
+                                                                     int nblocks, int2 *__restrict__ rebuild,
                                                                      int *__restrict__ rebuild_count) {
     constexpr int NW = NT < 16 ? NT : 16;  // waves
     constexpr int NTH = 64 * NW;
     constexpr int NJ = NT / NW;             // orientations per wave
+    static_assert(kListMax >= 16 && kListMax % 8 == 0, "list regions hold whole groups of 8");
+    typedef const __attribute__((address_space(4))) int32_t *ciptr;
     extern __shared__ double lds[];
     __shared__ float s_lo[NW], s_hi[NW];
+    __shared__ int s_bad[NW];
     __shared__ double s_err[NW], s_work[NW];
-    __shared__ int s_flag;
-    __shared__ int s_list_off[NT + 1];
-    const int j = block_job[blockIdx.x];
+    const int lb = xcd_block(nblocks);
+    if (lb < 0) return;
+    const int j = block_job[lb];
     const ConvJob job = jobs[j];
-    const int tile = static_cast<int>(blockIdx.x) - job.first_block;
+    const int tile = lb - job.first_block;
     const int ty = tile / job.tiles_x;
     const int tx = tile - ty * job.tiles_x;
     const int x0 = tx * kTile, y0 = ty * kTile;
-    const int R = job.R, W = 2 * R + 1, HW = kTile + 2 * R, npix = HW * HW;
+    const int R = job.R, HW = kTile + 2 * R, npix = HW * HW;
     const int nx = job.nx, ny = job.ny;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
     const int px = lane & 7, py = lane >> 3;
     const int gx = x0 + px, gy = y0 + py;
     const bool valid = gx < nx && gy < ny;
-    const size_t obase = (static_cast<size_t>(gy) * nx + gx) * NT;
+    const size_t obase = (static_cast<size_t>(min(gy, ny - 1)) * nx + min(gx, nx - 1)) * NT;
 
-    // ---------------- certificate ----------------
+    // ---------------- prefetch ----------------
+    int n[NJ];
+    float mr[NJ];
+    double ax[NJ], od[NJ];
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) {
+        const int ko = wave + NW * q;
+        n[q] = ((ciptr)(job.len))[static_cast<size_t>(tile) * NT + ko];
+        mr[q] = ((gfptr)job.mref)[obase + ko];
+        ax[q] = (job.epi != EPI_RAW) ? ((gdptr)job.aux)[obase + ko] : 0.0;
+        od[q] = (job.old != nullptr) ? ((gdptr)job.old)[obase + ko] : 0.0;
+    }
+
+    // ---------------- halo and certificate ----------------
     // drift delta = in - ref over the halo; only its spread matters: a common shift of the
     // inputs moves every exponent and the maximum alike
-    const double *ref = job.ref + static_cast<size_t>(tile) * NT * npix;
+    const gfptr ref = (gfptr)(job.ref + static_cast<size_t>(tile) * NT * npix);
+    const gdptr in = (gdptr)job.in;
     float dlo = INFINITY, dhi = -INFINITY;
     bool bad = false;
     {
         const float inv = 1.0f / static_cast<float>(HW);
-#pragma unroll 4
-        for (int e = threadIdx.x; e < npix * NT; e += NTH) {
-            const int p = e / NT;
-            const int kc = e - p * NT;
-            const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv);
-            const int hx = p - hy * HW;
-            const int qy = y0 - R + hy, qx = x0 - R + hx;
-            const bool inside = qy >= 0 && qy < ny && qx >= 0 && qx < nx;
-            const int cy = min(max(qy, 0), ny - 1), cx = min(max(qx, 0), nx - 1);
-            const double v = job.in[(static_cast<size_t>(cy) * nx + cx) * NT + kc];
-            const int li = kc * npix + p;
-            const double b = ref[li];
-            const double a = inside ? v : -INFINITY;
-            lds[li] = a;
-            const bool both = (a == -INFINITY) && (b == -INFINITY);
-            const double de = both ? 0.0 : a - b;  // +-inf or NaN when only one side is -inf
-            bad = bad || !(fabs(de) < 1e30);
-            const float df = static_cast<float>(de);
-            dlo = both ? dlo : fminf(dlo, df);
-            dhi = both ? dhi : fmaxf(dhi, df);
+        const int total = npix * NT;
+        for (int e0 = 0; e0 < total; e0 += kHaloBatch * NTH) {
+            double va[kHaloBatch];
+            float vb[kHaloBatch];
+            bool ok[kHaloBatch];
+#pragma unroll
+            for (int u = 0; u < kHaloBatch; ++u) {
+                const int e = min(e0 + u * NTH + static_cast<int>(threadIdx.x), total - 1);
+                const int p = e / NT;
+                const int kc = e - p * NT;
+                const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv);
+                const int hx = p - hy * HW;
+                const int qy = y0 - R + hy, qx = x0 - R + hx;
+                ok[u] = qy >= 0 && qy < ny && qx >= 0 && qx < nx;
+                const int cy = min(max(qy, 0), ny - 1), cx = min(max(qx, 0), nx - 1);
+                va[u] = in[(static_cast<size_t>(cy) * nx + cx) * NT + kc];
+                vb[u] = ref[kc * npix + p];
+            }
+#pragma unroll
+            for (int u = 0; u < kHaloBatch; ++u) {
+                const int e = e0 + u * NTH + static_cast<int>(threadIdx.x);
+                if (e < total) {
+                    const int p = e / NT;
+                    const int kc = e - p * NT;
+                    const float b = vb[u];
+                    const double a = ok[u] ? va[u] : -INFINITY;
+                    lds[kc * npix + p] = a;
+                    const bool both = (a == -INFINITY) && (b == -INFINITY);
+                    const double de = both ? 0.0 : a - static_cast<double>(b);  // +-inf or NaN when one side is -inf
+                    bad = bad || !(fabs(de) < 1e30) || !(fabsf(b) < kRefMax || b == -INFINITY);
+                    const float df = static_cast<float>(de);
+                    dlo = both ? dlo : fminf(dlo, df);
+                    dhi = both ? dhi : fmaxf(dhi, df);
+                }
+            }
         }
     }
-    if (threadIdx.x == 0) {
-        // list offsets of the tile's orientations; a missing/overflowed list or a total
-        // beyond the LDS staging capacity needs a rebuild
-        int acc = 0, ok = 1;
-        for (int k = 0; k < NT; ++k) {
-            const int n = job.len[static_cast<size_t>(tile) * NT + k];
-            s_list_off[k] = acc;
-            if (n < 0) ok = 0;
-            else acc += n;
-        }
-        s_list_off[NT] = acc;
-        s_flag = (ok && acc <= kListLds) ? 1 : 0;
-    }
-    __syncthreads();
-    if (bad) s_flag = 0;
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) bad = bad || n[q] < 0;  // no list (never built or overflowed)
     dlo = -wave_max(-dlo);
     dhi = wave_max(dhi);
+    const bool wbad = __ballot(bad) != 0ull;
     if (lane == 0) {
         s_lo[wave] = dlo;
         s_hi[wave] = dhi;
+        s_bad[wave] = wbad ? 1 : 0;
     }
     __syncthreads();
     float lo = s_lo[0], hi = s_hi[0];
+    int anybad = s_bad[0];
 #pragma unroll
     for (int w = 1; w < NW; ++w) {
         lo = fminf(lo, s_lo[w]);
         hi = fmaxf(hi, s_hi[w]);
+        anybad |= s_bad[w];
     }
     // all entries -inf on both sides: no spread at all
     const float spread = (hi >= lo) ? hi - lo : 0.0f;
     const float shift = (hi >= lo) ? 0.5f * (hi + lo) : 0.0f;
-    if (!(s_flag != 0 && spread <= kDriftSpread)) {
+    if (anybad != 0 || !(spread + kRefMargin <= kDriftSpread)) {
         // left to the rebuild kernel (block-uniform exit, nothing written here)
         if (threadIdx.x == 0) {
             const int slot = atomicAdd(rebuild_count, 1);
@@ -376,58 +418,57 @@ __global__ __launch_bounds__(64 * (NT < 16 ? NT : 16)) void k_sparse(const ConvJ
     }
 
     // ---------------- certified sparse evaluation ----------------
-    // Each wave stages the packed list entries of its own orientations (kernel value with
-    // the LDS offset in its low mantissa bits) and reads them back as wave-wide
-    // broadcasts, 8 per step; LDS operations of one wave complete in order, so no
-    // barrier is needed between its copy and its reads.
-    double *lst_lds = lds + static_cast<size_t>(NT) * npix;
-#pragma unroll
-    for (int q = 0; q < NJ; ++q) {
-        const int ko = wave + NW * q;
-        const int e0 = s_list_off[ko], n = s_list_off[ko + 1] - e0;
-        const ListEntry *src = job.lists + (static_cast<size_t>(tile) * NT + ko) * job.lmax;
-        for (int e = lane; e < n; e += 64) lst_lds[e0 + e] = src[e];
-    }
-    __builtin_amdgcn_wave_barrier();
+    // List entries are wave-uniform: they come through the scalar cache into SGPRs (8
+    // per step, the next 8 requested before the current ones are used) and are unpacked
+    // on the scalar unit, so LDS bandwidth goes to the per-lane halo gathers only.
     const int base = py * HW + px;
+    constexpr uint32_t kMask = (1u << kOffBits) - 1u;
     double err = 0.0, work = 0.0;
 #pragma unroll
     for (int q = 0; q < NJ; ++q) {
         const int ko = wave + NW * q;
-        const int e0 = s_list_off[ko], n = s_list_off[ko + 1] - e0;
-        const float mr = valid ? job.mref[obase + ko] : -INFINITY;
         // the reference maximum moved with the inputs by shift +- spread/2
-        const double M = (mr == -INFINITY) ? 0.0 : static_cast<double>(mr) + static_cast<double>(shift);
-        const double *Lp = lst_lds + e0;
+        const double M = (mr[q] == -INFINITY) ? 0.0 : static_cast<double>(mr[q]) + static_cast<double>(shift);
+        const cdptr Lp = (cdptr)(job.lists + (static_cast<size_t>(tile) * NT + ko) * job.lmax);
+        const int nq = n[q];
+        const int n8 = nq & ~7;
         double S = 0.0;
-        int e = 0;
-        for (; e + 8 <= n; e += 8) {
-            double v[8], lv[8];
+        double pk[8];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const double pk = Lp[e + t];
-                const unsigned int lo32 = static_cast<unsigned int>(__double2loint(pk));
-                lv[t] = __hiloint2double(__double2hiint(pk), static_cast<int>(lo32 & ~((1u << kOffBits) - 1u)));
-                v[t] = lds[(lo32 & ((1u << kOffBits) - 1u)) + base];
-            }
+        for (int u = 0; u < 8; ++u) pk[u] = Lp[u];  // in bounds: lmax >= 8
+        for (int e = 0; e < n8; e += 8) {
+            double nx8[8];
+            const int en = min(e + 8, job.lmax - 8);  // past the list: loaded, never used
+#pragma unroll
+            for (int u = 0; u < 8; ++u) nx8[u] = Lp[en + u];
             float s8 = 0.0f;
 #pragma unroll
-            for (int t = 0; t < 8; ++t) s8 += __builtin_amdgcn_exp2f(static_cast<float>((lv[t] + v[t]) - M));
+            for (int u = 0; u < 8; ++u) {
+                const unsigned int lo32 = static_cast<unsigned int>(__double2loint(pk[u]));
+                const double lv = __hiloint2double(__double2hiint(pk[u]), static_cast<int>(lo32 & ~kMask));
+                const double v = lds[static_cast<int>(lo32 & kMask) + base];
+                s8 += __builtin_amdgcn_exp2f(static_cast<float>((lv + v) - M));
+            }
             S += static_cast<double>(s8);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) pk[u] = nx8[u];
         }
+        // the last nq - n8 < 8 entries sit in pk
         float st = 0.0f;
-        for (; e < n; ++e) {
-            const double pk = Lp[e];
-            const unsigned int lo32 = static_cast<unsigned int>(__double2loint(pk));
-            const double lv =
-                __hiloint2double(__double2hiint(pk), static_cast<int>(lo32 & ~((1u << kOffBits) - 1u)));
-            st += __builtin_amdgcn_exp2f(static_cast<float>((lv + lds[(lo32 & ((1u << kOffBits) - 1u)) + base]) - M));
+#pragma unroll
+        for (int u = 0; u < 7; ++u) {
+            if (n8 + u < nq) {
+                const unsigned int lo32 = static_cast<unsigned int>(__double2loint(pk[u]));
+                const double lv = __hiloint2double(__double2hiint(pk[u]), static_cast<int>(lo32 & ~kMask));
+                const double v = lds[static_cast<int>(lo32 & kMask) + base];
+                st += __builtin_amdgcn_exp2f(static_cast<float>((lv + v) - M));
+            }
         }
         S += static_cast<double>(st);
-        const double lse = (mr == -INFINITY || !(S > 0.0)) ? -INFINITY : M + log2(S);
+        const double lse = (mr[q] == -INFINITY || !(S > 0.0)) ? -INFINITY : M + log2(S);
         if (valid) {
-            err += epilogue(job, obase + ko, lse);
-            work += static_cast<double>(n);
+            err += epilogue_pre(job, obase + ko, lse, ax[q], od[q]);
+            work += static_cast<double>(nq);
         }
     }
     // error partial of the tile (slot 0 of [tile][nt]) and the work counter, in wave order
@@ -520,7 +561,7 @@ __global__ __launch_bounds__(kConvThreads) void k_rebuild(const ConvJob *__restr
                 for (int kc = 0; kc < NT; ++kc) {
                     const double u = (lds[kc * npix + hb] + Lr[kc]) - M;
                     srow += __builtin_amdgcn_exp2f(static_cast<float>(u));
-                    m |= (__ballot(valid && u >= -kListCut) != 0ull ? 1u : 0u) << kc;
+                    m |= (__ballot(valid && u >= -(kListCut + 1.0)) != 0ull ? 1u : 0u) << kc;
                 }
                 if (lane == 0) masks[(dy + R) * W + (dx + R)] = m;
             }
@@ -547,7 +588,7 @@ __global__ __launch_bounds__(kConvThreads) void k_rebuild(const ConvJob *__restr
                 job.len[static_cast<size_t>(tile) * NT + ko] = (cnt <= job.lmax) ? cnt : -1;
                 s_cnt = cnt;
             }
-            if (valid) job.mref[idx] = mx;
+            if (valid) ((gfptr_w)job.mref)[idx] = mx;
             // epilogue of the 64 outputs (pixel, ko) and this item's error partial
             const double err = valid ? epilogue(job, idx, lse) : 0.0;
             const double es = wave_sum(err);
@@ -568,10 +609,10 @@ __global__ __launch_bounds__(kConvThreads) void k_rebuild(const ConvJob *__restr
         {
             // packed entries of (tile, ko), written by all threads
             const int n = s_cnt <= job.lmax ? s_cnt : 0;
-            ListEntry *dst = job.lists + (static_cast<size_t>(tile) * NT + ko) * job.lmax;
+            const gdptr_w dst = (gdptr_w)(job.lists + (static_cast<size_t>(tile) * NT + ko) * job.lmax);
             for (int e = threadIdx.x; e < n; e += kConvThreads) {
                 const uint32_t term = terms[e];
-                const double Lv = job.L64[((term / NT) * NT + ko) * NT + term % NT];
+                const double Lv = ((gdptr)job.L64)[((term / NT) * NT + ko) * NT + term % NT];
                 const uint32_t off = static_cast<uint32_t>(term_offset(term, NT, R, W, HW, npix));
                 const unsigned long long b =
                     (static_cast<unsigned long long>(__double_as_longlong(Lv)) & ~((1ull << kOffBits) - 1ull)) | off;
@@ -579,8 +620,8 @@ __global__ __launch_bounds__(kConvThreads) void k_rebuild(const ConvJob *__restr
             }
         }
         if (ko == 0) {
-            double *ref = job.ref + static_cast<size_t>(tile) * NT * npix;
-            for (int e = threadIdx.x; e < NT * npix; e += kConvThreads) ref[e] = lds[e];
+            const gfptr_w ref = (gfptr_w)(job.ref + static_cast<size_t>(tile) * NT * npix);
+            for (int e = threadIdx.x; e < NT * npix; e += kConvThreads) ref[e] = static_cast<float>(lds[e]);
             if (job.dense_flag != nullptr && threadIdx.x == 0) job.dense_flag[tile] += 1;
         }
     }
@@ -605,14 +646,14 @@ int launch_sparse_t(const ConvJob *d_jobs, int nblocks, const int32_t *d_block_j
                     int *rebuild_count, hipStream_t s) {
     constexpr int NW = NT < 16 ? NT : 16;
     const int HW = kTile + 2 * R_max, W = 2 * R_max + 1;
-    const size_t lds = static_cast<size_t>(HW) * HW * NT * sizeof(double) + kListLds * sizeof(double);
+    const size_t lds = static_cast<size_t>(HW) * HW * NT * sizeof(double);
     if (lds > 65536)
         SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sparse<NT>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
     int rc = launch_fill_i32(rebuild_count, 1, 0, s);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_sparse<NT>, dim3(nblocks), dim3(64 * NW), lds, s, d_jobs, d_block_job, rebuild,
-                       rebuild_count);
+    hipLaunchKernelGGL(k_sparse<NT>, dim3(xcd_grid(nblocks)), dim3(64 * NW), lds, s, d_jobs, d_block_job, nblocks,
+                       rebuild, rebuild_count);
     SE2_HIP(hipGetLastError());
     const size_t lr = static_cast<size_t>(HW) * HW * NT * sizeof(double) +
                       (static_cast<size_t>(W) * W + kListMax) * sizeof(uint32_t);

@@ -22,15 +22,24 @@ constexpr int kTile = 8;          // output tile of the log-domain kernels: 8 x 
 constexpr int kConvThreads = 256; // 4 waves of 64
 constexpr int kMaxRadius = 12;
 
-// Certified pruning of the log-domain convolution (base-2 units): entries within
-// kListCut of an output's maximum are listed; a list stays in use while the drift
-// of the input from the halo it was built on spreads over at most kDriftSpread, so
-// every skipped entry is below 2^-(kListCut - kDriftSpread) = 2^-48 of the
-// result's largest term.
-constexpr double kListCut = 80.0;
-constexpr float kDriftSpread = 32.0f;
+// Certified pruning of the log-domain convolution (base-2 units): the entries within
+// kListCut of an output's maximum are listed (the criterion has one unit of slack
+// for the FP32 rounding of the maximum it is measured from); a list stays in use
+// while the drift of the input from the halo it was built on spreads over at most
+// kDriftSpread (that halo is kept in FP32: |value| < kRefMax, rounding error below
+// kRefMargin / 2, added to the measured spread), so every skipped entry is below
+// 2^-(kListCut - kDriftSpread) = 2^-48 of the result's largest term.
+#ifndef SE2_LIST_CUT
+#define SE2_LIST_CUT 80
+#endif
+#ifndef SE2_DRIFT_SPREAD
+#define SE2_DRIFT_SPREAD 32
+#endif
+constexpr double kListCut = SE2_LIST_CUT;
+constexpr float kDriftSpread = SE2_DRIFT_SPREAD;
+constexpr float kRefMax = 1048576.0f;  // 2^20: FP32 rounding error < 2^-4
+constexpr float kRefMargin = 0.125f;
 constexpr int kListMax = 512;               // entries per (tile, ko); longer lists fall back to dense
-constexpr int kListLds = 4096;              // entries per tile staged in LDS; more fall back to dense
 constexpr size_t kSparseLdsMax = 98304;     // the sparse path keeps the full FP64 halo in LDS
 
 // A list entry is the FP64 log2 kernel value of a window term with its low kOffBits
@@ -70,7 +79,7 @@ struct ConvJob {
     const float *L32;   // the same in FP32 (max pass only)
     // certified pruning state of this (solve, direction); lists == nullptr: dense only
     ListEntry *lists;   // [tiles][nt][lmax] packed entries
-    double *ref;        // [tiles][nt * npix] input halo the lists were built on
+    float *ref;         // [tiles][nt * npix] input halo the lists were built on (FP32)
     int32_t *len;       // [tiles][nt], -1 = none
     float *mref;        // [E] per-output maximum exponent at build time
     int32_t *dense_flag; // [tiles] dense visits (diagnostics), may be null
@@ -82,7 +91,7 @@ struct ConvJob {
 // Pruning state of one convolution direction of one solve.
 struct ListSet {
     ListEntry *lists = nullptr;
-    double *ref = nullptr;
+    float *ref = nullptr;
     int32_t *len = nullptr;
     float *mref = nullptr;
     int32_t *dense_flag = nullptr;

@@ -51,7 +51,7 @@ ListSet carve_lists(Carver &c, const Kernel &k, size_t E, int tiles, bool prune)
     ListSet l;
     if (prune) {
         l.lists = c.take<ListEntry>(static_cast<size_t>(tiles) * nt * kListMax);
-        l.ref = c.take<double>(static_cast<size_t>(tiles) * nt * HW * HW);
+        l.ref = c.take<float>(static_cast<size_t>(tiles) * nt * HW * HW);
         l.len = c.take<int32_t>(static_cast<size_t>(tiles) * nt);
         l.mref = c.take<float>(E);
     }
