@@ -57,41 +57,49 @@ typedef const __attribute__((address_space(1))) int32_t *giptr;
 typedef __attribute__((address_space(1))) double *gdptr_w;
 typedef __attribute__((address_space(1))) float *gfptr_w;
 
-constexpr int kHaloBatch = 4;  // halo elements each thread loads before storing any
+constexpr int kHaloBatch = 4;        // halo items each thread loads before storing any
+constexpr int kHaloBatchSparse = 2;  // the same in the sparse kernel (fewer registers)
 
 // Stage the input halo (8+2R)^2 x KC orientations (from k0) in LDS as [kc][hy][hx],
-// -inf outside the grid.  Each thread issues kHaloBatch loads (clamped addresses, no
-// branches) before it stores any of them; hy = p / HW via a float reciprocal (exact
-// for p < 2^20: the +0.5 keeps the rounding error far below the gap to an integer).
+// -inf outside the grid.  A thread takes 4 consecutive orientations of one halo pixel
+// per item (two 16-byte loads), and issues the loads of kHaloBatch items (clamped
+// addresses, no branches) before it stores any; hy = p / HW via a float reciprocal
+// (exact for p < 2^20: the +0.5 keeps the rounding error far below the gap to an
+// integer).
 template <int KC>
 __device__ __forceinline__ void load_halo(double *lds, const double *in_, int nt, int k0, int x0, int y0, int R,
                                           int HW, int nx, int ny) {
+    static_assert(KC % 4 == 0, "orientations are staged in quads");
+    constexpr int QK = KC / 4;
     const gdptr in = (gdptr)in_;
     const int npix = HW * HW;
-    const int total = npix * KC;
+    const int total = npix * QK;
     const float inv = 1.0f / static_cast<float>(HW);
     for (int e0 = 0; e0 < total; e0 += kHaloBatch * kConvThreads) {
-        double v[kHaloBatch];
+        double v[kHaloBatch][4];
         bool ok[kHaloBatch];
 #pragma unroll
         for (int u = 0; u < kHaloBatch; ++u) {
             const int e = min(e0 + u * kConvThreads + static_cast<int>(threadIdx.x), total - 1);
-            const int p = e / KC;
-            const int kc = e - p * KC;
+            const int p = e / QK;
+            const int kq = e - p * QK;
             const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv);
             const int hx = p - hy * HW;
             const int gy = y0 - R + hy, gx = x0 - R + hx;
             ok[u] = gy >= 0 && gy < ny && gx >= 0 && gx < nx;
             const int cy = min(max(gy, 0), ny - 1), cx = min(max(gx, 0), nx - 1);
-            v[u] = in[(static_cast<size_t>(cy) * nx + cx) * nt + k0 + kc];
+            const gdptr src = in + (static_cast<size_t>(cy * nx + cx)) * nt + k0 + 4 * kq;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[u][c] = src[c];
         }
 #pragma unroll
         for (int u = 0; u < kHaloBatch; ++u) {
             const int e = e0 + u * kConvThreads + static_cast<int>(threadIdx.x);
             if (e < total) {
-                const int p = e / KC;
-                const int kc = e - p * KC;
-                lds[kc * npix + p] = ok[u] ? v[u] : -INFINITY;
+                const int p = e / QK;
+                const int kq = e - p * QK;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) lds[(4 * kq + c) * npix + p] = ok[u] ? v[u][c] : -INFINITY;
             }
         }
     }
@@ -343,45 +351,54 @@ __global__ __launch_bounds__(64 * (NT < 16 ? NT : 16)) void k_sparse(const ConvJ
     // ---------------- halo and certificate ----------------
     // drift delta = in - ref over the halo; only its spread matters: a common shift of the
     // inputs moves every exponent and the maximum alike
+    // reference halo, pixel-major [p][kc] in FP32
     const gfptr ref = (gfptr)(job.ref + static_cast<size_t>(tile) * NT * npix);
     const gdptr in = (gdptr)job.in;
     float dlo = INFINITY, dhi = -INFINITY;
     bool bad = false;
     {
+        constexpr int QK = NT / 4;
         const float inv = 1.0f / static_cast<float>(HW);
-        const int total = npix * NT;
-        for (int e0 = 0; e0 < total; e0 += kHaloBatch * NTH) {
-            double va[kHaloBatch];
-            float vb[kHaloBatch];
-            bool ok[kHaloBatch];
+        const int total = npix * QK;
+        for (int e0 = 0; e0 < total; e0 += kHaloBatchSparse * NTH) {
+            double va[kHaloBatchSparse][4];
+            float vb[kHaloBatchSparse][4];
+            bool ok[kHaloBatchSparse];
 #pragma unroll
-            for (int u = 0; u < kHaloBatch; ++u) {
+            for (int u = 0; u < kHaloBatchSparse; ++u) {
                 const int e = min(e0 + u * NTH + static_cast<int>(threadIdx.x), total - 1);
-                const int p = e / NT;
-                const int kc = e - p * NT;
+                const int p = e / QK;
+                const int kq = e - p * QK;
                 const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv);
                 const int hx = p - hy * HW;
                 const int qy = y0 - R + hy, qx = x0 - R + hx;
                 ok[u] = qy >= 0 && qy < ny && qx >= 0 && qx < nx;
                 const int cy = min(max(qy, 0), ny - 1), cx = min(max(qx, 0), nx - 1);
-                va[u] = in[(static_cast<size_t>(cy) * nx + cx) * NT + kc];
-                vb[u] = ref[kc * npix + p];
+                const gdptr src = in + static_cast<size_t>(cy * nx + cx) * NT + 4 * kq;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    va[u][c] = src[c];
+                    vb[u][c] = ref[4 * e + c];
+                }
             }
 #pragma unroll
-            for (int u = 0; u < kHaloBatch; ++u) {
+            for (int u = 0; u < kHaloBatchSparse; ++u) {
                 const int e = e0 + u * NTH + static_cast<int>(threadIdx.x);
                 if (e < total) {
-                    const int p = e / NT;
-                    const int kc = e - p * NT;
-                    const float b = vb[u];
-                    const double a = ok[u] ? va[u] : -INFINITY;
-                    lds[kc * npix + p] = a;
-                    const bool both = (a == -INFINITY) && (b == -INFINITY);
-                    const double de = both ? 0.0 : a - static_cast<double>(b);  // +-inf or NaN when one side is -inf
-                    bad = bad || !(fabs(de) < 1e30) || !(fabsf(b) < kRefMax || b == -INFINITY);
-                    const float df = static_cast<float>(de);
-                    dlo = both ? dlo : fminf(dlo, df);
-                    dhi = both ? dhi : fmaxf(dhi, df);
+                    const int p = e / QK;
+                    const int kq = e - p * QK;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const float b = vb[u][c];
+                        const double a = ok[u] ? va[u][c] : -INFINITY;
+                        lds[(4 * kq + c) * npix + p] = a;
+                        // both -inf: NaN, which the min/max below skip; one side -inf: +-inf,
+                        // which fails the certificate
+                        const float df = static_cast<float>(a - static_cast<double>(b));
+                        dlo = fminf(dlo, df);
+                        dhi = fmaxf(dhi, df);
+                        bad = bad || (fabsf(b) >= kRefMax && b != -INFINITY) || (a != a);
+                    }
                 }
             }
         }
@@ -405,7 +422,7 @@ __global__ __launch_bounds__(64 * (NT < 16 ? NT : 16)) void k_sparse(const ConvJ
         hi = fmaxf(hi, s_hi[w]);
         anybad |= s_bad[w];
     }
-    // all entries -inf on both sides: no spread at all
+    // all entries -inf on both sides: no spread at all (an infinite spread fails)
     const float spread = (hi >= lo) ? hi - lo : 0.0f;
     const float shift = (hi >= lo) ? 0.5f * (hi + lo) : 0.0f;
     if (anybad != 0 || !(spread + kRefMargin <= kDriftSpread)) {
@@ -620,8 +637,12 @@ __global__ __launch_bounds__(kConvThreads) void k_rebuild(const ConvJob *__restr
             }
         }
         if (ko == 0) {
+            // reference halo, pixel-major [p][kc]
             const gfptr_w ref = (gfptr_w)(job.ref + static_cast<size_t>(tile) * NT * npix);
-            for (int e = threadIdx.x; e < NT * npix; e += kConvThreads) ref[e] = static_cast<float>(lds[e]);
+            for (int e = threadIdx.x; e < NT * npix; e += kConvThreads) {
+                const int p = e / NT, kc = e - p * NT;
+                ref[e] = static_cast<float>(lds[kc * npix + p]);
+            }
             if (job.dense_flag != nullptr && threadIdx.x == 0) job.dense_flag[tile] += 1;
         }
     }

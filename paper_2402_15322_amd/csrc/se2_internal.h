@@ -79,7 +79,7 @@ struct ConvJob {
     const float *L32;   // the same in FP32 (max pass only)
     // certified pruning state of this (solve, direction); lists == nullptr: dense only
     ListEntry *lists;   // [tiles][nt][lmax] packed entries
-    float *ref;         // [tiles][nt * npix] input halo the lists were built on (FP32)
+    float *ref;         // [tiles][npix][nt] input halo the lists were built on (FP32, pixel-major)
     int32_t *len;       // [tiles][nt], -1 = none
     float *mref;        // [E] per-output maximum exponent at build time
     int32_t *dense_flag; // [tiles] dense visits (diagnostics), may be null
