@@ -66,7 +66,7 @@ constexpr int kHaloBatchSparse = 2;  // the same in the sparse kernel (fewer reg
 // addresses, no branches) before it stores any; hy = p / HW via a float reciprocal
 // (exact for p < 2^20: the +0.5 keeps the rounding error far below the gap to an
 // integer).
-template <int KC>
+template <int KC, int NTH = kConvThreads, int BATCH = kHaloBatch>
 __device__ __forceinline__ void load_halo(double *lds, const double *in_, int nt, int k0, int x0, int y0, int R,
                                           int HW, int nx, int ny) {
     static_assert(KC % 4 == 0, "orientations are staged in quads");
@@ -75,12 +75,12 @@ __device__ __forceinline__ void load_halo(double *lds, const double *in_, int nt
     const int npix = HW * HW;
     const int total = npix * QK;
     const float inv = 1.0f / static_cast<float>(HW);
-    for (int e0 = 0; e0 < total; e0 += kHaloBatch * kConvThreads) {
-        double v[kHaloBatch][4];
-        bool ok[kHaloBatch];
+    for (int e0 = 0; e0 < total; e0 += BATCH * NTH) {
+        double v[BATCH][4];
+        bool ok[BATCH];
 #pragma unroll
-        for (int u = 0; u < kHaloBatch; ++u) {
-            const int e = min(e0 + u * kConvThreads + static_cast<int>(threadIdx.x), total - 1);
+        for (int u = 0; u < BATCH; ++u) {
+            const int e = min(e0 + u * NTH + static_cast<int>(threadIdx.x), total - 1);
             const int p = e / QK;
             const int kq = e - p * QK;
             const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv);
@@ -93,8 +93,8 @@ __device__ __forceinline__ void load_halo(double *lds, const double *in_, int nt
             for (int c = 0; c < 4; ++c) v[u][c] = src[c];
         }
 #pragma unroll
-        for (int u = 0; u < kHaloBatch; ++u) {
-            const int e = e0 + u * kConvThreads + static_cast<int>(threadIdx.x);
+        for (int u = 0; u < BATCH; ++u) {
+            const int e = e0 + u * NTH + static_cast<int>(threadIdx.x);
             if (e < total) {
                 const int p = e / QK;
                 const int kq = e - p * QK;
@@ -509,19 +509,24 @@ __global__ __launch_bounds__(64 * (NT < 16 ? NT : 16)) void k_sparse(const ConvJ
         job.partial[static_cast<size_t>(tile) * NT + threadIdx.x] = 0.0;
 }
 
-// Dense rebuild of the tiles listed by k_sparse: one workgroup per (tile, ko); the
-// window rows dy = -R + w, -R + w + 4, ... belong to wave w, whose partial maxima and
-// sums are combined in LDS in wave order; lane = pixel of the tile.  Each wave also
-// records, per window offset of its rows, a ballot mask of the orientations ki whose
-// term is within kListCut of the maximum for some pixel; the masks are compacted
-// into the (tile, ko) list and the packed entries stored.
+// Dense rebuild of the tiles listed by k_sparse: one workgroup of kRbWaves waves per
+// (tile, ko) item, lane = pixel of the tile.  The window's (dy, dx) pairs are dealt
+// to the waves round-robin; partial maxima and sums are combined in LDS in wave
+// order.  Each wave records, per pair, a ballot mask of the orientations ki whose
+// term is within kListCut (+1) of the maximum for some pixel; a block-wide prefix
+// sum over the masks places every listed term, in (pair, ki) order, and the packed
+// entries are written.
+constexpr int kRbWaves = 8;
+constexpr int kRbThreads = 64 * kRbWaves;  // at least 6 waves per SIMD (80 VGPRs): 3 workgroups per CU
+
 template <int NT>
-__global__ __launch_bounds__(kConvThreads) void k_rebuild(const ConvJob *__restrict__ jobs,
-                                                          const int2 *__restrict__ rebuild,
-                                                          const int *__restrict__ rebuild_count) {
+__global__ __launch_bounds__(kRbThreads) void k_rebuild(const ConvJob *__restrict__ jobs,
+                                                        const int2 *__restrict__ rebuild,
+                                                        const int *__restrict__ rebuild_count) {
     extern __shared__ double lds[];
-    __shared__ float s_mx[kConvThreads / 64][64];
-    __shared__ double s_S[kConvThreads / 64][64];
+    __shared__ float s_mx[kRbWaves][64];
+    __shared__ double s_S[kRbWaves][64];
+    __shared__ int s_wsum[kRbWaves];
     __shared__ int s_cnt;
     static_assert(NT <= 32, "masks hold up to 32 input orientations");
     const int nitems = *rebuild_count * NT;
@@ -543,68 +548,88 @@ __global__ __launch_bounds__(kConvThreads) void k_rebuild(const ConvJob *__restr
         const size_t idx = (static_cast<size_t>(gy) * nx + gx) * NT + ko;
         const cdptr L64 = (cdptr)(job.L64);
         const cfptr L32 = (cfptr)(job.L32);
-        // LDS: halo, then W*W masks (one per window offset), then up to lmax term indices
+        // LDS: halo, then W*W masks (one per window pair), then up to lmax term indices
         uint32_t *masks = reinterpret_cast<uint32_t *>(lds + static_cast<size_t>(NT) * npix);
         uint32_t *terms = masks + W * W;
 
         __syncthreads();  // LDS of the previous item is free
-        load_halo<NT>(lds, job.in, NT, 0, x0, y0, R, HW, nx, ny);
+        load_halo<NT, kRbThreads, 2>(lds, job.in, NT, 0, x0, y0, R, HW, nx, ny);
         __syncthreads();
 
-        // pass 1: maximum over this wave's rows
+        // pass 1: maximum over this wave's pairs
         float mx = -INFINITY;
-        for (int dy = -R + wave; dy <= R; dy += 4) {
-            for (int dx = -R; dx <= R; ++dx) {
-                const int hb = (py + R - dy) * HW + (px + R - dx);
-                const cfptr Lr = L32 + (static_cast<size_t>((dy + R) * W + (dx + R)) * NT + ko) * NT;
-#pragma unroll
-                for (int kc = 0; kc < NT; ++kc) mx = fmaxf(mx, static_cast<float>(lds[kc * npix + hb]) + Lr[kc]);
-            }
+        for (int r = wave; r < W * W; r += kRbWaves) {
+            const int dyi = r / W, dxi = r - dyi * W;  // dy = dyi - R, dx = dxi - R
+            const int hb = (py + 2 * R - dyi) * HW + (px + 2 * R - dxi);
+            const cfptr Lr = L32 + (static_cast<size_t>(r) * NT + ko) * NT;
+#pragma unroll 8
+            for (int kc = 0; kc < NT; ++kc) mx = fmaxf(mx, static_cast<float>(lds[kc * npix + hb]) + Lr[kc]);
         }
         s_mx[wave][lane] = mx;
         __syncthreads();
-        mx = fmaxf(fmaxf(s_mx[0][lane], s_mx[1][lane]), fmaxf(s_mx[2][lane], s_mx[3][lane]));
+        mx = s_mx[0][lane];
+#pragma unroll
+        for (int w = 1; w < kRbWaves; ++w) mx = fmaxf(mx, s_mx[w][lane]);
         const double M = (mx == -INFINITY) ? 0.0 : static_cast<double>(mx);
 
-        // pass 2: sum and membership masks of this wave's rows
+        // pass 2: sum and membership masks of this wave's pairs
         double S = 0.0;
-        for (int dy = -R + wave; dy <= R; dy += 4) {
+        for (int r = wave; r < W * W; r += kRbWaves) {
+            const int dyi = r / W, dxi = r - dyi * W;
+            const int hb = (py + 2 * R - dyi) * HW + (px + 2 * R - dxi);
+            const cdptr Lr = L64 + (static_cast<size_t>(r) * NT + ko) * NT;
             float srow = 0.0f;
-            for (int dx = -R; dx <= R; ++dx) {
-                const int hb = (py + R - dy) * HW + (px + R - dx);
-                const cdptr Lr = L64 + (static_cast<size_t>((dy + R) * W + (dx + R)) * NT + ko) * NT;
-                uint32_t m = 0u;
-#pragma unroll
-                for (int kc = 0; kc < NT; ++kc) {
-                    const double u = (lds[kc * npix + hb] + Lr[kc]) - M;
-                    srow += __builtin_amdgcn_exp2f(static_cast<float>(u));
-                    m |= (__ballot(valid && u >= -(kListCut + 1.0)) != 0ull ? 1u : 0u) << kc;
-                }
-                if (lane == 0) masks[(dy + R) * W + (dx + R)] = m;
+            uint32_t m = 0u;
+#pragma unroll 4
+            for (int kc = 0; kc < NT; ++kc) {
+                const double u = (lds[kc * npix + hb] + Lr[kc]) - M;
+                srow += __builtin_amdgcn_exp2f(static_cast<float>(u));
+                m |= (__ballot(valid && u >= -(kListCut + 1.0)) != 0ull ? 1u : 0u) << kc;
             }
+            if (lane == 0) masks[r] = m;
             S += static_cast<double>(srow);
         }
         s_S[wave][lane] = S;
         __syncthreads();
-        S = ((s_S[0][lane] + s_S[1][lane]) + s_S[2][lane]) + s_S[3][lane];
+        S = s_S[0][lane];
+#pragma unroll
+        for (int w = 1; w < kRbWaves; ++w) S += s_S[w][lane];
         const double lse = (S > 0.0) ? M + log2(S) : -INFINITY;
 
+        // compaction: exclusive prefix sum of the mask popcounts over the pairs, in
+        // rounds of kRbThreads pairs
+        int base = 0;
+        for (int r0 = 0; r0 < W * W; r0 += kRbThreads) {
+            const int r = r0 + static_cast<int>(threadIdx.x);
+            const uint32_t m = (r < W * W) ? masks[r] : 0u;
+            const int c = __builtin_popcount(m);
+            int incl = c;  // inclusive scan within the wave
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int t = __shfl_up(incl, off);
+                if (lane >= off) incl += t;
+            }
+            if (lane == 63) s_wsum[wave] = incl;
+            __syncthreads();
+            int wbase = base;
+            for (int w = 0; w < wave; ++w) wbase += s_wsum[w];
+            int total = base;
+            for (int w = 0; w < kRbWaves; ++w) total += s_wsum[w];
+            int pos = wbase + incl - c;
+            uint32_t mm = m;
+            while (mm != 0u) {
+                const int b = __builtin_ctz(mm);
+                mm &= mm - 1u;
+                if (pos < job.lmax) terms[pos] = static_cast<uint32_t>(r * NT + b);
+                ++pos;
+            }
+            base = total;
+            __syncthreads();  // s_wsum reused by the next round
+        }
+        const int cnt = base;
+        if (threadIdx.x == 0) ((int32_t *)job.len)[static_cast<size_t>(tile) * NT + ko] = (cnt <= job.lmax) ? cnt : -1;
+
         if (wave == 0) {
-            // compaction: term index ((dy+R)*W + dx+R)*NT + ki for every set bit, in order
-            int cnt = 0;
-            for (int r = 0; r < W * W; ++r) {
-                uint32_t m = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(masks[r])));
-                while (m != 0u) {
-                    const int b = __builtin_ctz(m);
-                    m &= m - 1u;
-                    if (cnt < job.lmax && lane == 0) terms[cnt] = static_cast<uint32_t>(r * NT + b);
-                    ++cnt;
-                }
-            }
-            if (lane == 0) {
-                job.len[static_cast<size_t>(tile) * NT + ko] = (cnt <= job.lmax) ? cnt : -1;
-                s_cnt = cnt;
-            }
             if (valid) ((gfptr_w)job.mref)[idx] = mx;
             // epilogue of the 64 outputs (pixel, ko) and this item's error partial
             const double err = valid ? epilogue(job, idx, lse) : 0.0;
@@ -622,12 +647,11 @@ __global__ __launch_bounds__(kConvThreads) void k_rebuild(const ConvJob *__restr
                 if (lane == 0) atomicAdd(&job.work[2 * tile], ws);
             }
         }
-        __syncthreads();
         {
             // packed entries of (tile, ko), written by all threads
-            const int n = s_cnt <= job.lmax ? s_cnt : 0;
+            const int n = cnt <= job.lmax ? cnt : 0;
             const gdptr_w dst = (gdptr_w)(job.lists + (static_cast<size_t>(tile) * NT + ko) * job.lmax);
-            for (int e = threadIdx.x; e < n; e += kConvThreads) {
+            for (int e = threadIdx.x; e < n; e += kRbThreads) {
                 const uint32_t term = terms[e];
                 const double Lv = ((gdptr)job.L64)[((term / NT) * NT + ko) * NT + term % NT];
                 const uint32_t off = static_cast<uint32_t>(term_offset(term, NT, R, W, HW, npix));
@@ -639,7 +663,7 @@ __global__ __launch_bounds__(kConvThreads) void k_rebuild(const ConvJob *__restr
         if (ko == 0) {
             // reference halo, pixel-major [p][kc]
             const gfptr_w ref = (gfptr_w)(job.ref + static_cast<size_t>(tile) * NT * npix);
-            for (int e = threadIdx.x; e < NT * npix; e += kConvThreads) {
+            for (int e = threadIdx.x; e < NT * npix; e += kRbThreads) {
                 const int p = e / NT, kc = e - p * NT;
                 ref[e] = static_cast<float>(lds[kc * npix + p]);
             }
@@ -682,7 +706,7 @@ int launch_sparse_t(const ConvJob *d_jobs, int nblocks, const int32_t *d_block_j
         SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rebuild<NT>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lr)));
     const int grid = nblocks * NT < kRebuildGrid ? nblocks * NT : kRebuildGrid;
-    hipLaunchKernelGGL(k_rebuild<NT>, dim3(grid), dim3(kConvThreads), lr, s, d_jobs, rebuild, rebuild_count);
+    hipLaunchKernelGGL(k_rebuild<NT>, dim3(grid), dim3(kRbThreads), lr, s, d_jobs, rebuild, rebuild_count);
     SE2_HIP(hipGetLastError());
     return SE2_OK;
 }
