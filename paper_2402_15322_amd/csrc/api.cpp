@@ -203,7 +203,7 @@ int se2_conv_log(se2_kernel_t h, se2_prec_t prec, const double *in, double *out,
         SE2_HIP(hipMemcpyAsync(dj, jobs.data(), batch * sizeof(ConvJob), hipMemcpyHostToDevice, st));
         SE2_HIP(hipMemcpyAsync(dm, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
         rc = launch_conv_lse(dj, batch, tiles * batch, dm, k->grid.ntheta, k->metric.radius, prec == SE2_F64, false,
-                             nullptr, nullptr, st);
+                             nullptr, nullptr, nullptr, st);
     }
     if (rc == SE2_OK) rc = launch_scale(out, out, E * batch, kLn2, st);
     // host vectors are read by the async copies: wait before they go out of scope
@@ -263,7 +263,13 @@ int se2_sinkhorn(se2_kernel_t h, const double *mu, const double *nu, const se2_o
             }
         }
     }
-    return solve_finish_ot(s, f_out, g_out, report, st);
+    std::vector<FinishReq> fin(1);
+    fin[0].s = &s;
+    fin[0].f_out = f_out;
+    fin[0].g_out = g_out;
+    if ((rc = finish_solves(eng, fin, st))) return rc;
+    if (report) *report = fin[0].rep;
+    return fin[0].rc;
 }
 
 int se2_barycenter(se2_kernel_t h, int32_t n, const double *const *mus, const double *lambdas,
@@ -326,7 +332,12 @@ int se2_barycenter(se2_kernel_t h, int32_t n, const double *const *mus, const do
             }
         }
     }
-    return solve_finish_bary(s, bary_out, report, st);
+    std::vector<FinishReq> fin(1);
+    fin[0].s = &s;
+    fin[0].bary_out = bary_out;
+    if ((rc = finish_solves(eng, fin, st))) return rc;
+    if (report) *report = fin[0].rep;
+    return fin[0].rc;
 }
 
 }  // extern "C"

@@ -139,7 +139,7 @@ __device__ __forceinline__ double epilogue(const ConvJob &job, size_t idx, doubl
         const double bse = ((gdptr)job.aux)[idx];
         o = (bse == -INFINITY || lse == -INFINITY) ? -INFINITY : bse + lse;
     }
-    ((gdptr_w)job.out)[idx] = o;
+    if (job.out != nullptr) ((gdptr_w)job.out)[idx] = o;  // checks keep only the error
     return err;
 }
 
@@ -308,7 +308,8 @@ template <int NT>
 __global__ __launch_bounds__(64 * (NT < 16 ? NT : 16)) void k_sparse(const ConvJob *__restrict__ jobs,
                                                                      const int32_t *__restrict__ block_job,
                                                                      int nblocks, int2 *__restrict__ rebuild,
-                                                                     int *__restrict__ rebuild_count) {
+                                                                     int *__restrict__ rebuild_count,
+                                                                     int *__restrict__ next_count) {
     constexpr int NW = NT < 16 ? NT : 16;  // waves
     constexpr int NTH = 64 * NW;
     constexpr int NJ = NT / NW;             // orientations per wave
@@ -318,6 +319,8 @@ __global__ __launch_bounds__(64 * (NT < 16 ? NT : 16)) void k_sparse(const ConvJ
     __shared__ float s_lo[NW], s_hi[NW];
     __shared__ int s_bad[NW];
     __shared__ double s_err[NW], s_work[NW];
+    // the counter of the following launch (idle now: the previous rebuild has finished)
+    if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
     const int lb = xcd_block(nblocks);
     if (lb < 0) return;
     const int j = block_job[lb];
@@ -688,17 +691,15 @@ int launch_dense_t(const ConvJob *d_jobs, int nblocks, const int32_t *d_block_jo
 
 template <int NT>
 int launch_sparse_t(const ConvJob *d_jobs, int nblocks, const int32_t *d_block_job, int R_max, int2 *rebuild,
-                    int *rebuild_count, hipStream_t s) {
+                    int *rebuild_count, int *next_count, hipStream_t s) {
     constexpr int NW = NT < 16 ? NT : 16;
     const int HW = kTile + 2 * R_max, W = 2 * R_max + 1;
     const size_t lds = static_cast<size_t>(HW) * HW * NT * sizeof(double);
     if (lds > 65536)
         SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sparse<NT>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-    int rc = launch_fill_i32(rebuild_count, 1, 0, s);
-    if (rc) return rc;
     hipLaunchKernelGGL(k_sparse<NT>, dim3(xcd_grid(nblocks)), dim3(64 * NW), lds, s, d_jobs, d_block_job, nblocks,
-                       rebuild, rebuild_count);
+                       rebuild, rebuild_count, next_count);
     SE2_HIP(hipGetLastError());
     const size_t lr = static_cast<size_t>(HW) * HW * NT * sizeof(double) +
                       (static_cast<size_t>(W) * W + kListMax) * sizeof(uint32_t);
@@ -719,18 +720,23 @@ bool conv_lse_sparse_fits(int nt, int R) {
 }
 
 int launch_conv_lse(const ConvJob *d_jobs, int njobs, int nblocks, const int32_t *d_block_job, int nt, int R_max,
-                    bool f64exp, bool sparse, int2 *rebuild, int *rebuild_count, hipStream_t s) {
+                    bool f64exp, bool sparse, int2 *rebuild, int *rebuild_count, int *next_count, hipStream_t s) {
     (void)njobs;
     if (nblocks <= 0) return SE2_OK;
     if (R_max < 0 || R_max > kMaxRadius) return SE2_EINVAL;
     const int HW = kTile + 2 * R_max;
     if (sparse) {
         // every job of a sparse launch carries lists (the engine groups them apart)
-        if (f64exp || !conv_lse_sparse_fits(nt, R_max) || !rebuild || !rebuild_count) return SE2_EINVAL;
+        if (f64exp || !conv_lse_sparse_fits(nt, R_max) || !rebuild || !rebuild_count || !next_count ||
+            rebuild_count == next_count)
+            return SE2_EINVAL;
         switch (nt) {
-            case 8: return launch_sparse_t<8>(d_jobs, nblocks, d_block_job, R_max, rebuild, rebuild_count, s);
-            case 16: return launch_sparse_t<16>(d_jobs, nblocks, d_block_job, R_max, rebuild, rebuild_count, s);
-            case 32: return launch_sparse_t<32>(d_jobs, nblocks, d_block_job, R_max, rebuild, rebuild_count, s);
+            case 8:
+                return launch_sparse_t<8>(d_jobs, nblocks, d_block_job, R_max, rebuild, rebuild_count, next_count, s);
+            case 16:
+                return launch_sparse_t<16>(d_jobs, nblocks, d_block_job, R_max, rebuild, rebuild_count, next_count, s);
+            case 32:
+                return launch_sparse_t<32>(d_jobs, nblocks, d_block_job, R_max, rebuild, rebuild_count, next_count, s);
             default: return SE2_EINVAL;
         }
     }

@@ -105,6 +105,16 @@ __global__ __launch_bounds__(kThreads) void k_sum_partials(const double *__restr
     if (threadIdx.x == 0) out[j] = s;
 }
 
+// One workgroup per item, the same fixed-order reduction as k_sum_partials.
+__global__ __launch_bounds__(kThreads) void k_sum_items(const SumItem *__restrict__ items, double *__restrict__ out) {
+    __shared__ double sh[kThreads];
+    const SumItem it = items[blockIdx.x];
+    double s = 0.0;
+    for (int p = it.begin + threadIdx.x; p < it.end; p += kThreads) s += it.part[p];
+    s = block_tree_sum(s, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
 struct CombineArgs {
     double *lv[16];
     const double *ld[16];
@@ -258,6 +268,13 @@ int launch_reduce_fixed(const double *partials, int count, int stride, double *o
 int launch_sum_partials(const double *partials, const int32_t *offsets, int njobs, double *out, hipStream_t s) {
     if (njobs <= 0) return SE2_OK;
     hipLaunchKernelGGL(k_sum_partials, dim3(njobs), dim3(kThreads), 0, s, partials, offsets, out);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+int launch_sum_items(const SumItem *d_items, int n, double *out, hipStream_t s) {
+    if (n <= 0) return SE2_OK;
+    hipLaunchKernelGGL(k_sum_items, dim3(n), dim3(kThreads), 0, s, d_items, out);
     SE2_HIP(hipGetLastError());
     return SE2_OK;
 }

@@ -181,21 +181,38 @@ int admit_one(se2_queue_s *Q, Req *q) {
     return rc;
 }
 
-void finish_one(se2_queue_s *Q, Req *q) {
-    if (q->rc == SE2_OK) {
-        if (q->r.kind == SE2_REQ_OT)
-            q->rc = solve_finish_ot(q->s, q->r.f_out, q->r.g_out, &q->rep, Q->st);
-        else
-            q->rc = solve_finish_bary(q->s, q->r.bary_out, &q->rep, Q->st);
+// Finishes a group of requests that left the iteration together: the GPU finishing
+// of the successful ones is batched, then every request is marked done.
+void finish_group(se2_queue_s *Q, const std::vector<Req *> &done) {
+    std::vector<FinishReq> fin;
+    std::vector<Req *> who;
+    for (Req *q : done) {
+        if (q->rc != SE2_OK) continue;
+        FinishReq f;
+        f.s = &q->s;
+        f.f_out = q->r.f_out;
+        f.g_out = q->r.g_out;
+        f.bary_out = q->r.bary_out;
+        fin.push_back(f);
+        who.push_back(q);
+    }
+    if (!fin.empty()) {
+        const int rc = finish_solves(Q->eng, fin, Q->st);
+        for (size_t i = 0; i < fin.size(); ++i) {
+            who[i]->rc = rc ? rc : fin[i].rc;
+            who[i]->rep = fin[i].rep;
+        }
     }
     (void)hipStreamSynchronize(Q->st);
     std::lock_guard<std::mutex> lk(Q->mu);
-    Q->arena.release(q->mem);
-    q->mem = nullptr;
-    q->t_done = now_seconds();
-    q->rep.seconds = q->t_done - q->t_submit;
-    q->state = DONE;
-    Q->completed += 1;
+    for (Req *q : done) {
+        Q->arena.release(q->mem);
+        q->mem = nullptr;
+        q->t_done = now_seconds();
+        q->rep.seconds = q->t_done - q->t_submit;
+        q->state = DONE;
+        Q->completed += 1;
+    }
 }
 
 void worker_main(se2_queue_s *Q) {
@@ -245,10 +262,18 @@ void worker_main(se2_queue_s *Q) {
             if (static_cast<int64_t>(Q->active.size()) > Q->peak) Q->peak = static_cast<int64_t>(Q->active.size());
         }
         // failed admissions finish immediately
-        std::vector<Req *> run;
+        std::vector<Req *> run, failed;
         for (Req *q : Q->active) {
-            if (q->rc != SE2_OK) finish_one(Q, q);
+            if (q->rc != SE2_OK) failed.push_back(q);
             else run.push_back(q);
+        }
+        if (!failed.empty()) {
+            finish_group(Q, failed);
+            std::lock_guard<std::mutex> lk(Q->mu);
+            Q->active.erase(std::remove_if(Q->active.begin(), Q->active.end(),
+                                           [](Req *q) { return q->state == DONE; }),
+                            Q->active.end());
+            Q->done_cv.notify_all();
         }
         if (run.empty()) {
             std::lock_guard<std::mutex> lk(Q->mu);
@@ -304,7 +329,7 @@ void worker_main(se2_queue_s *Q) {
             Q->prof_snapshot[2] = static_cast<double>(Q->eng.prof_launches);
             Q->prof_snapshot[3] = Q->eng.prof_outputs;
         }
-        for (Req *q : finished) finish_one(Q, q);
+        if (!finished.empty()) finish_group(Q, finished);
         if (!finished.empty()) {
             std::lock_guard<std::mutex> lk(Q->mu);
             Q->active.erase(std::remove_if(Q->active.begin(), Q->active.end(),

@@ -123,7 +123,7 @@ int build_tables(Kernel &k);
 // Error partials of EPI_SCALE jobs are laid out [tile][nt]; `rebuild` must hold one
 // int2 per block of the launch (sparse launches only).
 int launch_conv_lse(const ConvJob *d_jobs, int njobs, int nblocks, const int32_t *d_block_job, int nt, int R_max,
-                    bool f64exp, bool sparse, int2 *rebuild, int *rebuild_count, hipStream_t s);
+                    bool f64exp, bool sparse, int2 *rebuild, int *rebuild_count, int *next_count, hipStream_t s);
 bool conv_lse_sparse_fits(int nt, int R);
 
 // launchers (conv_linear.hip)
@@ -139,6 +139,12 @@ int launch_log2_measure(const double *m, double *logm, size_t n, hipStream_t s);
 int launch_validate(const double *m, size_t n, double *d_stats /* 3 doubles */, hipStream_t s);
 int launch_fill(double *p, size_t n, double v, hipStream_t s);
 int launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t s);
+// One FP64 sum of part[begin, end): the marginal-error partials of one job.
+struct SumItem {
+    const double *part;
+    int32_t begin, end;
+};
+int launch_sum_items(const SumItem *d_items, int n, double *out, hipStream_t s);
 int launch_sum_partials(const double *partials, const int32_t *offsets, int njobs, double *out, hipStream_t s);
 int launch_ibp_combine(double *const *lv, const double *const *ld, const double *lambdas, int n, size_t len,
                        double *logbar, hipStream_t s);

@@ -98,7 +98,7 @@ size_t carve(Solve &s, int kind, const Kernel &k, int n, bool prune, void *mem) 
         }
     }
     s.partial = c.take<double>(npart > ncost ? npart : ncost);
-    s.err = c.take<double>(static_cast<size_t>(nj) + 8);
+    s.err = c.take<double>(3 * static_cast<size_t>(nj) + 8);
     s.offsets = c.take<int32_t>(static_cast<size_t>(nj) + 1);
     return c.used;
 }
@@ -230,11 +230,18 @@ Engine::~Engine() {
         (void)hipEventDestroy(p.b);
     }
     for (hipEvent_t e : spare_) (void)hipEventDestroy(e);
-    if (d_jobs_) (void)hipFree(d_jobs_);
-    if (d_map_) (void)hipFree(d_map_);
+    for (TableSlot &t : tables_) {
+        if (t.d_jobs) (void)hipFree(t.d_jobs);
+        if (t.d_map) (void)hipFree(t.d_map);
+        if (t.used) (void)hipEventDestroy(t.used);
+    }
     if (h_jobs_) (void)hipHostFree(h_jobs_);
     if (h_map_) (void)hipHostFree(h_map_);
     if (h_err_) (void)hipHostFree(h_err_);
+    if (h_items_) (void)hipHostFree(h_items_);
+    if (d_items_) (void)hipFree(d_items_);
+    if (d_errs_) (void)hipFree(d_errs_);
+    if (items_used_) (void)hipEventDestroy(items_used_);
     for (auto &e : staged_)
         if (e) (void)hipEventDestroy(e);
 }
@@ -250,13 +257,8 @@ int Engine::ensure(size_t njobs, size_t nblocks) {
         SE2_HIP(hipEventSynchronize(staged_[1]));
         size_t nj = njobs > cap_jobs_ ? njobs * 2 : cap_jobs_;
         size_t nb = nblocks > cap_blocks_ ? nblocks * 2 : cap_blocks_;
-        if (d_jobs_) SE2_HIP(hipFree(d_jobs_));
-        if (d_map_) SE2_HIP(hipFree(d_map_));
         if (h_jobs_) SE2_HIP(hipHostFree(h_jobs_));
         if (h_map_) SE2_HIP(hipHostFree(h_map_));
-        // device side: 2 halves as well, so an in-flight launch never sees its table rewritten
-        SE2_HIP(hipMalloc(&d_jobs_, 2 * nj * sizeof(ConvJob)));
-        SE2_HIP(hipMalloc(&d_map_, 2 * nb * sizeof(int32_t)));
         SE2_HIP(hipHostMalloc(&h_jobs_, 2 * nj * sizeof(ConvJob), hipHostMallocDefault));
         SE2_HIP(hipHostMalloc(&h_map_, 2 * nb * sizeof(int32_t), hipHostMallocDefault));
         cap_jobs_ = nj;
@@ -267,33 +269,70 @@ int Engine::ensure(size_t njobs, size_t nblocks) {
 
 int Engine::stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, int R_max, bool sparse, bool f64,
                              hipStream_t st) {
-    int rc = ensure(jobs.size(), nblocks);
-    if (rc) return rc;
-    const int h = flip_;
-    flip_ ^= 1;
-    SE2_HIP(hipEventSynchronize(staged_[h]));  // the copy that last read this half is done
-    ConvJob *hj = h_jobs_ + h * cap_jobs_;
-    int32_t *hm = h_map_ + h * cap_blocks_;
-    ConvJob *dj = d_jobs_ + h * cap_jobs_;
-    int32_t *dm = d_map_ + h * cap_blocks_;
-    std::memcpy(hj, jobs.data(), jobs.size() * sizeof(ConvJob));
-    for (size_t q = 0; q < jobs.size(); ++q)
-        for (int b = 0; b < jobs[q].tiles; ++b) hm[jobs[q].first_block + b] = static_cast<int32_t>(q);
-    SE2_HIP(hipMemcpyAsync(dj, hj, jobs.size() * sizeof(ConvJob), hipMemcpyHostToDevice, st));
-    SE2_HIP(hipMemcpyAsync(dm, hm, static_cast<size_t>(nblocks) * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    SE2_HIP(hipEventRecord(staged_[h], st));
+    const size_t nj = jobs.size();
+    TableSlot *t = nullptr;
+    for (TableSlot &c : tables_)
+        if (c.key.size() == nj && std::memcmp(c.key.data(), jobs.data(), nj * sizeof(ConvJob)) == 0) {
+            t = &c;
+            break;
+        }
+    if (!t) {
+        // least recently used slot; no launch still in flight may read it when it is rewritten
+        t = &tables_[0];
+        for (TableSlot &c : tables_)
+            if (c.last < t->last) t = &c;
+        if (!t->used) SE2_HIP(hipEventCreateWithFlags(&t->used, hipEventDisableTiming));
+        else SE2_HIP(hipEventSynchronize(t->used));
+        if (nj > t->cap_jobs || static_cast<size_t>(nblocks) > t->cap_blocks) {
+            if (t->d_jobs) SE2_HIP(hipFree(t->d_jobs));
+            if (t->d_map) SE2_HIP(hipFree(t->d_map));
+            t->cap_jobs = nj * 2;
+            t->cap_blocks = static_cast<size_t>(nblocks) * 2;
+            SE2_HIP(hipMalloc(&t->d_jobs, t->cap_jobs * sizeof(ConvJob)));
+            SE2_HIP(hipMalloc(&t->d_map, t->cap_blocks * sizeof(int32_t)));
+        }
+        int rc = ensure(nj, nblocks);
+        if (rc) return rc;
+        const int h = flip_;
+        flip_ ^= 1;
+        SE2_HIP(hipEventSynchronize(staged_[h]));  // the copy that last read this half is done
+        ConvJob *hj = h_jobs_ + h * cap_jobs_;
+        int32_t *hm = h_map_ + h * cap_blocks_;
+        std::memcpy(hj, jobs.data(), nj * sizeof(ConvJob));
+        for (size_t q = 0; q < nj; ++q)
+            for (int b = 0; b < jobs[q].tiles; ++b) hm[jobs[q].first_block + b] = static_cast<int32_t>(q);
+        SE2_HIP(hipMemcpyAsync(t->d_jobs, hj, nj * sizeof(ConvJob), hipMemcpyHostToDevice, st));
+        SE2_HIP(hipMemcpyAsync(t->d_map, hm, static_cast<size_t>(nblocks) * sizeof(int32_t), hipMemcpyHostToDevice,
+                               st));
+        SE2_HIP(hipEventRecord(staged_[h], st));
+        t->key = jobs;
+    }
+    t->last = ++clock_;
     if (sparse && static_cast<size_t>(nblocks) > cap_rebuild_) {
         // stream order: earlier launches that used the old buffers finish before it is freed
         SE2_HIP(hipStreamSynchronize(st));
         if (d_rebuild_) SE2_HIP(hipFree(d_rebuild_));
-        if (!d_rebuild_count_) SE2_HIP(hipMalloc(&d_rebuild_count_, sizeof(int)));
+        if (!d_rebuild_count_) {
+            // two counters used alternately: each sparse launch zeroes the other one
+            SE2_HIP(hipMalloc(&d_rebuild_count_, 2 * sizeof(int)));
+            SE2_HIP(hipMemsetAsync(d_rebuild_count_, 0, 2 * sizeof(int), st));
+        }
         cap_rebuild_ = static_cast<size_t>(nblocks) * 2;
         SE2_HIP(hipMalloc(&d_rebuild_, cap_rebuild_ * sizeof(int2)));
     }
-    // The device tables of half h are only rewritten after staged_[h] completes a second
-    // time, i.e. after this launch (stream order) has consumed them.
-    return launch_conv_lse(dj, static_cast<int>(jobs.size()), nblocks, dm, nt, R_max, f64, sparse,
-                           sparse ? d_rebuild_ : nullptr, sparse ? d_rebuild_count_ : nullptr, st);
+    int rc;
+    if (!sparse) {
+        rc = launch_conv_lse(t->d_jobs, static_cast<int>(nj), nblocks, t->d_map, nt, R_max, f64, false, nullptr, nullptr,
+                             nullptr, st);
+    } else {
+        int *cnt = d_rebuild_count_ + rc_flip_, *next = d_rebuild_count_ + (1 - rc_flip_);
+        rc_flip_ ^= 1;
+        rc = launch_conv_lse(t->d_jobs, static_cast<int>(nj), nblocks, t->d_map, nt, R_max, f64, true, d_rebuild_, cnt,
+                             next, st);
+    }
+    if (rc) return rc;
+    SE2_HIP(hipEventRecord(t->used, st));
+    return SE2_OK;
 }
 
 int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool with_err, hipStream_t st) {
@@ -435,37 +474,61 @@ int Engine::step(const std::vector<Solve *> &solves, bool check, hipStream_t st)
     if (rc) return rc;
     for (Solve *s : solves) {
         s->iter += 1;
-        if (check) {
-            rc = launch_sum_partials(s->partial, s->offsets, s->kind == SE2_REQ_OT ? 1 : s->n, s->err, st);
-            if (rc) return rc;
-        } else if (s->kind == SE2_REQ_OT) {
-            s->cur ^= 1;  // the new a-potential becomes current; nobody needs the old one
-        }
+        if (!check && s->kind == SE2_REQ_OT) s->cur ^= 1;  // the new a-potential becomes current
     }
+    return check ? sum_errors(solves, st) : SE2_OK;
+}
+
+int Engine::sum_errors(const std::vector<Solve *> &solves, hipStream_t st) {
+    std::vector<SumItem> items;
+    for (Solve *s : solves) {
+        const int nj = (s->kind == SE2_REQ_OT) ? 1 : s->n;
+        const int per = s->tiles * s->k->grid.ntheta;
+        for (int i = 0; i < nj; ++i) items.push_back(SumItem{s->partial, i * per, (i + 1) * per});
+    }
+    const size_t n = items.size();
+    const bool same = items_key_.size() == n &&
+                      std::memcmp(items_key_.data(), items.data(), n * sizeof(SumItem)) == 0;
+    if (!same) {
+        if (!items_used_) SE2_HIP(hipEventCreateWithFlags(&items_used_, hipEventDisableTiming));
+        else SE2_HIP(hipEventSynchronize(items_used_));  // no copy or sum in flight uses the table
+        if (n > cap_items_) {
+            if (h_items_) SE2_HIP(hipHostFree(h_items_));
+            if (d_items_) SE2_HIP(hipFree(d_items_));
+            if (d_errs_) SE2_HIP(hipFree(d_errs_));
+            cap_items_ = n * 2;
+            SE2_HIP(hipHostMalloc(&h_items_, cap_items_ * sizeof(SumItem), hipHostMallocDefault));
+            SE2_HIP(hipMalloc(&d_items_, cap_items_ * sizeof(SumItem)));
+            SE2_HIP(hipMalloc(&d_errs_, cap_items_ * sizeof(double)));
+        }
+        std::memcpy(h_items_, items.data(), n * sizeof(SumItem));
+        SE2_HIP(hipMemcpyAsync(d_items_, h_items_, n * sizeof(SumItem), hipMemcpyHostToDevice, st));
+        items_key_ = items;
+    }
+    int rc = launch_sum_items(d_items_, static_cast<int>(n), d_errs_, st);
+    if (rc) return rc;
+    SE2_HIP(hipEventRecord(items_used_, st));
     return SE2_OK;
 }
 
 int Engine::read_errors(const std::vector<Solve *> &solves, std::vector<double> &max_err, hipStream_t st) {
+    // the errors of the last check, in the item order of sum_errors()
     size_t total = 0;
     for (Solve *s : solves) total += (s->kind == SE2_REQ_OT) ? 1 : s->n;
+    if (total != items_key_.size() || !d_errs_) return SE2_EINVAL;
     if (total > cap_err_) {
         if (h_err_) SE2_HIP(hipHostFree(h_err_));
         SE2_HIP(hipHostMalloc(&h_err_, total * 2 * sizeof(double), hipHostMallocDefault));
         cap_err_ = total * 2;
     }
-    size_t off = 0;
-    for (Solve *s : solves) {
-        const size_t c = (s->kind == SE2_REQ_OT) ? 1 : s->n;
-        SE2_HIP(hipMemcpyAsync(h_err_ + off, s->err, c * sizeof(double), hipMemcpyDeviceToHost, st));
-        off += c;
-    }
+    SE2_HIP(hipMemcpyAsync(h_err_, d_errs_, total * sizeof(double), hipMemcpyDeviceToHost, st));
     SE2_HIP(hipStreamSynchronize(st));
     if (prof_) {
         int rc = collect_profile();
         if (rc) return rc;
     }
     max_err.assign(solves.size(), 0.0);
-    off = 0;
+    size_t off = 0;
     for (size_t q = 0; q < solves.size(); ++q) {
         const size_t c = (solves[q]->kind == SE2_REQ_OT) ? 1 : solves[q]->n;
         double m = 0.0;
@@ -485,12 +548,13 @@ int Engine::read_errors(const std::vector<Solve *> &solves, std::vector<double> 
 
 namespace {
 
-// FP64 re-check of the marginal error: out = aux - LSE_f64(L + in) vs old.
-int f64_check(const Kernel &k, const double *in, const double *aux, const double *old, double *scratch_out,
-              double *partial, double *err_out, const int32_t *offsets, int tiles, hipStream_t st) {
+// FP64 re-check of one marginal: aux - LSE_f64(L + in) compared with old; the output
+// itself is not stored, only the error partials [tile][nt] in `partial`.
+ConvJob check_job(const Kernel &k, const double *in, const double *aux, const double *old, double *partial,
+                  int tiles) {
     ConvJob j{};
     j.in = in;
-    j.out = scratch_out;
+    j.out = nullptr;
     j.aux = aux;
     j.old = old;
     j.partial = partial;
@@ -502,148 +566,157 @@ int f64_check(const Kernel &k, const double *in, const double *aux, const double
     j.epi = EPI_SCALE;
     j.tiles_x = tiles_of(k.grid.nx);
     j.tiles = tiles;
-    j.first_block = 0;
-    ConvJob *dj = nullptr;
-    int32_t *dm = nullptr;
-    SE2_HIP(hipMallocAsync(reinterpret_cast<void **>(&dj), sizeof(ConvJob), st));
-    SE2_HIP(hipMallocAsync(reinterpret_cast<void **>(&dm), tiles * sizeof(int32_t), st));
-    SE2_HIP(hipMemcpyAsync(dj, &j, sizeof(ConvJob), hipMemcpyHostToDevice, st));
-    SE2_HIP(hipMemsetAsync(dm, 0, tiles * sizeof(int32_t), st));
-    int rc = launch_conv_lse(dj, 1, tiles, dm, k.grid.ntheta, k.metric.radius, true, false, nullptr, nullptr, st);
-    if (rc) return rc;
-    rc = launch_sum_partials(partial, offsets, 1, err_out, st);
-    if (rc) return rc;
-    SE2_HIP(hipStreamSynchronize(st));  // `j` lives on this frame
-    SE2_HIP(hipFreeAsync(dj, st));
-    SE2_HIP(hipFreeAsync(dm, st));
-    return SE2_OK;
+    j.lmax = kListMax;
+    return j;
 }
 
-int read_scalar(const double *d, double *h, hipStream_t st) {
-    SE2_HIP(hipMemcpyAsync(h, d, sizeof(double), hipMemcpyDeviceToHost, st));
-    SE2_HIP(hipStreamSynchronize(st));
-    return SE2_OK;
-}
-
-}  // namespace
-
-namespace {
-// Sum of the dense and sparse term counters of a list set (host copy; syncs `st`).
-int read_work(const ListSet &l, int tiles, double *dense, double *sparse, hipStream_t st) {
+// Sum of the dense and sparse term counters of a list set (host copy, synchronous).
+int read_work(const ListSet &l, int tiles, double *dense, double *sparse) {
     if (!l.work) return SE2_OK;
     std::vector<double> h(2 * static_cast<size_t>(tiles));
-    SE2_HIP(hipMemcpyAsync(h.data(), l.work, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    SE2_HIP(hipStreamSynchronize(st));
+    SE2_HIP(hipMemcpy(h.data(), l.work, h.size() * sizeof(double), hipMemcpyDeviceToHost));
     for (int t = 0; t < tiles; ++t) {
         *dense += h[2 * t];
         *sparse += h[2 * t + 1];
     }
     return SE2_OK;
 }
+
 }  // namespace
 
-int solve_finish_ot(Solve &s, double *f_out, double *g_out, se2_report_t *rep, hipStream_t st) {
-    const Kernel &k = *s.k;
-    const double scale = k.metric.eps * kLn2;  // base-2 log-scaling -> eps * natural log
-    const double *phi = s.phi[s.cur];
-    int rc;
-    if (f_out && (rc = launch_scale(phi, f_out, s.E, scale, st))) return rc;
-    if (g_out && (rc = launch_scale(s.psi, g_out, s.E, scale, st))) return rc;
-    se2_report_t r{};
-    r.status = s.status;
-    r.iters = s.iter;
-    r.marg_l1 = s.last_err;
-    r.marg_l1_f64 = -1.0;
-    r.convs = s.convs;
-    // plan cost and mass
-    const int nb = cost_blocks(s.E);
-    double *part = s.partial;  // large enough: >= 2 * nb + 512
-    if ((rc = launch_plan_cost(k, phi, s.psi, part, nb, st))) return rc;
-    if ((rc = launch_reduce_fixed(part, nb, 2, s.err + 2, st))) return rc;
-    double cm[2] = {0, 0};
-    SE2_HIP(hipMemcpyAsync(cm, s.err + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-    // dual <f, mu> + <g, nu>
-    const int dnb = 256;
-    if ((rc = launch_dot_exp(phi, s.mu_lin, s.E, part, dnb, st))) return rc;
-    if ((rc = launch_reduce_fixed(part, dnb, 1, s.err + 4, st))) return rc;
-    if ((rc = launch_dot_exp(s.psi, s.nu_lin, s.E, part, dnb, st))) return rc;
-    if ((rc = launch_reduce_fixed(part, dnb, 1, s.err + 5, st))) return rc;
-    double dd[2] = {0, 0};
-    SE2_HIP(hipMemcpyAsync(dd, s.err + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-    SE2_HIP(hipStreamSynchronize(st));
-    r.cost = cm[0];
-    r.mass = cm[1];
-    r.dual = scale * (dd[0] + dd[1]);
-    if (s.opts.final_check) {
-        // first marginal: a-update from psi in FP64 vs phi; second: b-update from phi vs psi
-        double e1 = 0, e2 = 0;
-        double *scratch = s.phi[1 - s.cur];
-        if ((rc = f64_check(k, s.psi, s.lmu, phi, scratch, s.partial, s.err + 6, s.offsets, s.tiles, st))) return rc;
-        if ((rc = read_scalar(s.err + 6, &e1, st))) return rc;
-        if ((rc = f64_check(k, phi, s.lnu, s.psi, scratch, s.partial, s.err + 6, s.offsets, s.tiles, st))) return rc;
-        if ((rc = read_scalar(s.err + 6, &e2, st))) return rc;
-        r.marg_l1_f64 = e1 + e2;
+int Engine::launch_checks(const std::vector<ConvJob> &jobs, const std::vector<int> &nts, hipStream_t st) {
+    static const int kClasses[3] = {8, 16, 32};
+    for (int nt : kClasses) {
+        std::vector<ConvJob> group;
+        int nblocks = 0, R_max = 0;
+        for (size_t q = 0; q < jobs.size(); ++q) {
+            if (nts[q] != nt) continue;
+            ConvJob j = jobs[q];
+            j.first_block = nblocks;
+            nblocks += j.tiles;
+            if (j.R > R_max) R_max = j.R;
+            group.push_back(j);
+        }
+        if (group.empty()) continue;
+        const int rc = stage_and_launch(group, nblocks, nt, R_max, false, true, st);
+        if (rc) return rc;
     }
-    if ((rc = read_work(s.ls_phi, s.tiles, &r.terms_dense, &r.terms_sparse, st))) return rc;
-    if ((rc = read_work(s.ls_psi, s.tiles, &r.terms_dense, &r.terms_sparse, st))) return rc;
-    r.seconds = now_seconds() - s.t_start;
-    if (!std::isfinite(r.cost) || !std::isfinite(r.marg_l1)) rc = SE2_ENUMERIC;
-    else rc = SE2_OK;
-    if (rep) *rep = r;
-    return rc;
+    return SE2_OK;
 }
 
-int solve_finish_bary(Solve &s, double *bary_out, se2_report_t *rep, hipStream_t st) {
-    const Kernel &k = *s.k;
-    int rc;
-    if ((rc = launch_exp2_out(s.logbar, bary_out, s.E, st))) return rc;
-    se2_report_t r{};
-    r.status = s.status;
-    r.iters = s.iter;
-    r.marg_l1 = s.last_err;
-    r.marg_l1_f64 = -1.0;
-    r.convs = s.convs;
-    // sum_i lambda_i <pi_i, rho^2> with pi_i = diag(w_i) K diag(v_i) (first marginal exact)
-    const int nb = cost_blocks(s.E);
-    double cost = 0.0;
-    for (int i = 0; i < s.n; ++i) {
-        if ((rc = launch_plan_cost(k, s.lw[i], s.lv[i], s.partial, nb, st))) return rc;
-        if ((rc = launch_reduce_fixed(s.partial, nb, 2, s.err + 2, st))) return rc;
-        double cm[2];
-        SE2_HIP(hipMemcpyAsync(cm, s.err + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-        SE2_HIP(hipStreamSynchronize(st));
-        cost += s.lam[i] * cm[0];
-    }
-    // barycenter mass (FP64 fixed-order sum of bary_out, reusing the validation reduction)
-    double *stats = s.partial;
-    if ((rc = launch_validate(bary_out, s.E, stats, st))) return rc;
-    double mass = 0.0;
-    if ((rc = read_scalar(stats, &mass, st))) return rc;
-    r.cost = cost;
-    r.mass = mass;
-    r.dual = 0.0;
-    if (s.opts.final_check) {
-        // barycenter side of pi_i = diag(w_i) K diag(v_i) in FP64: sum bar |v_i (K*w_i) / bar - 1|
-        // (its mu_i side is exact by construction of the last w-update)
-        double worst = 0.0;
-        for (int i = 0; i < s.n; ++i) {
-            double e = 0.0;
-            if ((rc = f64_check(k, s.lw[i], s.logbar, s.lv[i], s.phi[0], s.partial, s.err + 6, s.offsets, s.tiles,
-                                st)))
-                return rc;
-            if ((rc = read_scalar(s.err + 6, &e, st))) return rc;
-            if (!(e <= worst)) worst = e;
+int finish_solves(Engine &eng, std::vector<FinishReq> &reqs, hipStream_t st) {
+    // 1. every GPU step of every solve, in stream order; results land in err slots
+    //    OT:  [2] cost, [3] plan mass, [4] <f, mu>, [5] <g, nu> (base 2), [6] [7] FP64 checks
+    //    IBP: [2+2i] cost and [3+2i] mass of plan i, [2+2n] barycenter mass, [3+2n+i] FP64 check i
+    std::vector<ConvJob> chk_a, chk_b;
+    std::vector<int> nt_a, nt_b;
+    for (FinishReq &q : reqs) {
+        Solve &s = *q.s;
+        const Kernel &k = *s.k;
+        const int nb = cost_blocks(s.E);
+        double *part = s.partial;  // scratch: >= 2 * nb + 512 doubles
+        int rc = SE2_OK;
+        if (s.kind == SE2_REQ_OT) {
+            const double scale = k.metric.eps * kLn2;  // base-2 log-scaling -> eps * natural log
+            const double *phi = s.phi[s.cur];
+            if (q.f_out && (rc = launch_scale(phi, q.f_out, s.E, scale, st))) return rc;
+            if (q.g_out && (rc = launch_scale(s.psi, q.g_out, s.E, scale, st))) return rc;
+            if ((rc = launch_plan_cost(k, phi, s.psi, part, nb, st))) return rc;
+            if ((rc = launch_reduce_fixed(part, nb, 2, s.err + 2, st))) return rc;
+            const int dnb = 256;
+            if ((rc = launch_dot_exp(phi, s.mu_lin, s.E, part, dnb, st))) return rc;
+            if ((rc = launch_reduce_fixed(part, dnb, 1, s.err + 4, st))) return rc;
+            if ((rc = launch_dot_exp(s.psi, s.nu_lin, s.E, part, dnb, st))) return rc;
+            if ((rc = launch_reduce_fixed(part, dnb, 1, s.err + 5, st))) return rc;
+            if (s.opts.final_check) {
+                // first marginal: the a-update from psi against phi; second: the b-update from phi against psi
+                chk_a.push_back(check_job(k, s.psi, s.lmu, phi, s.partial, s.tiles));
+                nt_a.push_back(k.grid.ntheta);
+                chk_b.push_back(check_job(k, phi, s.lnu, s.psi, s.partial, s.tiles));
+                nt_b.push_back(k.grid.ntheta);
+            }
+        } else {
+            if ((rc = launch_exp2_out(s.logbar, q.bary_out, s.E, st))) return rc;
+            // sum_i lambda_i <pi_i, rho^2> with pi_i = diag(w_i) K diag(v_i) (first marginal exact)
+            for (int i = 0; i < s.n; ++i) {
+                if ((rc = launch_plan_cost(k, s.lw[i], s.lv[i], part, nb, st))) return rc;
+                if ((rc = launch_reduce_fixed(part, nb, 2, s.err + 2 + 2 * i, st))) return rc;
+            }
+            // barycenter mass (FP64 fixed-order sum, the validation reduction)
+            if ((rc = launch_validate(q.bary_out, s.E, part, st))) return rc;
+            SE2_HIP(hipMemcpyAsync(s.err + 2 + 2 * s.n, part, sizeof(double), hipMemcpyDeviceToDevice, st));
+            if (s.opts.final_check) {
+                // barycenter side of pi_i in FP64: sum bar |v_i (K*w_i) / bar - 1| (its mu_i side is
+                // exact by construction of the last w-update)
+                const size_t per = static_cast<size_t>(s.tiles) * k.grid.ntheta;
+                for (int i = 0; i < s.n; ++i) {
+                    chk_a.push_back(check_job(k, s.lw[i], s.logbar, s.lv[i], s.partial + i * per, s.tiles));
+                    nt_a.push_back(k.grid.ntheta);
+                }
+            }
         }
-        r.marg_l1_f64 = worst;
     }
-    for (int i = 0; i < s.n; ++i) {
-        if ((rc = read_work(s.ls_v[i], s.tiles, &r.terms_dense, &r.terms_sparse, st))) return rc;
-        if ((rc = read_work(s.ls_w[i], s.tiles, &r.terms_dense, &r.terms_sparse, st))) return rc;
+    // 2. FP64 checks, batched over the solves: first marginals, then second marginals
+    int rc;
+    if (!chk_a.empty()) {
+        if ((rc = eng.launch_checks(chk_a, nt_a, st))) return rc;
+        for (FinishReq &q : reqs) {
+            Solve &s = *q.s;
+            if (!s.opts.final_check) continue;
+            const bool ot = s.kind == SE2_REQ_OT;
+            if ((rc = launch_sum_partials(s.partial, s.offsets, ot ? 1 : s.n, s.err + (ot ? 6 : 3 + 2 * s.n), st)))
+                return rc;
+        }
     }
-    r.seconds = now_seconds() - s.t_start;
-    rc = (std::isfinite(r.cost) && std::isfinite(r.marg_l1)) ? SE2_OK : SE2_ENUMERIC;
-    if (rep) *rep = r;
-    return rc;
+    if (!chk_b.empty()) {
+        if ((rc = eng.launch_checks(chk_b, nt_b, st))) return rc;
+        for (FinishReq &q : reqs) {
+            Solve &s = *q.s;
+            if (!s.opts.final_check || s.kind != SE2_REQ_OT) continue;
+            if ((rc = launch_sum_partials(s.partial, s.offsets, 1, s.err + 7, st))) return rc;
+        }
+    }
+    SE2_HIP(hipStreamSynchronize(st));
+    // 3. reports
+    for (FinishReq &q : reqs) {
+        Solve &s = *q.s;
+        const int nj = (s.kind == SE2_REQ_OT) ? 1 : s.n;
+        std::vector<double> e(3 * static_cast<size_t>(nj) + 8);
+        SE2_HIP(hipMemcpy(e.data(), s.err, e.size() * sizeof(double), hipMemcpyDeviceToHost));
+        se2_report_t r{};
+        r.status = s.status;
+        r.iters = s.iter;
+        r.marg_l1 = s.last_err;
+        r.marg_l1_f64 = -1.0;
+        r.convs = s.convs;
+        if (s.kind == SE2_REQ_OT) {
+            r.cost = e[2];
+            r.mass = e[3];
+            r.dual = s.k->metric.eps * kLn2 * (e[4] + e[5]);
+            if (s.opts.final_check) r.marg_l1_f64 = e[6] + e[7];
+            if ((rc = read_work(s.ls_phi, s.tiles, &r.terms_dense, &r.terms_sparse))) return rc;
+            if ((rc = read_work(s.ls_psi, s.tiles, &r.terms_dense, &r.terms_sparse))) return rc;
+        } else {
+            double cost = 0.0, worst = 0.0;
+            for (int i = 0; i < s.n; ++i) {
+                cost += s.lam[i] * e[2 + 2 * i];
+                const double c = e[3 + 2 * s.n + i];
+                if (!(c <= worst)) worst = c;
+            }
+            r.cost = cost;
+            r.mass = e[2 + 2 * s.n];
+            r.dual = 0.0;
+            if (s.opts.final_check) r.marg_l1_f64 = worst;
+            for (int i = 0; i < s.n; ++i) {
+                if ((rc = read_work(s.ls_v[i], s.tiles, &r.terms_dense, &r.terms_sparse))) return rc;
+                if ((rc = read_work(s.ls_w[i], s.tiles, &r.terms_dense, &r.terms_sparse))) return rc;
+            }
+        }
+        r.seconds = now_seconds() - s.t_start;
+        q.rc = (std::isfinite(r.cost) && std::isfinite(r.marg_l1)) ? SE2_OK : SE2_ENUMERIC;
+        q.rep = r;
+    }
+    return SE2_OK;
 }
 
 }  // namespace se2

@@ -38,7 +38,7 @@ struct Solve {
     double *logbar = nullptr;
     // common
     double *partial = nullptr;       // [job][tile][nt] error partials
-    double *err = nullptr;           // max(1, n) reduced errors (device)
+    double *err = nullptr;           // 3 * max(1, n) + 8 result slots of the finishing (device)
     int32_t *offsets = nullptr;      // per-job partial offsets (device), max(1, n) + 1
     int iter = 0;                    // completed iterations
     bool done = false;
@@ -83,6 +83,8 @@ public:
     int read_errors(const std::vector<Solve *> &solves, std::vector<double> &max_err, hipStream_t st);
     // Optional event timing of every log-domain convolution launch.
     void set_profiling(bool on);
+    // FP64 check convolutions (dense, FP64 exp): one launch per ntheta class.
+    int launch_checks(const std::vector<ConvJob> &jobs, const std::vector<int> &nts, hipStream_t st);
     int collect_profile();  // folds finished event pairs into the totals (after a sync)
     double prof_seconds = 0.0, prof_terms = 0.0, prof_outputs = 0.0;
     int64_t prof_launches = 0;
@@ -92,10 +94,23 @@ private:
     int stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, int R_max, bool sparse, bool f64,
                          hipStream_t st);
     int ensure(size_t njobs, size_t nblocks);
-    ConvJob *d_jobs_ = nullptr;
-    int32_t *d_map_ = nullptr;
+    // Device copies of job tables and block maps, kept while their content recurs (a
+    // solve set cycles through a few tables: two stages x two buffer parities, and the
+    // check variants); a table is uploaded only when it is not cached.
+    struct TableSlot {
+        std::vector<ConvJob> key;  // host copy of the table held
+        ConvJob *d_jobs = nullptr;
+        int32_t *d_map = nullptr;
+        size_t cap_jobs = 0, cap_blocks = 0;
+        hipEvent_t used = nullptr;  // recorded after each launch that reads the slot
+        uint64_t last = 0;
+    };
+    static constexpr int kTableSlots = 16;
+    TableSlot tables_[kTableSlots];
+    uint64_t clock_ = 0;
     int2 *d_rebuild_ = nullptr;      // tiles left to the wide rebuild kernel, one slot per block
-    int *d_rebuild_count_ = nullptr;
+    int *d_rebuild_count_ = nullptr;  // two counters, used alternately
+    int rc_flip_ = 0;
     size_t cap_rebuild_ = 0;
     ConvJob *h_jobs_ = nullptr;      // pinned staging (double-buffered)
     int32_t *h_map_ = nullptr;
@@ -104,6 +119,13 @@ private:
     hipEvent_t staged_[2] = {nullptr, nullptr};
     double *h_err_ = nullptr;
     size_t cap_err_ = 0;
+    // batched error sums of a check: one item per (solve, job), results contiguous
+    std::vector<SumItem> items_key_;   // the item table on the device
+    SumItem *h_items_ = nullptr, *d_items_ = nullptr;
+    double *d_errs_ = nullptr;
+    size_t cap_items_ = 0;
+    hipEvent_t items_used_ = nullptr;
+    int sum_errors(const std::vector<Solve *> &solves, hipStream_t st);
     bool prof_ = false;
     struct Pending {
         hipEvent_t a, b;
@@ -111,13 +133,20 @@ private:
     };
     std::vector<Pending> pending_;
     std::vector<hipEvent_t> spare_;
-    std::vector<double *> d_err_gather_;
 };
 
-// Final report pieces: potentials out (natural units), plan cost, mass, dual,
-// optional FP64 re-check of the marginal error.  Blocking on `st`.
-int solve_finish_ot(Solve &s, double *f_out, double *g_out, se2_report_t *rep, hipStream_t st);
-int solve_finish_bary(Solve &s, double *bary_out, se2_report_t *rep, hipStream_t st);
+// Finishing of a group of solves: potentials out (natural units), plan cost, mass,
+// dual, optional FP64 re-check of the marginal error.  Every solve's GPU work is
+// queued first (the FP64 checks batched over the group), then one synchronisation;
+// each request's report and status are filled in.  Blocking on `st`.
+struct FinishReq {
+    Solve *s = nullptr;
+    double *f_out = nullptr, *g_out = nullptr;  // OT outputs (may be null)
+    double *bary_out = nullptr;                 // barycenter output
+    se2_report_t rep{};
+    int rc = SE2_OK;
+};
+int finish_solves(Engine &eng, std::vector<FinishReq> &reqs, hipStream_t st);
 
 double now_seconds();
 
