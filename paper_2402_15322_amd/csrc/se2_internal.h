@@ -30,10 +30,10 @@ constexpr int kMaxRadius = 12;
 // kRefMargin / 2, added to the measured spread), so every skipped entry is below
 // 2^-(kListCut - kDriftSpread) = 2^-48 of the result's largest term.
 #ifndef SE2_LIST_CUT
-#define SE2_LIST_CUT 80
+#define SE2_LIST_CUT 88
 #endif
 #ifndef SE2_DRIFT_SPREAD
-#define SE2_DRIFT_SPREAD 32
+#define SE2_DRIFT_SPREAD 40
 #endif
 constexpr double kListCut = SE2_LIST_CUT;
 constexpr float kDriftSpread = SE2_DRIFT_SPREAD;
