@@ -276,7 +276,7 @@ int oc_ibp(int nx, int ny, int nt, int R, const double *logk, int nmeas,
             scaling_update(n, lmu, c, lw_new);
             if (it > 1) {
                 double em = marginal_gap(n, lmu, lw + n * m, lw_new);
-                if (em > e) e = em;
+                if (!(em <= e)) e = em; /* the largest error; a NaN one is reported as NaN */
             }
             memcpy(lw + n * m, lw_new, sizeof(double) * n);
         }
