@@ -116,6 +116,42 @@ def conv_linear(logk: np.ndarray, x: np.ndarray) -> np.ndarray:
     return out
 
 
+def _window_at(logk: np.ndarray, arr: np.ndarray, iy: int, ix: int, ko: int):
+    """Window terms of output (iy, ix, ko): (log K entries, input values) over the
+    in-grid offsets d = out - in, all input orientations (Section 4.2, zero boundary)."""
+    ny, nx, nt = arr.shape
+    R = (logk.shape[0] - 1) // 2
+    ks, vs = [], []
+    for dy in range(-R, R + 1):
+        for dx in range(-R, R + 1):
+            y, x = iy - dy, ix - dx
+            if 0 <= y < ny and 0 <= x < nx:
+                ks.append(logk[dy + R, dx + R, ko, :])
+                vs.append(arr[y, x, :])
+    return np.concatenate(ks), np.concatenate(vs)
+
+
+def conv_log_points(logk: np.ndarray, login: np.ndarray, pts) -> np.ndarray:
+    """log (K * exp(login)) at the given (iy, ix, ko) outputs only, one window sum each
+    (the same definition as conv_log, evaluated point by point for large grids)."""
+    out = np.empty(len(pts))
+    for n, (iy, ix, ko) in enumerate(pts):
+        k, v = _window_at(logk, login, iy, ix, ko)
+        a = k + v
+        m = np.max(a)
+        out[n] = -np.inf if m == -np.inf else m + np.log(np.sum(np.exp(a - m)))
+    return out
+
+
+def conv_linear_points(logk: np.ndarray, x: np.ndarray, pts) -> np.ndarray:
+    """(K * x) at the given (iy, ix, ko) outputs only, one window sum each."""
+    out = np.empty(len(pts))
+    for n, (iy, ix, ko) in enumerate(pts):
+        k, v = _window_at(logk, x, iy, ix, ko)
+        out[n] = np.sum(np.exp(k) * v)
+    return out
+
+
 def safe_log(m: np.ndarray) -> np.ndarray:
     with np.errstate(divide="ignore"):
         return np.log(m)

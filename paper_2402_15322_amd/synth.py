@@ -306,15 +306,23 @@ def lines64(instance: int = 0, paired: bool = True, n: int = 64) -> OTInstance:
     return OTInstance(g, (1.0, 3.0, 1.0), 0.1, 5, mu, nu, f"lines{n}x{n}x16-{tag}/{instance}")
 
 
+# Measures without a floor still get POSITIVE_FLOOR per element (about 2^-997, far
+# below any mass that matters): where one measure is exactly zero over a whole window,
+# the barycenter is zero there and mass of another measure has no partner inside the
+# truncated window, which makes the problem infeasible.
+POSITIVE_FLOOR = 1e-300
+
+
 def curves128(instance: int = 0, t: float = 0.5, n: int = 128) -> BaryInstance:
-    """Two measures of 4 cubic Beziers, 128x128x16, w=(1,3,1), eps=0.05, 15x15 window, no floor.
+    """Two measures of 4 cubic Beziers, 128x128x16, w=(1,3,1), eps=0.05, 15x15 window,
+    no floor beyond POSITIVE_FLOOR.
 
     Weights (1-t, t): t=0 returns the first measure's side (the interpolation
     reading that makes Phi_0 the first input).
     """
     g = Grid(n, n, 16)
     seed = 2 * 1000 + instance
-    mus = [splat_beziers(rng_for(seed, s), g, 4, 1.5, 0.0) for s in (0, 1)]
+    mus = [splat_beziers(rng_for(seed, s), g, 4, 1.5, POSITIVE_FLOOR) for s in (0, 1)]
     return BaryInstance(g, (1.0, 3.0, 1.0), 0.05, 7, mus, [1.0 - t, t], f"curves{n}x{n}x16/{instance}/t={t}")
 
 

@@ -109,6 +109,26 @@ def pin_conv_equals_dense_matrix():
         assert np.max(np.abs(np.where(finite, LM - LM.T, 0.0))) <= 1e-12 * np.max(np.abs(LM[finite]))
 
 
+def pin_pointwise_conv_equals_dense_matrix():
+    """The point-by-point window sums (used to check large grids at sampled outputs)
+    equal the explicit matrix product at every output of small grids, borders included."""
+    rng = np.random.default_rng(6)
+    for (nx, ny, nt, axial, R, w, eps) in ((7, 5, 4, False, 2, (1.0, 2.0, 1.0), 0.7),
+                                           (5, 6, 4, True, 2, (1.0, 3.0, 0.8), 0.9)):
+        LM = dense.dense_logk(nx, ny, nt, axial, w, eps, R)
+        logk, _ = oracle.kernel_table(nt, axial, w, eps, R)
+        pts = [(iy, ix, k) for iy in range(ny) for ix in range(nx) for k in range(nt)]
+        v = rng.uniform(0.0, 1.0, (ny, nx, nt))
+        ref = (np.exp(LM) @ v.reshape(-1)).reshape(-1)
+        got = oracle.conv_linear_points(logk, v, pts)
+        assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+        lv = rng.normal(0.0, 5.0, (ny, nx, nt))
+        lv[0, 0, :2] = -np.inf
+        want = dense.conv_log(LM, lv).reshape(-1)
+        got = oracle.conv_log_points(logk, lv, pts)
+        assert np.max(np.abs(got - want)) <= 1e-12 * max(1.0, np.max(np.abs(want)))
+
+
 # --------------------------------------------------------------------------
 # P4: one orientation -> separable anisotropic Gaussian (two 1-D passes)
 # P5: one pixel -> circulant theta convolution (FFT)
@@ -335,6 +355,7 @@ ALL_PINS = [
     pin_rho_inverse_symmetry,
     pin_table_identity_and_symmetry,
     pin_conv_equals_dense_matrix,
+    pin_pointwise_conv_equals_dense_matrix,
     pin_single_orientation_is_separable_gaussian,
     pin_single_pixel_is_circulant,
     pin_conv_equivariance,
