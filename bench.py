@@ -61,6 +61,13 @@ def parse():
     ap.add_argument("--conv-reps", type=int, default=20)
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size reference for HBM counters)")
+    ap.add_argument("--serving", action="store_true",
+                    help="serving workload instead: Poisson arrivals of mixed-size OT requests (own JSON line)")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--rate", type=float, default=200.0, help="arrivals per second")
+    ap.add_argument("--budget-gb", type=float, default=4.0, help="queue HBM budget")
+    ap.add_argument("--slots", type=int, default=64)
+    ap.add_argument("--plain-sample", type=int, default=2, help="one-at-a-time solves timed per grid size")
     return ap.parse_args()
 
 
@@ -132,6 +139,9 @@ def main():
         del src, dst
     if a.conv_only:
         print(json.dumps({"se2_conv": conv_measurements(native, torch, a.batch, a.conv_reps)}), flush=True)
+        return
+    if a.serving:
+        print(json.dumps(serving(native, torch, synth, a)), flush=True)
         return
     k = native.Kernel(NX, NX, NT, False, W_METRIC, EPS, R)
     insts = [synth.lines64(i, paired=True) for i in range(a.batch)]
@@ -236,6 +246,79 @@ def main():
                      "flops": "2 * batch * nx * ny * ntheta^2 * window", "launches": conv_meas},
     }
     print(json.dumps(out), flush=True)
+
+
+def serving(native, torch, synth, a):
+    """Poisson stream of OT requests with mixed grid sizes (32x32x8, 64x64x16, 128x128x16),
+    eps and w2, submitted at their arrival times to one queue; latency = completion -
+    submission.  Beside it, the same kind of solve one at a time (blocking, dense FP32
+    engine) on a stratified sample, extrapolated to the whole trace."""
+    import numpy as np
+    trace = synth.serving_trace(a.requests, a.rate)
+    kernels = {}
+
+    def kern(inst):
+        g = inst.grid
+        key = (g.nx, g.nt, inst.radius, inst.eps, inst.w)
+        if key not in kernels:
+            kernels[key] = native.Kernel(g.nx, g.ny, g.nt, False, inst.w, inst.eps, inst.radius)
+        return kernels[key]
+
+    dev = []
+    for r in trace:
+        mu = torch.from_numpy(r.inst.mu).cuda()
+        nu = torch.from_numpy(r.inst.nu).cuda()
+        dev.append((kern(r.inst), mu, nu, torch.empty_like(mu), torch.empty_like(mu)))
+    torch.cuda.synchronize()
+    o = native.opts(tol=a.tol, max_iter=a.max_iter, check_every=a.check_every, final_check=True, prune=not a.no_prune)
+    q = native.SolveQueue(hbm_budget_bytes=int(a.budget_gb * (1 << 30)), max_slots=a.slots)
+    tickets = []
+    t0 = time.perf_counter()
+    for r, (k, mu, nu, f, g) in zip(trace, dev):
+        dt = r.arrival_s - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(q.submit_ot(k, mu, nu, o, f, g))
+    reps = [q.wait(t) for t in tickets]
+    wall = time.perf_counter() - t0
+    lat = np.array([q.times(t)[2] - q.times(t)[0] for t in tickets])
+    st = q.stats()
+    q.close()
+    iters = sum(r["iters"] for r in reps)
+    conv = sum(1 for r in reps if r["status"] == native.SE2_CONVERGED)
+    # one at a time: plain FP32 engine, blocking, a few requests of each grid size
+    o_plain = native.opts(tol=a.tol, max_iter=a.max_iter, check_every=a.check_every, final_check=True, prune=False)
+    by_size = {}
+    for i, r in enumerate(trace):
+        by_size.setdefault(r.inst.grid.nx, []).append(i)
+    per_size = {}
+    for n, idx in sorted(by_size.items()):
+        ts = []
+        for i in idx[:a.plain_sample]:
+            k, mu, nu, f, g = dev[i]
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            native.se2_sinkhorn(k, mu, nu, o_plain, f, g)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - s0)
+        per_size[n] = (float(np.mean(ts)), len(idx))
+    plain_total = sum(m * c for m, c in per_size.values())
+    return {
+        "metric": "serving: p50/p99 latency and solves/s, Poisson OT requests of mixed sizes",
+        "mode": "serving",
+        "requests": len(trace), "rate_per_s": a.rate, "wall_s": wall,
+        "solves_per_s": len(reps) / wall, "converged_solves_per_s": conv / wall, "converged": conv,
+        "iters_per_s": iters / wall,
+        "p50_latency_ms": float(np.percentile(lat, 50) * 1e3), "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+        "queue": st, "budget_gb": a.budget_gb, "max_slots": a.slots,
+        "plain_one_at_a_time_solves_per_s_est": len(trace) / plain_total if plain_total > 0 else None,
+        "plain_seconds_per_solve": {str(n): m for n, (m, c) in per_size.items()},
+        "speedup_vs_plain": (len(reps) / wall) / (len(trace) / plain_total) if plain_total > 0 else None,
+        "config": {"workload": "serving trace: 32x32x8 r4, 64x64x16 r5, 128x128x16 r7; eps in {0.05, 0.1, 0.2}; "
+                               "w = (1, 2 or 3, 1); 4-12 segments; tol 1e-6, max_iter 1000",
+                   "seed": 3000},
+        "data": "synthetic",
+    }
 
 
 def cpu_baseline(inst, iters: int):
