@@ -41,6 +41,22 @@ SLOTS_SPARSE = 2 + 1 + EXP_SLOTS + 1
 # quoted as FP64-FMA equivalents (2 flops per slot): the published FP64 vector
 # peak of 78.6 TFLOP/s.
 PEAK_TFLOPS = 78.6
+# HBM bytes of one convolution launch (k_sparse + k_rebuild) on this workload, from
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (each scaled by what the counter reads for
+# a plain 256 MiB copy: x2.0 and x1.0), averaged over the 2004 launches of one bench
+# step; profiles/conv_lse_traffic_lines64x64x16_batch32.md.  Reported only while the
+# kernel sources are the ones measured.
+TRAFFIC = {"sources_sha256": "60c6fc12ab2efdd0dd90b677937bb452477493e8f919e275f92b94d3b9ea1d7e", "bytes_per_launch": 173301312.6,
+           "sources": ("paper_2402_15322_amd/csrc/conv_lse.hip", "paper_2402_15322_amd/csrc/se2_internal.h")}
+
+
+def measured_traffic():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return TRAFFIC["bytes_per_launch"] if h.hexdigest() == TRAFFIC["sources_sha256"] else None
 
 
 def parse():
@@ -236,7 +252,7 @@ def main():
         "plain_one_at_a_time_iters_per_s": plain_rate,
         "speedup_vs_plain": (value / plain_rate) if plain_rate else None,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_TFLOPS, "traffic": measured_traffic(),
                      "kernel": "log-domain convolution (k_sparse + k_rebuild)", "avg_launch_us": avg_launch * 1e6,
                      "dense_terms_per_launch": td / launches, "sparse_terms_per_launch": ts / launches,
                      "window_terms_per_launch": kt["terms"] / launches,
