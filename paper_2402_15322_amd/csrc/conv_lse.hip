@@ -299,6 +299,70 @@ __device__ __forceinline__ double epilogue_pre(const ConvJob &job, size_t idx, d
     return err;
 }
 
+// Sum over the `len` packed list entries at Lp (wave-uniform) of 2^(L + in - M) for
+// the lane's output, whose input halo starts at LDS offset `base`; groups of 8 entries
+// are summed in FP32, the groups in FP64.  Groups alternate between two register sets, and the next group is
+// requested only once the current group's gathers are back: lgkmcnt counts the scalar
+// loads as well, and these return out of order, so a request issued before the
+// gathers would be waited for together with them.  Reads run up to 8 entries past the
+// list (loaded, never used).
+__device__ __forceinline__ double eval_list(const cdptr Lp, int len, double M, const double *lds, int base) {
+    constexpr uint32_t kMask = (1u << kOffBits) - 1u;
+    double S = 0.0;
+    auto step = [&](const double (&P)[8], double (&Q)[8], const cdptr nxt) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            v[u] = lds[static_cast<int>(static_cast<uint32_t>(__double2loint(P[u])) & kMask) + base];
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the gathers
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) Q[u] = nxt[u];
+        __builtin_amdgcn_sched_barrier(0);
+        float s8 = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const unsigned int lo32 = static_cast<unsigned int>(__double2loint(P[u]));
+            const double lv = __hiloint2double(__double2hiint(P[u]), static_cast<int>(lo32 & ~kMask));
+            s8 += __builtin_amdgcn_exp2f(static_cast<float>((lv + v[u]) - M));
+        }
+        S += static_cast<double>(s8);
+    };
+    // the last r < 8 entries as a full group: the unused slots read the lane's own halo
+    // corner with a kernel value of -inf, i.e. add exact zeros (selects on the scalar unit)
+    auto tail = [&](const double (&P)[8], int r) {
+        double T8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            T8[u] = (u < r) ? P[u] : __hiloint2double(static_cast<int>(0xfff00000u), 0);
+        float st = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const unsigned int lo32 = static_cast<unsigned int>(__double2loint(T8[u]));
+            const double lv = __hiloint2double(__double2hiint(T8[u]), static_cast<int>(lo32 & ~kMask));
+            const double v = lds[static_cast<int>(lo32 & kMask) + base];
+            st += __builtin_amdgcn_exp2f(static_cast<float>((lv + v) - M));
+        }
+        S += static_cast<double>(st);
+    };
+    const int n8 = len & ~7;
+    double A[8], B[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) A[u] = Lp[u];
+    int e = 0;
+    for (; e + 16 <= n8; e += 16) {
+        step(A, B, Lp + e + 8);
+        step(B, A, Lp + e + 16);
+    }
+    if (e < n8) {
+        step(A, B, Lp + e + 8);
+        tail(B, len - n8);
+    } else {
+        tail(A, len - n8);
+    }
+    return S;
+}
+
 // Certified sparse evaluation of pruned jobs: one workgroup per 8 x 8 tile with
 // NW = min(nt, 16) waves (wave w owns ko = w, w+NW, ...; lane = pixel).  Every global
 // load of the tile's lanes (list lengths, per-output operands, the input halo and its
@@ -359,6 +423,7 @@ __global__ __launch_bounds__(64 * (NT < 16 ? NT : 16)) void k_sparse(const ConvJ
     const gdptr in = (gdptr)job.in;
     float dlo = INFINITY, dhi = -INFINITY;
     bool bad = false;
+    int pf[NJ];
     {
         constexpr int QK = NT / 4;
         const float inv = 1.0f / static_cast<float>(HW);
@@ -382,6 +447,16 @@ __global__ __launch_bounds__(64 * (NT < 16 ? NT : 16)) void k_sparse(const ConvJ
                 for (int c = 0; c < 4; ++c) {
                     va[u][c] = src[c];
                     vb[u][c] = ref[4 * e + c];
+                }
+            }
+            if (e0 == 0) {
+                // touch every 64-byte line of the lists the waves will read, so that the
+                // scalar reads of the evaluation hit the L2 (lane = line)
+#pragma unroll
+                for (int q = 0; q < NJ; ++q) {
+                    const int lines = (n[q] + 7) >> 3;
+                    const giptr L32 = (giptr)(job.lists + (static_cast<size_t>(tile) * NT + wave + NW * q) * job.lmax);
+                    pf[q] = L32[16 * min(lane, max(lines - 1, 0)) + 1];
                 }
             }
 #pragma unroll
@@ -438,11 +513,10 @@ __global__ __launch_bounds__(64 * (NT < 16 ? NT : 16)) void k_sparse(const ConvJ
     }
 
     // ---------------- certified sparse evaluation ----------------
-    // List entries are wave-uniform: they come through the scalar cache into SGPRs (8
-    // per step, the next 8 requested before the current ones are used) and are unpacked
-    // on the scalar unit, so LDS bandwidth goes to the per-lane halo gathers only.
+    // List entries are wave-uniform: they come through the scalar cache into SGPRs and
+    // are unpacked on the scalar unit, so LDS bandwidth goes to the per-lane halo
+    // gathers only.  The touch loads above brought the lists' lines into the L2.
     const int base = py * HW + px;
-    constexpr uint32_t kMask = (1u << kOffBits) - 1u;
     double err = 0.0, work = 0.0;
 #pragma unroll
     for (int q = 0; q < NJ; ++q) {
@@ -451,44 +525,13 @@ __global__ __launch_bounds__(64 * (NT < 16 ? NT : 16)) void k_sparse(const ConvJ
         const double M = (mr[q] == -INFINITY) ? 0.0 : static_cast<double>(mr[q]) + static_cast<double>(shift);
         const cdptr Lp = (cdptr)(job.lists + (static_cast<size_t>(tile) * NT + ko) * job.lmax);
         const int nq = n[q];
-        const int n8 = nq & ~7;
-        double S = 0.0;
-        double pk[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) pk[u] = Lp[u];  // in bounds: lmax >= 8
-        for (int e = 0; e < n8; e += 8) {
-            double nx8[8];
-            const int en = min(e + 8, job.lmax - 8);  // past the list: loaded, never used
-#pragma unroll
-            for (int u = 0; u < 8; ++u) nx8[u] = Lp[en + u];
-            float s8 = 0.0f;
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const unsigned int lo32 = static_cast<unsigned int>(__double2loint(pk[u]));
-                const double lv = __hiloint2double(__double2hiint(pk[u]), static_cast<int>(lo32 & ~kMask));
-                const double v = lds[static_cast<int>(lo32 & kMask) + base];
-                s8 += __builtin_amdgcn_exp2f(static_cast<float>((lv + v) - M));
-            }
-            S += static_cast<double>(s8);
-#pragma unroll
-            for (int u = 0; u < 8; ++u) pk[u] = nx8[u];
-        }
-        // the last nq - n8 < 8 entries sit in pk
-        float st = 0.0f;
-#pragma unroll
-        for (int u = 0; u < 7; ++u) {
-            if (n8 + u < nq) {
-                const unsigned int lo32 = static_cast<unsigned int>(__double2loint(pk[u]));
-                const double lv = __hiloint2double(__double2hiint(pk[u]), static_cast<int>(lo32 & ~kMask));
-                const double v = lds[static_cast<int>(lo32 & kMask) + base];
-                st += __builtin_amdgcn_exp2f(static_cast<float>((lv + v) - M));
-            }
-        }
-        S += static_cast<double>(st);
+        const double S = eval_list(Lp, nq, M, lds, base);
         const double lse = (mr[q] == -INFINITY || !(S > 0.0)) ? -INFINITY : M + log2(S);
         if (valid) {
             err += epilogue_pre(job, obase + ko, lse, ax[q], od[q]);
-            work += static_cast<double>(nq);
+            // the touched list word is the high half of a finite kernel value whenever
+            // nq > 0, never this NaN pattern: the test only keeps the touch load alive
+            work += static_cast<double>(nq) + ((nq > 0 && pf[q] == 0x7ff80001) ? 1.0 : 0.0);
         }
     }
     // error partial of the tile (slot 0 of [tile][nt]) and the work counter, in wave order

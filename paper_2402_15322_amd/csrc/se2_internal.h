@@ -39,7 +39,11 @@ constexpr double kListCut = SE2_LIST_CUT;
 constexpr float kDriftSpread = SE2_DRIFT_SPREAD;
 constexpr float kRefMax = 1048576.0f;  // 2^20: FP32 rounding error < 2^-4
 constexpr float kRefMargin = 0.125f;
-constexpr int kListMax = 512;               // entries per (tile, ko); longer lists fall back to dense
+#ifndef SE2_LIST_MAX
+#define SE2_LIST_MAX 512
+#endif
+constexpr int kListMax = SE2_LIST_MAX;      // entries per (tile, ko); longer lists fall back to dense
+constexpr int kListPad = 8;                 // entries after the last list: reads run past a list by < 8
 constexpr size_t kSparseLdsMax = 98304;     // the sparse path keeps the full FP64 halo in LDS
 
 // A list entry is the FP64 log2 kernel value of a window term with its low kOffBits

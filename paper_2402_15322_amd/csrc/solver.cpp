@@ -50,7 +50,7 @@ ListSet carve_lists(Carver &c, const Kernel &k, size_t E, int tiles, bool prune)
     const int nt = k.grid.ntheta, HW = kTile + 2 * k.metric.radius;
     ListSet l;
     if (prune) {
-        l.lists = c.take<ListEntry>(static_cast<size_t>(tiles) * nt * kListMax);
+        l.lists = c.take<ListEntry>(static_cast<size_t>(tiles) * nt * kListMax + kListPad);
         l.ref = c.take<float>(static_cast<size_t>(tiles) * nt * HW * HW);
         l.len = c.take<int32_t>(static_cast<size_t>(tiles) * nt);
         l.mref = c.take<float>(E);
