@@ -46,7 +46,7 @@ PEAK_TFLOPS = 78.6
 # a plain 256 MiB copy: x2.0 and x1.0), averaged over the 2004 launches of one bench
 # step; profiles/conv_lse_traffic_lines64x64x16_batch32.md.  Reported only while the
 # kernel sources are the ones measured.
-TRAFFIC = {"sources_sha256": "60c6fc12ab2efdd0dd90b677937bb452477493e8f919e275f92b94d3b9ea1d7e", "bytes_per_launch": 173301312.6,
+TRAFFIC = {"sources_sha256": "868a064b216fab6c5bae269ae55af879949730323dc36202c2d81d30eba35040", "bytes_per_launch": 148100091.7,
            "sources": ("paper_2402_15322_amd/csrc/conv_lse.hip", "paper_2402_15322_amd/csrc/se2_internal.h")}
 
 
