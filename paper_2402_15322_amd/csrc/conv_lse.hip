@@ -619,6 +619,7 @@ __global__ __launch_bounds__(kRbThreads) void k_rebuild(const ConvJob *__restric
         const double M = (mx == -INFINITY) ? 0.0 : static_cast<double>(mx);
 
         // pass 2: sum and membership masks of this wave's pairs
+        const unsigned long long vmask = __builtin_amdgcn_ballot_w64(valid);  // pixels inside the grid
         double S = 0.0;
         for (int r = wave; r < W * W; r += kRbWaves) {
             const int dyi = r / W, dxi = r - dyi * W;
@@ -630,7 +631,10 @@ __global__ __launch_bounds__(kRbThreads) void k_rebuild(const ConvJob *__restric
             for (int kc = 0; kc < NT; ++kc) {
                 const double u = (lds[kc * npix + hb] + Lr[kc]) - M;
                 srow += __builtin_amdgcn_exp2f(static_cast<float>(u));
-                m |= (__ballot(valid && u >= -(kListCut + 1.0)) != 0ull ? 1u : 0u) << kc;
+                // any lane inside the grid: the ballot of the bare compare, masked with
+                // the valid lanes and tested by a select, keeps the mask on the scalar unit
+                const unsigned long long b = __builtin_amdgcn_ballot_w64(u >= -(kListCut + 1.0)) & vmask;
+                m |= (b != 0ull) ? (1u << kc) : 0u;
             }
             if (lane == 0) masks[r] = m;
             S += static_cast<double>(srow);
