@@ -38,33 +38,39 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def load_library(path: str) -> ctypes.CDLL:
+    """Load an oracle build from `path` with its ctypes signatures set.  `lib()` uses
+    it for the normal build; the mutation tests load deliberately broken builds."""
+    L = ctypes.CDLL(path)
+    i, d = ctypes.c_int, ctypes.c_double
+    L.oc_rho2.restype = d
+    L.oc_rho2.argtypes = [d, d, d, d, d, d]
+    L.oc_half_angle.restype = None
+    L.oc_half_angle.argtypes = [d, d, d, _D]
+    L.oc_kernel_table.restype = None
+    L.oc_kernel_table.argtypes = [i, i, d, d, d, d, i, _D, _D]
+    for fn in (L.oc_conv_log, L.oc_conv_linear):
+        fn.restype = None
+        fn.argtypes = [i, i, i, i, _D, _D, _D]
+    L.oc_sinkhorn.restype = i
+    L.oc_sinkhorn.argtypes = [i, i, i, i, _D, _D, _D, _D, i, d, _D, _D, _D, _D]
+    L.oc_ibp.restype = i
+    L.oc_ibp.argtypes = [i, i, i, i, _D, i, _D, _D, i, d, _D, _D, _D]
+    L.oc_plan_stats.restype = None
+    L.oc_plan_stats.argtypes = [i, i, i, i, _D, _D, _D, _D, _D, _D, _D, _D]
+    L.oc_plan_l1.restype = d
+    L.oc_plan_l1.argtypes = [i, i, i, i, _D, _D, _D, _D, _D]
+    L.oc_num_threads.restype = i
+    L.oc_num_threads.argtypes = []
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
-        L = ctypes.CDLL(_LIB)
-        i, d = ctypes.c_int, ctypes.c_double
-        L.oc_rho2.restype = d
-        L.oc_rho2.argtypes = [d, d, d, d, d, d]
-        L.oc_half_angle.restype = None
-        L.oc_half_angle.argtypes = [d, d, d, _D]
-        L.oc_kernel_table.restype = None
-        L.oc_kernel_table.argtypes = [i, i, d, d, d, d, i, _D, _D]
-        for fn in (L.oc_conv_log, L.oc_conv_linear):
-            fn.restype = None
-            fn.argtypes = [i, i, i, i, _D, _D, _D]
-        L.oc_sinkhorn.restype = i
-        L.oc_sinkhorn.argtypes = [i, i, i, i, _D, _D, _D, _D, i, d, _D, _D, _D, _D]
-        L.oc_ibp.restype = i
-        L.oc_ibp.argtypes = [i, i, i, i, _D, i, _D, _D, i, d, _D, _D, _D]
-        L.oc_plan_stats.restype = None
-        L.oc_plan_stats.argtypes = [i, i, i, i, _D, _D, _D, _D, _D, _D, _D, _D]
-        L.oc_plan_l1.restype = d
-        L.oc_plan_l1.argtypes = [i, i, i, i, _D, _D, _D, _D, _D]
-        L.oc_num_threads.restype = i
-        L.oc_num_threads.argtypes = []
-        _lib = L
+        _lib = load_library(_LIB)
     return _lib
 
 

@@ -1,0 +1,117 @@
+"""The pins catch plausible mistakes in the oracle.
+
+Each mutant is a copy of `oracle/se2_oracle.c` with one deliberate mistake of the
+kind a careful reader could still make (a dropped term, a wrong sign, a swapped
+index, a transposed operand, a wrong weight).  The copy is built with gcc into a
+temporary directory on the CPU, swapped in for the real oracle build, and the pins
+of `pins.py` are run against it: at least one of them must fail.  The real oracle
+is restored afterwards and still passes every pin (`test_oracle_pins.py`).
+"""
+from __future__ import annotations
+
+import contextlib
+import os
+import subprocess
+
+import pytest
+
+import oracle
+import pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "se2_oracle.c")
+
+# (name, text in se2_oracle.c, replacement, occurrence to replace (0 = first))
+MUTANTS = [
+    # Section 4.3, eq. (logcomp): half-angle coordinates
+    ("b2_sign", "b[1] = -x * s + y * c;", "b[1] = x * s + y * c;", 0),
+    ("full_angle_not_half", "double c = cos(0.5 * t), s = sin(0.5 * t);", "double c = cos(t), s = sin(t);", 0),
+    ("no_small_angle_wrap", "double t = wrap_angle(theta);", "double t = theta;", 0),
+    # Section 4.3, eq. (rhob): weighted sum of squares
+    ("w3_term_dropped", " + (w3 * b[2]) * (w3 * b[2])", "", 0),
+    ("w1_w2_swapped", "(w1 * b[0]) * (w1 * b[0]) + (w2 * b[1]) * (w2 * b[1])",
+     "(w2 * b[0]) * (w2 * b[0]) + (w1 * b[1]) * (w1 * b[1])", 0),
+    # Section 2.3: h^-1 g = (R_{-theta_h}(x_g - x_h), theta_g - theta_h)
+    ("rotation_by_plus_theta", "out[0] = c * dx + s * dy;\n    out[1] = -s * dx + c * dy;",
+     "out[0] = c * dx - s * dy;\n    out[1] = s * dx + c * dy;", 0),
+    ("angle_difference_reversed", "out[2] = tg - th;", "out[2] = th - tg;", 0),
+    ("rotation_by_output_angle", "rel_element((double)dx, (double)dy, th_i, th_o, r);",
+     "rel_element((double)dx, (double)dy, th_o, th_o, r);", 0),
+    # axial grids: the smaller of the two lifts
+    ("axial_min_dropped", "if (d2b < d2) d2 = d2b;", "(void)d2b;", 0),
+    # Gibbs kernel K = exp(-rho^2/eps)
+    ("kernel_half_eps", "if (logk) logk[idx] = -d2 / eps;", "if (logk) logk[idx] = -d2 / (2.0 * eps);", 0),
+    # Section 4.2: (K * f)(g) = sum_h K(h^-1 g) f(h) over the window, log form
+    ("conv_dx_dy_transposed", "const double *kr = logk + ((((size_t)(dy + R) * W + (dx + R)) * nt + ko) * nt);",
+     "const double *kr = logk + ((((size_t)(dx + R) * W + (dy + R)) * nt + ko) * nt);", 0),
+    ("conv_offset_sign", "int jy = iy - dy;", "int jy = iy + dy;", 0),
+    # (swapping ko and ki in the table alone is no mistake: negating the offset only flips
+    #  the signs of b1 and b2, so the table is symmetric in (ko, ki) at every offset)
+    ("conv_input_at_output_orientation", "for (int ki = 0; ki < nt; ++ki) t[n++] = kr[ki] + fr[ki];",
+     "for (int ki = 0; ki < nt; ++ki) t[n++] = kr[ki] + fr[ko];", 0),
+    ("conv_window_misses_last_row", "for (int dy = -R; dy <= R; ++dy) {\n                        int jy = iy - dy;",
+     "for (int dy = -R; dy < R; ++dy) {\n                        int jy = iy - dy;", 0),
+    ("lse_shift_lost", "return m + log(s);", "return log(s);", 0),
+    ("linear_conv_missing_exp", "s += exp(kr[ki]) * fr[ki];", "s += kr[ki] * fr[ki];", 0),
+    # Section 4.1: a = mu / K b, b = nu / K^T a
+    ("b_update_uses_mu", "scaling_update(n, lognu, c, psi);", "scaling_update(n, logmu, c, psi);", 0),
+    ("a_update_reads_old_psi", "oc_conv_log(nx, ny, nt, R, logk, psi, c);\n        scaling_update(n, logmu, c, phi_next);",
+     "oc_conv_log(nx, ny, nt, R, logk, phi, c);\n        scaling_update(n, logmu, c, phi_next);", 0),
+    ("marginal_gap_unweighted", "e += exp(logmu[i]) * fabs(expm1(p_old[i] - p_new[i]));",
+     "e += fabs(expm1(p_old[i] - p_new[i]));", 0),
+    # Appendix A: barycenter = prod_i d_i^lambda_i, v_i <- v_i * bar / d_i
+    ("ibp_equal_weights", "logbar[i] += lambdas[m] * ld[n * m + i];", "logbar[i] += ld[n * m + i] / nmeas;", 0),
+    ("ibp_v_update_sign", "else lv[n * m + i] += logbar[i] - ld[n * m + i];",
+     "else lv[n * m + i] += ld[n * m + i] - logbar[i];", 0),
+    ("ibp_d_without_v", "ld[n * m + i] = (v == -INFINITY || c[i] == -INFINITY) ? -INFINITY : v + c[i];",
+     "ld[n * m + i] = (v == -INFINITY || c[i] == -INFINITY) ? -INFINITY : c[i];", 0),
+    # Section 2.2 / 4.1: cost sum pi rho^2 and the plan's marginals
+    ("cost_with_log_kernel", "if (cost_tab) rc += p * cost_tab[kb + ki];", "if (cost_tab) rc += p * (-logk[kb + ki]);", 0),
+    ("second_marginal_offset_sign", "int iy = jy + dy;", "int iy = jy - dy;", 0),
+]
+
+
+def _mutate(src: str, old: str, new: str, occurrence: int) -> str:
+    pos = -1
+    for _ in range(occurrence + 1):
+        pos = src.find(old, pos + 1)
+        assert pos >= 0, f"mutation site not found: {old!r}"
+    return src[:pos] + new + src[pos + len(old):]
+
+
+@contextlib.contextmanager
+def _oracle_build(path: str):
+    saved = oracle._lib
+    oracle._lib = oracle.load_library(path)
+    try:
+        yield
+    finally:
+        oracle._lib = saved
+
+
+def _first_failing_pin():
+    for pin in pins.ALL_PINS:
+        try:
+            pin()
+        except Exception:          # an assertion, or a mutant that breaks a run outright
+            return pin.__name__
+    return None
+
+
+def test_mutation_sites_are_unique_enough():
+    src = open(SRC).read()
+    for name, old, _, occ in MUTANTS:
+        assert src.count(old) >= occ + 1, name
+
+
+@pytest.mark.parametrize("name,old,new,occ", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_mutant(tmp_path, name, old, new, occ):
+    src = open(SRC).read()
+    mutated = _mutate(src, old, new, occ)
+    assert mutated != src
+    csrc = tmp_path / f"mut_{name}.c"
+    csrc.write_text(mutated)
+    so = tmp_path / f"libmut_{name}.so"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", str(so), str(csrc), "-lm"])
+    with _oracle_build(str(so)):
+        caught = _first_failing_pin()
+    assert caught is not None, f"no pin fails for the mutant {name}"
