@@ -84,6 +84,10 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=4.0, help="queue HBM budget")
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--plain-sample", type=int, default=2, help="one-at-a-time solves timed per grid size")
+    ap.add_argument("--eps-start", type=float, default=1.6,
+                    help="eps-scaling leg: first eps of the schedule (<= 0.1 skips the leg)")
+    ap.add_argument("--eps-factor", type=float, default=0.5)
+    ap.add_argument("--stage-iters", type=int, default=100)
     return ap.parse_args()
 
 
@@ -219,6 +223,30 @@ def main():
         plain_iters += rep["iters"]
     plain_rate = plain_iters / plain_wall if plain_wall > 0 else None
 
+    # eps-scaling leg (outside the timed region): the same batch with the same iteration budget,
+    # stage_iters iterations at each eps of eps_start * factor^s above 0.1, the rest at 0.1
+    eps_leg = None
+    if a.eps_start > EPS:
+        o_s = native.opts(tol=a.tol, max_iter=a.max_iter, check_every=a.check_every, final_check=True,
+                          prune=not a.no_prune, eps_start=a.eps_start, eps_factor=a.eps_factor,
+                          stage_iters=a.stage_iters)
+        qs = native.SolveQueue(hbm_budget_bytes=native.ot_request_bytes(k, o_s) * a.batch + (64 << 20),
+                               max_slots=a.batch)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        ts_ = [qs.submit_ot(k, mus[i], nus[i], o_s, fs[i], gs[i]) for i in range(a.batch)]
+        rs_ = [qs.wait(t) for t in ts_]
+        torch.cuda.synchronize()
+        w_s = time.perf_counter() - s0
+        qs.close()
+        eps_leg = {"schedule": {"eps_start": a.eps_start, "factor": a.eps_factor, "stage_iters": a.stage_iters},
+                   "iters_per_s": sum(r["iters"] for r in rs_) / w_s, "wall_s": w_s,
+                   "coarse_iters_per_solve": rs_[0]["scaling_iters"],
+                   "converged": sum(1 for r in rs_ if r["status"] == native.SE2_CONVERGED),
+                   "marg_l1_mean": float(np.mean([r["marg_l1"] for r in rs_])),
+                   "marg_l1_f64_mean": float(np.mean([r["marg_l1_f64"] for r in rs_])),
+                   "plain_marg_l1_mean": float(np.mean([r["marg_l1"] for r in all_r]))}
+
     conv_meas = None if a.no_conv else conv_measurements(native, torch, a.batch, a.conv_reps)
 
     cpu = None
@@ -258,6 +286,7 @@ def main():
                      "window_terms_per_launch": kt["terms"] / launches,
                      "slots_per_term": {"dense": SLOTS_DENSE, "sparse": SLOTS_SPARSE}},
         "cpu_baseline": cpu,
+        "eps_scaling": eps_leg,
         "se2_conv": {"bound": "mfma", "peak_bf16_tflops": PEAK_BF16_TFLOPS, "peak_f32_tflops": PEAK_F32_TFLOPS,
                      "flops": "2 * batch * nx * ny * ntheta^2 * window", "launches": conv_meas},
     }

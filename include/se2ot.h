@@ -86,12 +86,28 @@ typedef struct {
     int32_t final_check;  /* 1: recompute the final marginal error with an FP64 convolution */
     int32_t prune;        /* 1: certified pruning of negligible window entries (results equal the dense
                              sum to 2^-48 relative per skipped entry); 0: every entry, every time */
-    const double *init_g; /* device, may be NULL: warm start g/eps-scaled potential, natural log units */
+    const double *init_g; /* device, may be NULL: warm start log b = g/eps (natural log units) at the
+                             first eps of the schedule */
+    /* eps-scaling (an outer loop around the scaling iterations; not in the paper, it is the
+     * published warm-start scheme of Schmitzer, "Stabilized sparse scaling algorithms for
+     * entropy regularized transport problems", SIAM J. Sci. Comput. 2019).  With
+     * eps_start > eps the solve first runs stage_iters iterations at each of the coarser
+     * values eps_start, eps_start*eps_factor, eps_start*eps_factor^2, ... that lie above
+     * eps (at most 32 of them), then continues at eps.  Between stages the scalings are
+     * carried over in absolute units (g kept, so log b is multiplied by eps_old/eps_new)
+     * and the next a-update is taken with the new kernel.  Iterations of every stage count
+     * towards max_iter, which must exceed the coarse ones; the stopping test applies at eps
+     * only.  eps_start <= eps (e.g. 0) switches the scheme off and the other two fields are
+     * ignored.  Kernels at the coarser values are built once per kernel handle and kept
+     * with it. */
+    double eps_start;
+    double eps_factor;    /* in (0, 1) */
+    int32_t stage_iters;  /* >= 1 */
 } se2_opts_t;
 
 typedef struct {
     int32_t status;     /* SE2_CONVERGED, SE2_MAX_ITER */
-    int32_t iters;      /* iterations done by the returned iterate */
+    int32_t iters;      /* iterations done by the returned iterate (every eps stage) */
     double marg_l1;     /* L1 error of the non-exact marginal(s) of the returned iterate */
     double marg_l1_f64; /* same, from an FP64 convolution (final_check = 1), else -1 */
     double cost;        /* sum pi * rho_b^2 (OT) or sum_i lambda_i <pi_i, rho_b^2> (barycenter) */
@@ -101,7 +117,7 @@ typedef struct {
     double terms_dense;  /* in-grid window terms evaluated by dense convolution visits */
     double terms_sparse; /* list entries evaluated by certified sparse visits (per output) */
     int32_t convs;      /* group convolutions applied */
-    int32_t reserved;
+    int32_t scaling_iters; /* iterations run at coarser eps (eps-scaling), included in iters */
 } se2_report_t;
 
 typedef struct se2_kernel_s *se2_kernel_t; /* library-owned, immutable, usable from any thread */

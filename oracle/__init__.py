@@ -55,7 +55,7 @@ def load_library(path: str) -> ctypes.CDLL:
     L.oc_sinkhorn.restype = i
     L.oc_sinkhorn.argtypes = [i, i, i, i, _D, _D, _D, _D, i, d, _D, _D, _D, _D]
     L.oc_ibp.restype = i
-    L.oc_ibp.argtypes = [i, i, i, i, _D, i, _D, _D, i, d, _D, _D, _D]
+    L.oc_ibp.argtypes = [i, i, i, i, _D, i, _D, _D, i, d, _D, _D, _D, _D, _D]
     L.oc_plan_stats.restype = None
     L.oc_plan_stats.argtypes = [i, i, i, i, _D, _D, _D, _D, _D, _D, _D, _D]
     L.oc_plan_l1.restype = d
@@ -180,8 +180,10 @@ def sinkhorn(logk: np.ndarray, mu: np.ndarray, nu: np.ndarray, max_iter: int, to
     return phi, psi, it, err.value, hist[:it]
 
 
-def ibp(logk: np.ndarray, mus: Sequence[np.ndarray], lambdas: Sequence[float], max_iter: int, tol: float):
-    """Log-domain IBP barycenter.  Returns (bary, iters, err, err_hist)."""
+def ibp(logk: np.ndarray, mus: Sequence[np.ndarray], lambdas: Sequence[float], max_iter: int, tol: float,
+        lv_init: Optional[np.ndarray] = None, return_lv: bool = False):
+    """Log-domain IBP barycenter.  Returns (bary, iters, err, err_hist), plus the log v_i of the
+    returned iterate ([n][ny][nx][nt]) when return_lv; lv_init starts them (default 0)."""
     ny, nx, nt = mus[0].shape
     R = (logk.shape[0] - 1) // 2
     lm = np.ascontiguousarray(np.stack([safe_log(m) for m in mus]))
@@ -189,11 +191,65 @@ def ibp(logk: np.ndarray, mus: Sequence[np.ndarray], lambdas: Sequence[float], m
     logbar = np.zeros_like(mus[0])
     hist = np.zeros(max(max_iter, 1))
     err = ctypes.c_double(0.0)
+    lv_out = np.zeros_like(lm)
+    lv0 = None if lv_init is None else np.ascontiguousarray(lv_init, dtype=np.float64).reshape(lm.shape)
     it = lib().oc_ibp(nx, ny, nt, R, _p(np.ascontiguousarray(logk)), len(mus), _p(lm), _p(lam),
-                      max_iter, tol, _p(logbar), _p(hist), ctypes.byref(err))
+                      max_iter, tol, _p(logbar), _p(hist), ctypes.byref(err), _p(lv0), _p(lv_out))
     if it < 0:
         raise ValueError("oracle ibp failed")
+    if return_lv:
+        return np.exp(logbar), it, err.value, hist[:it], lv_out
     return np.exp(logbar), it, err.value, hist[:it]
+
+
+# --------------------------------------------------------------------------
+# eps-scaling: not in the paper.  The published warm-start scheme of Schmitzer,
+# "Stabilized sparse scaling algorithms for entropy regularized transport problems"
+# (SIAM J. Sci. Comput. 2019, Section 3.2): solve at a decreasing sequence of eps,
+# each stage started from the previous stage's dual potentials in absolute units
+# (g = eps log b kept, so log b is multiplied by eps_old / eps_new).
+# --------------------------------------------------------------------------
+
+def eps_schedule(eps: float, eps_start: float, factor: float):
+    """eps_start * factor^s for every such value above eps, then eps (only eps when eps_start <= eps)."""
+    if not eps_start > eps:
+        return [eps]
+    out = []
+    e = eps_start
+    while e > eps * (1.0 + 1e-12):
+        out.append(e)
+        e *= factor
+    return out + [eps]
+
+
+def sinkhorn_eps_scaling(kernel_at, eps: float, mu: np.ndarray, nu: np.ndarray, eps_start: float,
+                         factor: float, stage_iters: int, max_iter: int, tol: float):
+    """Sinkhorn with eps-scaling: stage_iters iterations at each coarser eps of the schedule, then
+    at eps up to max_iter iterations in all (tol applies at eps only).  kernel_at(e) returns the
+    log-kernel table at e.  Returns (phi, psi, iters, err, err_hist) as sinkhorn(), at eps."""
+    sched = eps_schedule(eps, eps_start, factor)
+    psi = None
+    for s, e in enumerate(sched[:-1]):
+        init = None if psi is None else psi * (sched[s - 1] / e)
+        _, psi, _, _, _ = sinkhorn(kernel_at(e), mu, nu, stage_iters, -1.0, init)
+    coarse = (len(sched) - 1) * stage_iters
+    init = None if psi is None else psi * (sched[-2] / eps)
+    phi, psi, it, err, hist = sinkhorn(kernel_at(eps), mu, nu, max_iter - coarse, tol, init)
+    return phi, psi, it + coarse, err, hist
+
+
+def ibp_eps_scaling(kernel_at, eps: float, mus: Sequence[np.ndarray], lambdas: Sequence[float], eps_start: float,
+                    factor: float, stage_iters: int, max_iter: int, tol: float):
+    """IBP with eps-scaling (the log v_i carried over as psi above).  Returns (bary, iters, err, err_hist)."""
+    sched = eps_schedule(eps, eps_start, factor)
+    lv = None
+    for s, e in enumerate(sched[:-1]):
+        init = None if lv is None else lv * (sched[s - 1] / e)
+        _, _, _, _, lv = ibp(kernel_at(e), mus, lambdas, stage_iters, -1.0, init, return_lv=True)
+    coarse = (len(sched) - 1) * stage_iters
+    init = None if lv is None else lv * (sched[-2] / eps)
+    bar, it, err, hist = ibp(kernel_at(eps), mus, lambdas, max_iter - coarse, tol, init)
+    return bar, it + coarse, err, hist
 
 
 def plan_stats(logk: np.ndarray, cost_tab: np.ndarray, phi: np.ndarray, psi: np.ndarray):

@@ -245,12 +245,14 @@ int oc_sinkhorn(int nx, int ny, int nt, int R, const double *logk,
  * marginal error of iterate j (the barycenter side is exact after the v-update),
  * read off the next w-update.  Stops at the first j with err_j <= tol or at
  * j = max_iter.  logbar receives log of iterate j's barycenter.
- * logmus: the nmeas log-measures back to back.  Returns the iteration count, or -1
- * when max_iter < 1 or memory runs out.
+ * logmus: the nmeas log-measures back to back.  lv_init (may be NULL: all zero, v = 1
+ * as in Appendix A) starts the lv_i; lv_out (may be NULL) receives the lv_i of iterate j.
+ * Returns the iteration count, or -1 when max_iter < 1 or memory runs out.
  */
 int oc_ibp(int nx, int ny, int nt, int R, const double *logk, int nmeas,
            const double *logmus, const double *lambdas, int max_iter, double tol,
-           double *logbar, double *err_hist, double *err_out)
+           double *logbar, double *err_hist, double *err_out,
+           const double *lv_init, double *lv_out)
 {
     size_t n = (size_t)nx * ny * nt;
     if (max_iter < 1) return -1;
@@ -263,7 +265,7 @@ int oc_ibp(int nx, int ny, int nt, int R, const double *logk, int nmeas,
         free(lv); free(lw); free(ld); free(c); free(lw_new);
         return -1;
     }
-    for (size_t i = 0; i < n * nmeas; ++i) { lv[i] = 0.0; lw[i] = 0.0; }
+    for (size_t i = 0; i < n * nmeas; ++i) { lv[i] = lv_init ? lv_init[i] : 0.0; lw[i] = 0.0; }
     int j = 0;
     double err = INFINITY;
     for (int it = 1; it <= max_iter + 1; ++it) {
@@ -307,6 +309,7 @@ int oc_ibp(int nx, int ny, int nt, int R, const double *logk, int nmeas,
         j = it;
     }
     if (err_out) *err_out = err;
+    if (lv_out) memcpy(lv_out, lv, sizeof(double) * n * nmeas);
     free(lv); free(lw); free(ld); free(c); free(lw_new);
     return j;
 }

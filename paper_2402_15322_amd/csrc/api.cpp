@@ -5,6 +5,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "solver.h"
 
@@ -33,12 +34,59 @@ bool valid_metric(const se2_metric_t *m) {
            m->w1 > 0 && m->w2 > 0 && m->w3 > 0 && m->eps > 0 && m->radius >= 0 && m->radius <= kMaxRadius;
 }
 
-bool valid_opts(const se2_opts_t *o) {
-    return o && o->max_iter >= 1 && o->check_every >= 1 && (o->prec == SE2_F32 || o->prec == SE2_F64) &&
-           !std::isnan(o->tol_marg_l1);
+bool valid_opts(const se2_opts_t *o, double eps) {
+    if (!(o && o->max_iter >= 1 && o->check_every >= 1 && (o->prec == SE2_F32 || o->prec == SE2_F64) &&
+          !std::isnan(o->tol_marg_l1) && !std::isnan(o->eps_start)))
+        return false;
+    std::vector<double> sched;
+    return eps_schedule(*o, eps, sched) == SE2_OK;
 }
 
 }  // namespace
+
+void kernel_free(Kernel *k) {
+    if (!k) return;
+    for (auto &e : k->scaled) kernel_free(e.second);
+    (void)hipFree(k->d_L64);
+    (void)hipFree(k->d_L32);
+    (void)hipFree(k->d_cost);
+    (void)hipFree(k->d_K32);
+    (void)hipFree(k->d_Kbf16);
+    (void)hipFree(k->d_K64);
+    (void)hipFree(k->d_Bpack);
+    delete k;
+}
+
+int kernel_at_eps(const Kernel &base, double eps, const Kernel **out) {
+    if (eps == base.metric.eps) {
+        *out = &base;
+        return SE2_OK;
+    }
+    std::lock_guard<std::mutex> lk(base.scaled_mu);
+    for (auto &e : base.scaled)
+        if (e.first == eps) {
+            *out = e.second;
+            return SE2_OK;
+        }
+    Kernel *k = new (std::nothrow) Kernel();
+    if (!k) return SE2_ENOMEM;
+    k->grid = base.grid;
+    k->metric = base.metric;
+    k->metric.eps = eps;
+    k->device = base.device;
+    int dev = 0;
+    SE2_HIP(hipGetDevice(&dev));
+    if (dev != base.device) SE2_HIP(hipSetDevice(base.device));
+    const int rc = build_tables(*k);
+    if (dev != base.device) SE2_HIP(hipSetDevice(dev));
+    if (rc) {
+        kernel_free(k);
+        return rc;
+    }
+    base.scaled.emplace_back(eps, k);
+    *out = k;
+    return SE2_OK;
+}
 
 // Device-side FP64 validation of a probability vector: finite, >= 0, |sum - 1| <= tol.
 int validate_measure(const double *m, size_t n, double tol, hipStream_t st) {
@@ -119,14 +167,7 @@ int se2_kernel_build(const se2_grid_t *grid, const se2_metric_t *metric, se2_ker
 int se2_kernel_destroy(se2_kernel_t h) {
     Kernel *k = reinterpret_cast<Kernel *>(h);
     if (!k) return SE2_EINVAL;
-    (void)hipFree(k->d_L64);
-    (void)hipFree(k->d_L32);
-    (void)hipFree(k->d_cost);
-    (void)hipFree(k->d_K32);
-    (void)hipFree(k->d_Kbf16);
-    (void)hipFree(k->d_K64);
-    (void)hipFree(k->d_Bpack);
-    delete k;
+    kernel_free(k);
     return SE2_OK;
 }
 
@@ -217,7 +258,7 @@ int se2_conv_log(se2_kernel_t h, se2_prec_t prec, const double *in, double *out,
 int se2_sinkhorn(se2_kernel_t h, const double *mu, const double *nu, const se2_opts_t *opts, double *f_out,
                  double *g_out, se2_report_t *report, se2_stream_t stream) {
     const Kernel *k = reinterpret_cast<const Kernel *>(h);
-    if (!k || !mu || !nu || !valid_opts(opts)) return SE2_EINVAL;
+    if (!k || !mu || !nu || !valid_opts(opts, k->metric.eps)) return SE2_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const double t0 = now_seconds();
     const size_t E = static_cast<size_t>(k->grid.nx) * k->grid.ny * k->grid.ntheta;
@@ -230,6 +271,7 @@ int se2_sinkhorn(se2_kernel_t h, const double *mu, const double *nu, const se2_o
     s.opts = *opts;
     s.n = 1;
     s.t_start = t0;
+    if ((rc = plan_stages(s, *k))) return rc;
     DeviceBlock mem;
     mem.st = st;
     const size_t bytes = solve_bytes(SE2_REQ_OT, *k, 1, prune_wanted(*opts));
@@ -252,7 +294,7 @@ int se2_sinkhorn(se2_kernel_t h, const double *mu, const double *nu, const se2_o
                 g_last_error = "non-finite marginal error";
                 return SE2_ENUMERIC;
             }
-            if (opts->tol_marg_l1 >= 0 && errs[0] <= opts->tol_marg_l1) {
+            if (final_stage(s) && opts->tol_marg_l1 >= 0 && errs[0] <= opts->tol_marg_l1) {
                 s.done = true;
                 s.status = SE2_CONVERGED;
             } else if (last) {
@@ -262,6 +304,7 @@ int se2_sinkhorn(se2_kernel_t h, const double *mu, const double *nu, const se2_o
                 s.cur ^= 1;
             }
         }
+        if (!s.done && (rc = advance_stages(eng, one, st))) return rc;
     }
     std::vector<FinishReq> fin(1);
     fin[0].s = &s;
@@ -275,7 +318,8 @@ int se2_sinkhorn(se2_kernel_t h, const double *mu, const double *nu, const se2_o
 int se2_barycenter(se2_kernel_t h, int32_t n, const double *const *mus, const double *lambdas,
                    const se2_opts_t *opts, double *bary_out, se2_report_t *report, se2_stream_t stream) {
     const Kernel *k = reinterpret_cast<const Kernel *>(h);
-    if (!k || n < 1 || n > 16 || !mus || !lambdas || !bary_out || !valid_opts(opts)) return SE2_EINVAL;
+    if (!k || n < 1 || n > 16 || !mus || !lambdas || !bary_out || !valid_opts(opts, k->metric.eps))
+        return SE2_EINVAL;
     double lsum = 0.0;
     for (int i = 0; i < n; ++i) {
         if (!(lambdas[i] >= 0.0) || !std::isfinite(lambdas[i]) || !mus[i]) return SE2_EINVAL;
@@ -302,6 +346,7 @@ int se2_barycenter(se2_kernel_t h, int32_t n, const double *const *mus, const do
     s.n = static_cast<int>(act.size());
     s.lam = lam;
     s.t_start = t0;
+    if ((rc = plan_stages(s, *k))) return rc;
     DeviceBlock mem;
     mem.st = st;
     SE2_HIP(hipMallocAsync(&mem.p, solve_bytes(SE2_REQ_BARYCENTER, *k, s.n, prune_wanted(*opts)), st));
@@ -323,7 +368,7 @@ int se2_barycenter(se2_kernel_t h, int32_t n, const double *const *mus, const do
                 g_last_error = "non-finite marginal error";
                 return SE2_ENUMERIC;
             }
-            if (opts->tol_marg_l1 >= 0 && errs[0] <= opts->tol_marg_l1) {
+            if (final_stage(s) && opts->tol_marg_l1 >= 0 && errs[0] <= opts->tol_marg_l1) {
                 s.done = true;
                 s.status = SE2_CONVERGED;
             } else if (last) {
@@ -331,6 +376,7 @@ int se2_barycenter(se2_kernel_t h, int32_t n, const double *const *mus, const do
                 s.status = SE2_MAX_ITER;
             }
         }
+        if (!s.done && (rc = advance_stages(eng, one, st))) return rc;
     }
     std::vector<FinishReq> fin(1);
     fin[0].s = &s;

@@ -27,8 +27,8 @@ __device__ __forceinline__ double block_tree_sum(double v, double *sh) {
     return r;
 }
 
-__global__ __launch_bounds__(kThreads) void k_scale(const double *__restrict__ in, double *__restrict__ out, size_t n,
-                                                    double mul) {
+// in == out allowed (each element is read and written by one thread)
+__global__ __launch_bounds__(kThreads) void k_scale(const double *in, double *out, size_t n, double mul) {
     for (size_t i = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x; i < n;
          i += static_cast<size_t>(gridDim.x) * kThreads)
         out[i] = in[i] * mul;

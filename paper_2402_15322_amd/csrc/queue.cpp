@@ -150,6 +150,8 @@ int admit_one(se2_queue_s *Q, Req *q) {
     s.opts = q->r.opts;
     s.opts.init_g = nullptr;
     s.t_start = now_seconds();
+    int rc = plan_stages(s, *k);  // the stage kernels were built at submit: found in the cache
+    if (rc) return rc;
     char *p = static_cast<char *>(q->mem);
     const int nin = q->r.kind == SE2_REQ_OT ? 2 : static_cast<int>(q->mus_all.size());
     for (int i = 0; i < nin; ++i) {
@@ -159,7 +161,6 @@ int admit_one(se2_queue_s *Q, Req *q) {
         q->inputs.push_back(dst);
     }
     char *solve_mem = p + static_cast<size_t>(nin) * in_bytes;
-    int rc;
     for (int i = 0; i < nin; ++i)
         if ((rc = validate_measure(q->inputs[i], E, 1e-9, Q->st))) return rc;
     if (q->r.kind == SE2_REQ_OT) {
@@ -312,7 +313,7 @@ void worker_main(se2_queue_s *Q) {
             if (!std::isfinite(errs[i])) {
                 q->rc = SE2_ENUMERIC;
                 finished.push_back(q);
-            } else if (s.opts.tol_marg_l1 >= 0 && errs[i] <= s.opts.tol_marg_l1) {
+            } else if (final_stage(s) && s.opts.tol_marg_l1 >= 0 && errs[i] <= s.opts.tol_marg_l1) {
                 s.status = SE2_CONVERGED;
                 finished.push_back(q);
             } else if (s.iter >= s.opts.max_iter) {
@@ -321,6 +322,22 @@ void worker_main(se2_queue_s *Q) {
             } else if (s.kind == SE2_REQ_OT) {
                 s.cur ^= 1;
             }
+        }
+        if (rc == SE2_OK) {
+            // eps-scaling: solves whose coarse stage has ended move to the next eps
+            std::vector<Req *> going;
+            std::vector<Solve *> going_s;
+            for (Req *q : run)
+                if (std::find(finished.begin(), finished.end(), q) == finished.end()) {
+                    going.push_back(q);
+                    going_s.push_back(&q->s);
+                }
+            const int rc2 = advance_stages(Q->eng, going_s, Q->st);
+            if (rc2)
+                for (Req *q : going) {
+                    q->rc = rc2;
+                    finished.push_back(q);
+                }
         }
         if (check) {
             std::lock_guard<std::mutex> lk(Q->mu);
@@ -387,7 +404,20 @@ int se2_request_bytes(const se2_request_t *req, size_t *bytes) {
 int se2_solve_queue_submit(se2_queue_t Q, const se2_request_t *req, uint64_t *ticket) {
     if (!Q || !req || !ticket || !req->kernel) return SE2_EINVAL;
     const se2_opts_t &o = req->opts;
-    if (o.max_iter < 1 || o.check_every < 1 || std::isnan(o.tol_marg_l1)) return SE2_EINVAL;
+    if (o.max_iter < 1 || o.check_every < 1 || std::isnan(o.tol_marg_l1) || std::isnan(o.eps_start) ||
+        (o.prec != SE2_F32 && o.prec != SE2_F64))
+        return SE2_EINVAL;
+    {
+        // build the kernels of an eps-scaling schedule here, so admission only looks them up
+        const Kernel &base = *reinterpret_cast<const Kernel *>(req->kernel);
+        std::vector<double> sched;
+        int rc = eps_schedule(o, base.metric.eps, sched);
+        if (rc) return rc;
+        for (double e : sched) {
+            const Kernel *kk = nullptr;
+            if ((rc = kernel_at_eps(base, e, &kk))) return rc;
+        }
+    }
     auto q = std::make_unique<Req>();
     q->r = *req;
     q->r.opts.init_g = nullptr;

@@ -5,7 +5,10 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/se2ot.h"
@@ -118,7 +121,16 @@ struct Kernel {
     uint16_t *d_Bpack = nullptr; // bfloat16 kernel packed in MFMA B-operand order
     int nonzero_bf16 = 0;       // window offsets with any nonzero bfloat16 entry
     int device = 0;
+    // eps-scaling: kernels of the same grid, weights and window at coarser eps, built on
+    // first use and owned by this handle (the handle stays immutable for its callers)
+    mutable std::mutex scaled_mu;
+    mutable std::vector<std::pair<double, Kernel *>> scaled;
 };
+
+// The kernel of `base`'s grid, weights and window at `eps` (base itself when eps equals
+// its own), built on first use and kept with `base`; thread-safe.
+int kernel_at_eps(const Kernel &base, double eps, const Kernel **out);
+void kernel_free(Kernel *k);
 
 // kernel_table.cpp
 int build_tables(Kernel &k);

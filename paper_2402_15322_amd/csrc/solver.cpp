@@ -155,6 +155,64 @@ int solve_reset_lists(Solve &s, hipStream_t st) {
     return rc;
 }
 
+int eps_schedule(const se2_opts_t &o, double eps, std::vector<double> &out) {
+    out.clear();
+    if (!(o.eps_start > eps)) {
+        out.push_back(eps);
+        return SE2_OK;
+    }
+    if (!std::isfinite(o.eps_start) || !(o.eps_factor > 0.0 && o.eps_factor < 1.0) || o.stage_iters < 1)
+        return SE2_EINVAL;
+    for (double e = o.eps_start; e > eps * (1.0 + 1e-12); e *= o.eps_factor) {
+        if (out.size() >= 32) return SE2_EINVAL;
+        out.push_back(e);
+    }
+    if (static_cast<long long>(out.size()) * o.stage_iters >= o.max_iter) return SE2_EINVAL;
+    out.push_back(eps);
+    return SE2_OK;
+}
+
+int plan_stages(Solve &s, const Kernel &base) {
+    int rc = eps_schedule(s.opts, base.metric.eps, s.stage_eps);
+    if (rc) return rc;
+    s.stage_k.assign(s.stage_eps.size(), nullptr);
+    for (size_t i = 0; i < s.stage_eps.size(); ++i)
+        if ((rc = kernel_at_eps(base, s.stage_eps[i], &s.stage_k[i]))) return rc;
+    s.stage = 0;
+    s.scaling_iters = 0;
+    s.k = s.stage_k[0];
+    return SE2_OK;
+}
+
+namespace {
+int drop_lists(const ListSet &l, const Solve &s, hipStream_t st) {
+    return l.len ? launch_fill_i32(l.len, static_cast<size_t>(s.tiles) * s.k->grid.ntheta, -1, st) : SE2_OK;
+}
+}  // namespace
+
+int advance_stages(Engine &eng, const std::vector<Solve *> &solves, hipStream_t st) {
+    std::vector<Solve *> moved;
+    int rc;
+    for (Solve *s : solves) {
+        if (s->done || final_stage(*s) || s->iter < (s->stage + 1) * s->opts.stage_iters) continue;
+        const double r = s->stage_eps[s->stage] / s->stage_eps[s->stage + 1];
+        if (s->kind == SE2_REQ_OT) {
+            if ((rc = launch_scale(s->psi, s->psi, s->E, r, st))) return rc;
+            if ((rc = drop_lists(s->ls_phi, *s, st)) || (rc = drop_lists(s->ls_psi, *s, st))) return rc;
+        } else {
+            for (int i = 0; i < s->n; ++i) {
+                if ((rc = launch_scale(s->lv[i], s->lv[i], s->E, r, st))) return rc;
+                if ((rc = drop_lists(s->ls_v[i], *s, st)) || (rc = drop_lists(s->ls_w[i], *s, st))) return rc;
+            }
+        }
+        s->stage += 1;
+        s->k = s->stage_k[s->stage];
+        s->scaling_iters = s->iter;
+        moved.push_back(s);
+    }
+    return moved.empty() ? SE2_OK : eng.init_first_halfstep(moved, st);
+}
+
 int solve_setup_ot(Solve &s, const double *mu, const double *nu, const double *init_g, hipStream_t st) {
     s.mu_lin = mu;
     s.nu_lin = nu;
@@ -689,6 +747,7 @@ int finish_solves(Engine &eng, std::vector<FinishReq> &reqs, hipStream_t st) {
         r.marg_l1 = s.last_err;
         r.marg_l1_f64 = -1.0;
         r.convs = s.convs;
+        r.scaling_iters = s.scaling_iters;
         if (s.kind == SE2_REQ_OT) {
             r.cost = e[2];
             r.mass = e[3];

@@ -46,6 +46,11 @@ struct Solve {
     double last_err = -1.0;
     int convs = 0;
     double t_start = 0.0;
+    // eps-scaling: the kernels of the stages (coarser eps first, the requested eps last)
+    std::vector<double> stage_eps;
+    std::vector<const Kernel *> stage_k;
+    int stage = 0;
+    int scaling_iters = 0;           // iterations run before the last stage began
     // memory
     void *block = nullptr;           // single allocation holding every buffer
     size_t bytes = 0;
@@ -69,6 +74,15 @@ void solve_bind(Solve &s, void *mem);
 int solve_reset_lists(Solve &s, hipStream_t st);
 int solve_setup_ot(Solve &s, const double *mu, const double *nu, const double *init_g_natural, hipStream_t st);
 int solve_setup_bary(Solve &s, const std::vector<const double *> &mus, hipStream_t st);
+
+// eps-scaling schedule of `o` for a kernel at `eps`: eps_start * factor^s while above eps,
+// then eps itself (only eps when the scheme is off).  SE2_EINVAL for a bad schedule (factor
+// outside (0, 1), stage_iters < 1, more than 32 coarse stages, coarse iterations >= max_iter).
+int eps_schedule(const se2_opts_t &o, double eps, std::vector<double> &out);
+// Resolves the stage kernels of `s` (from s.opts and the kernel of the requested eps) and
+// starts the solve at the first stage.  Call before solve_bind.
+int plan_stages(Solve &s, const Kernel &base);
+inline bool final_stage(const Solve &s) { return s.stage + 1 >= static_cast<int>(s.stage_k.size()); }
 
 // Advances a set of solves (same ntheta or not) by one iteration each, with batched
 // launches: one launch per (stage, ntheta class).  If `check` is true, also reduces
@@ -134,6 +148,13 @@ private:
     std::vector<Pending> pending_;
     std::vector<hipEvent_t> spare_;
 };
+
+// Moves every solve of `solves` whose coarse eps stage has run its iterations to the next
+// eps: its scalings are carried over in absolute units (log b times eps_old / eps_new), its
+// pruning lists are dropped, and the next a-update (w-update) is taken with the new kernel,
+// batched over the solves that move.  A solve's stage boundaries depend on its own iteration
+// count only.  Stream-ordered.
+int advance_stages(Engine &eng, const std::vector<Solve *> &solves, hipStream_t st);
 
 // Finishing of a group of solves: potentials out (natural units), plan cost, mass,
 // dual, optional FP64 re-check of the marginal error.  Every solve's GPU work is

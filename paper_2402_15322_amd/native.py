@@ -47,17 +47,18 @@ class Metric(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("tol_marg_l1", ctypes.c_double), ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("final_check", ctypes.c_int32), ("prune", ctypes.c_int32),
-                ("init_g", ctypes.c_void_p)]
+                ("init_g", ctypes.c_void_p), ("eps_start", ctypes.c_double), ("eps_factor", ctypes.c_double),
+                ("stage_iters", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("marg_l1", ctypes.c_double),
                 ("marg_l1_f64", ctypes.c_double), ("cost", ctypes.c_double), ("mass", ctypes.c_double),
                 ("dual", ctypes.c_double), ("seconds", ctypes.c_double), ("terms_dense", ctypes.c_double),
-                ("terms_sparse", ctypes.c_double), ("convs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("terms_sparse", ctypes.c_double), ("convs", ctypes.c_int32), ("scaling_iters", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class Request(ctypes.Structure):
@@ -144,8 +145,11 @@ def _stream(stream) -> Optional[int]:
 
 
 def opts(tol: float = 1e-6, max_iter: int = 1000, check_every: int = 10, prec: int = SE2_F32,
-         final_check: bool = True, prune: bool = True, init_g=None) -> Opts:
-    return Opts(tol, max_iter, check_every, prec, int(final_check), int(prune), _ptr(init_g))
+         final_check: bool = True, prune: bool = True, init_g=None, eps_start: float = 0.0,
+         eps_factor: float = 0.5, stage_iters: int = 0) -> Opts:
+    """se2_opts_t; eps_start > eps turns on eps-scaling (stage_iters iterations per coarser eps)."""
+    return Opts(tol, max_iter, check_every, prec, int(final_check), int(prune), _ptr(init_g), float(eps_start),
+                float(eps_factor), int(stage_iters))
 
 
 def se2_init() -> None:

@@ -350,6 +350,48 @@ def pin_small_eps_matches_linear_program():
         assert c - res.fun <= eps * 2 * math.log(n)
 
 
+# --------------------------------------------------------------------------
+# eps-scaling (not in the paper; Schmitzer 2019): off means plain Sinkhorn; the converged
+# result is the unique minimiser at the final eps whatever the warm start; the carry-over
+# keeps the dual potential g = eps log b, which the theory fixes as the quantity that
+# converges as eps -> 0 (a converged stage at 2 eps is then a much better start at eps
+# than log b carried over as it is, or a cold start)
+# --------------------------------------------------------------------------
+
+def pin_eps_scaling():
+    rng = np.random.default_rng(17)
+    nt, w, R = 8, (1.0, 2.0, 1.0), 2
+    kat = lambda e: oracle.kernel_table(nt, False, w, e, R)[0]
+    assert oracle.eps_schedule(0.1, 3.2, 0.5) == [3.2, 1.6, 0.8, 0.4, 0.2, 0.1]
+    assert oracle.eps_schedule(0.1, 0.1, 0.5) == [0.1] and oracle.eps_schedule(0.1, 0.0, 0.5) == [0.1]
+    mu = _rand_measure(rng, (6, 6, nt))
+    nu = _rand_measure(rng, (6, 6, nt))
+    eps = 0.3
+    a = oracle.sinkhorn_eps_scaling(kat, eps, mu, nu, eps, 0.5, 5, 40, -1.0)
+    b = oracle.sinkhorn(kat(eps), mu, nu, 40, -1.0)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2] == 40
+    phi, psi, it, err, _ = oracle.sinkhorn_eps_scaling(kat, eps, mu, nu, 2.4, 0.5, 30, 5000, 1e-12)
+    phi2, psi2, it2, err2, _ = oracle.sinkhorn(kat(eps), mu, nu, 5000, 1e-12)
+    assert err <= 1e-12 and err2 <= 1e-12 and 90 < it < 5000
+    assert oracle.plan_l1(kat(eps), phi, psi, phi2, psi2) < 1e-10
+    # carry-over from a converged stage at 2 eps, one iteration at eps
+    eps = 0.15
+    _, psi_c, itc, errc, _ = oracle.sinkhorn(kat(2 * eps), mu, nu, 20000, 1e-13)
+    assert errc <= 1e-13
+    e_ok = oracle.sinkhorn_eps_scaling(kat, eps, mu, nu, 2 * eps, 0.5, itc, itc + 1, -1.0)[3]
+    e_logb = oracle.sinkhorn(kat(eps), mu, nu, 1, -1.0, psi_c)[3]
+    e_cold = oracle.sinkhorn(kat(eps), mu, nu, 1, -1.0)[3]
+    assert e_ok < 0.5 * e_logb and e_ok < 0.5 * e_cold, (e_ok, e_logb, e_cold)
+    # IBP: the converged barycenter does not depend on the warm start
+    mus = [_rand_measure(rng, (5, 5, nt)) for _ in range(3)]
+    lam = [0.3, 0.3, 0.4]
+    eps = 0.4
+    b1, it1, e1, _ = oracle.ibp_eps_scaling(kat, eps, mus, lam, 1.6, 0.5, 20, 5000, 1e-12)
+    b2, it2, e2, _ = oracle.ibp(kat(eps), mus, lam, 5000, 1e-12)
+    assert e1 <= 1e-12 and e2 <= 1e-12 and 40 < it1 < 5000
+    assert np.max(np.abs(b1 - b2)) < 1e-10 * np.max(b2)
+
+
 ALL_PINS = [
     pin_rho_closed_forms,
     pin_rho_inverse_symmetry,
@@ -366,4 +408,5 @@ ALL_PINS = [
     pin_barycenter_closed_form,
     pin_dense_sinkhorn_and_ibp,
     pin_small_eps_matches_linear_program,
+    pin_eps_scaling,
 ]

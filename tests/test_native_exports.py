@@ -30,3 +30,31 @@ def test_library_exports_every_declared_symbol():
 def test_binding_names_match_header():
     from paper_2402_15322_amd import native
     assert sorted(native.EXPORTED) == declared_functions()
+
+
+def test_binding_struct_layouts_match_header(tmp_path):
+    """Sizes and field offsets of the ctypes structures equal the C header's (gcc on the host)."""
+    import subprocess
+    from paper_2402_15322_amd import native
+    structs = {"se2_grid_t": native.Grid, "se2_metric_t": native.Metric, "se2_opts_t": native.Opts,
+               "se2_report_t": native.Report, "se2_request_t": native.Request}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-o", str(exe), str(src)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    got = {}
+    for line in out:
+        if line:
+            c, f, v = line.split()
+            got[(c, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
