@@ -137,6 +137,42 @@ def conv_measurements(native, torch, batch: int, reps: int):
     return out
 
 
+PEAK_HBM_GBS = 8000.0
+
+
+def field_measurements(native, torch, reps: int):
+    """Lift and projection (HBM-bound) on the orientation-field workload's grid: 4 fields of
+    256 x 256 pixels, 32 axial orientation bins.  Bytes are the algorithmic ones: the lift
+    reads magnitude and angle and writes ntheta values per pixel; the projection reads
+    ntheta values and writes mass, argmax and angle per pixel."""
+    n, nt, b = 256, 32, 4
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    mag = torch.rand((b, n, n), device="cuda", dtype=torch.float64, generator=g)
+    ang = torch.rand((b, n, n), device="cuda", dtype=torch.float64, generator=g) * math.pi
+    u = torch.empty((b, n, n, nt), device="cuda", dtype=torch.float64)
+    mass = torch.empty((b, n, n), device="cuda", dtype=torch.float64)
+    angle = torch.empty_like(mass)
+    arg = torch.empty((b, n, n), device="cuda", dtype=torch.int32)
+    npix = b * n * n
+    legs = {"lift": (lambda: native.se2_lift_field(nt, True, mag, ang, u), npix * (16 + 8 * nt)),
+            "project": (lambda: native.se2_project(True, u, mass, argmax=arg, angle=angle), npix * (8 * nt + 20))}
+    out = {"shape": f"{b} x {n}x{n}x{nt} axial", "bound": "hbm", "peak_gbs": PEAK_HBM_GBS}
+    for name, (fn, nbytes) in legs.items():
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3 / reps
+        out[name] = {"us": t * 1e6, "bytes": nbytes, "gbs": nbytes / t / 1e9, "frac": nbytes / t / 1e9 / PEAK_HBM_GBS}
+    return out
+
+
 def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -158,7 +194,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if a.conv_only:
-        print(json.dumps({"se2_conv": conv_measurements(native, torch, a.batch, a.conv_reps)}), flush=True)
+        print(json.dumps({"se2_conv": conv_measurements(native, torch, a.batch, a.conv_reps),
+                          "lift_project": field_measurements(native, torch, a.conv_reps)}), flush=True)
         return
     if a.serving:
         print(json.dumps(serving(native, torch, synth, a)), flush=True)
@@ -248,6 +285,7 @@ def main():
                    "plain_marg_l1_mean": float(np.mean([r["marg_l1"] for r in all_r]))}
 
     conv_meas = None if a.no_conv else conv_measurements(native, torch, a.batch, a.conv_reps)
+    field_meas = None if a.no_conv else field_measurements(native, torch, a.conv_reps)
 
     cpu = None
     if not a.no_cpu:
@@ -287,6 +325,7 @@ def main():
                      "slots_per_term": {"dense": SLOTS_DENSE, "sparse": SLOTS_SPARSE}},
         "cpu_baseline": cpu,
         "eps_scaling": eps_leg,
+        "lift_project": field_meas,
         "se2_conv": {"bound": "mfma", "peak_bf16_tflops": PEAK_BF16_TFLOPS, "peak_f32_tflops": PEAK_F32_TFLOPS,
                      "flops": "2 * batch * nx * ny * ntheta^2 * window", "launches": conv_meas},
     }

@@ -191,6 +191,41 @@ int se2_barycenter(se2_kernel_t k, int32_t n, const double *const *mus, const do
                    const se2_opts_t *opts, double *bary_out, se2_report_t *report, se2_stream_t stream);
 
 /*
+ * Lift and projection around the transport path.  Grid arrays as above; images and
+ * fields are [batch][iy][ix].  Stream-ordered, no host synchronisation.
+ *
+ * se2_lift_field -- the orientation-field lift of Section 5.3, eq. (lifting_vector_field):
+ *   out(x, y, theta_k) = mag(x, y) in the orientation bin of angle(x, y), 0 in the others.
+ *   The bin of an angle a is the k nearest to a on the circle of circumference Theta
+ *   (theta_k = k Theta / ntheta; a at a bin edge goes to the upper bin), i.e. the bin
+ *   with circular distance below half a step (the paper's pi/N for Theta = 2 pi).  mag
+ *   (>= 0) and angle (radians, any finite value) are batch * nx * ny doubles; out holds
+ *   batch * nx * ny * ntheta doubles.  Mass is preserved.
+ *
+ * se2_project -- the projection P(U) = integral of U over theta (Section 2.3, eq. (proj)),
+ *   for arrays of mass per grid cell the sum over the orientation bins, and the argmax
+ *   reconstruction of Section 5.3, eq. (reconstruction_vector_field):
+ *     mass(x, y)   = sum_k u(x, y, k) - sum_k u_minus(x, y, k)   (u_minus may be NULL;
+ *                    with both, the difference of projections b_t = P(U+) - P(U-) of
+ *                    Section 5.2, eq. (final));
+ *     argmax(x, y) = the k of the largest u(x, y, k), the lowest such k on ties (may be NULL);
+ *     angle(x, y)  = theta_argmax = argmax * Theta / ntheta (may be NULL).
+ *   The field is v = mass * (cos angle, sin angle).  u, u_minus: batch * nx * ny * ntheta
+ *   doubles; mass, angle: batch * nx * ny doubles; argmax: batch * nx * ny int32.
+ *
+ * se2_split_signed -- step 2 of the image pipeline of Section 5.2: the positive and
+ *   negative parts of a signed array u of n doubles, each normalised to sum 1 (FP64 sums
+ *   in a fixed order): plus = max(u, 0) / sum max(u, 0), minus = max(-u, 0) / sum max(-u, 0);
+ *   a part with zero sum is returned as zeros.  Allocates and frees a small scratch
+ *   stream-ordered (hipMallocAsync / hipFreeAsync on `stream`).
+ */
+int se2_lift_field(const se2_grid_t *grid, const double *mag, const double *angle, double *out, int32_t batch,
+                   se2_stream_t stream);
+int se2_project(const se2_grid_t *grid, const double *u, const double *u_minus, double *mass, int32_t *argmax,
+                double *angle, int32_t batch, se2_stream_t stream);
+int se2_split_signed(const double *u, size_t n, double *plus, double *minus, se2_stream_t stream);
+
+/*
  * Serving queue.  A worker thread owns one stream on the current device.  Requests
  * are admitted in arrival order while the HBM budget and the slot count allow;
  * every admitted solve keeps its potentials resident and all admitted solves

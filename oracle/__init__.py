@@ -203,6 +203,43 @@ def ibp(logk: np.ndarray, mus: Sequence[np.ndarray], lambdas: Sequence[float], m
 
 
 # --------------------------------------------------------------------------
+# Lift and projection around the transport path
+# --------------------------------------------------------------------------
+
+def lift_field(mag: np.ndarray, angle: np.ndarray, nt: int, axial: bool) -> np.ndarray:
+    """Orientation-field lift, Section 5.3 eq. (lifting_vector_field): U(x, y, theta_k) = |v(x, y)|
+    where the circular distance between the field's angle and theta_k is below half a step
+    (pi/N for Theta = 2 pi), else 0.  Reading: the bin of theta_k is the half-open arc
+    [theta_k - step/2, theta_k + step/2), so an angle exactly between two centres belongs to
+    the upper one and every angle has exactly one bin.  mag, angle: [..., ny, nx]."""
+    period = PI if axial else 2 * PI
+    step = period / nt
+    th = step * np.arange(nt)
+    rel = np.mod(angle[..., None] - th + period / 2, period) - period / 2   # psi - theta_k in [-T/2, T/2)
+    take = (rel >= -step / 2) & (rel < step / 2)
+    return np.where(take, mag[..., None], 0.0)
+
+
+def project(u: np.ndarray, u_minus: Optional[np.ndarray] = None):
+    """Projection P(U) = integral over theta (Section 2.3, eq. (proj)) of an array of mass per cell:
+    the sum over the orientation bins (minus that of u_minus: b_t = P(U+) - P(U-), Section 5.2
+    eq. (final)), and the argmax bin of u (the first one on ties) of eq.
+    (reconstruction_vector_field).  Returns (mass, argmax)."""
+    mass = u.sum(axis=-1)
+    if u_minus is not None:
+        mass = mass - u_minus.sum(axis=-1)
+    return mass, np.argmax(u, axis=-1)
+
+
+def split_signed(u: np.ndarray):
+    """Positive and negative parts of a signed score, each normalised to sum 1 (Section 5.2, step 2)."""
+    plus = np.maximum(u, 0.0)
+    minus = np.maximum(-u, 0.0)
+    sp, sn = plus.sum(), minus.sum()
+    return (plus / sp if sp > 0 else plus), (minus / sn if sn > 0 else minus)
+
+
+# --------------------------------------------------------------------------
 # eps-scaling: not in the paper.  The published warm-start scheme of Schmitzer,
 # "Stabilized sparse scaling algorithms for entropy regularized transport problems"
 # (SIAM J. Sci. Comput. 2019, Section 3.2): solve at a decreasing sequence of eps,

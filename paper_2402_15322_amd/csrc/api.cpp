@@ -255,6 +255,34 @@ int se2_conv_log(se2_kernel_t h, se2_prec_t prec, const double *in, double *out,
     return rc;
 }
 
+int se2_lift_field(const se2_grid_t *grid, const double *mag, const double *angle, double *out, int32_t batch,
+                   se2_stream_t stream) {
+    if (!valid_grid(grid) || !mag || !angle || !out || batch < 0) return SE2_EINVAL;
+    const size_t npix = static_cast<size_t>(grid->nx) * grid->ny * static_cast<size_t>(batch);
+    const double period = grid->theta_axial ? M_PI : 2.0 * M_PI;
+    return launch_lift_field(mag, angle, out, npix, grid->ntheta, period, reinterpret_cast<hipStream_t>(stream));
+}
+
+int se2_project(const se2_grid_t *grid, const double *u, const double *u_minus, double *mass, int32_t *argmax,
+                double *angle, int32_t batch, se2_stream_t stream) {
+    if (!valid_grid(grid) || !u || !mass || batch < 0) return SE2_EINVAL;
+    const size_t npix = static_cast<size_t>(grid->nx) * grid->ny * static_cast<size_t>(batch);
+    const double period = grid->theta_axial ? M_PI : 2.0 * M_PI;
+    return launch_project(u, u_minus, npix, grid->ntheta, period, mass, argmax, angle,
+                          reinterpret_cast<hipStream_t>(stream));
+}
+
+int se2_split_signed(const double *u, size_t n, double *plus, double *minus, se2_stream_t stream) {
+    if ((!u || !plus || !minus) && n > 0) return SE2_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    double *scratch = nullptr;
+    SE2_HIP(hipMallocAsync(reinterpret_cast<void **>(&scratch), (2 * static_cast<size_t>(split_blocks(n)) + 2) *
+                                                                    sizeof(double), st));
+    const int rc = launch_split_signed(u, n, plus, minus, scratch, st);
+    SE2_HIP(hipFreeAsync(scratch, st));
+    return rc;
+}
+
 int se2_sinkhorn(se2_kernel_t h, const double *mu, const double *nu, const se2_opts_t *opts, double *f_out,
                  double *g_out, se2_report_t *report, se2_stream_t stream) {
     const Kernel *k = reinterpret_cast<const Kernel *>(h);

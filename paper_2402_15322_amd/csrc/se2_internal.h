@@ -170,6 +170,14 @@ int launch_reduce_fixed(const double *partials, int count, int stride, double *o
 int launch_exp2_out(const double *in2, double *out, size_t n, hipStream_t s);
 int launch_dot_exp(const double *f2, const double *m, size_t n, double *partials, int nblocks, hipStream_t s);
 
+// field.hip: lift and projection (period = Theta of the grid)
+int launch_lift_field(const double *mag, const double *angle, double *out, size_t npix, int nt, double period,
+                      hipStream_t s);
+int launch_project(const double *u, const double *um, size_t npix, int nt, double period, double *mass,
+                   int32_t *argmax, double *ang, hipStream_t s);
+int split_blocks(size_t n);  // the scratch of launch_split_signed holds 2 * split_blocks(n) + 2 doubles
+int launch_split_signed(const double *u, size_t n, double *plus, double *minus, double *scratch, hipStream_t s);
+
 // api.cpp: device-side FP64 check of a probability vector (finite, >= 0, |sum - 1| <= tol); syncs `st`.
 int validate_measure(const double *m, size_t n, double tol, hipStream_t st);
 

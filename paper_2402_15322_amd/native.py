@@ -31,6 +31,7 @@ EXPORTED = [
     "se2_conv", "se2_conv_log", "se2_sinkhorn", "se2_barycenter", "se2_solve_queue_create",
     "se2_request_bytes", "se2_solve_queue_submit", "se2_solve_queue_poll", "se2_solve_queue_wait", "se2_solve_queue_times",
     "se2_solve_queue_stats", "se2_solve_queue_profile", "se2_solve_queue_kernel_time", "se2_solve_queue_destroy",
+    "se2_lift_field", "se2_project", "se2_split_signed",
 ]
 
 
@@ -94,6 +95,9 @@ def load() -> ctypes.CDLL:
             "se2_kernel_info": ([vp, ctypes.POINTER(Grid), ctypes.POINTER(Metric), ctypes.POINTER(i32)], ctypes.c_int),
             "se2_conv": ([vp, ctypes.c_int, vp, vp, i32, vp], ctypes.c_int),
             "se2_conv_log": ([vp, ctypes.c_int, vp, vp, i32, vp], ctypes.c_int),
+            "se2_lift_field": ([ctypes.POINTER(Grid), vp, vp, vp, i32, vp], ctypes.c_int),
+            "se2_project": ([ctypes.POINTER(Grid), vp, vp, vp, vp, vp, i32, vp], ctypes.c_int),
+            "se2_split_signed": ([vp, sz, vp, vp, vp], ctypes.c_int),
             "se2_sinkhorn": ([vp, vp, vp, ctypes.POINTER(Opts), vp, vp, ctypes.POINTER(Report), vp], ctypes.c_int),
             "se2_barycenter": ([vp, i32, vp, vp, ctypes.POINTER(Opts), vp, ctypes.POINTER(Report), vp],
                                ctypes.c_int),
@@ -199,6 +203,32 @@ def se2_conv(k: Kernel, prec: int, x, out, stream=None) -> None:
 def se2_conv_log(k: Kernel, prec: int, x, out, stream=None) -> None:
     batch = x.numel() // (k.shape[0] * k.shape[1] * k.shape[2])
     _check(load().se2_conv_log(k.handle, prec, _ptr(x), _ptr(out), batch, _stream(stream)), "se2_conv_log")
+
+
+def _grid(nx: int, ny: int, nt: int, axial: bool) -> Grid:
+    return Grid(int(nx), int(ny), int(nt), int(bool(axial)))
+
+
+def se2_lift_field(nt: int, axial: bool, mag, angle, out, stream=None) -> None:
+    """mag, angle: [..., ny, nx] float64 device tensors; out: [..., ny, nx, nt]."""
+    ny, nx = mag.shape[-2], mag.shape[-1]
+    batch = mag.numel() // (nx * ny)
+    g = _grid(nx, ny, nt, axial)
+    _check(load().se2_lift_field(ctypes.byref(g), _ptr(mag), _ptr(angle), _ptr(out), batch, _stream(stream)),
+           "se2_lift_field")
+
+
+def se2_project(axial: bool, u, mass, u_minus=None, argmax=None, angle=None, stream=None) -> None:
+    """u (and u_minus): [..., ny, nx, nt] float64; mass, angle: [..., ny, nx] float64; argmax int32."""
+    ny, nx, nt = u.shape[-3], u.shape[-2], u.shape[-1]
+    batch = u.numel() // (nx * ny * nt)
+    g = _grid(nx, ny, nt, axial)
+    _check(load().se2_project(ctypes.byref(g), _ptr(u), _ptr(u_minus), _ptr(mass), _ptr(argmax), _ptr(angle), batch,
+                              _stream(stream)), "se2_project")
+
+
+def se2_split_signed(u, plus, minus, stream=None) -> None:
+    _check(load().se2_split_signed(_ptr(u), u.numel(), _ptr(plus), _ptr(minus), _stream(stream)), "se2_split_signed")
 
 
 def se2_sinkhorn(k: Kernel, mu, nu, o: Opts, f_out=None, g_out=None, stream=None) -> dict:

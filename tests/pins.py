@@ -392,6 +392,52 @@ def pin_eps_scaling():
     assert np.max(np.abs(b1 - b2)) < 1e-10 * np.max(b2)
 
 
+# --------------------------------------------------------------------------
+# Lift and projection (Sections 2.3, 5.2, 5.3): projecting a lifted field returns its
+# magnitude exactly and its angle to within half an orientation step; lifting commutes
+# with the exact 90-degree grid symmetry; a split score recombines to the score
+# --------------------------------------------------------------------------
+
+def pin_lift_and_project():
+    rng = np.random.default_rng(18)
+    for nt, axial in ((8, False), (16, False), (32, True)):
+        period = PI if axial else 2 * PI
+        step = period / nt
+        mag = rng.uniform(0.0, 1.0, (2, 9, 9))
+        ang = rng.uniform(-3 * PI, 3 * PI, (2, 9, 9))
+        U = oracle.lift_field(mag, ang, nt, axial)
+        assert U.shape == (2, 9, 9, nt)
+        assert np.all(np.count_nonzero(U, axis=-1) == (mag > 0))   # exactly one bin per pixel
+        assert abs(U.sum() - mag.sum()) <= 1e-13
+        m, k = oracle.project(U)
+        assert np.array_equal(m, mag)
+        d = np.abs(np.mod(k * step - ang + period / 2, period) - period / 2)
+        assert np.all(d <= step / 2 + 1e-12)
+        # away from the edges the bin is the nearest centre
+        off = rng.uniform(-0.49, 0.49, 20) * step
+        e = oracle.lift_field(np.ones(20), 3 * step + off, nt, axial)
+        assert np.all(e[:, 3] == 1.0) and e.sum() == 20.0
+        # the 90-degree rotation of the grid: pixels rotated and angles turned by a quarter turn
+        f = rng.uniform(0.0, 1.0, (7, 7))
+        a = rng.uniform(0.0, period, (7, 7))
+        rot_f = np.empty_like(f)
+        rot_a = np.empty_like(a)
+        for iy in range(7):
+            for ix in range(7):
+                rot_f[ix, 6 - iy] = f[iy, ix]
+                rot_a[ix, 6 - iy] = a[iy, ix] + PI / 2
+        assert np.array_equal(oracle.lift_field(rot_f, rot_a, nt, axial),
+                              rot90(oracle.lift_field(f, a, nt, axial), axial))
+    # two measures, difference of projections
+    u = rng.normal(0.0, 1.0, (5, 6, 8))
+    plus, minus = oracle.split_signed(u)
+    assert plus.min() >= 0 and minus.min() >= 0 and abs(plus.sum() - 1) < 1e-14 and abs(minus.sum() - 1) < 1e-14
+    sp, sn = np.maximum(u, 0).sum(), np.maximum(-u, 0).sum()
+    assert np.max(np.abs(sp * plus - sn * minus - u)) < 1e-14
+    b, _ = oracle.project(plus, minus)
+    assert np.max(np.abs(b - (plus.sum(-1) - minus.sum(-1)))) < 1e-15
+
+
 ALL_PINS = [
     pin_rho_closed_forms,
     pin_rho_inverse_symmetry,
@@ -409,4 +455,5 @@ ALL_PINS = [
     pin_dense_sinkhorn_and_ibp,
     pin_small_eps_matches_linear_program,
     pin_eps_scaling,
+    pin_lift_and_project,
 ]
