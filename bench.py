@@ -84,6 +84,9 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=4.0, help="queue HBM budget")
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--plain-sample", type=int, default=2, help="one-at-a-time solves timed per grid size")
+    ap.add_argument("--bary-n", type=int, default=6000,
+                    help="class-barycenter leg: measures of 28x28x16 (0 skips the leg)")
+    ap.add_argument("--bary-iters", type=int, default=20)
     ap.add_argument("--eps-start", type=float, default=1.6,
                     help="eps-scaling leg: first eps of the schedule (<= 0.1 skips the leg)")
     ap.add_argument("--eps-factor", type=float, default=0.5)
@@ -173,6 +176,48 @@ def field_measurements(native, torch, reps: int):
     return out
 
 
+def class_barycenter(native, torch, images, iters: int):
+    """Barycenter of a whole class of small images (the paper's MNIST/QuickDraw setting:
+    28 x 28 images, 16 orientations, spatial anisotropy 1.5, ~6000 images per class), here
+    seeded stroke images: w = (1, 1.5, 1), eps = 0.5, 9 x 9 window, equal weights, IBP on the
+    dense engine, through the queue with convolution timing on.  Run at `iters` and at
+    2 * `iters` iterations: the difference is the steady-state cost of `iters` iterations
+    (admission, validation and finishing cancel)."""
+    n = images.shape[0]
+    k = native.Kernel(28, 28, 16, False, (1.0, 1.5, 1.0), 0.5, 4)
+    dev = torch.from_numpy(images).cuda()
+    mus = [dev[i] for i in range(n)]
+    out = torch.empty(images.shape[1:], dtype=torch.float64, device="cuda")
+    runs = []
+    for it in (iters, 2 * iters):
+        o = native.opts(tol=-1.0, max_iter=it, check_every=it, final_check=False, prune=False)
+        q = native.SolveQueue(hbm_budget_bytes=int(n) * (1 << 20) + (1 << 30), max_slots=1)
+        q.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ticket = q.submit_barycenter(k, mus, [1.0 / n] * n, o, out)
+        rep = q.wait(ticket)
+        wall = time.perf_counter() - t0
+        kt = q.kernel_time()
+        q.close()
+        runs.append((wall, kt, rep))
+    (w1, k1, r1), (w2, k2, r2) = runs
+    per_iter = (w2 - w1) / iters
+    conv_s = k2["seconds"] - k1["seconds"]
+    terms = k2["terms"] - k1["terms"]
+    achieved = 2.0 * 8 * terms / conv_s / 1e12 if conv_s > 0 else 0.0
+    return {"workload": f"{n} stroke images 28x28x16, w=(1,1.5,1), eps=0.5, 9x9 window, equal weights",
+            "measures": n, "iters": [r1["iters"], r2["iters"]], "wall_s": [w1, w2],
+            "steady_ms_per_iter": per_iter * 1e3, "steady_iters_per_s": 1.0 / per_iter if per_iter > 0 else None,
+            "convs_per_s": 2.0 * n / per_iter if per_iter > 0 else None,
+            "conv_ms_per_iter": conv_s / iters * 1e3,
+            "avg_conv_launch_us": conv_s / max(1.0, k2["launches"] - k1["launches"]) * 1e6,
+            "lse_terms_per_s": terms / conv_s if conv_s > 0 else None,
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_TFLOPS, "kernel": "dense log-domain convolution (k_conv_lse)"},
+            "marg_l1": r2["marg_l1"], "mass": r2["mass"]}
+
+
 def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -184,6 +229,11 @@ def main():
     import torch
 
     from paper_2402_15322_amd import native, synth
+
+    # inputs of the class-barycenter leg, drawn in forked workers before any GPU work
+    class_images = None
+    if a.bary_n > 0 and not (a.conv_only or a.serving):
+        class_images = synth.stroke_images(a.bary_n, workers=min(16, os.cpu_count() or 1))
 
     torch.cuda.set_device(0)
     native.se2_init()
@@ -284,6 +334,7 @@ def main():
                    "marg_l1_f64_mean": float(np.mean([r["marg_l1_f64"] for r in rs_])),
                    "plain_marg_l1_mean": float(np.mean([r["marg_l1"] for r in all_r]))}
 
+    class_meas = None if class_images is None else class_barycenter(native, torch, class_images, a.bary_iters)
     conv_meas = None if a.no_conv else conv_measurements(native, torch, a.batch, a.conv_reps)
     field_meas = None if a.no_conv else field_measurements(native, torch, a.conv_reps)
 
@@ -326,6 +377,7 @@ def main():
         "cpu_baseline": cpu,
         "eps_scaling": eps_leg,
         "lift_project": field_meas,
+        "class_barycenter": class_meas,
         "se2_conv": {"bound": "mfma", "peak_bf16_tflops": PEAK_BF16_TFLOPS, "peak_f32_tflops": PEAK_F32_TFLOPS,
                      "flops": "2 * batch * nx * ny * ntheta^2 * window", "launches": conv_meas},
     }

@@ -181,7 +181,10 @@ int se2_sinkhorn(se2_kernel_t k, const double *mu, const double *nu, const se2_o
 
 /*
  * se2_barycenter -- entropic Wasserstein barycenter of n measures with weights
- * lambda (Appendix A, iterative Bregman projections), log form.
+ * lambda (Appendix A, iterative Bregman projections), log form.  1 <= n <= 65535: the
+ * convolutions of all measures go out in one batched launch per half-step, and the
+ * product of the d_i^lambda_i is summed in index order within chunks of 64 measures,
+ * then over the chunks in order.
  * mus: HOST array of n device pointers to FP64 probability vectors;
  * lambdas: HOST array of n weights on the simplex (>= 0, |sum - 1| <= 1e-12);
  * bary_out: device FP64 grid array receiving the barycenter.  Measures with
@@ -191,8 +194,9 @@ int se2_barycenter(se2_kernel_t k, int32_t n, const double *const *mus, const do
                    const se2_opts_t *opts, double *bary_out, se2_report_t *report, se2_stream_t stream);
 
 /*
- * Lift and projection around the transport path.  Grid arrays as above; images and
- * fields are [batch][iy][ix].  Stream-ordered, no host synchronisation.
+ * Lift and projection around the transport path.  Grid arrays as above, 16-byte aligned
+ * (SE2_EINVAL otherwise); images and fields are [batch][iy][ix].  Stream-ordered, no host
+ * synchronisation.
  *
  * se2_lift_field -- the orientation-field lift of Section 5.3, eq. (lifting_vector_field):
  *   out(x, y, theta_k) = mag(x, y) in the orientation bin of angle(x, y), 0 in the others.
@@ -238,7 +242,7 @@ int se2_split_signed(const double *u, size_t n, double *plus, double *minus, se2
 
 typedef struct {
     int32_t kind;               /* SE2_REQ_OT or SE2_REQ_BARYCENTER */
-    int32_t n;                  /* barycenter: number of measures (<= 16) */
+    int32_t n;                  /* barycenter: number of measures, 1 ... 65535 */
     se2_kernel_t kernel;        /* must outlive the request */
     const double *mu, *nu;      /* OT: device inputs, copied into slot memory at admission */
     const double *const *mus;   /* barycenter: host array of n device pointers, copied at admission */

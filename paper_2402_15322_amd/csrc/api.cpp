@@ -107,6 +107,36 @@ int validate_measure(const double *m, size_t n, double tol, hipStream_t st) {
     return SE2_OK;
 }
 
+int validate_measures(const std::vector<const double *> &ms, size_t n, double tol, hipStream_t st) {
+    const int m = static_cast<int>(ms.size());
+    if (m == 0) return SE2_OK;
+    if (m == 1) return validate_measure(ms[0], n, tol, st);
+    const size_t nb = static_cast<size_t>(validate_many_blocks(n));
+    const size_t tab_bytes = (m * sizeof(double *) + 255) / 256 * 256;
+    const size_t bytes = tab_bytes + (2 * static_cast<size_t>(m) + 2 * m * nb) * sizeof(double);
+    char *mem = nullptr;
+    SE2_HIP(hipMallocAsync(reinterpret_cast<void **>(&mem), bytes, st));
+    const double **tab = reinterpret_cast<const double **>(mem);
+    double *stats = reinterpret_cast<double *>(mem + tab_bytes);
+    std::vector<double> h(2 * static_cast<size_t>(m));
+    int rc = SE2_OK;
+    if (hipMemcpyAsync(tab, ms.data(), m * sizeof(double *), hipMemcpyHostToDevice, st) != hipSuccess) rc = SE2_EHIP;
+    if (rc == SE2_OK) rc = launch_validate_many(tab, m, n, stats, stats + 2 * m, st);
+    if (rc == SE2_OK && hipMemcpyAsync(h.data(), stats, h.size() * sizeof(double), hipMemcpyDeviceToHost, st) !=
+                            hipSuccess)
+        rc = SE2_EHIP;
+    SE2_HIP(hipStreamSynchronize(st));  // also keeps `ms` and `h` alive for the copies
+    SE2_HIP(hipFreeAsync(mem, st));
+    if (rc) return rc;
+    for (int j = 0; j < m; ++j)
+        if (h[2 * j + 1] != 0.0 || !(std::fabs(h[2 * j] - 1.0) <= tol)) {
+            g_last_error = "input measure " + std::to_string(j) +
+                           " is not a probability vector (negative, non-finite or |sum-1| > tol)";
+            return SE2_EINVAL;
+        }
+    return SE2_OK;
+}
+
 namespace {
 
 struct DeviceBlock {
@@ -257,7 +287,8 @@ int se2_conv_log(se2_kernel_t h, se2_prec_t prec, const double *in, double *out,
 
 int se2_lift_field(const se2_grid_t *grid, const double *mag, const double *angle, double *out, int32_t batch,
                    se2_stream_t stream) {
-    if (!valid_grid(grid) || !mag || !angle || !out || batch < 0) return SE2_EINVAL;
+    if (!valid_grid(grid) || !mag || !angle || !out || batch < 0 || (reinterpret_cast<uintptr_t>(out) & 15))
+        return SE2_EINVAL;
     const size_t npix = static_cast<size_t>(grid->nx) * grid->ny * static_cast<size_t>(batch);
     const double period = grid->theta_axial ? M_PI : 2.0 * M_PI;
     return launch_lift_field(mag, angle, out, npix, grid->ntheta, period, reinterpret_cast<hipStream_t>(stream));
@@ -265,7 +296,9 @@ int se2_lift_field(const se2_grid_t *grid, const double *mag, const double *angl
 
 int se2_project(const se2_grid_t *grid, const double *u, const double *u_minus, double *mass, int32_t *argmax,
                 double *angle, int32_t batch, se2_stream_t stream) {
-    if (!valid_grid(grid) || !u || !mass || batch < 0) return SE2_EINVAL;
+    if (!valid_grid(grid) || !u || !mass || batch < 0 || (reinterpret_cast<uintptr_t>(u) & 15) ||
+        (reinterpret_cast<uintptr_t>(u_minus) & 15))
+        return SE2_EINVAL;
     const size_t npix = static_cast<size_t>(grid->nx) * grid->ny * static_cast<size_t>(batch);
     const double period = grid->theta_axial ? M_PI : 2.0 * M_PI;
     return launch_project(u, u_minus, npix, grid->ntheta, period, mass, argmax, angle,
@@ -346,7 +379,7 @@ int se2_sinkhorn(se2_kernel_t h, const double *mu, const double *nu, const se2_o
 int se2_barycenter(se2_kernel_t h, int32_t n, const double *const *mus, const double *lambdas,
                    const se2_opts_t *opts, double *bary_out, se2_report_t *report, se2_stream_t stream) {
     const Kernel *k = reinterpret_cast<const Kernel *>(h);
-    if (!k || n < 1 || n > 16 || !mus || !lambdas || !bary_out || !valid_opts(opts, k->metric.eps))
+    if (!k || n < 1 || n > kMaxMeasures || !mus || !lambdas || !bary_out || !valid_opts(opts, k->metric.eps))
         return SE2_EINVAL;
     double lsum = 0.0;
     for (int i = 0; i < n; ++i) {
@@ -360,8 +393,8 @@ int se2_barycenter(se2_kernel_t h, int32_t n, const double *const *mus, const do
     std::vector<const double *> act;
     std::vector<double> lam;
     int rc;
+    if ((rc = validate_measures(std::vector<const double *>(mus, mus + n), E, 1e-9, st))) return rc;
     for (int i = 0; i < n; ++i) {
-        if ((rc = validate_measure(mus[i], E, 1e-9, st))) return rc;
         if (lambdas[i] > 0.0) {
             act.push_back(mus[i]);
             lam.push_back(lambdas[i]);

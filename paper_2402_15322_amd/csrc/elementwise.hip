@@ -81,6 +81,42 @@ __global__ __launch_bounds__(kThreads) void k_validate_partial(const double *__r
     }
 }
 
+// The same check for many arrays of one length (blockIdx.y = array, pointers from a
+// device table): part[(j * gridDim.x + block) * 2 + {0, 1}].
+__global__ __launch_bounds__(kThreads) void k_validate_partial_tab(const double *const *__restrict__ tab, size_t n,
+                                                                   size_t chunk, double *__restrict__ part) {
+    __shared__ double sh[kThreads];
+    const double *m = tab[blockIdx.y];
+    const size_t b0 = blockIdx.x * chunk;
+    const size_t b1 = (b0 + chunk < n) ? b0 + chunk : n;
+    double s = 0.0, bad = 0.0;
+    for (size_t i = b0 + threadIdx.x; i < b1; i += kThreads) {
+        const double v = m[i];
+        if (!(v >= 0.0) || !isfinite(v)) bad += 1.0;
+        else s += v;
+    }
+    s = block_tree_sum(s, sh);
+    bad = block_tree_sum(bad, sh);
+    if (threadIdx.x == 0) {
+        const size_t o = (static_cast<size_t>(blockIdx.y) * gridDim.x + blockIdx.x) * 2;
+        part[o] = s;
+        part[o + 1] = bad;
+    }
+}
+
+// One block per array j: out[2 j + c] = sum over p < count of part[(j count + p) 2 + c].
+__global__ __launch_bounds__(kThreads) void k_reduce_pairs(const double *__restrict__ part, int count,
+                                                           double *__restrict__ out) {
+    __shared__ double sh[kThreads];
+    const double *pj = part + static_cast<size_t>(blockIdx.x) * count * 2;
+    for (int c = 0; c < 2; ++c) {
+        double s = 0.0;
+        for (int p = threadIdx.x; p < count; p += kThreads) s += pj[2 * static_cast<size_t>(p) + c];
+        s = block_tree_sum(s, sh);
+        if (threadIdx.x == 0) out[2 * static_cast<size_t>(blockIdx.x) + c] = s;
+    }
+}
+
 // out[c] = sum over p < count of part[p * stride + c], c < stride, in index order.
 __global__ __launch_bounds__(kThreads) void k_reduce_fixed(const double *__restrict__ part, int count, int stride,
                                                            double *__restrict__ out) {
@@ -115,33 +151,89 @@ __global__ __launch_bounds__(kThreads) void k_sum_items(const SumItem *__restric
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
-struct CombineArgs {
-    double *lv[16];
-    const double *ld[16];
-    double lam[16];
-};
+// IBP combine (Appendix A): log bar = sum_i lambda_i log d_i, then log v_i += log bar -
+// log d_i (log v_i = -inf where the barycenter is 0).  The sum runs in a fixed order: in
+// index order within chunks of kCombineChunk measures (one block row per chunk), then the
+// chunk partials in chunk order; with one chunk the partial is the sum itself.
+__device__ __forceinline__ double acc_log(double bar, double lam, double d) {
+    return (d == -INFINITY || bar == -INFINITY) ? -INFINITY : bar + lam * d;
+}
 
-// IBP combine (Appendix A): log bar = sum_i lambda_i log d_i (fixed i order),
-// then log v_i += log bar - log d_i (log v_i = -inf where the barycenter is 0).
-__global__ __launch_bounds__(kThreads) void k_ibp_combine(CombineArgs a, int n, size_t len,
-                                                          double *__restrict__ logbar) {
+__global__ __launch_bounds__(kThreads) void k_ibp_bar_partial(const double *const *__restrict__ ld,
+                                                              const double *__restrict__ lam, int n, size_t len,
+                                                              double *__restrict__ part) {
+    const int i0 = blockIdx.y * kCombineChunk;
+    const int i1 = (i0 + kCombineChunk < n) ? i0 + kCombineChunk : n;
     for (size_t x = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x; x < len;
          x += static_cast<size_t>(gridDim.x) * kThreads) {
         double bar = 0.0;
-        for (int i = 0; i < n; ++i) {
-            const double d = a.ld[i][x];
-            bar = (d == -INFINITY || bar == -INFINITY) ? -INFINITY : bar + a.lam[i] * d;
+        for (int i = i0; i < i1; ++i) bar = acc_log(bar, lam[i], ld[i][x]);
+        part[blockIdx.y * len + x] = bar;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_ibp_bar_total(const double *__restrict__ part, int nchunks, size_t len,
+                                                            double *__restrict__ logbar) {
+    for (size_t x = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x; x < len;
+         x += static_cast<size_t>(gridDim.x) * kThreads) {
+        double bar = part[x];
+        for (int c = 1; c < nchunks; ++c) {
+            const double p = part[c * len + x];
+            bar = (p == -INFINITY || bar == -INFINITY) ? -INFINITY : bar + p;
         }
         logbar[x] = bar;
-        for (int i = 0; i < n; ++i) {
-            const double v = a.lv[i][x];
-            a.lv[i][x] = (bar == -INFINITY || v == -INFINITY) ? -INFINITY : v + (bar - a.ld[i][x]);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_ibp_vupdate(double *const *__restrict__ lv,
+                                                          const double *const *__restrict__ ld, int n, size_t len,
+                                                          const double *__restrict__ logbar) {
+    const int i0 = blockIdx.y * kCombineChunk;
+    const int i1 = (i0 + kCombineChunk < n) ? i0 + kCombineChunk : n;
+    for (size_t x = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x; x < len;
+         x += static_cast<size_t>(gridDim.x) * kThreads) {
+        const double bar = logbar[x];
+        for (int i = i0; i < i1; ++i) {
+            const double v = lv[i][x];
+            lv[i][x] = (bar == -INFINITY || v == -INFINITY) ? -INFINITY : v + (bar - ld[i][x]);
         }
     }
 }
 
-// Plan statistics of pi(x, y) = 2^(phi2(x) + L2(x - y) + psi2(y)) over the window:
-// per block [sum pi * rho^2, sum pi].  One thread per output element (x, ko).
+// Plan statistics of pi(x, y) = 2^(phi2(x) + L2(x - y) + psi2(y)) over the window of the
+// output element i = (x, ko): its terms of sum pi * rho^2 and sum pi.
+template <int NT>
+__device__ __forceinline__ void plan_terms(const double *__restrict__ phi2, const double *__restrict__ psi2,
+                                           const double *__restrict__ L64, const double *__restrict__ cost, int nx,
+                                           int ny, int R, size_t i, double &c, double &m) {
+    const int W = 2 * R + 1;
+    const int ko = static_cast<int>(i % NT);
+    const size_t pix = i / NT;
+    const int ix = static_cast<int>(pix % nx), iy = static_cast<int>(pix / nx);
+    const double f = phi2[i];
+    if (f == -INFINITY) return;
+    for (int dy = -R; dy <= R; ++dy) {
+        const int jy = iy - dy;
+        if (jy < 0 || jy >= ny) continue;
+        for (int dx = -R; dx <= R; ++dx) {
+            const int jx = ix - dx;
+            if (jx < 0 || jx >= nx) continue;
+            const size_t kb = (static_cast<size_t>((dy + R) * W + (dx + R)) * NT + ko) * NT;
+            const double *g = psi2 + (static_cast<size_t>(jy) * nx + jx) * NT;
+            float rs = 0.0f, rc = 0.0f;
+            for (int ki = 0; ki < NT; ++ki) {
+                const double u = (f + L64[kb + ki]) + g[ki];
+                const float p = __builtin_amdgcn_exp2f(static_cast<float>(u));
+                rs += p;
+                rc += p * static_cast<float>(cost[kb + ki]);
+            }
+            m += rs;
+            c += rc;
+        }
+    }
+}
+
+// Per block [sum pi * rho^2, sum pi].  One thread per output element (x, ko).
 template <int NT>
 __global__ __launch_bounds__(kThreads) void k_plan_cost(const double *__restrict__ phi2,
                                                         const double *__restrict__ psi2,
@@ -151,40 +243,35 @@ __global__ __launch_bounds__(kThreads) void k_plan_cost(const double *__restrict
     __shared__ double sh[kThreads];
     const size_t n = static_cast<size_t>(nx) * ny * NT;
     const size_t i = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x;
-    const int W = 2 * R + 1;
     double c = 0.0, m = 0.0;
-    if (i < n) {
-        const int ko = static_cast<int>(i % NT);
-        const size_t pix = i / NT;
-        const int ix = static_cast<int>(pix % nx), iy = static_cast<int>(pix / nx);
-        const double f = phi2[i];
-        if (f != -INFINITY) {
-            for (int dy = -R; dy <= R; ++dy) {
-                const int jy = iy - dy;
-                if (jy < 0 || jy >= ny) continue;
-                for (int dx = -R; dx <= R; ++dx) {
-                    const int jx = ix - dx;
-                    if (jx < 0 || jx >= nx) continue;
-                    const size_t kb = (static_cast<size_t>((dy + R) * W + (dx + R)) * NT + ko) * NT;
-                    const double *g = psi2 + (static_cast<size_t>(jy) * nx + jx) * NT;
-                    float rs = 0.0f, rc = 0.0f;
-                    for (int ki = 0; ki < NT; ++ki) {
-                        const double u = (f + L64[kb + ki]) + g[ki];
-                        const float p = __builtin_amdgcn_exp2f(static_cast<float>(u));
-                        rs += p;
-                        rc += p * static_cast<float>(cost[kb + ki]);
-                    }
-                    m += rs;
-                    c += rc;
-                }
-            }
-        }
-    }
+    if (i < n) plan_terms<NT>(phi2, psi2, L64, cost, nx, ny, R, i, c, m);
     c = block_tree_sum(c, sh);
     m = block_tree_sum(m, sh);
     if (threadIdx.x == 0) {
         part[2 * blockIdx.x] = c;
         part[2 * blockIdx.x + 1] = m;
+    }
+}
+
+// The same for many plans of one grid (blockIdx.y = plan j, scalings from device tables):
+// part[(2 j) nb + block] = sum pi * rho^2, part[(2 j + 1) nb + block] = sum pi.
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_plan_cost_tab(const double *const *__restrict__ phi_tab,
+                                                            const double *const *__restrict__ psi_tab,
+                                                            const double *__restrict__ L64,
+                                                            const double *__restrict__ cost, int nx, int ny, int R,
+                                                            double *__restrict__ part) {
+    __shared__ double sh[kThreads];
+    const size_t n = static_cast<size_t>(nx) * ny * NT;
+    const size_t i = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x;
+    const int j = blockIdx.y;
+    double c = 0.0, m = 0.0;
+    if (i < n) plan_terms<NT>(phi_tab[j], psi_tab[j], L64, cost, nx, ny, R, i, c, m);
+    c = block_tree_sum(c, sh);
+    m = block_tree_sum(m, sh);
+    if (threadIdx.x == 0) {
+        part[(2 * static_cast<size_t>(j)) * gridDim.x + blockIdx.x] = c;
+        part[(2 * static_cast<size_t>(j) + 1) * gridDim.x + blockIdx.x] = m;
     }
 }
 
@@ -259,6 +346,23 @@ int launch_validate(const double *m, size_t n, double *d_stats, hipStream_t s) {
     return SE2_OK;
 }
 
+int validate_many_blocks(size_t n) {
+    const size_t b = (n + 4095) / 4096;
+    return static_cast<int>(b < 1 ? 1 : (b > 256 ? 256 : b));
+}
+
+int launch_validate_many(const double *const *d_tab, int m, size_t n, double *d_stats, double *d_part, hipStream_t s) {
+    if (m < 1) return SE2_OK;
+    const int nb = validate_many_blocks(n);
+    const size_t chunk = (n + nb - 1) / nb;
+    hipLaunchKernelGGL(k_validate_partial_tab, dim3(nb, m), dim3(kThreads), 0, s, d_tab, n, chunk == 0 ? 1 : chunk,
+                       d_part);
+    SE2_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce_pairs, dim3(m), dim3(kThreads), 0, s, d_part, nb, d_stats);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
 int launch_reduce_fixed(const double *partials, int count, int stride, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce_fixed, dim3(1), dim3(kThreads), 0, s, partials, count, stride, out);
     SE2_HIP(hipGetLastError());
@@ -279,16 +383,19 @@ int launch_sum_items(const SumItem *d_items, int n, double *out, hipStream_t s) 
     return SE2_OK;
 }
 
-int launch_ibp_combine(double *const *lv, const double *const *ld, const double *lambdas, int n, size_t len,
-                       double *logbar, hipStream_t s) {
-    if (n < 1 || n > 16) return SE2_EINVAL;
-    CombineArgs a{};
-    for (int i = 0; i < n; ++i) {
-        a.lv[i] = lv[i];
-        a.ld[i] = ld[i];
-        a.lam[i] = lambdas[i];
+int launch_ibp_combine(double *const *d_lv, const double *const *d_ld, const double *d_lam, int n, size_t len,
+                       double *part, double *logbar, hipStream_t s) {
+    if (n < 1 || len == 0) return n < 1 ? SE2_EINVAL : SE2_OK;
+    const int nchunks = combine_chunks(n);
+    const int gx = grid_for(len);
+    hipLaunchKernelGGL(k_ibp_bar_partial, dim3(gx, nchunks), dim3(kThreads), 0, s, d_ld, d_lam, n, len,
+                       nchunks == 1 ? logbar : part);
+    SE2_HIP(hipGetLastError());
+    if (nchunks > 1) {
+        hipLaunchKernelGGL(k_ibp_bar_total, dim3(gx), dim3(kThreads), 0, s, part, nchunks, len, logbar);
+        SE2_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_ibp_combine, dim3(grid_for(len)), dim3(kThreads), 0, s, a, n, len, logbar);
+    hipLaunchKernelGGL(k_ibp_vupdate, dim3(gx, nchunks), dim3(kThreads), 0, s, d_lv, d_ld, n, len, logbar);
     SE2_HIP(hipGetLastError());
     return SE2_OK;
 }
@@ -312,6 +419,24 @@ int launch_plan_cost(const Kernel &k, const double *phi2, const double *psi2, do
             break;
         default:
             return SE2_EINVAL;
+    }
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+int launch_plan_cost_tab(const Kernel &k, const double *const *phi_tab, const double *const *psi_tab, int njobs,
+                         double *partials, int nblocks, hipStream_t s) {
+    const int nx = k.grid.nx, ny = k.grid.ny, R = k.metric.radius;
+    if (njobs < 1) return SE2_OK;
+    const dim3 g(nblocks, njobs), b(kThreads);
+    switch (k.grid.ntheta) {
+        case 8: hipLaunchKernelGGL(k_plan_cost_tab<8>, g, b, 0, s, phi_tab, psi_tab, k.d_L64, k.d_cost, nx, ny, R,
+                                   partials); break;
+        case 16: hipLaunchKernelGGL(k_plan_cost_tab<16>, g, b, 0, s, phi_tab, psi_tab, k.d_L64, k.d_cost, nx, ny, R,
+                                    partials); break;
+        case 32: hipLaunchKernelGGL(k_plan_cost_tab<32>, g, b, 0, s, phi_tab, psi_tab, k.d_L64, k.d_cost, nx, ny, R,
+                                    partials); break;
+        default: return SE2_EINVAL;
     }
     SE2_HIP(hipGetLastError());
     return SE2_OK;

@@ -7,8 +7,8 @@
 //
 // All of it is HBM-bound elementwise and segmented-reduction work: no contraction, so
 // no matrix cores.  Arrays are [batch][iy][ix][k] with theta innermost; a pixel's
-// ntheta values are contiguous, so one wave reads 64 consecutive doubles and reduces
-// them in groups of ntheta lanes with cross-lane moves (fixed butterfly order).
+// ntheta values are contiguous and move as 16-byte vectors (grid arrays must be 16-byte
+// aligned).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -35,62 +35,74 @@ __device__ __forceinline__ int angle_bin(double psi, double inv_step, int nt) {
     return static_cast<int>(b);
 }
 
-// One thread per output element (pixel, k): the lifted value is the pixel's magnitude in
-// the bin of its angle and 0 elsewhere.
+// One thread per four consecutive outputs of a pixel (two 16-byte stores): the lifted
+// value is the pixel's magnitude in the bin of its angle and 0 elsewhere.
+template <int NT>
 __global__ __launch_bounds__(kThreads) void k_lift_field(const double *__restrict__ mag,
                                                          const double *__restrict__ angle, double *__restrict__ out,
-                                                         size_t n_out, int nt, double inv_step) {
-    for (size_t i = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x; i < n_out;
-         i += static_cast<size_t>(gridDim.x) * kThreads) {
-        const size_t p = i / nt;
-        const int k = static_cast<int>(i - p * nt);
-        const double a = angle[p];
-        out[i] = (angle_bin(a, inv_step, nt) == k) ? mag[p] : 0.0;
+                                                         size_t nquads, double inv_step) {
+    constexpr int Q = NT / 4;  // quads per pixel
+    for (size_t j = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x; j < nquads;
+         j += static_cast<size_t>(gridDim.x) * kThreads) {
+        const size_t p = j / Q;
+        const int k0 = static_cast<int>(j - p * Q) * 4;
+        const int b = angle_bin(angle[p], inv_step, NT);
+        const double m = mag[p];
+        double2 lo, hi;
+        lo.x = (b == k0) ? m : 0.0;
+        lo.y = (b == k0 + 1) ? m : 0.0;
+        hi.x = (b == k0 + 2) ? m : 0.0;
+        hi.y = (b == k0 + 3) ? m : 0.0;
+        double2 *o = reinterpret_cast<double2 *>(out + 4 * j);
+        o[0] = lo;
+        o[1] = hi;
     }
 }
 
-// Butterfly sum and (max, lowest index) over aligned groups of NT lanes.
-template <int NT>
-__device__ __forceinline__ void group_reduce(double &s, double &m, int &arg) {
-#pragma unroll
-    for (int off = 1; off < NT; off <<= 1) {
-        const double so = __shfl_xor(s, off, 64);
-        const double mo = __shfl_xor(m, off, 64);
-        const int ao = __shfl_xor(arg, off, 64);
-        s += so;
-        // the larger value wins; on equal values the lower orientation index
-        if (mo > m || (mo == m && ao < arg)) {
-            m = mo;
-            arg = ao;
-        }
-    }
-}
-
-// One thread per element, NT consecutive lanes per pixel: mass = sum_k u - sum_k u_minus,
-// argmax_k u (lowest k on ties), its angle theta_argmax.
+// One thread per pixel, its NT values read with 16-byte loads: mass = sum_k u - sum_k
+// u_minus (k in order), argmax_k u (the first maximum, i.e. the lowest k on ties) and its
+// angle theta_argmax.  The lanes of a wave read 64 neighbouring pixels, so every fetched
+// line is used by the wave's loads.
 template <int NT>
 __global__ __launch_bounds__(kThreads) void k_project(const double *__restrict__ u, const double *__restrict__ um,
                                                       size_t npix, double step, double *__restrict__ mass,
                                                       int32_t *__restrict__ argmax, double *__restrict__ ang) {
-    const size_t n = npix * NT;
-    const size_t stride = static_cast<size_t>(gridDim.x) * kThreads;
-    // every lane of a wave runs the same number of rounds (the butterflies need all 64)
-    const size_t rounds = (n + stride - 1) / stride;
-    size_t i = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x;
-    for (size_t r = 0; r < rounds; ++r, i += stride) {
-        const bool in = i < n;
-        const int k = static_cast<int>(i % NT);
-        double v = in ? u[i] : 0.0;
-        double s = v - ((in && um) ? um[i] : 0.0);
-        double m = in ? v : -INFINITY;
-        int a = k;
-        group_reduce<NT>(s, m, a);
-        if (in && k == 0) {
-            const size_t p = i / NT;
-            mass[p] = s;
-            if (argmax) argmax[p] = a;
-            if (ang) ang[p] = a * step;
+    for (size_t p = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x; p < npix;
+         p += static_cast<size_t>(gridDim.x) * kThreads) {
+        const double2 *row = reinterpret_cast<const double2 *>(u + p * NT);
+        double2 v[NT / 2];
+#pragma unroll
+        for (int q = 0; q < NT / 2; ++q) v[q] = row[q];
+        double s = 0.0, m = v[0].x;
+        int a = 0;
+#pragma unroll
+        for (int q = 0; q < NT / 2; ++q) {
+            s += v[q].x;
+            s += v[q].y;
+            if (v[q].x > m) {
+                m = v[q].x;
+                a = 2 * q;
+            }
+            if (v[q].y > m) {
+                m = v[q].y;
+                a = 2 * q + 1;
+            }
         }
+        if (um) {
+            const double2 *rm = reinterpret_cast<const double2 *>(um + p * NT);
+#pragma unroll
+            for (int q = 0; q < NT / 2; ++q) v[q] = rm[q];
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < NT / 2; ++q) {
+                t += v[q].x;
+                t += v[q].y;
+            }
+            s -= t;
+        }
+        mass[p] = s;
+        if (argmax) argmax[p] = a;
+        if (ang) ang[p] = a * step;
     }
 }
 
@@ -163,9 +175,16 @@ __global__ __launch_bounds__(kThreads) void k_signed_split(const double *__restr
 
 int launch_lift_field(const double *mag, const double *angle, double *out, size_t npix, int nt, double period,
                       hipStream_t s) {
-    const size_t n = npix * nt;
-    if (n == 0) return SE2_OK;
-    hipLaunchKernelGGL(k_lift_field, dim3(blocks_for(n)), dim3(kThreads), 0, s, mag, angle, out, n, nt, nt / period);
+    const size_t nq = npix * nt / 4;
+    if (nq == 0) return SE2_OK;
+    const dim3 g(blocks_for(nq)), b(kThreads);
+    const double inv = nt / period;
+    switch (nt) {
+        case 8: hipLaunchKernelGGL(k_lift_field<8>, g, b, 0, s, mag, angle, out, nq, inv); break;
+        case 16: hipLaunchKernelGGL(k_lift_field<16>, g, b, 0, s, mag, angle, out, nq, inv); break;
+        case 32: hipLaunchKernelGGL(k_lift_field<32>, g, b, 0, s, mag, angle, out, nq, inv); break;
+        default: return SE2_EINVAL;
+    }
     SE2_HIP(hipGetLastError());
     return SE2_OK;
 }
@@ -173,9 +192,8 @@ int launch_lift_field(const double *mag, const double *angle, double *out, size_
 int launch_project(const double *u, const double *um, size_t npix, int nt, double period, double *mass,
                    int32_t *argmax, double *ang, hipStream_t s) {
     if (npix == 0) return SE2_OK;
-    const size_t n = npix * nt;
     const double step = period / nt;
-    const dim3 g(blocks_for(n)), b(kThreads);
+    const dim3 g(blocks_for(npix)), b(kThreads);
     switch (nt) {
         case 8: hipLaunchKernelGGL(k_project<8>, g, b, 0, s, u, um, npix, step, mass, argmax, ang); break;
         case 16: hipLaunchKernelGGL(k_project<16>, g, b, 0, s, u, um, npix, step, mass, argmax, ang); break;

@@ -161,8 +161,8 @@ int admit_one(se2_queue_s *Q, Req *q) {
         q->inputs.push_back(dst);
     }
     char *solve_mem = p + static_cast<size_t>(nin) * in_bytes;
-    for (int i = 0; i < nin; ++i)
-        if ((rc = validate_measure(q->inputs[i], E, 1e-9, Q->st))) return rc;
+    if ((rc = validate_measures(std::vector<const double *>(q->inputs.begin(), q->inputs.end()), E, 1e-9, Q->st)))
+        return rc;
     if (q->r.kind == SE2_REQ_OT) {
         s.n = 1;
         solve_bind(s, solve_mem);
@@ -389,7 +389,7 @@ int se2_request_bytes(const se2_request_t *req, size_t *bytes) {
     Req q;
     q.r = *req;
     if (req->kind == SE2_REQ_BARYCENTER) {
-        if (req->n < 1 || req->n > 16 || !req->lambdas) return SE2_EINVAL;
+        if (req->n < 1 || req->n > kMaxMeasures || !req->lambdas) return SE2_EINVAL;
         for (int i = 0; i < req->n; ++i) {
             q.mus_all.push_back(nullptr);
             q.lambdas_all.push_back(req->lambdas[i]);
@@ -424,7 +424,7 @@ int se2_solve_queue_submit(se2_queue_t Q, const se2_request_t *req, uint64_t *ti
     if (req->kind == SE2_REQ_OT) {
         if (!req->mu || !req->nu) return SE2_EINVAL;
     } else if (req->kind == SE2_REQ_BARYCENTER) {
-        if (req->n < 1 || req->n > 16 || !req->mus || !req->lambdas || !req->bary_out) return SE2_EINVAL;
+        if (req->n < 1 || req->n > kMaxMeasures || !req->mus || !req->lambdas || !req->bary_out) return SE2_EINVAL;
         double lsum = 0.0;
         int npos = 0;
         for (int i = 0; i < req->n; ++i) {

@@ -24,6 +24,7 @@ constexpr double kLog2e = 1.442695040888963407359924681001892137;
 constexpr int kTile = 8;          // output tile of the log-domain kernels: 8 x 8 pixels
 constexpr int kConvThreads = 256; // 4 waves of 64
 constexpr int kMaxRadius = 12;
+constexpr int kMaxMeasures = 65535;  // measures of one barycenter (a launch grid dimension)
 
 // Certified pruning of the log-domain convolution (base-2 units): the entries within
 // kListCut of an output's maximum are listed (the criterion has one unit of slack
@@ -162,10 +163,18 @@ struct SumItem {
 };
 int launch_sum_items(const SumItem *d_items, int n, double *out, hipStream_t s);
 int launch_sum_partials(const double *partials, const int32_t *offsets, int njobs, double *out, hipStream_t s);
-int launch_ibp_combine(double *const *lv, const double *const *ld, const double *lambdas, int n, size_t len,
-                       double *logbar, hipStream_t s);
+// IBP combine over device tables of the measures' log v_i and log d_i pointers and weights;
+// `part` holds combine_chunks(n) * len doubles (unused when that is 1).
+constexpr int kCombineChunk = 64;
+inline int combine_chunks(int n) { return (n + kCombineChunk - 1) / kCombineChunk; }
+int launch_ibp_combine(double *const *d_lv, const double *const *d_ld, const double *d_lam, int n, size_t len,
+                       double *part, double *logbar, hipStream_t s);
 int launch_plan_cost(const Kernel &k, const double *phi2, const double *psi2, double *partials /* per tile x 3 */,
                      int tiles, hipStream_t s);
+// Plan statistics of njobs plans of one grid in one launch (blockIdx.y = plan), partials
+// laid out [job][cost | mass][nblocks].
+int launch_plan_cost_tab(const Kernel &k, const double *const *phi_tab, const double *const *psi_tab, int njobs,
+                         double *partials, int nblocks, hipStream_t s);
 int launch_reduce_fixed(const double *partials, int count, int stride, double *out, hipStream_t s);
 int launch_exp2_out(const double *in2, double *out, size_t n, hipStream_t s);
 int launch_dot_exp(const double *f2, const double *m, size_t n, double *partials, int nblocks, hipStream_t s);
@@ -178,8 +187,15 @@ int launch_project(const double *u, const double *um, size_t npix, int nt, doubl
 int split_blocks(size_t n);  // the scratch of launch_split_signed holds 2 * split_blocks(n) + 2 doubles
 int launch_split_signed(const double *u, size_t n, double *plus, double *minus, double *scratch, hipStream_t s);
 
+// Sums and bad-entry counts of m arrays of length n (pointers in a device table): d_stats
+// receives [m][2], d_part holds m * validate_many_blocks(n) * 2 doubles.
+int validate_many_blocks(size_t n);
+int launch_validate_many(const double *const *d_tab, int m, size_t n, double *d_stats, double *d_part, hipStream_t s);
+
 // api.cpp: device-side FP64 check of a probability vector (finite, >= 0, |sum - 1| <= tol); syncs `st`.
 int validate_measure(const double *m, size_t n, double tol, hipStream_t st);
+// The same check for many vectors of one length with one launch and one synchronisation.
+int validate_measures(const std::vector<const double *> &ms, size_t n, double tol, hipStream_t st);
 
 // helpers
 inline int tiles_of(int n) { return (n + kTile - 1) / kTile; }

@@ -46,7 +46,7 @@ struct Carver {
 
 int cost_blocks(size_t E) { return static_cast<int>((E + 255) / 256); }
 
-ListSet carve_lists(Carver &c, const Kernel &k, size_t E, int tiles, bool prune) {
+ListSet carve_lists(Carver &c, const Kernel &k, size_t E, int tiles, bool prune, double *work = nullptr) {
     const int nt = k.grid.ntheta, HW = kTile + 2 * k.metric.radius;
     ListSet l;
     if (prune) {
@@ -56,7 +56,7 @@ ListSet carve_lists(Carver &c, const Kernel &k, size_t E, int tiles, bool prune)
         l.mref = c.take<float>(E);
     }
     l.dense_flag = c.take<int32_t>(static_cast<size_t>(tiles));
-    l.work = c.take<double>(2 * static_cast<size_t>(tiles));
+    l.work = work ? work : c.take<double>(2 * static_cast<size_t>(tiles));
     return l;
 }
 
@@ -90,11 +90,19 @@ size_t carve(Solve &s, int kind, const Kernel &k, int n, bool prune, void *mem) 
         }
         s.logbar = c.take<double>(E);
         s.phi[0] = c.take<double>(E);  // scratch for the FP64 check
+        s.d_lv = c.take<double *>(n);
+        s.d_ld = c.take<const double *>(n);
+        s.d_lw = c.take<const double *>(n);
+        s.d_lam = c.take<double>(n);
+        s.d_cost_items = c.take<SumItem>(2 * static_cast<size_t>(n));
+        s.combine_part = combine_chunks(n) > 1 ? c.take<double>(static_cast<size_t>(combine_chunks(n)) * E) : nullptr;
+        s.work_all = c.take<double>(4 * static_cast<size_t>(n) * tiles);
         s.ls_v.assign(n, ListSet());
         s.ls_w.assign(n, ListSet());
         for (int i = 0; i < n; ++i) {
-            s.ls_v[i] = carve_lists(c, k, E, tiles, prune);
-            s.ls_w[i] = carve_lists(c, k, E, tiles, prune);
+            double *w = s.work_all ? s.work_all + 4 * static_cast<size_t>(i) * tiles : nullptr;
+            s.ls_v[i] = carve_lists(c, k, E, tiles, prune, w);
+            s.ls_w[i] = carve_lists(c, k, E, tiles, prune, w ? w + 2 * static_cast<size_t>(tiles) : nullptr);
         }
     }
     s.partial = c.take<double>(npart > ncost ? npart : ncost);
@@ -246,7 +254,15 @@ int solve_setup_bary(Solve &s, const std::vector<const double *> &mus, hipStream
     std::vector<int32_t> off(s.n + 1);
     for (int i = 0; i <= s.n; ++i) off[i] = i * s.tiles * s.k->grid.ntheta;
     SE2_HIP(hipMemcpyAsync(s.offsets, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    SE2_HIP(hipStreamSynchronize(st));
+    SE2_HIP(hipMemcpyAsync(s.d_lv, s.lv.data(), s.n * sizeof(double *), hipMemcpyHostToDevice, st));
+    SE2_HIP(hipMemcpyAsync(s.d_ld, s.ld.data(), s.n * sizeof(double *), hipMemcpyHostToDevice, st));
+    SE2_HIP(hipMemcpyAsync(s.d_lw, s.lw.data(), s.n * sizeof(double *), hipMemcpyHostToDevice, st));
+    const int nb = cost_blocks(s.E);
+    std::vector<SumItem> items(2 * static_cast<size_t>(s.n));
+    for (int j = 0; j < 2 * s.n; ++j) items[j] = SumItem{s.partial, j * nb, (j + 1) * nb};
+    SE2_HIP(hipMemcpyAsync(s.d_cost_items, items.data(), items.size() * sizeof(SumItem), hipMemcpyHostToDevice, st));
+    SE2_HIP(hipMemcpyAsync(s.d_lam, s.lam.data(), s.n * sizeof(double), hipMemcpyHostToDevice, st));
+    SE2_HIP(hipStreamSynchronize(st));  // the host vectors are read by the copies
     s.iter = 0;
     s.done = false;
     return SE2_OK;
@@ -524,8 +540,7 @@ int Engine::step(const std::vector<Solve *> &solves, bool check, hipStream_t st)
     if (rc) return rc;
     for (Solve *s : solves) {
         if (s->kind != SE2_REQ_BARYCENTER) continue;
-        std::vector<const double *> ld(s->ld.begin(), s->ld.end());
-        rc = launch_ibp_combine(s->lv.data(), ld.data(), s->lam.data(), s->n, s->E, s->logbar, st);
+        rc = launch_ibp_combine(s->d_lv, s->d_ld, s->d_lam, s->n, s->E, s->combine_part, s->logbar, st);
         if (rc) return rc;
     }
     rc = launch_stage(solves, 1, check, st);
@@ -695,11 +710,11 @@ int finish_solves(Engine &eng, std::vector<FinishReq> &reqs, hipStream_t st) {
             }
         } else {
             if ((rc = launch_exp2_out(s.logbar, q.bary_out, s.E, st))) return rc;
-            // sum_i lambda_i <pi_i, rho^2> with pi_i = diag(w_i) K diag(v_i) (first marginal exact)
-            for (int i = 0; i < s.n; ++i) {
-                if ((rc = launch_plan_cost(k, s.lw[i], s.lv[i], part, nb, st))) return rc;
-                if ((rc = launch_reduce_fixed(part, nb, 2, s.err + 2 + 2 * i, st))) return rc;
-            }
+            // sum_i lambda_i <pi_i, rho^2> with pi_i = diag(w_i) K diag(v_i) (first marginal exact):
+            // every plan in one launch, then the cost and mass sums of each in one launch
+            if ((rc = launch_plan_cost_tab(k, s.d_lw, const_cast<const double *const *>(s.d_lv), s.n, part, nb, st)))
+                return rc;
+            if ((rc = launch_sum_items(s.d_cost_items, 2 * s.n, s.err + 2, st))) return rc;
             // barycenter mass (FP64 fixed-order sum, the validation reduction)
             if ((rc = launch_validate(q.bary_out, s.E, part, st))) return rc;
             SE2_HIP(hipMemcpyAsync(s.err + 2 + 2 * s.n, part, sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -766,9 +781,12 @@ int finish_solves(Engine &eng, std::vector<FinishReq> &reqs, hipStream_t st) {
             r.mass = e[2 + 2 * s.n];
             r.dual = 0.0;
             if (s.opts.final_check) r.marg_l1_f64 = worst;
-            for (int i = 0; i < s.n; ++i) {
-                if ((rc = read_work(s.ls_v[i], s.tiles, &r.terms_dense, &r.terms_sparse))) return rc;
-                if ((rc = read_work(s.ls_w[i], s.tiles, &r.terms_dense, &r.terms_sparse))) return rc;
+            // every list's counters in one copy ([measure][v, w][tile][dense, sparse])
+            std::vector<double> h(4 * static_cast<size_t>(s.n) * s.tiles);
+            SE2_HIP(hipMemcpy(h.data(), s.work_all, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+            for (size_t t = 0; t < h.size(); t += 2) {
+                r.terms_dense += h[t];
+                r.terms_sparse += h[t + 1];
             }
         }
         r.seconds = now_seconds() - s.t_start;

@@ -36,6 +36,13 @@ struct Solve {
     std::vector<ListSet> ls_v, ls_w;  // pruning state of the w-update (input lv_i) and d-update (input lw_i)
     std::vector<const double *> m_lin;
     double *logbar = nullptr;
+    double **d_lv = nullptr;         // device tables of lv[i], ld[i], lw[i] and the weights
+    const double **d_ld = nullptr;
+    const double **d_lw = nullptr;
+    SumItem *d_cost_items = nullptr; // [2n] cost and mass sums of the finishing
+    double *work_all = nullptr;      // [2n][tiles][2] work counters of every list, contiguous
+    double *d_lam = nullptr;
+    double *combine_part = nullptr;  // [combine_chunks(n)][E] chunk partials of the combine
     // common
     double *partial = nullptr;       // [job][tile][nt] error partials
     double *err = nullptr;           // 3 * max(1, n) + 8 result slots of the finishing (device)

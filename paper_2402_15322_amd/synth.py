@@ -369,3 +369,37 @@ def serving_trace(nreq: int = 512, rate: float = 200.0, seed: int = 3000, paired
             nu = splat_segments(g, draw_segments(r, g, nseg, 10.0 * n / 64, 40.0 * n / 64), 1.0, 1e-6)
         out.append(Request(float(t[i]), OTInstance(g, (1.0, w2, 1.0), eps, rad, mu, nu, f"serve/{i}")))
     return out
+
+
+# ---------------------------------------------------------------------------
+# many small stroke images (barycenters of a whole class of 28 x 28 images)
+# ---------------------------------------------------------------------------
+
+STROKE_GRID = Grid(28, 28, 16)
+
+
+def stroke_image(seed: int, index: int) -> np.ndarray:
+    """One 28 x 28 x 16 stroke image: 2-4 segments of 6-14 px (two to four pen strokes of a
+    digit-sized drawing), kept 2 px inside the frame, sigma_xy = 1 px, floor 1e-6."""
+    r = rng_for(seed, index)
+    nseg = int(r.integers(2, 5))
+    segs = draw_segments(r, STROKE_GRID, nseg, 6.0, 14.0, margin=2.0)
+    return splat_segments(STROKE_GRID, segs, 1.0, 1e-6)
+
+
+def _stroke_chunk(args):
+    seed, lo, hi = args
+    return np.stack([stroke_image(seed, i) for i in range(lo, hi)])
+
+
+def stroke_images(n: int, seed: int = 6000, workers: int = 1) -> np.ndarray:
+    """n stroke images [n][28][28][16], image i from stream i of `seed` (the same arrays for
+    any worker count; workers > 1 forks processes, so call it before any GPU work)."""
+    if workers <= 1 or n < 64:
+        return _stroke_chunk((seed, 0, n))
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    step = (n + workers - 1) // workers
+    parts = [(seed, lo, min(n, lo + step)) for lo in range(0, n, step)]
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        return np.concatenate(list(ex.map(_stroke_chunk, parts)))
