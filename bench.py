@@ -87,6 +87,7 @@ def parse():
     ap.add_argument("--bary-n", type=int, default=6000,
                     help="class-barycenter leg: measures of 28x28x16 (0 skips the leg)")
     ap.add_argument("--bary-iters", type=int, default=20)
+    ap.add_argument("--flow-steps", type=int, default=5, help="gradient-flow leg: JKO steps (0 skips the leg)")
     ap.add_argument("--eps-start", type=float, default=1.6,
                     help="eps-scaling leg: first eps of the schedule (<= 0.1 skips the leg)")
     ap.add_argument("--eps-factor", type=float, default=0.5)
@@ -218,6 +219,32 @@ def class_barycenter(native, torch, images, iters: int):
             "marg_l1": r2["marg_l1"], "mass": r2["mass"]}
 
 
+def gradient_flow(native, torch, synth, steps: int):
+    """Porous-medium gradient flow of a line-completion image (Section 5.4: m = 5,
+    w = (1, sqrt 10, sqrt 2)) on 64 x 64 x 16: a dashed dominant line amid short line
+    elements; eps = 0.5, 11 x 11 window, tau = 1e-4, F on densities against the cell measure
+    1/(64*64*16); `steps` JKO steps on the device, each to first-marginal L1 1e-6 (max 500
+    inner iterations), warm-started from the previous step."""
+    mu = synth.line_completion()
+    E = mu.size
+    k = native.Kernel(64, 64, 16, False, (1.0, math.sqrt(10.0), math.sqrt(2.0)), 0.5, 5)
+    mud = torch.from_numpy(mu).cuda()
+    out = torch.empty_like(mud)
+    o = native.opts(tol=1e-6, max_iter=500, check_every=10, final_check=False, prune=True)
+    native.se2_gradient_flow(k, mud, 1e-4, 5.0, 1.0 / E, 1, o, out)   # warm-up (kernel tables, lists)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = native.se2_gradient_flow(k, mud, 1e-4, 5.0, 1.0 / E, steps, o, out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    inner = sum(r["iters"] for r in reps)
+    return {"workload": "line-completion image 64x64x16, m=5, w=(1,sqrt10,sqrt2), eps=0.5, 11x11 window, "
+                        "tau=1e-4, ref=1/E, tol 1e-6", "steps": steps, "wall_s": wall,
+            "jko_steps_per_s": steps / wall, "inner_iters": [r["iters"] for r in reps],
+            "inner_iters_per_s": inner / wall, "converged": sum(1 for r in reps if r["status"] == 0),
+            "energy": [r["dual"] for r in reps], "transport_cost": [r["cost"] for r in reps]}
+
+
 def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -335,6 +362,7 @@ def main():
                    "plain_marg_l1_mean": float(np.mean([r["marg_l1"] for r in all_r]))}
 
     class_meas = None if class_images is None else class_barycenter(native, torch, class_images, a.bary_iters)
+    flow_meas = None if a.flow_steps <= 0 else gradient_flow(native, torch, synth, a.flow_steps)
     conv_meas = None if a.no_conv else conv_measurements(native, torch, a.batch, a.conv_reps)
     field_meas = None if a.no_conv else field_measurements(native, torch, a.conv_reps)
 
@@ -378,6 +406,7 @@ def main():
         "eps_scaling": eps_leg,
         "lift_project": field_meas,
         "class_barycenter": class_meas,
+        "gradient_flow": flow_meas,
         "se2_conv": {"bound": "mfma", "peak_bf16_tflops": PEAK_BF16_TFLOPS, "peak_f32_tflops": PEAK_F32_TFLOPS,
                      "flops": "2 * batch * nx * ny * ntheta^2 * window", "launches": conv_meas},
     }

@@ -194,6 +194,46 @@ int se2_barycenter(se2_kernel_t k, int32_t n, const double *const *mus, const do
                    const se2_opts_t *opts, double *bary_out, se2_report_t *report, se2_stream_t stream);
 
 /*
+ * se2_jko_step -- one step of the entropic JKO scheme for the Wasserstein gradient flow of
+ * the porous-medium energy (Section 5.4, eqs. (GF_JKO) and (cost_GF), with the equation
+ * d mu / dt = Laplacian_G mu^m of eq. (pde_ndiff)):
+ *     mu_next = argmin_nu  W_eps(mu, nu) + tau F(nu),   F(nu) = ref/(m-1) sum_x (nu(x)/ref)^m,
+ * where W_eps is the entropic transport cost of Section 4.1 with this kernel's cost rho_b^2
+ * and ref is the measure of one grid cell against which densities are taken (the paper's
+ * integral of the density to the power m; e.g. 1/(nx ny ntheta) for a domain of volume 1).
+ * Solved with the entropic scheme the paper cites (Peyre 2015): the scaling iterations
+ *     a = mu / K b,   b = prox^KL_{tau F / eps}(K^T a) / K^T a,
+ * in log form, the proximal step solved per element (see the kernels).  Stops as
+ * se2_sinkhorn does on the L1 error of the first marginal (the second marginal is free: it
+ * is mu_next).  opts->init_g warm-starts log b (e.g. from the previous step of a flow);
+ * eps-scaling is not available here (eps_start must be <= eps).
+ * mu: device FP64 probability vector; mu_next (device, required) receives
+ * nu = b K^T a of the returned iterate; f_out, g_out as in se2_sinkhorn (may be NULL).
+ * report->cost is the transport cost of the plan, report->mass its mass, report->dual
+ * holds F(mu_next).  SE2_EINVAL for tau < 0, m <= 1, ref <= 0 or non-finite values.
+ * Blocking.
+ */
+typedef struct {
+    double tau; /* time step, >= 0 (0: the entropic blur of mu, K^T (mu / K 1)) */
+    double m;   /* exponent, > 1 (the paper's experiments use 5) */
+    double ref; /* reference cell measure, > 0 */
+} se2_flow_t;
+int se2_jko_step(se2_kernel_t k, const double *mu, const se2_flow_t *flow, const se2_opts_t *opts, double *mu_next,
+                 double *f_out, double *g_out, se2_report_t *report, se2_stream_t stream);
+
+/*
+ * se2_gradient_flow -- nsteps JKO steps from mu0 (the time marching of Section 2.2,
+ * eq. (GF_JKO), for the energy of se2_jko_step), all on the device: step t starts from the
+ * measure of step t-1 scaled to mass one (the inner iterations stop at a tolerance) and from
+ * its log b (step 0 from opts->init_g).  mu_out (device, required) receives the last
+ * measure; traj (device, may be NULL) receives every step's measure, [nsteps][grid];
+ * reports (HOST array of nsteps, may be NULL) one report per step.  Blocking.
+ */
+int se2_gradient_flow(se2_kernel_t k, const double *mu0, const se2_flow_t *flow, int32_t nsteps,
+                      const se2_opts_t *opts, double *mu_out, double *traj, se2_report_t *reports,
+                      se2_stream_t stream);
+
+/*
  * Lift and projection around the transport path.  Grid arrays as above, 16-byte aligned
  * (SE2_EINVAL otherwise); images and fields are [batch][iy][ix].  Stream-ordered, no host
  * synchronisation.

@@ -203,6 +203,88 @@ def ibp(logk: np.ndarray, mus: Sequence[np.ndarray], lambdas: Sequence[float], m
 
 
 # --------------------------------------------------------------------------
+# Entropic JKO step for the porous-medium gradient flow (Section 5.4: the flow of
+# F(nu) = 1/(m-1) int nu^m, eqs. (GF_JKO), (cost_GF); solved with the entropic scheme the
+# paper cites, Peyre 2015: a = mu / K b, b = prox^KL_{tau F / eps}(K^T a) / K^T a)
+# --------------------------------------------------------------------------
+
+def porous_prox_log(s: np.ndarray, c: float, m: float) -> np.ndarray:
+    """log q of the KL proximal step of the porous-medium energy at p = exp(s): the q > 0 with
+    log q + c q^(m-1) = log p, the optimality condition of min_q c/m q^m + KL(q | p) (one
+    scalar equation per element).  Solved by bisection in FP64 on [s - D, s],
+    D = max(1, s + log(c)/(m - 1)), where the left end has a non-positive residual; -inf
+    stays -inf."""
+    s = np.asarray(s, dtype=np.float64)
+    if c == 0.0:
+        return s.copy()
+    fin = np.isfinite(s)
+    hi = np.where(fin, s, 0.0)
+    lo = hi - np.maximum(1.0, hi + math.log(c) / (m - 1.0))
+    target = np.where(fin, s, 0.0)
+    for _ in range(200):          # the bracket (width < 2^11 here) shrinks to FP64 resolution
+        mid = 0.5 * (lo + hi)
+        with np.errstate(over="ignore"):
+            pos = mid + c * np.exp((m - 1.0) * mid) - target > 0
+        hi = np.where(pos, mid, hi)
+        lo = np.where(pos, lo, mid)
+    y = 0.5 * (lo + hi)
+    return np.where(fin, y, s)
+
+
+def porous_c(tau: float, eps: float, m: float, ref: float) -> float:
+    """c of porous_prox_log for F(nu) = ref/(m-1) sum (nu/ref)^m (densities against a reference
+    cell measure ref): c = (tau/eps) * m/(m-1) * ref^(1-m)."""
+    return (tau / eps) * m / (m - 1.0) * ref ** (1.0 - m)
+
+
+def jko_step(logk: np.ndarray, mu: np.ndarray, tau: float, m: float, eps: float, ref: float, max_iter: int,
+             tol: float, psi_init: Optional[np.ndarray] = None):
+    """One entropic JKO step from mu: the scaling iterations a = mu / K b and
+    b = prox(K^T a) / K^T a in log form (phi = log a, psi = log b), psi_0 = psi_init (0 if None).
+    Stops when the first-marginal L1 error sum mu |exp(phi_l - phi_{l+1}) - 1| <= tol or at
+    max_iter.  Returns (phi_l, psi_l, nu_l, iters, err) with nu_l = b_l K^T a_l, the second
+    marginal of the plan of iterate l (the next measure of the flow)."""
+    c = porous_c(tau, eps, m, ref)
+    lmu = safe_log(mu)
+    psi = np.zeros_like(mu) if psi_init is None else np.array(psi_init, dtype=np.float64)
+    phi = np.where(lmu == -np.inf, -np.inf, lmu - conv_log(logk, psi))
+    err = math.inf
+    nu = None
+    for l in range(1, max_iter + 1):
+        sv = conv_log(logk, phi)
+        y = porous_prox_log(sv, c, m)
+        psi = np.where(np.isfinite(sv), y - sv, -np.inf)
+        nu = np.exp(y)
+        phi_new = np.where(lmu == -np.inf, -np.inf, lmu - conv_log(logk, psi))
+        with np.errstate(invalid="ignore"):
+            err = float(np.sum(np.where(lmu == -np.inf, 0.0, mu * np.abs(np.expm1(phi - phi_new)))))
+        if err <= tol or l == max_iter:
+            return phi, psi, nu, l, err
+        phi = phi_new
+    return phi, psi, nu, max_iter, err
+
+
+def gradient_flow(logk: np.ndarray, mu0: np.ndarray, tau: float, m: float, eps: float, ref: float, nsteps: int,
+                  max_iter: int, tol: float):
+    """nsteps JKO steps (the time marching of eq. (GF_JKO)): step t starts from the measure of
+    step t-1 divided by its mass and from its log b.  Returns the list of the steps' measures
+    (each scaled to mass one) and of (iters, err) per step."""
+    mu, psi = mu0, None
+    traj, info = [], []
+    for _ in range(nsteps):
+        _, psi, nu, it, err = jko_step(logk, mu, tau, m, eps, ref, max_iter, tol, psi)
+        mu = nu / nu.sum()
+        traj.append(mu)
+        info.append((it, err))
+    return traj, info
+
+
+def porous_energy(nu: np.ndarray, m: float, ref: float) -> float:
+    """F(nu) = ref/(m-1) sum (nu/ref)^m."""
+    return float(ref / (m - 1.0) * np.sum((nu / ref) ** m))
+
+
+# --------------------------------------------------------------------------
 # Lift and projection around the transport path
 # --------------------------------------------------------------------------
 

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "solver.h"
@@ -146,6 +147,81 @@ struct DeviceBlock {
         if (p) (void)hipFreeAsync(p, st);
     }
 };
+
+}  // namespace
+}  // namespace se2
+
+namespace se2 {
+namespace {
+
+bool valid_flow(const Kernel *k, const se2_flow_t *flow, const se2_opts_t *opts) {
+    return flow && valid_opts(opts, k->metric.eps) && std::isfinite(flow->tau) && flow->tau >= 0.0 &&
+           std::isfinite(flow->m) && flow->m > 1.0 && std::isfinite(flow->ref) && flow->ref > 0.0 &&
+           !(opts->eps_start > k->metric.eps) &&
+           std::isfinite((flow->tau / k->metric.eps) * flow->m / (flow->m - 1.0) * std::pow(flow->ref, 1.0 - flow->m));
+}
+
+// One JKO step from the (validated) device measure mu: the scaling iterations of
+// se2_jko_step, log b started from init * init_scale (init may be null: log b = 0).
+// psi_out (device, may be null) receives the returned iterate's log b in base 2.
+int jko_run(const Kernel *k, const double *mu, const double *init, double init_scale, const se2_flow_t &flow,
+            const se2_opts_t &opts, double *mu_next, double *f_out, double *g_out, double *psi_out,
+            se2_report_t *report, hipStream_t st) {
+    Solve s;
+    s.kind = kKindJKO;
+    s.k = k;
+    s.opts = opts;
+    s.n = 1;
+    s.t_start = now_seconds();
+    // prox constant of min_q (tau/eps) F(q) + KL(q | p): log q + c q^(m-1) = log p
+    const double m = flow.m;
+    s.jko_m = m;
+    s.jko_ref = flow.ref;
+    s.jko_c = (flow.tau / k->metric.eps) * m / (m - 1.0) * std::pow(flow.ref, 1.0 - m);
+    int rc;
+    if ((rc = plan_stages(s, *k))) return rc;
+    DeviceBlock mem;
+    mem.st = st;
+    SE2_HIP(hipMallocAsync(&mem.p, solve_bytes(kKindJKO, *k, 1, prune_wanted(opts)), st));
+    solve_bind(s, mem.p);
+    if ((rc = solve_setup_jko(s, mu, init, init_scale, st))) return rc;
+    Engine eng;
+    std::vector<Solve *> one = {&s};
+    if ((rc = eng.init_first_halfstep(one, st))) return rc;
+    s.convs = 1;
+    std::vector<double> errs;
+    while (!s.done) {
+        const bool last = s.iter + 1 >= opts.max_iter;
+        const bool check = last || ((s.iter + 1) % opts.check_every == 0);
+        if ((rc = eng.step(one, check, st))) return rc;
+        if (check) {
+            if ((rc = eng.read_errors(one, errs, st))) return rc;
+            s.last_err = errs[0];
+            if (!std::isfinite(errs[0])) {
+                g_last_error = "non-finite marginal error";
+                return SE2_ENUMERIC;
+            }
+            if (opts.tol_marg_l1 >= 0 && errs[0] <= opts.tol_marg_l1) {
+                s.done = true;
+                s.status = SE2_CONVERGED;
+            } else if (last) {
+                s.done = true;
+                s.status = SE2_MAX_ITER;
+            } else {
+                s.cur ^= 1;
+            }
+        }
+    }
+    std::vector<FinishReq> fin(1);
+    fin[0].s = &s;
+    fin[0].f_out = f_out;
+    fin[0].g_out = g_out;
+    fin[0].bary_out = mu_next;
+    if ((rc = finish_solves(eng, fin, st))) return rc;
+    if (psi_out) SE2_HIP(hipMemcpyAsync(psi_out, s.psi, s.E * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (report) *report = fin[0].rep;
+    return fin[0].rc;
+}
 
 }  // namespace
 }  // namespace se2
@@ -374,6 +450,53 @@ int se2_sinkhorn(se2_kernel_t h, const double *mu, const double *nu, const se2_o
     if ((rc = finish_solves(eng, fin, st))) return rc;
     if (report) *report = fin[0].rep;
     return fin[0].rc;
+}
+
+int se2_jko_step(se2_kernel_t h, const double *mu, const se2_flow_t *flow, const se2_opts_t *opts, double *mu_next,
+                 double *f_out, double *g_out, se2_report_t *report, se2_stream_t stream) {
+    const Kernel *k = reinterpret_cast<const Kernel *>(h);
+    if (!k || !mu || !mu_next || !valid_flow(k, flow, opts)) return SE2_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const size_t E = static_cast<size_t>(k->grid.nx) * k->grid.ny * k->grid.ntheta;
+    int rc = validate_measure(mu, E, 1e-9, st);
+    if (rc) return rc;
+    return jko_run(k, mu, opts->init_g, kLog2e, *flow, *opts, mu_next, f_out, g_out, nullptr, report, st);
+}
+
+int se2_gradient_flow(se2_kernel_t h, const double *mu0, const se2_flow_t *flow, int32_t nsteps,
+                      const se2_opts_t *opts, double *mu_out, double *traj, se2_report_t *reports,
+                      se2_stream_t stream) {
+    const Kernel *k = reinterpret_cast<const Kernel *>(h);
+    if (!k || !mu0 || !mu_out || nsteps < 1 || !valid_flow(k, flow, opts)) return SE2_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const size_t E = static_cast<size_t>(k->grid.nx) * k->grid.ny * k->grid.ntheta;
+    int rc = validate_measure(mu0, E, 1e-9, st);
+    if (rc) return rc;
+    // current measure, next measure, log b carried between steps (base 2), mass scratch
+    const size_t Eb = (E * sizeof(double) + 255) / 256 * 256;
+    DeviceBlock mem;
+    mem.st = st;
+    SE2_HIP(hipMallocAsync(&mem.p, 3 * Eb + (2 + 2 * 256) * sizeof(double), st));
+    double *cur = reinterpret_cast<double *>(static_cast<char *>(mem.p));
+    double *nxt = reinterpret_cast<double *>(static_cast<char *>(mem.p) + Eb);
+    double *psi = reinterpret_cast<double *>(static_cast<char *>(mem.p) + 2 * Eb);
+    double *stats = reinterpret_cast<double *>(static_cast<char *>(mem.p) + 3 * Eb);
+    SE2_HIP(hipMemcpyAsync(cur, mu0, E * sizeof(double), hipMemcpyDeviceToDevice, st));
+    for (int t = 0; t < nsteps; ++t) {
+        se2_report_t rep{};
+        const double *init = t == 0 ? opts->init_g : psi;
+        const double scale = t == 0 ? kLog2e : 1.0;
+        if ((rc = jko_run(k, cur, init, scale, *flow, *opts, nxt, nullptr, nullptr, psi, &rep, st))) return rc;
+        if (reports) reports[t] = rep;
+        // the next step starts from the step's measure scaled to mass one (the inner iterations
+        // stop at a tolerance, so its mass is one to within that tolerance)
+        if ((rc = launch_normalise(nxt, E, stats, st))) return rc;
+        if (traj) SE2_HIP(hipMemcpyAsync(traj + E * t, nxt, E * sizeof(double), hipMemcpyDeviceToDevice, st));
+        std::swap(cur, nxt);
+    }
+    SE2_HIP(hipMemcpyAsync(mu_out, cur, E * sizeof(double), hipMemcpyDeviceToDevice, st));
+    SE2_HIP(hipStreamSynchronize(st));
+    return SE2_OK;
 }
 
 int se2_barycenter(se2_kernel_t h, int32_t n, const double *const *mus, const double *lambdas,

@@ -290,6 +290,71 @@ __global__ __launch_bounds__(kThreads) void k_dot_pos(const double *__restrict__
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// KL proximal step of the porous-medium energy (JKO step of the gradient flow of
+// F(nu) = ref/(m-1) sum (nu/ref)^m): from s = ln K^T a, the log q with
+// log q + c q^(m-1) = s, and the new b-potential log b = log q - s (base-2 units in and
+// out).  With z = c (m-1) q^(m-1) the equation becomes z + ln z = A,
+// A = (m-1) s + ln(c (m-1)) (Wright's omega function of A), solved by Newton's method in
+// u = ln z from a start right of the root (e^u + u - A is increasing and convex, so the
+// iterates decrease monotonically): u0 = A for A <= 1, else ln A.  Then
+// ln q = s - z / (m-1), so ln b = -z / (m-1).
+__global__ __launch_bounds__(kThreads) void k_porous_prox(const double *__restrict__ lsum, double *__restrict__ psi,
+                                                          size_t n, double c, double m) {
+    const double lc = (c > 0.0) ? log(c * (m - 1.0)) : 0.0;
+    for (size_t i = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<size_t>(gridDim.x) * kThreads) {
+        const double s2 = lsum[i];
+        if (s2 == -INFINITY) {
+            psi[i] = -INFINITY;  // no mass reaches this element: b is arbitrary there
+            continue;
+        }
+        double lb = 0.0;  // ln b = ln q - s; exactly 0 (b = 1) when the energy is off
+        if (c > 0.0) {
+            const double s = s2 * kLn2;
+            const double A = (m - 1.0) * s + lc;
+            double u = (A <= 1.0) ? A : log(A);
+            for (int it = 0; it < 64; ++it) {
+                const double e = exp(u);
+                const double du = (e + u - A) / (e + 1.0);
+                u -= du;
+                if (!(fabs(du) > 1e-15 * (1.0 + fabs(u)))) break;
+            }
+            lb = -exp(u) / (m - 1.0);
+        }
+        psi[i] = lb * kLog2e;
+    }
+}
+
+// p /= sums[0] (a measure scaled to mass one; the sum from the validation reduction).
+__global__ __launch_bounds__(kThreads) void k_div_by(double *__restrict__ p, size_t n, const double *__restrict__ sums) {
+    const double t = sums[0];
+    for (size_t i = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<size_t>(gridDim.x) * kThreads)
+        p[i] = p[i] / t;
+}
+
+// out = 2^(a + b) (the next measure of a JKO step: nu = b K^T a).
+__global__ __launch_bounds__(kThreads) void k_exp2_sum(const double *__restrict__ a, const double *__restrict__ b,
+                                                       double *__restrict__ out, size_t n) {
+    for (size_t i = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<size_t>(gridDim.x) * kThreads)
+        out[i] = exp2(a[i] + b[i]);
+}
+
+// Per block: sum of ref/(m-1) (nu/ref)^m with nu = 2^(a + b), fixed tree order.
+__global__ __launch_bounds__(kThreads) void k_porous_energy(const double *__restrict__ a,
+                                                            const double *__restrict__ b, size_t n, size_t chunk,
+                                                            double m, double lref2, double scale,
+                                                            double *__restrict__ part) {
+    __shared__ double sh[kThreads];
+    const size_t b0 = blockIdx.x * chunk;
+    const size_t b1 = (b0 + chunk < n) ? b0 + chunk : n;
+    double s = 0.0;
+    for (size_t i = b0 + threadIdx.x; i < b1; i += kThreads) s += exp2(m * ((a[i] + b[i]) - lref2));
+    s = block_tree_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s * scale;
+}
+
 int grid_for(size_t n) {
     size_t b = (n + kThreads - 1) / kThreads;
     if (b > 8192) b = 8192;
@@ -438,6 +503,38 @@ int launch_plan_cost_tab(const Kernel &k, const double *const *phi_tab, const do
                                     partials); break;
         default: return SE2_EINVAL;
     }
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+int launch_porous_prox(const double *lsum, double *psi, size_t n, double c, double m, hipStream_t s) {
+    if (n == 0) return SE2_OK;
+    hipLaunchKernelGGL(k_porous_prox, dim3(grid_for(n)), dim3(kThreads), 0, s, lsum, psi, n, c, m);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+int launch_normalise(double *p, size_t n, double *stats, hipStream_t s) {
+    if (n == 0) return SE2_OK;
+    int rc = launch_validate(p, n, stats, s);  // stats[0] = sum (fixed order)
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_div_by, dim3(grid_for(n)), dim3(kThreads), 0, s, p, n, stats);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+int launch_exp2_sum(const double *a, const double *b, double *out, size_t n, hipStream_t s) {
+    if (n == 0) return SE2_OK;
+    hipLaunchKernelGGL(k_exp2_sum, dim3(grid_for(n)), dim3(kThreads), 0, s, a, b, out, n);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+int launch_porous_energy(const double *a, const double *b, size_t n, double m, double ref, double *partials,
+                         int nblocks, hipStream_t s) {
+    const size_t chunk = (n + nblocks - 1) / nblocks;
+    hipLaunchKernelGGL(k_porous_energy, dim3(nblocks), dim3(kThreads), 0, s, a, b, n, chunk == 0 ? 1 : chunk, m,
+                       std::log2(ref), ref / (m - 1.0), partials);
     SE2_HIP(hipGetLastError());
     return SE2_OK;
 }

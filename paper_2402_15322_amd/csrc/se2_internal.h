@@ -153,7 +153,7 @@ int launch_conv_f64(const Kernel &k, const double *in, double *out, int batch, h
 // elementwise.hip
 int launch_scale(const double *in, double *out, size_t n, double mul, hipStream_t s);
 int launch_log2_measure(const double *m, double *logm, size_t n, hipStream_t s);
-int launch_validate(const double *m, size_t n, double *d_stats /* 3 doubles */, hipStream_t s);
+int launch_validate(const double *m, size_t n, double *d_stats /* 2 + 2 * 256 doubles */, hipStream_t s);
 int launch_fill(double *p, size_t n, double v, hipStream_t s);
 int launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t s);
 // One FP64 sum of part[begin, end): the marginal-error partials of one job.
@@ -175,6 +175,14 @@ int launch_plan_cost(const Kernel &k, const double *phi2, const double *psi2, do
 // laid out [job][cost | mass][nblocks].
 int launch_plan_cost_tab(const Kernel &k, const double *const *phi_tab, const double *const *psi_tab, int njobs,
                          double *partials, int nblocks, hipStream_t s);
+// JKO step of the porous-medium flow: psi = prox(lsum) - lsum (base 2), nu = 2^(psi + lsum),
+// and per-block partials of F(nu) = ref/(m-1) sum (nu/ref)^m.
+int launch_porous_prox(const double *lsum, double *psi, size_t n, double c, double m, hipStream_t s);
+int launch_exp2_sum(const double *a, const double *b, double *out, size_t n, hipStream_t s);
+// p /= sum(p) on the device; stats holds 2 + 2 * 256 doubles.
+int launch_normalise(double *p, size_t n, double *stats, hipStream_t s);
+int launch_porous_energy(const double *a, const double *b, size_t n, double m, double ref, double *partials,
+                         int nblocks, hipStream_t s);
 int launch_reduce_fixed(const double *partials, int count, int stride, double *out, hipStream_t s);
 int launch_exp2_out(const double *in2, double *out, size_t n, hipStream_t s);
 int launch_dot_exp(const double *f2, const double *m, size_t n, double *partials, int nblocks, hipStream_t s);

@@ -65,11 +65,11 @@ size_t carve(Solve &s, int kind, const Kernel &k, int n, bool prune, void *mem) 
     const size_t E = static_cast<size_t>(k.grid.nx) * k.grid.ny * k.grid.ntheta;
     const int tiles = tiles_of(k.grid.nx) * tiles_of(k.grid.ny);
     prune = prune && conv_lse_sparse_fits(k.grid.ntheta, k.metric.radius);
-    const int nj = kind == SE2_REQ_OT ? 1 : n;
+    const int nj = kind != SE2_REQ_BARYCENTER ? 1 : n;
     const size_t npart = static_cast<size_t>(tiles) * k.grid.ntheta * nj;
     const size_t ncost = 2 * static_cast<size_t>(cost_blocks(E)) * nj + 512;
     Carver c{static_cast<char *>(mem)};
-    if (kind == SE2_REQ_OT) {
+    if (kind != SE2_REQ_BARYCENTER) {
         s.lmu = c.take<double>(E);
         s.lnu = c.take<double>(E);
         s.phi[0] = c.take<double>(E);
@@ -77,6 +77,7 @@ size_t carve(Solve &s, int kind, const Kernel &k, int n, bool prune, void *mem) 
         s.psi = c.take<double>(E);
         s.ls_phi = carve_lists(c, k, E, tiles, prune);
         s.ls_psi = carve_lists(c, k, E, tiles, prune);
+        if (kind == kKindJKO) s.lsum = c.take<double>(E);
     } else {
         s.lm.assign(n, nullptr);
         s.lv.assign(n, nullptr);
@@ -152,7 +153,7 @@ int reset_list(const ListSet &l, const Solve &s, hipStream_t st) {
 
 int solve_reset_lists(Solve &s, hipStream_t st) {
     int rc = SE2_OK;
-    if (s.kind == SE2_REQ_OT) {
+    if (ot_like(s)) {
         if ((rc = reset_list(s.ls_phi, s, st))) return rc;
         return reset_list(s.ls_psi, s, st);
     }
@@ -204,7 +205,7 @@ int advance_stages(Engine &eng, const std::vector<Solve *> &solves, hipStream_t 
     for (Solve *s : solves) {
         if (s->done || final_stage(*s) || s->iter < (s->stage + 1) * s->opts.stage_iters) continue;
         const double r = s->stage_eps[s->stage] / s->stage_eps[s->stage + 1];
-        if (s->kind == SE2_REQ_OT) {
+        if (ot_like(*s)) {
             if ((rc = launch_scale(s->psi, s->psi, s->E, r, st))) return rc;
             if ((rc = drop_lists(s->ls_phi, *s, st)) || (rc = drop_lists(s->ls_psi, *s, st))) return rc;
         } else {
@@ -236,6 +237,25 @@ int solve_setup_ot(Solve &s, const double *mu, const double *nu, const double *i
     if ((rc = solve_reset_lists(s, st))) return rc;
     std::vector<int32_t> off = {0, s.tiles * s.k->grid.ntheta};
     SE2_HIP(hipMemcpyAsync(s.offsets, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    SE2_HIP(hipStreamSynchronize(st));  // `off` is a host temporary
+    s.cur = 0;
+    s.iter = 0;
+    s.done = false;
+    return SE2_OK;
+}
+
+int solve_setup_jko(Solve &s, const double *mu, const double *init, double init_scale, hipStream_t st) {
+    s.mu_lin = mu;
+    int rc;
+    if ((rc = launch_log2_measure(mu, s.lmu, s.E, st))) return rc;
+    if (init) {
+        if ((rc = launch_scale(init, s.psi, s.E, init_scale, st))) return rc;
+    } else if ((rc = launch_fill(s.psi, s.E, 0.0, st))) {
+        return rc;
+    }
+    if ((rc = solve_reset_lists(s, st))) return rc;
+    const int32_t off[2] = {0, s.tiles * s.k->grid.ntheta};
+    SE2_HIP(hipMemcpyAsync(s.offsets, off, sizeof(off), hipMemcpyHostToDevice, st));
     SE2_HIP(hipStreamSynchronize(st));  // `off` is a host temporary
     s.cur = 0;
     s.iter = 0;
@@ -447,9 +467,14 @@ int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool wit
                 nblocks[g] += j.tiles;
                 jobs[g].push_back(j);
             };
-            if (s->kind == SE2_REQ_OT) {
+            if (ot_like(*s)) {
                 ConvJob j = base;
-                if (stage == 0) {  // b-update: psi = log nu - LSE(L + phi[cur])
+                if (stage == 0 && s->kind == kKindJKO) {  // JKO: lsum = LSE(L + phi[cur]); the prox follows
+                    j.in = s->phi[s->cur];
+                    j.out = s->lsum;
+                    j.epi = EPI_RAW;
+                    attach(j, s->ls_phi);
+                } else if (stage == 0) {  // b-update: psi = log nu - LSE(L + phi[cur])
                     j.in = s->phi[s->cur];
                     j.out = s->psi;
                     j.aux = s->lnu;
@@ -506,7 +531,7 @@ int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool wit
             }
             for (Solve *s : solves) {
                 if (s->k->grid.ntheta != nt) continue;
-                const double c = (s->kind == SE2_REQ_OT) ? 1.0 : s->n;
+                const double c = ot_like(*s) ? 1.0 : s->n;
                 pe.terms += c * conv_terms(*s->k);
                 pe.outputs += c * static_cast<double>(s->E);
             }
@@ -521,7 +546,7 @@ int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool wit
             SE2_HIP(hipEventRecord(pe.b, st));
             pending_.push_back(pe);
         }
-        for (Solve *s : solves) s->convs += (s->k->grid.ntheta == nt) ? (s->kind == SE2_REQ_OT ? 1 : s->n) : 0;
+        for (Solve *s : solves) s->convs += (s->k->grid.ntheta == nt) ? (ot_like(*s) ? 1 : s->n) : 0;
     }
     return SE2_OK;
 }
@@ -531,7 +556,7 @@ int Engine::init_first_halfstep(const std::vector<Solve *> &solves, hipStream_t 
     if (rc) return rc;
     // the first a-update wrote phi[1 - cur]: that is the current a-potential now
     for (Solve *s : solves)
-        if (s->kind == SE2_REQ_OT) s->cur ^= 1;
+        if (ot_like(*s)) s->cur ^= 1;
     return SE2_OK;
 }
 
@@ -539,6 +564,11 @@ int Engine::step(const std::vector<Solve *> &solves, bool check, hipStream_t st)
     int rc = launch_stage(solves, 0, false, st);
     if (rc) return rc;
     for (Solve *s : solves) {
+        if (s->kind == kKindJKO) {
+            // b = prox(K^T a) / K^T a
+            if ((rc = launch_porous_prox(s->lsum, s->psi, s->E, s->jko_c, s->jko_m, st))) return rc;
+            continue;
+        }
         if (s->kind != SE2_REQ_BARYCENTER) continue;
         rc = launch_ibp_combine(s->d_lv, s->d_ld, s->d_lam, s->n, s->E, s->combine_part, s->logbar, st);
         if (rc) return rc;
@@ -547,7 +577,7 @@ int Engine::step(const std::vector<Solve *> &solves, bool check, hipStream_t st)
     if (rc) return rc;
     for (Solve *s : solves) {
         s->iter += 1;
-        if (!check && s->kind == SE2_REQ_OT) s->cur ^= 1;  // the new a-potential becomes current
+        if (!check && ot_like(*s)) s->cur ^= 1;  // the new a-potential becomes current
     }
     return check ? sum_errors(solves, st) : SE2_OK;
 }
@@ -555,7 +585,7 @@ int Engine::step(const std::vector<Solve *> &solves, bool check, hipStream_t st)
 int Engine::sum_errors(const std::vector<Solve *> &solves, hipStream_t st) {
     std::vector<SumItem> items;
     for (Solve *s : solves) {
-        const int nj = (s->kind == SE2_REQ_OT) ? 1 : s->n;
+        const int nj = ot_like(*s) ? 1 : s->n;
         const int per = s->tiles * s->k->grid.ntheta;
         for (int i = 0; i < nj; ++i) items.push_back(SumItem{s->partial, i * per, (i + 1) * per});
     }
@@ -587,7 +617,7 @@ int Engine::sum_errors(const std::vector<Solve *> &solves, hipStream_t st) {
 int Engine::read_errors(const std::vector<Solve *> &solves, std::vector<double> &max_err, hipStream_t st) {
     // the errors of the last check, in the item order of sum_errors()
     size_t total = 0;
-    for (Solve *s : solves) total += (s->kind == SE2_REQ_OT) ? 1 : s->n;
+    for (Solve *s : solves) total += ot_like(*s) ? 1 : s->n;
     if (total != items_key_.size() || !d_errs_) return SE2_EINVAL;
     if (total > cap_err_) {
         if (h_err_) SE2_HIP(hipHostFree(h_err_));
@@ -603,7 +633,7 @@ int Engine::read_errors(const std::vector<Solve *> &solves, std::vector<double> 
     max_err.assign(solves.size(), 0.0);
     size_t off = 0;
     for (size_t q = 0; q < solves.size(); ++q) {
-        const size_t c = (solves[q]->kind == SE2_REQ_OT) ? 1 : solves[q]->n;
+        const size_t c = ot_like(*solves[q]) ? 1 : solves[q]->n;
         double m = 0.0;
         for (size_t i = 0; i < c; ++i) {
             const double e = h_err_[off + i];
@@ -689,7 +719,7 @@ int finish_solves(Engine &eng, std::vector<FinishReq> &reqs, hipStream_t st) {
         const int nb = cost_blocks(s.E);
         double *part = s.partial;  // scratch: >= 2 * nb + 512 doubles
         int rc = SE2_OK;
-        if (s.kind == SE2_REQ_OT) {
+        if (ot_like(s)) {
             const double scale = k.metric.eps * kLn2;  // base-2 log-scaling -> eps * natural log
             const double *phi = s.phi[s.cur];
             if (q.f_out && (rc = launch_scale(phi, q.f_out, s.E, scale, st))) return rc;
@@ -697,6 +727,17 @@ int finish_solves(Engine &eng, std::vector<FinishReq> &reqs, hipStream_t st) {
             if ((rc = launch_plan_cost(k, phi, s.psi, part, nb, st))) return rc;
             if ((rc = launch_reduce_fixed(part, nb, 2, s.err + 2, st))) return rc;
             const int dnb = 256;
+            if (s.kind == kKindJKO) {
+                // the next measure nu = b K^T a and its energy F(nu)
+                if (q.bary_out && (rc = launch_exp2_sum(s.psi, s.lsum, q.bary_out, s.E, st))) return rc;
+                if ((rc = launch_porous_energy(s.psi, s.lsum, s.E, s.jko_m, s.jko_ref, part, dnb, st))) return rc;
+                if ((rc = launch_reduce_fixed(part, dnb, 1, s.err + 4, st))) return rc;
+                if (s.opts.final_check) {
+                    chk_a.push_back(check_job(k, s.psi, s.lmu, phi, s.partial, s.tiles));
+                    nt_a.push_back(k.grid.ntheta);
+                }
+                continue;
+            }
             if ((rc = launch_dot_exp(phi, s.mu_lin, s.E, part, dnb, st))) return rc;
             if ((rc = launch_reduce_fixed(part, dnb, 1, s.err + 4, st))) return rc;
             if ((rc = launch_dot_exp(s.psi, s.nu_lin, s.E, part, dnb, st))) return rc;
@@ -736,7 +777,7 @@ int finish_solves(Engine &eng, std::vector<FinishReq> &reqs, hipStream_t st) {
         for (FinishReq &q : reqs) {
             Solve &s = *q.s;
             if (!s.opts.final_check) continue;
-            const bool ot = s.kind == SE2_REQ_OT;
+            const bool ot = ot_like(s);
             if ((rc = launch_sum_partials(s.partial, s.offsets, ot ? 1 : s.n, s.err + (ot ? 6 : 3 + 2 * s.n), st)))
                 return rc;
         }
@@ -753,7 +794,7 @@ int finish_solves(Engine &eng, std::vector<FinishReq> &reqs, hipStream_t st) {
     // 3. reports
     for (FinishReq &q : reqs) {
         Solve &s = *q.s;
-        const int nj = (s.kind == SE2_REQ_OT) ? 1 : s.n;
+        const int nj = ot_like(s) ? 1 : s.n;
         std::vector<double> e(3 * static_cast<size_t>(nj) + 8);
         SE2_HIP(hipMemcpy(e.data(), s.err, e.size() * sizeof(double), hipMemcpyDeviceToHost));
         se2_report_t r{};
@@ -763,7 +804,14 @@ int finish_solves(Engine &eng, std::vector<FinishReq> &reqs, hipStream_t st) {
         r.marg_l1_f64 = -1.0;
         r.convs = s.convs;
         r.scaling_iters = s.scaling_iters;
-        if (s.kind == SE2_REQ_OT) {
+        if (s.kind == kKindJKO) {
+            r.cost = e[2];
+            r.mass = e[3];
+            r.dual = e[4];  // F(nu) of the next measure
+            if (s.opts.final_check) r.marg_l1_f64 = e[6];
+            if ((rc = read_work(s.ls_phi, s.tiles, &r.terms_dense, &r.terms_sparse))) return rc;
+            if ((rc = read_work(s.ls_psi, s.tiles, &r.terms_dense, &r.terms_sparse))) return rc;
+        } else if (ot_like(s)) {
             r.cost = e[2];
             r.mass = e[3];
             r.dual = s.k->metric.eps * kLn2 * (e[4] + e[5]);

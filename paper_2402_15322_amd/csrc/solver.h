@@ -17,6 +17,9 @@ struct DevBuf {
     size_t n = 0;
 };
 
+// Solve kinds: the two public request kinds and the JKO step of a gradient flow.
+constexpr int kKindJKO = 2;
+
 // One solve, resident on the device.  All potentials are base-2 log-scalings.
 struct Solve {
     int kind = SE2_REQ_OT;           // SE2_REQ_OT or SE2_REQ_BARYCENTER
@@ -29,6 +32,9 @@ struct Solve {
     ListSet ls_phi, ls_psi;          // pruning state of the b-update (input phi) and a-update (input psi)
     const double *mu_lin = nullptr, *nu_lin = nullptr;  // FP64 inputs (dual, final checks)
     int cur = 0;
+    // JKO step: lsum = log2 K^T a of the last b-update; prox constant c, exponent m, cell measure
+    double *lsum = nullptr;
+    double jko_c = 0.0, jko_m = 2.0, jko_ref = 1.0;
     // barycenter: only measures with lambda > 0
     int n = 0;
     std::vector<double> lam;
@@ -63,6 +69,9 @@ struct Solve {
     size_t bytes = 0;
 };
 
+// OT and JKO solves have one scaling pair (a, b) with a double-buffered a-potential.
+inline bool ot_like(const Solve &s) { return s.kind != SE2_REQ_BARYCENTER; }
+
 // Window entries inside the grid summed over all outputs: the algorithmic LSE
 // terms of one convolution of a grid array with this kernel.
 double conv_terms(const Kernel &k);
@@ -81,6 +90,8 @@ void solve_bind(Solve &s, void *mem);
 int solve_reset_lists(Solve &s, hipStream_t st);
 int solve_setup_ot(Solve &s, const double *mu, const double *nu, const double *init_g_natural, hipStream_t st);
 int solve_setup_bary(Solve &s, const std::vector<const double *> &mus, hipStream_t st);
+// init (may be null: log b = 0) times init_scale gives the first log2 b.
+int solve_setup_jko(Solve &s, const double *mu, const double *init, double init_scale, hipStream_t st);
 
 // eps-scaling schedule of `o` for a kernel at `eps`: eps_start * factor^s while above eps,
 // then eps itself (only eps when the scheme is off).  SE2_EINVAL for a bad schedule (factor
@@ -169,8 +180,8 @@ int advance_stages(Engine &eng, const std::vector<Solve *> &solves, hipStream_t 
 // each request's report and status are filled in.  Blocking on `st`.
 struct FinishReq {
     Solve *s = nullptr;
-    double *f_out = nullptr, *g_out = nullptr;  // OT outputs (may be null)
-    double *bary_out = nullptr;                 // barycenter output
+    double *f_out = nullptr, *g_out = nullptr;  // OT and JKO outputs (may be null)
+    double *bary_out = nullptr;                 // barycenter output, or the next measure of a JKO step
     se2_report_t rep{};
     int rc = SE2_OK;
 };

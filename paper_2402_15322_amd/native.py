@@ -31,7 +31,7 @@ EXPORTED = [
     "se2_conv", "se2_conv_log", "se2_sinkhorn", "se2_barycenter", "se2_solve_queue_create",
     "se2_request_bytes", "se2_solve_queue_submit", "se2_solve_queue_poll", "se2_solve_queue_wait", "se2_solve_queue_times",
     "se2_solve_queue_stats", "se2_solve_queue_profile", "se2_solve_queue_kernel_time", "se2_solve_queue_destroy",
-    "se2_lift_field", "se2_project", "se2_split_signed",
+    "se2_lift_field", "se2_project", "se2_split_signed", "se2_jko_step", "se2_gradient_flow",
 ]
 
 
@@ -60,6 +60,10 @@ class Report(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Flow(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("m", ctypes.c_double), ("ref", ctypes.c_double)]
 
 
 class Request(ctypes.Structure):
@@ -98,6 +102,10 @@ def load() -> ctypes.CDLL:
             "se2_lift_field": ([ctypes.POINTER(Grid), vp, vp, vp, i32, vp], ctypes.c_int),
             "se2_project": ([ctypes.POINTER(Grid), vp, vp, vp, vp, vp, i32, vp], ctypes.c_int),
             "se2_split_signed": ([vp, sz, vp, vp, vp], ctypes.c_int),
+            "se2_jko_step": ([vp, vp, ctypes.POINTER(Flow), ctypes.POINTER(Opts), vp, vp, vp, ctypes.POINTER(Report),
+                              vp], ctypes.c_int),
+            "se2_gradient_flow": ([vp, vp, ctypes.POINTER(Flow), i32, ctypes.POINTER(Opts), vp, vp,
+                                   ctypes.POINTER(Report), vp], ctypes.c_int),
             "se2_sinkhorn": ([vp, vp, vp, ctypes.POINTER(Opts), vp, vp, ctypes.POINTER(Report), vp], ctypes.c_int),
             "se2_barycenter": ([vp, i32, vp, vp, ctypes.POINTER(Opts), vp, ctypes.POINTER(Report), vp],
                                ctypes.c_int),
@@ -236,6 +244,24 @@ def se2_sinkhorn(k: Kernel, mu, nu, o: Opts, f_out=None, g_out=None, stream=None
     _check(load().se2_sinkhorn(k.handle, _ptr(mu), _ptr(nu), ctypes.byref(o), _ptr(f_out), _ptr(g_out),
                                ctypes.byref(rep), _stream(stream)), "se2_sinkhorn")
     return rep.as_dict()
+
+
+def se2_jko_step(k: Kernel, mu, tau: float, m: float, ref: float, o: Opts, mu_next, f_out=None, g_out=None,
+                 stream=None) -> dict:
+    rep = Report()
+    fl = Flow(float(tau), float(m), float(ref))
+    _check(load().se2_jko_step(k.handle, _ptr(mu), ctypes.byref(fl), ctypes.byref(o), _ptr(mu_next), _ptr(f_out),
+                               _ptr(g_out), ctypes.byref(rep), _stream(stream)), "se2_jko_step")
+    return rep.as_dict()
+
+
+def se2_gradient_flow(k: Kernel, mu0, tau: float, m: float, ref: float, nsteps: int, o: Opts, mu_out, traj=None,
+                      stream=None) -> List[dict]:
+    reps = (Report * int(nsteps))()
+    fl = Flow(float(tau), float(m), float(ref))
+    _check(load().se2_gradient_flow(k.handle, _ptr(mu0), ctypes.byref(fl), int(nsteps), ctypes.byref(o), _ptr(mu_out),
+                                    _ptr(traj), reps, _stream(stream)), "se2_gradient_flow")
+    return [r.as_dict() for r in reps]
 
 
 def se2_barycenter(k: Kernel, mus: Sequence, lambdas: Sequence[float], o: Opts, bary_out, stream=None) -> dict:

@@ -403,3 +403,17 @@ def stroke_images(n: int, seed: int = 6000, workers: int = 1) -> np.ndarray:
     parts = [(seed, lo, min(n, lo + step)) for lo in range(0, n, step)]
     with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
         return np.concatenate(list(ex.map(_stroke_chunk, parts)))
+
+
+def line_completion(seed: int = 7000, n: int = 64) -> np.ndarray:
+    """The gradient-flow input of the line-completion experiment (Section 5.4): one dominant
+    line through the middle, broken into 6 dashes of 6 px with 3 px gaps, amid 16 random short
+    line elements (2-4 px), on an n x n x 16 grid; sigma_xy = 1 px, floor 1e-6."""
+    g = Grid(n, n, 16)
+    r = rng_for(seed, 0)
+    alpha = r.uniform(0.0, math.pi)
+    c = (n - 1) / 2.0
+    segs = [Segment(c + t * math.cos(alpha), c + t * math.sin(alpha), alpha, 6.0)
+            for t in (-22.5, -13.5, -4.5, 4.5, 13.5, 22.5)]
+    segs += draw_segments(r, g, 16, 2.0, 4.0, margin=1.0)
+    return splat_segments(g, segs, 1.0, 1e-6)

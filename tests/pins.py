@@ -438,6 +438,69 @@ def pin_lift_and_project():
     assert np.max(np.abs(b - (plus.sum(-1) - minus.sum(-1)))) < 1e-15
 
 
+# --------------------------------------------------------------------------
+# JKO step of the porous-medium flow (Section 5.4; entropic scheme of Peyre 2015): the
+# proximal step solves its scalar optimality condition and minimises its objective; tau = 0
+# gives the entropic blur K^T (mu / K 1) after one iteration; the converged plan is a
+# stationary point of the JKO objective on its constraint set {pi 1 = mu}; mass is kept;
+# the step commutes with the 90-degree grid symmetry
+# --------------------------------------------------------------------------
+
+def pin_jko_step():
+    rng = np.random.default_rng(19)
+    for c in (1e-3, 1.0, 1e3):
+        for m in (2.0, 5.0):
+            sv = rng.uniform(-40.0, 40.0, 200)
+            y = oracle.porous_prox_log(sv, c, m)
+            assert np.all(np.abs(y + c * np.exp((m - 1) * y) - sv) <= 1e-11 * (1 + np.abs(sv)))
+            p = np.exp(sv)
+            obj = lambda q: c / m * q ** m + q * (np.log(q) - sv) - q
+            q = np.exp(y)
+            for f in (1 + 1e-5, 1 - 1e-5):
+                assert np.all(obj(q) <= obj(q * f) + 1e-12 * np.abs(obj(q)))
+    assert np.array_equal(oracle.porous_prox_log(sv, 0.0, 5.0), sv)
+    # tau = 0: the entropic blur after one iteration
+    nx, ny, nt, R, w, eps = 4, 3, 4, 2, (1.0, 2.0, 1.0), 0.7
+    logk, cost = oracle.kernel_table(nt, False, w, eps, R)
+    K = np.exp(dense.dense_logk(nx, ny, nt, False, w, eps, R))
+    mu = _rand_measure(rng, (ny, nx, nt))
+    phi, psi, nu, it, err = oracle.jko_step(logk, mu, 0.0, 5.0, eps, 1.0, 50, 1e-14)
+    assert it == 1 and err == 0.0
+    blur = K.T @ (mu.reshape(-1) / (K @ np.ones(mu.size)))
+    assert np.max(np.abs(nu.reshape(-1) - blur)) <= 1e-14
+    # converged step: mass, stationarity of J(pi) = <C, pi> + eps sum pi (log pi - 1) + tau F(pi^T 1)
+    ref = 1.0 / mu.size
+    for tau, m in ((1e-3, 5.0), (0.05, 2.0)):
+        phi, psi, nu, it, err = oracle.jko_step(logk, mu, tau, m, eps, ref, 5000, 1e-13)
+        assert err <= 1e-13 and abs(nu.sum() - 1.0) <= 1e-12
+        LM = dense.dense_logk(nx, ny, nt, False, w, eps, R)          # -inf outside the window
+        win = np.isfinite(LM)
+        C = np.where(win, -eps * LM, 0.0)
+        P = np.exp(phi.reshape(-1)[:, None] + LM + psi.reshape(-1)[None, :])
+        assert np.max(np.abs(P.sum(axis=1) - mu.reshape(-1))) <= 1e-13
+        assert np.max(np.abs(P.sum(axis=0) - nu.reshape(-1))) <= 1e-14
+        F = lambda v: ref / (m - 1) * np.sum((v / ref) ** m)
+        J = lambda Q: (np.sum(Q * C) + eps * np.sum(np.where(win, Q * (np.log(np.where(win, Q, 1.0)) - 1), 0.0))
+                       + tau * F(Q.sum(axis=0)))
+        h = rng.normal(0.0, 1.0, P.shape)
+        h -= (P * h).sum(axis=1, keepdims=True) / P.sum(axis=1, keepdims=True)   # keeps pi 1 = mu
+        t = 1e-4
+        jp, j0, jm = J(P * (1 + t * h)), J(P), J(P * (1 - t * h))
+        assert jp >= j0 and jm >= j0
+        assert abs(jp - jm) <= 1e-6 * (jp + jm - 2 * j0) / t    # first variation vanishes
+        # a wrong proximal constant breaks stationarity
+        _, psi2, nu2, _, _ = oracle.jko_step(logk, mu, 2 * tau, m, eps, ref, 5000, 1e-13)
+        P2 = np.exp(oracle.jko_step(logk, mu, 2 * tau, m, eps, ref, 5000, 1e-13)[0].reshape(-1)[:, None] + LM
+                    + psi2.reshape(-1)[None, :])
+        assert abs(J(P2 * (1 + t * h)) - J(P2 * (1 - t * h))) > 1e3 * abs(jp - jm)
+    # the 90-degree grid symmetry
+    logk, _ = oracle.kernel_table(8, False, (1.0, 2.0, 1.0), 0.5, 2)
+    mu = _rand_measure(rng, (6, 6, 8))
+    a = oracle.jko_step(logk, mu, 1e-4, 5.0, 0.5, 1.0 / mu.size, 40, -1.0)[2]
+    b = oracle.jko_step(logk, rot90(mu), 1e-4, 5.0, 0.5, 1.0 / mu.size, 40, -1.0)[2]
+    assert np.max(np.abs(b - rot90(a))) <= 1e-12 * np.max(a)
+
+
 ALL_PINS = [
     pin_rho_closed_forms,
     pin_rho_inverse_symmetry,
@@ -456,4 +519,5 @@ ALL_PINS = [
     pin_small_eps_matches_linear_program,
     pin_eps_scaling,
     pin_lift_and_project,
+    pin_jko_step,
 ]

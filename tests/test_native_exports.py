@@ -37,7 +37,7 @@ def test_binding_struct_layouts_match_header(tmp_path):
     import subprocess
     from paper_2402_15322_amd import native
     structs = {"se2_grid_t": native.Grid, "se2_metric_t": native.Metric, "se2_opts_t": native.Opts,
-               "se2_report_t": native.Report, "se2_request_t": native.Request}
+               "se2_report_t": native.Report, "se2_request_t": native.Request, "se2_flow_t": native.Flow}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
