@@ -270,10 +270,11 @@ int se2_project(const se2_grid_t *grid, const double *u, const double *u_minus, 
 int se2_split_signed(const double *u, size_t n, double *plus, double *minus, se2_stream_t stream);
 
 /*
- * Serving queue.  A worker thread owns one stream on the current device.  Requests
- * are admitted in arrival order while the HBM budget and the slot count allow;
- * every admitted solve keeps its potentials resident and all admitted solves
- * advance together, one batched launch per half-step for each (ntheta) class.
+ * Serving queue.  A worker thread owns two streams ("lanes") on the current device.
+ * Requests are admitted in arrival order while the HBM budget and the slot count
+ * allow, each on the lane with less work; every admitted solve keeps its potentials
+ * resident and all admitted solves advance together, one batched launch per half-step,
+ * lane and (ntheta) class; the lanes' launches overlap on the GPU.
  * A solve's arithmetic (tiling, reduction order) does not depend on what else is
  * admitted, so its result is bitwise the same alone or in a mix.
  */
@@ -306,10 +307,11 @@ int se2_solve_queue_times(se2_queue_t q, uint64_t ticket, double *t_submit, doub
 /* Counters: admitted, completed, rejected, peak slots in use, batched steps run. */
 int se2_solve_queue_stats(se2_queue_t q, int64_t *out5);
 /* Kernel timing of the queue's log-domain convolutions, measured with HIP events on
- * the queue's own stream (diagnostics for benchmarks).  enable = 1 starts
- * recording (and zeroes the totals); out4 receives [seconds inside convolution
- * launches, algorithmic LSE terms (window entries inside the grid), launches,
- * output elements]. */
+ * the queue's own streams (diagnostics for benchmarks).  enable = 1 starts
+ * recording (and zeroes the totals); out4 receives [seconds during which any
+ * convolution launch of the queue ran (the union of the launch intervals of its
+ * streams), algorithmic LSE terms (window entries inside the grid), batched
+ * half-steps issued (two per iteration of the resident solves), output elements]. */
 int se2_solve_queue_profile(se2_queue_t q, int32_t enable);
 int se2_solve_queue_kernel_time(se2_queue_t q, double *out4);
 /* Waits for all submitted work, then frees the queue. */

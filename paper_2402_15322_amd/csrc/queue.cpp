@@ -1,13 +1,18 @@
 // Serving queue: admission by HBM budget, continuous batching of resident solves.
 //
-// A worker thread owns one HIP stream and one device arena of the budget size.
-// Each request is admitted in arrival order once a slot and enough arena memory
-// are free; its inputs are copied into its slot, its potentials stay resident,
-// and every admitted solve advances one iteration per engine step (one batched
-// launch per half-step and ntheta class covering all of them).  A solve only
-// decides to stop at its own check iterations (multiples of its check_every, or
-// its max_iter), and its tiles and reductions never mix with other solves', so
-// its result is bitwise the same alone or admitted next to others.
+// The queue owns one device arena of the budget size and two lanes; a lane is a
+// worker thread with its own engine and HIP stream.  Each request is placed at submit
+// on the lane with less outstanding work and admitted, in arrival order within its
+// lane, once a slot (counted over both lanes) and enough arena memory are free; its
+// inputs are copied into its slot, its potentials stay resident, and every admitted
+// solve of a lane advances one iteration per step of that lane's worker (one batched
+// launch per half-step and ntheta class covering the lane's solves).  The lanes run
+// independently, so their launches overlap on the GPU: the dense rebuild of one lane's
+// uncertified tiles, which occupies few compute units, runs beside the other lane's
+// sparse evaluation, and one lane's convergence checks do not stall the other.  A
+// solve only decides to stop at its own check iterations (multiples of its
+// check_every, or its max_iter), and its tiles and reductions never mix with other
+// solves', so its result is bitwise the same alone, in a mix, and on either lane.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -98,7 +103,18 @@ struct Req {
     size_t bytes = 0;
     void *mem = nullptr;
     std::vector<double *> inputs;  // copies in slot memory
+    int lane = 0;
 };
+
+constexpr int kLanes = 2;
+
+// Work of one request per iteration, for balancing the lanes: output elements of its
+// convolutions.
+double request_load(const Req &q) {
+    const Kernel &k = *reinterpret_cast<const Kernel *>(q.r.kernel);
+    const double E = static_cast<double>(k.grid.nx) * k.grid.ny * k.grid.ntheta;
+    return E * (q.r.kind == SE2_REQ_OT ? 1.0 : static_cast<double>(q.mus_all.size()));
+}
 
 }  // namespace
 }  // namespace se2
@@ -106,22 +122,30 @@ struct Req {
 struct se2_queue_s {
     std::mutex mu;
     std::condition_variable cv, done_cv;
-    std::thread worker;
-    hipStream_t st = nullptr;
+    std::thread worker[se2::kLanes];
+    hipStream_t st[se2::kLanes] = {nullptr, nullptr};
     int device = 0;
     size_t budget = 0;
     int max_slots = 1;
     se2::Arena arena;
-    std::deque<se2::Req *> waiting;
-    std::vector<se2::Req *> active;
+    std::deque<se2::Req *> waiting[se2::kLanes];
+    std::vector<se2::Req *> active[se2::kLanes];
+    double load[se2::kLanes] = {0.0, 0.0};  // work of the lane's waiting and active requests
     std::map<uint64_t, std::unique_ptr<se2::Req>> all;
     uint64_t next_ticket = 1;
+    uint64_t gen = 0;  // bumped whenever a lane may find new work (submit, finish, profile, stop)
     bool stop = false;
     int64_t admitted = 0, completed = 0, rejected = 0, peak = 0, steps = 0;
+    // profiling: each lane resets its engine when it sees its flag; at checks it publishes
+    // its launch intervals (ms after prof_ref) and totals, and the snapshot is rebuilt
     int prof_request = 0;
-    bool prof_reset = false;
+    bool prof_reset[se2::kLanes] = {false, false};
+    hipEvent_t prof_ref = nullptr;
+    std::vector<std::pair<double, double>> prof_iv[se2::kLanes];
+    double prof_terms[se2::kLanes] = {0, 0}, prof_outputs[se2::kLanes] = {0, 0};
+    int64_t prof_rounds[se2::kLanes] = {0, 0};
     double prof_snapshot[4] = {0, 0, 0, 0};
-    se2::Engine eng;
+    se2::Engine eng[se2::kLanes];
 };
 
 namespace se2 {
@@ -157,16 +181,17 @@ int admit_one(se2_queue_s *Q, Req *q) {
     for (int i = 0; i < nin; ++i) {
         double *dst = reinterpret_cast<double *>(p + static_cast<size_t>(i) * in_bytes);
         const double *src = q->r.kind == SE2_REQ_OT ? (i == 0 ? q->r.mu : q->r.nu) : q->mus_all[i];
-        SE2_HIP(hipMemcpyAsync(dst, src, E * sizeof(double), hipMemcpyDeviceToDevice, Q->st));
+        SE2_HIP(hipMemcpyAsync(dst, src, E * sizeof(double), hipMemcpyDeviceToDevice, Q->st[q->lane]));
         q->inputs.push_back(dst);
     }
     char *solve_mem = p + static_cast<size_t>(nin) * in_bytes;
-    if ((rc = validate_measures(std::vector<const double *>(q->inputs.begin(), q->inputs.end()), E, 1e-9, Q->st)))
+    if ((rc = validate_measures(std::vector<const double *>(q->inputs.begin(), q->inputs.end()), E, 1e-9,
+                                Q->st[q->lane])))
         return rc;
     if (q->r.kind == SE2_REQ_OT) {
         s.n = 1;
         solve_bind(s, solve_mem);
-        return solve_setup_ot(s, q->inputs[0], q->inputs[1], nullptr, Q->st);
+        return solve_setup_ot(s, q->inputs[0], q->inputs[1], nullptr, Q->st[q->lane]);
     }
     std::vector<const double *> act;
     s.lam.clear();
@@ -178,13 +203,13 @@ int admit_one(se2_queue_s *Q, Req *q) {
     }
     s.n = static_cast<int>(act.size());
     solve_bind(s, solve_mem);
-    rc = solve_setup_bary(s, act, Q->st);
+    rc = solve_setup_bary(s, act, Q->st[q->lane]);
     return rc;
 }
 
-// Finishes a group of requests that left the iteration together: the GPU finishing
-// of the successful ones is batched, then every request is marked done.
-void finish_group(se2_queue_s *Q, const std::vector<Req *> &done) {
+// Finishes a group of requests of lane l that left the iteration together: the GPU
+// finishing of the successful ones is batched, then every request is marked done.
+void finish_group(se2_queue_s *Q, int l, const std::vector<Req *> &done) {
     std::vector<FinishReq> fin;
     std::vector<Req *> who;
     for (Req *q : done) {
@@ -198,13 +223,13 @@ void finish_group(se2_queue_s *Q, const std::vector<Req *> &done) {
         who.push_back(q);
     }
     if (!fin.empty()) {
-        const int rc = finish_solves(Q->eng, fin, Q->st);
+        const int rc = finish_solves(Q->eng[l], fin, Q->st[l]);
         for (size_t i = 0; i < fin.size(); ++i) {
             who[i]->rc = rc ? rc : fin[i].rc;
             who[i]->rep = fin[i].rep;
         }
     }
-    (void)hipStreamSynchronize(Q->st);
+    (void)hipStreamSynchronize(Q->st[l]);
     std::lock_guard<std::mutex> lk(Q->mu);
     for (Req *q : done) {
         Q->arena.release(q->mem);
@@ -213,33 +238,73 @@ void finish_group(se2_queue_s *Q, const std::vector<Req *> &done) {
         q->rep.seconds = q->t_done - q->t_submit;
         q->state = DONE;
         Q->completed += 1;
+        Q->load[l] -= request_load(*q);
     }
+    auto &act = Q->active[l];
+    act.erase(std::remove_if(act.begin(), act.end(), [](Req *q) { return q->state == DONE; }), act.end());
+    Q->done_cv.notify_all();
+    Q->gen += 1;
+    Q->cv.notify_all();  // freed slots and memory may let the other lane admit
 }
 
-void worker_main(se2_queue_s *Q) {
+// The union of both lanes' published launch intervals, in seconds (under Q->mu).
+double union_seconds(const se2_queue_s *Q) {
+    std::vector<std::pair<double, double>> iv;
+    for (int l = 0; l < kLanes; ++l) iv.insert(iv.end(), Q->prof_iv[l].begin(), Q->prof_iv[l].end());
+    std::sort(iv.begin(), iv.end());
+    double busy = 0.0, a = 0.0, b = -1.0;
+    for (const auto &x : iv) {
+        if (x.first > b) {
+            if (b > a) busy += b - a;
+            a = x.first;
+            b = x.second;
+        } else if (x.second > b) {
+            b = x.second;
+        }
+    }
+    if (b > a) busy += b - a;
+    return 1e-3 * busy;
+}
+
+void lane_main(se2_queue_s *Q, int l) {
     (void)hipSetDevice(Q->device);
+    Engine &eng = Q->eng[l];
+    hipStream_t st = Q->st[l];
     std::vector<double> errs;
     for (;;) {
         std::vector<Req *> fresh;
         {
             std::unique_lock<std::mutex> lk(Q->mu);
-            Q->cv.wait(lk, [&] { return Q->stop || !Q->waiting.empty() || !Q->active.empty(); });
-            if (Q->prof_reset) {
-                Q->prof_reset = false;
-                (void)Q->eng.collect_profile();
-                Q->eng.set_profiling(Q->prof_request != 0);
-                for (double &v : Q->prof_snapshot) v = 0.0;
+            for (;;) {
+                if (Q->prof_reset[l]) {
+                    Q->prof_reset[l] = false;
+                    (void)eng.collect_profile();
+                    eng.set_profiling(Q->prof_request != 0, Q->prof_request ? Q->prof_ref : nullptr);
+                    Q->prof_iv[l].clear();
+                    Q->prof_terms[l] = Q->prof_outputs[l] = 0.0;
+                    Q->prof_rounds[l] = 0;
+                }
+                if (Q->stop && Q->waiting[l].empty() && Q->active[l].empty()) return;
+                // admission in arrival order within the lane: stop at the first request that does not fit
+                while (!Q->waiting[l].empty() &&
+                       static_cast<int>(Q->active[0].size() + Q->active[1].size()) < Q->max_slots) {
+                    Req *q = Q->waiting[l].front();
+                    void *m = Q->arena.alloc(q->bytes);
+                    if (!m) break;
+                    q->mem = m;
+                    Q->waiting[l].pop_front();
+                    fresh.push_back(q);
+                    Q->active[l].push_back(q);
+                }
+                if (!fresh.empty() || !Q->active[l].empty()) break;
+                // nothing to run: sleep until a submit, a finish (freed slots or memory), a
+                // profiling change or the stop
+                const uint64_t g = Q->gen;
+                Q->cv.wait(lk, [&] { return Q->stop || Q->gen != g; });
             }
-            if (Q->stop && Q->waiting.empty() && Q->active.empty()) return;
-            // admission in arrival order: stop at the first request that does not fit
-            while (!Q->waiting.empty() && static_cast<int>(Q->active.size() + fresh.size()) < Q->max_slots) {
-                Req *q = Q->waiting.front();
-                void *m = Q->arena.alloc(q->bytes);
-                if (!m) break;
-                q->mem = m;
-                Q->waiting.pop_front();
-                fresh.push_back(q);
-            }
+            Q->admitted += static_cast<int64_t>(fresh.size());
+            const int64_t n_act = static_cast<int64_t>(Q->active[0].size() + Q->active[1].size());
+            if (n_act > Q->peak) Q->peak = n_act;
         }
         std::vector<Solve *> init;
         for (Req *q : fresh) {
@@ -249,40 +314,27 @@ void worker_main(se2_queue_s *Q) {
             if (q->rc == SE2_OK) init.push_back(&q->s);
         }
         if (!init.empty()) {
-            const int rc = Q->eng.init_first_halfstep(init, Q->st);
+            const int rc = eng.init_first_halfstep(init, st);
             for (Solve *s : init) s->convs = (s->kind == SE2_REQ_OT) ? 1 : s->n;
             if (rc)
                 for (Req *q : fresh) q->rc = rc;
         }
+        // the lane's requests (only this worker changes its lane's active list, apart from
+        // the admissions above, so a copy taken under the lock stays valid)
+        std::vector<Req *> mine;
         {
             std::lock_guard<std::mutex> lk(Q->mu);
-            for (Req *q : fresh) {
-                Q->active.push_back(q);
-                Q->admitted += 1;
-            }
-            if (static_cast<int64_t>(Q->active.size()) > Q->peak) Q->peak = static_cast<int64_t>(Q->active.size());
+            mine = Q->active[l];
         }
         // failed admissions finish immediately
         std::vector<Req *> run, failed;
-        for (Req *q : Q->active) {
+        for (Req *q : mine) {
             if (q->rc != SE2_OK) failed.push_back(q);
             else run.push_back(q);
         }
-        if (!failed.empty()) {
-            finish_group(Q, failed);
-            std::lock_guard<std::mutex> lk(Q->mu);
-            Q->active.erase(std::remove_if(Q->active.begin(), Q->active.end(),
-                                           [](Req *q) { return q->state == DONE; }),
-                            Q->active.end());
-            Q->done_cv.notify_all();
-        }
-        if (run.empty()) {
-            std::lock_guard<std::mutex> lk(Q->mu);
-            Q->active.clear();
-            Q->done_cv.notify_all();
-            continue;
-        }
-        // one iteration for every running solve
+        if (!failed.empty()) finish_group(Q, l, failed);
+        if (run.empty()) continue;
+        // one iteration for every running solve of the lane
         std::vector<Solve *> solves;
         bool check = false;
         for (Req *q : run) {
@@ -291,10 +343,9 @@ void worker_main(se2_queue_s *Q) {
             const int next = s.iter + 1;
             if (next % s.opts.check_every == 0 || next >= s.opts.max_iter) check = true;
         }
-        int rc = Q->eng.step(solves, check, Q->st);
-        Q->steps += 1;
+        int rc = eng.step(solves, check, st);
+        if (rc == SE2_OK && check) rc = eng.read_errors(solves, errs, st);
         std::vector<Req *> finished;
-        if (rc == SE2_OK && check) rc = Q->eng.read_errors(solves, errs, Q->st);
         for (size_t i = 0; i < run.size(); ++i) {
             Req *q = run[i];
             Solve &s = q->s;
@@ -332,28 +383,29 @@ void worker_main(se2_queue_s *Q) {
                     going.push_back(q);
                     going_s.push_back(&q->s);
                 }
-            const int rc2 = advance_stages(Q->eng, going_s, Q->st);
+            const int rc2 = advance_stages(eng, going_s, st);
             if (rc2)
                 for (Req *q : going) {
                     q->rc = rc2;
                     finished.push_back(q);
                 }
         }
-        if (check) {
+        {
             std::lock_guard<std::mutex> lk(Q->mu);
-            Q->prof_snapshot[0] = Q->eng.prof_seconds;
-            Q->prof_snapshot[1] = Q->eng.prof_terms;
-            Q->prof_snapshot[2] = static_cast<double>(Q->eng.prof_launches);
-            Q->prof_snapshot[3] = Q->eng.prof_outputs;
+            Q->steps += 1;
+            if (Q->prof_request) Q->prof_rounds[l] += 2;
+            if (check && Q->prof_request) {
+                // publish this lane's intervals; the convolution time is their union over both lanes
+                Q->prof_iv[l] = eng.prof_intervals;
+                Q->prof_terms[l] = eng.prof_terms;
+                Q->prof_outputs[l] = eng.prof_outputs;
+                Q->prof_snapshot[0] = union_seconds(Q);
+                Q->prof_snapshot[1] = Q->prof_terms[0] + Q->prof_terms[1];
+                Q->prof_snapshot[2] = static_cast<double>(std::max(Q->prof_rounds[0], Q->prof_rounds[1]));
+                Q->prof_snapshot[3] = Q->prof_outputs[0] + Q->prof_outputs[1];
+            }
         }
-        if (!finished.empty()) finish_group(Q, finished);
-        if (!finished.empty()) {
-            std::lock_guard<std::mutex> lk(Q->mu);
-            Q->active.erase(std::remove_if(Q->active.begin(), Q->active.end(),
-                                           [](Req *q) { return q->state == DONE; }),
-                            Q->active.end());
-            Q->done_cv.notify_all();
-        }
+        if (!finished.empty()) finish_group(Q, l, finished);
     }
 }
 
@@ -370,16 +422,21 @@ int se2_solve_queue_create(size_t hbm_budget_bytes, int32_t max_slots, se2_queue
     if (!Q) return SE2_ENOMEM;
     Q->budget = hbm_budget_bytes;
     Q->max_slots = max_slots;
-    if (hipGetDevice(&Q->device) != hipSuccess || hipStreamCreateWithFlags(&Q->st, hipStreamNonBlocking) != hipSuccess) {
+    // default-priority streams, one per lane
+    if (hipGetDevice(&Q->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&Q->st[0], hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&Q->st[1], hipStreamNonBlocking) != hipSuccess) {
+        for (hipStream_t x : Q->st)
+            if (x) (void)hipStreamDestroy(x);
         delete Q;
         return SE2_EHIP;
     }
     if (!Q->arena.init(hbm_budget_bytes)) {
-        (void)hipStreamDestroy(Q->st);
+        for (hipStream_t x : Q->st) (void)hipStreamDestroy(x);
         delete Q;
         return SE2_ENOMEM;
     }
-    Q->worker = std::thread(worker_main, Q);
+    for (int l = 0; l < kLanes; ++l) Q->worker[l] = std::thread(lane_main, Q, l);
     *out = Q;
     return SE2_OK;
 }
@@ -449,8 +506,11 @@ int se2_solve_queue_submit(se2_queue_t Q, const se2_request_t *req, uint64_t *ti
     }
     q->ticket = Q->next_ticket++;
     *ticket = q->ticket;
-    Q->waiting.push_back(q.get());
+    q->lane = Q->load[1] < Q->load[0] ? 1 : 0;  // the lane with less outstanding work
+    Q->load[q->lane] += request_load(*q);
+    Q->waiting[q->lane].push_back(q.get());
     Q->all[q->ticket] = std::move(q);
+    Q->gen += 1;
     Q->cv.notify_all();
     return SE2_OK;
 }
@@ -503,8 +563,19 @@ int se2_solve_queue_stats(se2_queue_t Q, int64_t *out5) {
 int se2_solve_queue_profile(se2_queue_t Q, int32_t enable) {
     if (!Q) return SE2_EINVAL;
     std::lock_guard<std::mutex> lk(Q->mu);
+    if (enable) {
+        // a common time origin for both lanes: recorded on lane 0, lane 1 waits for it, and
+        // the lanes start timing only after this call
+        if (!Q->prof_ref) SE2_HIP(hipEventCreate(&Q->prof_ref));
+        SE2_HIP(hipEventRecord(Q->prof_ref, Q->st[0]));
+        SE2_HIP(hipStreamWaitEvent(Q->st[1], Q->prof_ref, 0));
+    }
     Q->prof_request = enable ? 1 : 0;
-    Q->prof_reset = true;
+    for (bool &f : Q->prof_reset) f = true;
+    for (double &v : Q->prof_snapshot) v = 0.0;
+    for (auto &v : Q->prof_iv) v.clear();
+    Q->gen += 1;
+    Q->cv.notify_all();
     return SE2_OK;
 }
 
@@ -523,11 +594,16 @@ int se2_solve_queue_destroy(se2_queue_t Q) {
     {
         std::lock_guard<std::mutex> lk(Q->mu);
         Q->stop = true;
+        Q->gen += 1;
         Q->cv.notify_all();
     }
-    if (Q->worker.joinable()) Q->worker.join();
-    (void)hipStreamSynchronize(Q->st);
-    (void)hipStreamDestroy(Q->st);
+    for (std::thread &w : Q->worker)
+        if (w.joinable()) w.join();
+    for (hipStream_t x : Q->st) {
+        (void)hipStreamSynchronize(x);
+        (void)hipStreamDestroy(x);
+    }
+    if (Q->prof_ref) (void)hipEventDestroy(Q->prof_ref);
     delete Q;
     return SE2_OK;
 }

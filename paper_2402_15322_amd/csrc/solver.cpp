@@ -294,10 +294,12 @@ int solve_setup_bary(Solve &s, const std::vector<const double *> &mus, hipStream
 
 Engine::Engine() {}
 
-void Engine::set_profiling(bool on) {
+void Engine::set_profiling(bool on, hipEvent_t ref) {
     prof_ = on;
+    prof_ref_ = ref;
     prof_seconds = prof_terms = prof_outputs = 0.0;
     prof_launches = 0;
+    prof_intervals.clear();
 }
 
 int Engine::collect_profile() {
@@ -305,6 +307,12 @@ int Engine::collect_profile() {
         float ms = 0.0f;
         SE2_HIP(hipEventSynchronize(p.b));
         SE2_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+        if (prof_ref_) {
+            float t0 = 0.0f, t1 = 0.0f;
+            SE2_HIP(hipEventElapsedTime(&t0, prof_ref_, p.a));
+            SE2_HIP(hipEventElapsedTime(&t1, prof_ref_, p.b));
+            prof_intervals.emplace_back(t0, t1);
+        }
         prof_seconds += 1e-3 * ms;
         prof_terms += p.terms;
         prof_outputs += p.outputs;
@@ -561,7 +569,22 @@ int Engine::init_first_halfstep(const std::vector<Solve *> &solves, hipStream_t 
 }
 
 int Engine::step(const std::vector<Solve *> &solves, bool check, hipStream_t st) {
-    int rc = launch_stage(solves, 0, false, st);
+    const int rc = step_half(solves, 0, false, st);
+    return rc ? rc : step_half(solves, 1, check, st);
+}
+
+int Engine::step_half(const std::vector<Solve *> &solves, int half, bool check, hipStream_t st) {
+    int rc;
+    if (half == 1) {
+        rc = launch_stage(solves, 1, check, st);
+        if (rc) return rc;
+        for (Solve *s : solves) {
+            s->iter += 1;
+            if (!check && ot_like(*s)) s->cur ^= 1;  // the new a-potential becomes current
+        }
+        return check ? sum_errors(solves, st) : SE2_OK;
+    }
+    rc = launch_stage(solves, 0, false, st);
     if (rc) return rc;
     for (Solve *s : solves) {
         if (s->kind == kKindJKO) {
@@ -573,13 +596,7 @@ int Engine::step(const std::vector<Solve *> &solves, bool check, hipStream_t st)
         rc = launch_ibp_combine(s->d_lv, s->d_ld, s->d_lam, s->n, s->E, s->combine_part, s->logbar, st);
         if (rc) return rc;
     }
-    rc = launch_stage(solves, 1, check, st);
-    if (rc) return rc;
-    for (Solve *s : solves) {
-        s->iter += 1;
-        if (!check && ot_like(*s)) s->cur ^= 1;  // the new a-potential becomes current
-    }
-    return check ? sum_errors(solves, st) : SE2_OK;
+    return SE2_OK;
 }
 
 int Engine::sum_errors(const std::vector<Solve *> &solves, hipStream_t st) {

@@ -111,10 +111,18 @@ public:
     ~Engine();
     int init_first_halfstep(const std::vector<Solve *> &solves, hipStream_t st);
     int step(const std::vector<Solve *> &solves, bool check, hipStream_t st);
+    // One half of step(): half 0 is the b-update (d-update and combine for barycenters,
+    // the proximal step for JKO), half 1 the a-update (w-update) with the iteration count,
+    // and the error sums when `check`.
+    int step_half(const std::vector<Solve *> &solves, int half, bool check, hipStream_t st);
     // Copies err slots of the given solves to host (synchronises the stream).
     int read_errors(const std::vector<Solve *> &solves, std::vector<double> &max_err, hipStream_t st);
-    // Optional event timing of every log-domain convolution launch.
-    void set_profiling(bool on);
+    // Optional event timing of every log-domain convolution launch.  With a reference event
+    // (recorded before any profiled launch on this engine's stream), every launch's
+    // [start, end] in ms after it is kept in prof_intervals, so the intervals of engines
+    // on different streams can be merged.
+    void set_profiling(bool on, hipEvent_t ref = nullptr);
+    std::vector<std::pair<double, double>> prof_intervals;
     // FP64 check convolutions (dense, FP64 exp): one launch per ntheta class.
     int launch_checks(const std::vector<ConvJob> &jobs, const std::vector<int> &nts, hipStream_t st);
     int collect_profile();  // folds finished event pairs into the totals (after a sync)
@@ -159,6 +167,7 @@ private:
     hipEvent_t items_used_ = nullptr;
     int sum_errors(const std::vector<Solve *> &solves, hipStream_t st);
     bool prof_ = false;
+    hipEvent_t prof_ref_ = nullptr;
     struct Pending {
         hipEvent_t a, b;
         double terms, outputs;
