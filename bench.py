@@ -88,6 +88,8 @@ def parse():
                     help="class-barycenter leg: measures of 28x28x16 (0 skips the leg)")
     ap.add_argument("--bary-iters", type=int, default=20)
     ap.add_argument("--flow-steps", type=int, default=5, help="gradient-flow leg: JKO steps (0 skips the leg)")
+    ap.add_argument("--c4-iters", type=int, default=5,
+                    help="barycenter legs: IBP iterations of the 256x256x32 field workload (0 skips both legs)")
     ap.add_argument("--eps-start", type=float, default=1.6,
                     help="eps-scaling leg: first eps of the schedule (<= 0.1 skips the leg)")
     ap.add_argument("--eps-factor", type=float, default=0.5)
@@ -245,6 +247,47 @@ def gradient_flow(native, torch, synth, steps: int):
             "energy": [r["dual"] for r in reps], "transport_cost": [r["cost"] for r in reps]}
 
 
+def barycenter_workloads(native, torch, synth, c4_iters: int):
+    """The two barycenter workloads through the queue, convolution timing on.
+    128x128x16 interpolation: two Bezier-stroke measures, w = (1,3,1), eps = 0.05, 15x15
+    window, the five weights t in {0, 1/4, 1/2, 3/4, 1} as five resident requests, tol 1e-6,
+    max 1000 IBP iterations, pruned engine.  256x256x32 axial fields: four measures, equal
+    weights, w = (1,4,1), eps = 0.03, 21x21 window (the dense engine: the FP64 halo does not
+    fit the sparse kernel's LDS), `c4_iters` IBP iterations."""
+    out = {}
+    for name, insts, o in (
+            ("curves128x128x16_t5", [synth.curves128(0, t=t) for t in (0.0, 0.25, 0.5, 0.75, 1.0)],
+             native.opts(tol=1e-6, max_iter=1000, check_every=10, final_check=True, prune=True)),
+            ("fields256x256x32_axial_n4", [synth.fields256(0)],
+             native.opts(tol=-1.0, max_iter=c4_iters, check_every=c4_iters, final_check=False, prune=True))):
+        g = insts[0].grid
+        k = native.Kernel(g.nx, g.ny, g.nt, g.axial, insts[0].w, insts[0].eps, insts[0].radius)
+        dev = [[torch.from_numpy(m).cuda() for m in inst.mus] for inst in insts]
+        outs = [torch.empty_like(d[0]) for d in dev]
+        q = native.SolveQueue(hbm_budget_bytes=8 << 30, max_slots=len(insts))
+        q.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ts = [q.submit_barycenter(k, d, inst.lambdas, o, b) for d, inst, b in zip(dev, insts, outs)]
+        reps = [q.wait(t) for t in ts]
+        wall = time.perf_counter() - t0
+        kt = q.kernel_time()
+        q.close()
+        slots = SLOTS_DENSE * sum(r["terms_dense"] for r in reps) + SLOTS_SPARSE * sum(r["terms_sparse"] for r in reps)
+        achieved = 2.0 * slots / kt["seconds"] / 1e12 if kt["seconds"] > 0 else 0.0
+        out[name] = {"requests": len(insts), "iters": [r["iters"] for r in reps],
+                     "converged": sum(1 for r in reps if r["status"] == native.SE2_CONVERGED),
+                     "wall_s": wall, "ibp_iters_per_s": sum(r["iters"] for r in reps) / wall,
+                     "marg_l1": [r["marg_l1"] for r in reps], "mass": [r["mass"] for r in reps],
+                     "conv_seconds": kt["seconds"], "half_steps": kt["launches"],
+                     "dense_terms": sum(r["terms_dense"] for r in reps),
+                     "sparse_terms": sum(r["terms_sparse"] for r in reps),
+                     "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": achieved / PEAK_TFLOPS}}
+        del dev, outs, k
+    return out
+
+
 def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -363,6 +406,7 @@ def main():
 
     class_meas = None if class_images is None else class_barycenter(native, torch, class_images, a.bary_iters)
     flow_meas = None if a.flow_steps <= 0 else gradient_flow(native, torch, synth, a.flow_steps)
+    bary_meas = None if a.c4_iters <= 0 else barycenter_workloads(native, torch, synth, a.c4_iters)
     conv_meas = None if a.no_conv else conv_measurements(native, torch, a.batch, a.conv_reps)
     field_meas = None if a.no_conv else field_measurements(native, torch, a.conv_reps)
 
@@ -407,6 +451,7 @@ def main():
         "lift_project": field_meas,
         "class_barycenter": class_meas,
         "gradient_flow": flow_meas,
+        "barycenters": bary_meas,
         "se2_conv": {"bound": "mfma", "peak_bf16_tflops": PEAK_BF16_TFLOPS, "peak_f32_tflops": PEAK_F32_TFLOPS,
                      "flops": "2 * batch * nx * ny * ntheta^2 * window", "launches": conv_meas},
     }
