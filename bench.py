@@ -412,7 +412,7 @@ def main():
 
     cpu = None
     if not a.no_cpu:
-        cpu = cpu_baseline(insts[0], a.cpu_iters)
+        cpu = cpu_baseline(insts[0], a.cpu_iters, native, torch, k)
 
     out = {
         "metric": "Sinkhorn iters/sec & solves/sec at 64x64x16 (marg err<=1e-6); p50/p99 latency",
@@ -531,20 +531,36 @@ def serving(native, torch, synth, a):
     }
 
 
-def cpu_baseline(inst, iters: int):
-    """FP64 oracle Sinkhorn on this host, a bounded sample of the same workload."""
+def cpu_baseline(inst, iters: int, native=None, torch=None, kernel=None):
+    """FP64 oracle Sinkhorn on this host, a bounded sample of the same workload; with the
+    library given, the same solve on the GPU at the same iteration count beside it, and the
+    GPU result's errors against the oracle's (plan L1, marginal L1, relative cost)."""
     import oracle
-    logk, _ = oracle.kernel_table(NT, False, W_METRIC, EPS, R)
+    logk, cost = oracle.kernel_table(NT, False, W_METRIC, EPS, R)
     if iters <= 0:
         t = time.perf_counter()
         oracle.sinkhorn(logk, inst.mu, inst.nu, 1, -1.0)
         one = time.perf_counter() - t  # 3 convolutions
         iters = max(2, int(15.0 / max(one * 2.0 / 3.0, 1e-3)))
     t = time.perf_counter()
-    _, _, it, _, _ = oracle.sinkhorn(logk, inst.mu, inst.nu, iters, -1.0)
+    phi_o, psi_o, it, err_o, _ = oracle.sinkhorn(logk, inst.mu, inst.nu, iters, -1.0)
     dt = time.perf_counter() - t
-    return {"value": it / dt, "unit": "Sinkhorn iterations/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"one 64x64x16 solve, {it} iterations, FP64 log-domain C + OpenMP"}
+    out = {"value": it / dt, "unit": "Sinkhorn iterations/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"one 64x64x16 solve, {it} iterations, FP64 log-domain C + OpenMP"}
+    if native is not None:
+        mu = torch.from_numpy(inst.mu).cuda()
+        nu = torch.from_numpy(inst.nu).cuda()
+        f, g = torch.empty_like(mu), torch.empty_like(mu)
+        rep = native.se2_sinkhorn(kernel, mu, nu, native.opts(tol=-1.0, max_iter=it, check_every=10), f, g)
+        phi_g = f.cpu().numpy() / EPS
+        psi_g = g.cpu().numpy() / EPS
+        c_o = oracle.plan_stats(logk, cost, phi_o, psi_o)[0]
+        out["gpu_vs_oracle"] = {
+            "iterations": it, "plan_l1": oracle.plan_l1(logk, phi_g, psi_g, phi_o, psi_o),
+            "marg_l1_gpu": rep["marg_l1"], "marg_l1_oracle": err_o,
+            "marg_l1_diff": abs(rep["marg_l1"] - err_o), "rel_cost_diff": abs(rep["cost"] - c_o) / c_o,
+            "engine": "FP32-exp log-domain engine with certified pruning"}
+    return out
 
 
 if __name__ == "__main__":

@@ -116,3 +116,36 @@ def test_admission_respects_budget(nat):
         q.submit_ot(big, bm, bm, o)
     assert e.value.code == nat.SE2_ENOMEM
     q.close()
+
+
+def test_kernel_time_accounts_every_convolution(nat):
+    """Queue profiling: the algorithmic terms are exactly those of every convolution applied
+    (one first a-update and two half-steps per iteration of each solve), the half-steps
+    counted are those of the busiest lane, and the convolution time (the union of both
+    lanes' launch intervals) is positive and within the wall time."""
+    import time
+    torch = torch_dev()
+    n, nt, R = 24, 16, 5
+    g = synth.Grid(n, n, nt)
+    k = nat.Kernel(n, n, nt, False, (1.0, 3.0, 1.0), 0.2, R)
+    reqs = []
+    for i in range(4):
+        r = synth.rng_for(9400 + i, 0)
+        segs = synth.draw_segments(r, g, 3, 3.0, 8.0)
+        reqs.append((to_dev(synth.splat_segments(g, segs, 1.0, 1e-6)),
+                     to_dev(synth.splat_segments(g, synth.moved_segments(r, g, segs, 1.0, 0.1), 1.0, 1e-6))))
+    it = 30
+    o = nat.opts(tol=-1, max_iter=it, check_every=10)
+    q = nat.SolveQueue(hbm_budget_bytes=256 << 20, max_slots=8)
+    q.profile(True)
+    t0 = time.perf_counter()
+    ts = [q.submit_ot(k, mu, nu, o, torch.empty_like(mu), torch.empty_like(mu)) for mu, nu in reqs]
+    reps = [q.wait(t) for t in ts]
+    wall = time.perf_counter() - t0
+    kt = q.kernel_time()
+    q.close()
+    per_conv = sum(max(0, n - abs(d)) for d in range(-R, R + 1)) ** 2 * nt * nt
+    assert kt["terms"] == 4 * (2 * it + 1) * per_conv
+    assert all(r["iters"] == it for r in reps)
+    assert 2 * it <= kt["launches"] <= 2 * (it + 4)
+    assert 0.0 < kt["seconds"] <= wall
