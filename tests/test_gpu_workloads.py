@@ -151,3 +151,35 @@ def test_barycenter_fields256_symmetry(nat):
     l1 = float(np.sum(np.abs(pins.rot90(a, axial=True) - b)))
     assert l1 <= 1e-5 * a.sum(), l1
     assert abs(ra["marg_l1"] - rb["marg_l1"]) <= 1e-6
+
+
+def test_bench_batch_matches_oracle(nat):
+    """The benchmarked configuration: 32 paired 64x64x16 solves submitted together to the
+    serving queue (two lanes, certified pruning), here for 20 iterations.  Two solves, one
+    per lane, are compared with the oracle at the same iteration count; every solve of the
+    batch is bitwise the blocking solve of the same pair."""
+    torch = torch_dev()
+    k = nat.Kernel(64, 64, 16, False, (1.0, 3.0, 1.0), 0.1, 5)
+    insts = [synth.lines64(i, paired=True) for i in range(32)]
+    mus = [to_dev(x.mu) for x in insts]
+    nus = [to_dev(x.nu) for x in insts]
+    fs = [torch.empty_like(m) for m in mus]
+    gs = [torch.empty_like(m) for m in mus]
+    it = 20
+    o = nat.opts(tol=1e-6, max_iter=it, check_every=10)
+    q = nat.SolveQueue(hbm_budget_bytes=nat.ot_request_bytes(k, o) * 32 + (64 << 20), max_slots=32)
+    ts = [q.submit_ot(k, mus[i], nus[i], o, fs[i], gs[i]) for i in range(32)]
+    reps = [q.wait(t) for t in ts]
+    st = q.stats()
+    q.close()
+    assert st["peak_slots"] == 32 and all(r["iters"] == it for r in reps)
+    logk, _ = oracle.kernel_table(16, False, (1.0, 3.0, 1.0), 0.1, 5)
+    for i in (0, 17):
+        phi_o, psi_o, it_o, err_o, _ = oracle.sinkhorn(logk, insts[i].mu, insts[i].nu, it, -1.0)
+        l1 = oracle.plan_l1(logk, to_host(fs[i]) / 0.1, to_host(gs[i]) / 0.1, phi_o, psi_o)
+        assert l1 <= 1e-5, (i, l1)
+        assert abs(reps[i]["marg_l1"] - err_o) <= 1e-6
+    for i in (0, 17, 31):
+        f, g = torch.empty_like(mus[i]), torch.empty_like(mus[i])
+        nat.se2_sinkhorn(k, mus[i], nus[i], o, f, g)
+        assert np.array_equal(to_host(f), to_host(fs[i])) and np.array_equal(to_host(g), to_host(gs[i]))
