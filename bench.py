@@ -79,6 +79,8 @@ def parse():
                     help="first run one plain device copy of this many MiB (a known-size reference for HBM counters)")
     ap.add_argument("--serving", action="store_true",
                     help="serving workload instead: Poisson arrivals of mixed-size OT requests (own JSON line)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving trace that the default line carries as its `serving` object")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--rate", type=float, default=200.0, help="arrivals per second")
     ap.add_argument("--budget-gb", type=float, default=4.0, help="queue HBM budget")
@@ -302,8 +304,12 @@ def main():
 
     # inputs of the class-barycenter leg, drawn in forked workers before any GPU work
     class_images = None
+    workers = min(16, os.cpu_count() or 1)
     if a.bary_n > 0 and not (a.conv_only or a.serving):
-        class_images = synth.stroke_images(a.bary_n, workers=min(16, os.cpu_count() or 1))
+        class_images = synth.stroke_images(a.bary_n, workers=workers)
+    trace = None
+    if a.serving or not (a.conv_only or a.no_serving):
+        trace = synth.serving_trace(a.requests, a.rate, workers=workers)
 
     torch.cuda.set_device(0)
     native.se2_init()
@@ -318,7 +324,7 @@ def main():
                           "lift_project": field_measurements(native, torch, a.conv_reps)}), flush=True)
         return
     if a.serving:
-        print(json.dumps(serving(native, torch, synth, a)), flush=True)
+        print(json.dumps(serving(native, torch, synth, a, trace)), flush=True)
         return
     k = native.Kernel(NX, NX, NT, False, W_METRIC, EPS, R)
     insts = [synth.lines64(i, paired=True) for i in range(a.batch)]
@@ -407,6 +413,7 @@ def main():
     class_meas = None if class_images is None else class_barycenter(native, torch, class_images, a.bary_iters)
     flow_meas = None if a.flow_steps <= 0 else gradient_flow(native, torch, synth, a.flow_steps)
     bary_meas = None if a.c4_iters <= 0 else barycenter_workloads(native, torch, synth, a.c4_iters)
+    serving_meas = None if a.no_serving else serving(native, torch, synth, a, trace)
     conv_meas = None if a.no_conv else conv_measurements(native, torch, a.batch, a.conv_reps)
     field_meas = None if a.no_conv else field_measurements(native, torch, a.conv_reps)
 
@@ -452,19 +459,19 @@ def main():
         "class_barycenter": class_meas,
         "gradient_flow": flow_meas,
         "barycenters": bary_meas,
+        "serving": serving_meas,
         "se2_conv": {"bound": "mfma", "peak_bf16_tflops": PEAK_BF16_TFLOPS, "peak_f32_tflops": PEAK_F32_TFLOPS,
                      "flops": "2 * batch * nx * ny * ntheta^2 * window", "launches": conv_meas},
     }
     print(json.dumps(out), flush=True)
 
 
-def serving(native, torch, synth, a):
+def serving(native, torch, synth, a, trace):
     """Poisson stream of OT requests with mixed grid sizes (32x32x8, 64x64x16, 128x128x16),
     eps and w2, submitted at their arrival times to one queue; latency = completion -
     submission.  Beside it, the same kind of solve one at a time (blocking, dense FP32
     engine) on a stratified sample, extrapolated to the whole trace."""
     import numpy as np
-    trace = synth.serving_trace(a.requests, a.rate)
     kernels = {}
 
     def kern(inst):

@@ -345,29 +345,48 @@ class Request:
     inst: OTInstance
 
 
+def _serve_request(seed: int, i: int, arrival: float, grids, paired: bool) -> Request:
+    r = rng_for(seed + 1 + i, 0)
+    n, nt, rad = grids[int(r.integers(len(grids)))]
+    eps = float(SERVE_EPS[int(r.integers(len(SERVE_EPS)))])
+    w2 = float(SERVE_W2[int(r.integers(len(SERVE_W2)))])
+    nseg = int(r.integers(4, 13))
+    g = Grid(n, n, nt)
+    margin = PAIRED_MARGIN if paired else None
+    segs = draw_segments(r, g, nseg, 10.0 * n / 64, 40.0 * n / 64, margin)
+    mu = splat_segments(g, segs, 1.0, 1e-6)
+    if paired:
+        nu = splat_segments(g, moved_segments(r, g, segs, PAIRED_SHIFT, PAIRED_ROT, margin), 1.0, 1e-6)
+    else:
+        nu = splat_segments(g, draw_segments(r, g, nseg, 10.0 * n / 64, 40.0 * n / 64), 1.0, 1e-6)
+    return Request(float(arrival), OTInstance(g, (1.0, w2, 1.0), eps, rad, mu, nu, f"serve/{i}"))
+
+
+def _serve_chunk(args):
+    seed, idx, arrivals, grids, paired = args
+    return [_serve_request(seed, i, a, grids, paired) for i, a in zip(idx, arrivals)]
+
+
 def serving_trace(nreq: int = 512, rate: float = 200.0, seed: int = 3000, paired: bool = True,
-                  grids: Optional[Sequence[Tuple[int, int, int]]] = None) -> List[Request]:
-    """Poisson stream of OT requests with mixed grid sizes, eps and w2."""
+                  grids: Optional[Sequence[Tuple[int, int, int]]] = None, workers: int = 1) -> List[Request]:
+    """Poisson stream of OT requests with mixed grid sizes, eps and w2.  Request i draws from
+    its own stream, so the trace is the same for any worker count (workers > 1 forks
+    processes: call it before any GPU work)."""
     grids = list(grids or SERVE_GRIDS)
     arr = rng_for(seed, 0)
     gaps = arr.exponential(1.0 / rate, nreq)
     t = np.cumsum(gaps) - gaps[0]
-    out = []
-    for i in range(nreq):
-        r = rng_for(seed + 1 + i, 0)
-        n, nt, rad = grids[int(r.integers(len(grids)))]
-        eps = float(SERVE_EPS[int(r.integers(len(SERVE_EPS)))])
-        w2 = float(SERVE_W2[int(r.integers(len(SERVE_W2)))])
-        nseg = int(r.integers(4, 13))
-        g = Grid(n, n, nt)
-        margin = PAIRED_MARGIN if paired else None
-        segs = draw_segments(r, g, nseg, 10.0 * n / 64, 40.0 * n / 64, margin)
-        mu = splat_segments(g, segs, 1.0, 1e-6)
-        if paired:
-            nu = splat_segments(g, moved_segments(r, g, segs, PAIRED_SHIFT, PAIRED_ROT, margin), 1.0, 1e-6)
-        else:
-            nu = splat_segments(g, draw_segments(r, g, nseg, 10.0 * n / 64, 40.0 * n / 64), 1.0, 1e-6)
-        out.append(Request(float(t[i]), OTInstance(g, (1.0, w2, 1.0), eps, rad, mu, nu, f"serve/{i}")))
+    if workers <= 1 or nreq < 32:
+        return _serve_chunk((seed, list(range(nreq)), list(t), grids, paired))
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    parts = [(seed, list(range(w, nreq, workers)), list(t[w::workers]), grids, paired) for w in range(workers)]
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        chunks = list(ex.map(_serve_chunk, parts))
+    out = [None] * nreq
+    for w, chunk in enumerate(chunks):
+        for j, req in enumerate(chunk):
+            out[w + j * workers] = req
     return out
 
 
