@@ -286,6 +286,18 @@ def barycenter_workloads(native, torch, synth, c4_iters: int):
                      "sparse_terms": sum(r["terms_sparse"] for r in reps),
                      "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
                                   "frac": achieved / PEAK_TFLOPS}}
+        if name.startswith("curves"):
+            # the t = 1/2 problem again, blocking, 2 iterations, against the oracle's 2 iterations
+            import numpy as np
+            import oracle
+            inst = insts[2]
+            b = torch.empty_like(dev[2][0])
+            rep = native.se2_barycenter(k, dev[2], inst.lambdas, native.opts(tol=-1.0, max_iter=2, check_every=2), b)
+            logk, _ = oracle.kernel_table(g.nt, g.axial, inst.w, inst.eps, inst.radius)
+            bar_o, it_o, err_o, _ = oracle.ibp(logk, inst.mus, inst.lambdas, 2, -1.0)
+            out[name]["gpu_vs_oracle"] = {"t": 0.5, "iterations": it_o,
+                                          "barycenter_l1": float(np.sum(np.abs(b.cpu().numpy() - bar_o))),
+                                          "marg_l1_diff": abs(rep["marg_l1"] - err_o)}
         del dev, outs, k
     return out
 
