@@ -270,11 +270,12 @@ int se2_project(const se2_grid_t *grid, const double *u, const double *u_minus, 
 int se2_split_signed(const double *u, size_t n, double *plus, double *minus, se2_stream_t stream);
 
 /*
- * Serving queue.  A worker thread owns two streams ("lanes") on the current device.
- * Requests are admitted in arrival order while the HBM budget and the slot count
- * allow, each on the lane with less work; every admitted solve keeps its potentials
- * resident and all admitted solves advance together, one batched launch per half-step,
- * lane and (ntheta) class; the lanes' launches overlap on the GPU.
+ * Serving queue.  Three lanes, each a worker thread with its own stream on the current
+ * device.  A request goes at submit to the lane with the least outstanding work and is
+ * admitted, in arrival order within its lane, while the HBM budget and the slot count
+ * (shared by the lanes) allow; every admitted solve keeps its potentials resident and
+ * the solves of a lane advance together, one batched launch per half-step and (ntheta)
+ * class; the lanes run independently and their launches overlap on the GPU.
  * A solve's arithmetic (tiling, reduction order) does not depend on what else is
  * admitted, so its result is bitwise the same alone or in a mix.
  */

@@ -1,18 +1,19 @@
 // Serving queue: admission by HBM budget, continuous batching of resident solves.
 //
-// The queue owns one device arena of the budget size and two lanes; a lane is a
-// worker thread with its own engine and HIP stream.  Each request is placed at submit
+// The queue owns one device arena of the budget size and three lanes; a lane is a
+// worker thread with its own engine and HIP stream (three streams and the caller's
+// stay within the four hardware queues a process gets by default).  Each request is placed at submit
 // on the lane with less outstanding work and admitted, in arrival order within its
-// lane, once a slot (counted over both lanes) and enough arena memory are free; its
+// lane, once a slot (counted over all lanes) and enough arena memory are free; its
 // inputs are copied into its slot, its potentials stay resident, and every admitted
 // solve of a lane advances one iteration per step of that lane's worker (one batched
 // launch per half-step and ntheta class covering the lane's solves).  The lanes run
 // independently, so their launches overlap on the GPU: the dense rebuild of one lane's
-// uncertified tiles, which occupies few compute units, runs beside the other lane's
-// sparse evaluation, and one lane's convergence checks do not stall the other.  A
+// uncertified tiles, which occupies few compute units, runs beside the other lanes'
+// sparse evaluation, and one lane's convergence checks do not stall the others.  A
 // solve only decides to stop at its own check iterations (multiples of its
 // check_every, or its max_iter), and its tiles and reductions never mix with other
-// solves', so its result is bitwise the same alone, in a mix, and on either lane.
+// solves', so its result is bitwise the same alone, in a mix, and on any lane.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -106,7 +107,10 @@ struct Req {
     int lane = 0;
 };
 
-constexpr int kLanes = 2;
+#ifndef SE2_QUEUE_LANES
+#define SE2_QUEUE_LANES 3
+#endif
+constexpr int kLanes = SE2_QUEUE_LANES;
 
 // Work of one request per iteration, for balancing the lanes: output elements of its
 // convolutions.
@@ -123,14 +127,14 @@ struct se2_queue_s {
     std::mutex mu;
     std::condition_variable cv, done_cv;
     std::thread worker[se2::kLanes];
-    hipStream_t st[se2::kLanes] = {nullptr, nullptr};
+    hipStream_t st[se2::kLanes] = {};
     int device = 0;
     size_t budget = 0;
     int max_slots = 1;
     se2::Arena arena;
     std::deque<se2::Req *> waiting[se2::kLanes];
     std::vector<se2::Req *> active[se2::kLanes];
-    double load[se2::kLanes] = {0.0, 0.0};  // work of the lane's waiting and active requests
+    double load[se2::kLanes] = {};  // work of the lane's waiting and active requests
     std::map<uint64_t, std::unique_ptr<se2::Req>> all;
     uint64_t next_ticket = 1;
     uint64_t gen = 0;  // bumped whenever a lane may find new work (submit, finish, profile, stop)
@@ -139,11 +143,11 @@ struct se2_queue_s {
     // profiling: each lane resets its engine when it sees its flag; at checks it publishes
     // its launch intervals (ms after prof_ref) and totals, and the snapshot is rebuilt
     int prof_request = 0;
-    bool prof_reset[se2::kLanes] = {false, false};
+    bool prof_reset[se2::kLanes] = {};
     hipEvent_t prof_ref = nullptr;
     std::vector<std::pair<double, double>> prof_iv[se2::kLanes];
-    double prof_terms[se2::kLanes] = {0, 0}, prof_outputs[se2::kLanes] = {0, 0};
-    int64_t prof_rounds[se2::kLanes] = {0, 0};
+    double prof_terms[se2::kLanes] = {}, prof_outputs[se2::kLanes] = {};
+    int64_t prof_rounds[se2::kLanes] = {};
     double prof_snapshot[4] = {0, 0, 0, 0};
     se2::Engine eng[se2::kLanes];
 };
@@ -247,7 +251,7 @@ void finish_group(se2_queue_s *Q, int l, const std::vector<Req *> &done) {
     Q->cv.notify_all();  // freed slots and memory may let the other lane admit
 }
 
-// The union of both lanes' published launch intervals, in seconds (under Q->mu).
+// The union of all lanes' published launch intervals, in seconds (under Q->mu).
 double union_seconds(const se2_queue_s *Q) {
     std::vector<std::pair<double, double>> iv;
     for (int l = 0; l < kLanes; ++l) iv.insert(iv.end(), Q->prof_iv[l].begin(), Q->prof_iv[l].end());
@@ -264,6 +268,13 @@ double union_seconds(const se2_queue_s *Q) {
     }
     if (b > a) busy += b - a;
     return 1e-3 * busy;
+}
+
+// Requests admitted on all lanes (under Q->mu).
+int active_count(const se2_queue_s *Q) {
+    size_t n = 0;
+    for (int l = 0; l < kLanes; ++l) n += Q->active[l].size();
+    return static_cast<int>(n);
 }
 
 void lane_main(se2_queue_s *Q, int l) {
@@ -287,7 +298,7 @@ void lane_main(se2_queue_s *Q, int l) {
                 if (Q->stop && Q->waiting[l].empty() && Q->active[l].empty()) return;
                 // admission in arrival order within the lane: stop at the first request that does not fit
                 while (!Q->waiting[l].empty() &&
-                       static_cast<int>(Q->active[0].size() + Q->active[1].size()) < Q->max_slots) {
+                       active_count(Q) < Q->max_slots) {
                     Req *q = Q->waiting[l].front();
                     void *m = Q->arena.alloc(q->bytes);
                     if (!m) break;
@@ -303,7 +314,7 @@ void lane_main(se2_queue_s *Q, int l) {
                 Q->cv.wait(lk, [&] { return Q->stop || Q->gen != g; });
             }
             Q->admitted += static_cast<int64_t>(fresh.size());
-            const int64_t n_act = static_cast<int64_t>(Q->active[0].size() + Q->active[1].size());
+            const int64_t n_act = static_cast<int64_t>(active_count(Q));
             if (n_act > Q->peak) Q->peak = n_act;
         }
         std::vector<Solve *> init;
@@ -395,14 +406,21 @@ void lane_main(se2_queue_s *Q, int l) {
             Q->steps += 1;
             if (Q->prof_request) Q->prof_rounds[l] += 2;
             if (check && Q->prof_request) {
-                // publish this lane's intervals; the convolution time is their union over both lanes
+                // publish this lane's intervals; the convolution time is their union over all lanes
                 Q->prof_iv[l] = eng.prof_intervals;
                 Q->prof_terms[l] = eng.prof_terms;
                 Q->prof_outputs[l] = eng.prof_outputs;
                 Q->prof_snapshot[0] = union_seconds(Q);
-                Q->prof_snapshot[1] = Q->prof_terms[0] + Q->prof_terms[1];
-                Q->prof_snapshot[2] = static_cast<double>(std::max(Q->prof_rounds[0], Q->prof_rounds[1]));
-                Q->prof_snapshot[3] = Q->prof_outputs[0] + Q->prof_outputs[1];
+                double terms = 0.0, outputs = 0.0;
+                int64_t rounds = 0;
+                for (int j = 0; j < kLanes; ++j) {
+                    terms += Q->prof_terms[j];
+                    outputs += Q->prof_outputs[j];
+                    rounds = std::max(rounds, Q->prof_rounds[j]);
+                }
+                Q->prof_snapshot[1] = terms;
+                Q->prof_snapshot[2] = static_cast<double>(rounds);
+                Q->prof_snapshot[3] = outputs;
             }
         }
         if (!finished.empty()) finish_group(Q, l, finished);
@@ -423,9 +441,9 @@ int se2_solve_queue_create(size_t hbm_budget_bytes, int32_t max_slots, se2_queue
     Q->budget = hbm_budget_bytes;
     Q->max_slots = max_slots;
     // default-priority streams, one per lane
-    if (hipGetDevice(&Q->device) != hipSuccess ||
-        hipStreamCreateWithFlags(&Q->st[0], hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&Q->st[1], hipStreamNonBlocking) != hipSuccess) {
+    bool ok = hipGetDevice(&Q->device) == hipSuccess;
+    for (int l = 0; l < kLanes && ok; ++l) ok = hipStreamCreateWithFlags(&Q->st[l], hipStreamNonBlocking) == hipSuccess;
+    if (!ok) {
         for (hipStream_t x : Q->st)
             if (x) (void)hipStreamDestroy(x);
         delete Q;
@@ -506,7 +524,9 @@ int se2_solve_queue_submit(se2_queue_t Q, const se2_request_t *req, uint64_t *ti
     }
     q->ticket = Q->next_ticket++;
     *ticket = q->ticket;
-    q->lane = Q->load[1] < Q->load[0] ? 1 : 0;  // the lane with less outstanding work
+    q->lane = 0;  // the lane with the least outstanding work
+    for (int l = 1; l < kLanes; ++l)
+        if (Q->load[l] < Q->load[q->lane]) q->lane = l;
     Q->load[q->lane] += request_load(*q);
     Q->waiting[q->lane].push_back(q.get());
     Q->all[q->ticket] = std::move(q);
@@ -564,11 +584,11 @@ int se2_solve_queue_profile(se2_queue_t Q, int32_t enable) {
     if (!Q) return SE2_EINVAL;
     std::lock_guard<std::mutex> lk(Q->mu);
     if (enable) {
-        // a common time origin for both lanes: recorded on lane 0, lane 1 waits for it, and
+        // a common time origin for all lanes: recorded on lane 0, the others wait for it, and
         // the lanes start timing only after this call
         if (!Q->prof_ref) SE2_HIP(hipEventCreate(&Q->prof_ref));
         SE2_HIP(hipEventRecord(Q->prof_ref, Q->st[0]));
-        SE2_HIP(hipStreamWaitEvent(Q->st[1], Q->prof_ref, 0));
+        for (int l = 1; l < kLanes; ++l) SE2_HIP(hipStreamWaitEvent(Q->st[l], Q->prof_ref, 0));
     }
     Q->prof_request = enable ? 1 : 0;
     for (bool &f : Q->prof_reset) f = true;
