@@ -422,6 +422,15 @@ def main():
                    "marg_l1_f64_mean": float(np.mean([r["marg_l1_f64"] for r in rs_])),
                    "plain_marg_l1_mean": float(np.mean([r["marg_l1"] for r in all_r]))}
 
+    # kernel tables (built once per grid and metric, host FP64 then uploaded)
+    build_ms = {}
+    for n, nt, rad, axial, w, eps, _ in CONV_SHAPES:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kk = native.Kernel(n, n, nt, axial, w, eps, rad)
+        torch.cuda.synchronize()
+        build_ms[f"{n}x{n}x{nt}{' axial' if axial else ''}, {2 * rad + 1}x{2 * rad + 1}"] = (time.perf_counter() - t0) * 1e3
+        del kk
     class_meas = None if class_images is None else class_barycenter(native, torch, class_images, a.bary_iters)
     flow_meas = None if a.flow_steps <= 0 else gradient_flow(native, torch, synth, a.flow_steps)
     bary_meas = None if a.c4_iters <= 0 else barycenter_workloads(native, torch, synth, a.c4_iters)
@@ -466,6 +475,7 @@ def main():
                      "window_terms_per_launch": kt["terms"] / launches,
                      "slots_per_term": {"dense": SLOTS_DENSE, "sparse": SLOTS_SPARSE}},
         "cpu_baseline": cpu,
+        "kernel_build_ms": build_ms,
         "eps_scaling": eps_leg,
         "lift_project": field_meas,
         "class_barycenter": class_meas,
