@@ -350,7 +350,7 @@ int se2_conv_log(se2_kernel_t h, se2_prec_t prec, const double *in, double *out,
         SE2_HIP(hipMemcpyAsync(dj, jobs.data(), batch * sizeof(ConvJob), hipMemcpyHostToDevice, st));
         SE2_HIP(hipMemcpyAsync(dm, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
         rc = launch_conv_lse(dj, batch, tiles * batch, dm, k->grid.ntheta, k->metric.radius, prec == SE2_F64, false,
-                             nullptr, nullptr, nullptr, st);
+                             nullptr, nullptr, nullptr, 8, nullptr, st);
     }
     if (rc == SE2_OK) rc = launch_scale(out, out, E * batch, kLn2, st);
     // host vectors are read by the async copies: wait before they go out of scope

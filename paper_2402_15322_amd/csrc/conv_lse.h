@@ -48,7 +48,9 @@ constexpr size_t kSparseLdsMax = 98304;     // the sparse path keeps the full FP
 // of the exponents it enters.
 typedef double ListEntry;
 constexpr uint32_t kOffBits = 15;
-constexpr int kRebuildGrid = 2048;          // workgroups of the wide rebuild kernel
+constexpr int kRebuildGrid = 2048;          // workgroups of the rebuild kernel at 8 waves per item
+constexpr int kRebuildGridWide = 256;       // the same at 16 waves per item (one item per workgroup and CU)
+constexpr int kRebuildWideItems = 256;      // at most this many queued items: rebuild at 16 waves per item
 
 // Device-side description of one log-domain convolution applied to one grid array.
 enum Epilogue : int32_t {

@@ -555,27 +555,38 @@ __global__ __launch_bounds__(64 * (NT < 16 ? NT : 16)) void k_sparse(const ConvJ
         job.partial[static_cast<size_t>(tile) * NT + threadIdx.x] = 0.0;
 }
 
-// Dense rebuild of the tiles listed by k_sparse: one workgroup of kRbWaves waves per
-// (tile, ko) item, lane = pixel of the tile.  The window's (dy, dx) pairs are dealt
-// to the waves round-robin; partial maxima and sums are combined in LDS in wave
-// order.  Each wave records, per pair, a ballot mask of the orientations ki whose
-// term is within kListCut (+1) of the maximum for some pixel; a block-wide prefix
-// sum over the masks places every listed term, in (pair, ki) order, and the packed
-// entries are written.
-constexpr int kRbWaves = 8;
-constexpr int kRbThreads = 64 * kRbWaves;  // at least 6 waves per SIMD (80 VGPRs): 3 workgroups per CU
+// Dense rebuild of the tiles listed by k_sparse: one workgroup of RBW (8 or 16) waves
+// per (tile, ko) item, lane = pixel of the tile.  The window's (dy, dx) pairs are dealt
+// to the waves round-robin; partial maxima and sums are combined in LDS.  Each wave
+// records, per pair, a ballot mask of the orientations ki whose term is within
+// kListCut (+1) of the maximum for some pixel; a block-wide prefix sum over the masks
+// places every listed term, in (pair, ki) order, and the packed entries are written.
+//
+// The sum is split the same way for either width: pair r belongs to class r mod 16,
+// each class is summed over its pairs in increasing r, classes c and c + 8 are added,
+// and the eight results are summed in order of c.  A rebuild of 8 waves keeps two
+// accumulators per wave (classes w and w + 8), one of 16 waves one per wave; both give
+// bitwise identical outputs and lists, so the width is a free choice per launch.  Wide
+// items finish sooner (half the pairs per wave); narrow workgroups pack two to a CU
+// (~118 VGPRs: 4 waves per SIMD), against one wide one, and win when many tiles are
+// queued.
+constexpr int kRbClasses = 16;
 
-template <int NT>
-__global__ __launch_bounds__(kRbThreads) void k_rebuild(const ConvJob *__restrict__ jobs,
-                                                        const int2 *__restrict__ rebuild,
-                                                        const int *__restrict__ rebuild_count) {
+template <int NT, int RBW>
+__global__ __launch_bounds__(64 * RBW) void k_rebuild(const ConvJob *__restrict__ jobs,
+                                                      const int2 *__restrict__ rebuild,
+                                                      const int *__restrict__ rebuild_count,
+                                                      int *__restrict__ published) {
+    static_assert(RBW == 8 || RBW == 16, "8 or 16 waves per item");
+    constexpr int NTH = 64 * RBW;
     extern __shared__ double lds[];
-    __shared__ float s_mx[kRbWaves][64];
-    __shared__ double s_S[kRbWaves][64];
-    __shared__ int s_wsum[kRbWaves];
-    __shared__ int s_cnt;
+    __shared__ float s_mx[RBW][64];
+    __shared__ double s_S[RBW][64];
+    __shared__ int s_wsum[RBW];
     static_assert(NT <= 32, "masks hold up to 32 input orientations");
     const int nitems = *rebuild_count * NT;
+    // the host reads this (pinned memory, a vector store) to size the next rebuild
+    if (published != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *(volatile int *)published = nitems;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
     const int px = lane & 7, py = lane >> 3;
@@ -599,12 +610,12 @@ __global__ __launch_bounds__(kRbThreads) void k_rebuild(const ConvJob *__restric
         uint32_t *terms = masks + W * W;
 
         __syncthreads();  // LDS of the previous item is free
-        load_halo<NT, kRbThreads, 2>(lds, job.in, NT, 0, x0, y0, R, HW, nx, ny);
+        load_halo<NT, NTH, 2>(lds, job.in, NT, 0, x0, y0, R, HW, nx, ny);
         __syncthreads();
 
         // pass 1: maximum over this wave's pairs
         float mx = -INFINITY;
-        for (int r = wave; r < W * W; r += kRbWaves) {
+        for (int r = wave; r < W * W; r += RBW) {
             const int dyi = r / W, dxi = r - dyi * W;  // dy = dyi - R, dx = dxi - R
             const int hb = (py + 2 * R - dyi) * HW + (px + 2 * R - dxi);
             const cfptr Lr = L32 + (static_cast<size_t>(r) * NT + ko) * NT;
@@ -615,13 +626,14 @@ __global__ __launch_bounds__(kRbThreads) void k_rebuild(const ConvJob *__restric
         __syncthreads();
         mx = s_mx[0][lane];
 #pragma unroll
-        for (int w = 1; w < kRbWaves; ++w) mx = fmaxf(mx, s_mx[w][lane]);
+        for (int w = 1; w < RBW; ++w) mx = fmaxf(mx, s_mx[w][lane]);
         const double M = (mx == -INFINITY) ? 0.0 : static_cast<double>(mx);
 
-        // pass 2: sum and membership masks of this wave's pairs
+        // pass 2: sum (per class) and membership masks of this wave's pairs
         const unsigned long long vmask = __builtin_amdgcn_ballot_w64(valid);  // pixels inside the grid
-        double S = 0.0;
-        for (int r = wave; r < W * W; r += kRbWaves) {
+        double Sc[2] = {0.0, 0.0};  // classes wave and wave + 8 (RBW = 8); class wave (RBW = 16)
+        int half = 0;
+        for (int r = wave; r < W * W; r += RBW) {
             const int dyi = r / W, dxi = r - dyi * W;
             const int hb = (py + 2 * R - dyi) * HW + (px + 2 * R - dxi);
             const cdptr Lr = L64 + (static_cast<size_t>(r) * NT + ko) * NT;
@@ -637,19 +649,29 @@ __global__ __launch_bounds__(kRbThreads) void k_rebuild(const ConvJob *__restric
                 m |= (b != 0ull) ? (1u << kc) : 0u;
             }
             if (lane == 0) masks[r] = m;
-            S += static_cast<double>(srow);
+            if (RBW == kRbClasses / 2 && half) Sc[1] += static_cast<double>(srow);
+            else Sc[0] += static_cast<double>(srow);
+            half ^= 1;
         }
-        s_S[wave][lane] = S;
+        // slot w holds classes w and w + 8 added (RBW = 8) or class w alone (RBW = 16)
+        s_S[wave][lane] = (RBW == kRbClasses / 2) ? Sc[0] + Sc[1] : Sc[0];
         __syncthreads();
-        S = s_S[0][lane];
+        double S;
+        if constexpr (RBW == kRbClasses / 2) {
+            S = s_S[0][lane];
 #pragma unroll
-        for (int w = 1; w < kRbWaves; ++w) S += s_S[w][lane];
+            for (int w = 1; w < RBW; ++w) S += s_S[w][lane];
+        } else {
+            S = s_S[0][lane] + s_S[8][lane];
+#pragma unroll
+            for (int w = 1; w < kRbClasses / 2; ++w) S += s_S[w][lane] + s_S[w + 8][lane];
+        }
         const double lse = (S > 0.0) ? M + log2(S) : -INFINITY;
 
         // compaction: exclusive prefix sum of the mask popcounts over the pairs, in
-        // rounds of kRbThreads pairs
+        // rounds of NTH pairs
         int base = 0;
-        for (int r0 = 0; r0 < W * W; r0 += kRbThreads) {
+        for (int r0 = 0; r0 < W * W; r0 += NTH) {
             const int r = r0 + static_cast<int>(threadIdx.x);
             const uint32_t m = (r < W * W) ? masks[r] : 0u;
             const int c = __builtin_popcount(m);
@@ -664,7 +686,7 @@ __global__ __launch_bounds__(kRbThreads) void k_rebuild(const ConvJob *__restric
             int wbase = base;
             for (int w = 0; w < wave; ++w) wbase += s_wsum[w];
             int total = base;
-            for (int w = 0; w < kRbWaves; ++w) total += s_wsum[w];
+            for (int w = 0; w < RBW; ++w) total += s_wsum[w];
             int pos = wbase + incl - c;
             uint32_t mm = m;
             while (mm != 0u) {
@@ -701,7 +723,7 @@ __global__ __launch_bounds__(kRbThreads) void k_rebuild(const ConvJob *__restric
             // packed entries of (tile, ko), written by all threads
             const int n = cnt <= job.lmax ? cnt : 0;
             const gdptr_w dst = (gdptr_w)(job.lists + (static_cast<size_t>(tile) * NT + ko) * job.lmax);
-            for (int e = threadIdx.x; e < n; e += kRbThreads) {
+            for (int e = threadIdx.x; e < n; e += NTH) {
                 const uint32_t term = terms[e];
                 const double Lv = ((gdptr)job.L64)[((term / NT) * NT + ko) * NT + term % NT];
                 const uint32_t off = static_cast<uint32_t>(term_offset(term, NT, R, W, HW, npix));
@@ -713,7 +735,7 @@ __global__ __launch_bounds__(kRbThreads) void k_rebuild(const ConvJob *__restric
         if (ko == 0) {
             // reference halo, pixel-major [p][kc]
             const gfptr_w ref = (gfptr_w)(job.ref + static_cast<size_t>(tile) * NT * npix);
-            for (int e = threadIdx.x; e < NT * npix; e += kRbThreads) {
+            for (int e = threadIdx.x; e < NT * npix; e += NTH) {
                 const int p = e / NT, kc = e - p * NT;
                 ref[e] = static_cast<float>(lds[kc * npix + p]);
             }
@@ -736,11 +758,28 @@ int launch_dense_t(const ConvJob *d_jobs, int nblocks, const int32_t *d_block_jo
     return SE2_OK;
 }
 
+template <int NT, int RBW>
+int launch_rebuild_t(const ConvJob *d_jobs, int nblocks, int R_max, const int2 *rebuild, const int *rebuild_count,
+                     int *published, hipStream_t s) {
+    const int HW = kTile + 2 * R_max, W = 2 * R_max + 1;
+    const size_t lr = static_cast<size_t>(HW) * HW * NT * sizeof(double) +
+                      (static_cast<size_t>(W) * W + kListMax) * sizeof(uint32_t);
+    if (lr > 65536)
+        SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rebuild<NT, RBW>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lr)));
+    const int cap = (RBW == 16) ? kRebuildGridWide : kRebuildGrid;
+    const int grid = nblocks * NT < cap ? nblocks * NT : cap;
+    hipLaunchKernelGGL((k_rebuild<NT, RBW>), dim3(grid), dim3(64 * RBW), lr, s, d_jobs, rebuild, rebuild_count,
+                       published);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
 template <int NT>
 int launch_sparse_t(const ConvJob *d_jobs, int nblocks, const int32_t *d_block_job, int R_max, int2 *rebuild,
-                    int *rebuild_count, int *next_count, hipStream_t s) {
+                    int *rebuild_count, int *next_count, int rb_waves, int *published, hipStream_t s) {
     constexpr int NW = NT < 16 ? NT : 16;
-    const int HW = kTile + 2 * R_max, W = 2 * R_max + 1;
+    const int HW = kTile + 2 * R_max;
     const size_t lds = static_cast<size_t>(HW) * HW * NT * sizeof(double);
     if (lds > 65536)
         SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sparse<NT>),
@@ -748,15 +787,8 @@ int launch_sparse_t(const ConvJob *d_jobs, int nblocks, const int32_t *d_block_j
     hipLaunchKernelGGL(k_sparse<NT>, dim3(xcd_grid(nblocks)), dim3(64 * NW), lds, s, d_jobs, d_block_job, nblocks,
                        rebuild, rebuild_count, next_count);
     SE2_HIP(hipGetLastError());
-    const size_t lr = static_cast<size_t>(HW) * HW * NT * sizeof(double) +
-                      (static_cast<size_t>(W) * W + kListMax) * sizeof(uint32_t);
-    if (lr > 65536)
-        SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rebuild<NT>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lr)));
-    const int grid = nblocks * NT < kRebuildGrid ? nblocks * NT : kRebuildGrid;
-    hipLaunchKernelGGL(k_rebuild<NT>, dim3(grid), dim3(kRbThreads), lr, s, d_jobs, rebuild, rebuild_count);
-    SE2_HIP(hipGetLastError());
-    return SE2_OK;
+    return rb_waves == 16 ? launch_rebuild_t<NT, 16>(d_jobs, nblocks, R_max, rebuild, rebuild_count, published, s)
+                          : launch_rebuild_t<NT, 8>(d_jobs, nblocks, R_max, rebuild, rebuild_count, published, s);
 }
 
 }  // namespace
@@ -767,7 +799,8 @@ bool conv_lse_sparse_fits(int nt, int R) {
 }
 
 int launch_conv_lse(const ConvJob *d_jobs, int njobs, int nblocks, const int32_t *d_block_job, int nt, int R_max,
-                    bool f64exp, bool sparse, int2 *rebuild, int *rebuild_count, int *next_count, hipStream_t s) {
+                    bool f64exp, bool sparse, int2 *rebuild, int *rebuild_count, int *next_count, int rb_waves,
+                    int *published, hipStream_t s) {
     (void)njobs;
     if (nblocks <= 0) return SE2_OK;
     if (R_max < 0 || R_max > kMaxRadius) return SE2_EINVAL;
@@ -775,15 +808,18 @@ int launch_conv_lse(const ConvJob *d_jobs, int njobs, int nblocks, const int32_t
     if (sparse) {
         // every job of a sparse launch carries lists (the engine groups them apart)
         if (f64exp || !conv_lse_sparse_fits(nt, R_max) || !rebuild || !rebuild_count || !next_count ||
-            rebuild_count == next_count)
+            rebuild_count == next_count || (rb_waves != 8 && rb_waves != 16))
             return SE2_EINVAL;
         switch (nt) {
             case 8:
-                return launch_sparse_t<8>(d_jobs, nblocks, d_block_job, R_max, rebuild, rebuild_count, next_count, s);
+                return launch_sparse_t<8>(d_jobs, nblocks, d_block_job, R_max, rebuild, rebuild_count, next_count,
+                                             rb_waves, published, s);
             case 16:
-                return launch_sparse_t<16>(d_jobs, nblocks, d_block_job, R_max, rebuild, rebuild_count, next_count, s);
+                return launch_sparse_t<16>(d_jobs, nblocks, d_block_job, R_max, rebuild, rebuild_count, next_count,
+                                             rb_waves, published, s);
             case 32:
-                return launch_sparse_t<32>(d_jobs, nblocks, d_block_job, R_max, rebuild, rebuild_count, next_count, s);
+                return launch_sparse_t<32>(d_jobs, nblocks, d_block_job, R_max, rebuild, rebuild_count, next_count,
+                                             rb_waves, published, s);
             default: return SE2_EINVAL;
         }
     }

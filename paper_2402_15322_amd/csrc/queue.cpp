@@ -280,6 +280,7 @@ int active_count(const se2_queue_s *Q) {
 void lane_main(se2_queue_s *Q, int l) {
     (void)hipSetDevice(Q->device);
     Engine &eng = Q->eng[l];
+    eng.set_wide_rebuild(false);  // the lanes' kernels share the GPU
     hipStream_t st = Q->st[l];
     std::vector<double> errs;
     for (;;) {

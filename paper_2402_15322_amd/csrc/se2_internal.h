@@ -71,9 +71,13 @@ int build_tables(Kernel &k);
 
 // launchers (conv_lse.hip)
 // Error partials of EPI_SCALE jobs are laid out [tile][nt]; `rebuild` must hold one
-// int2 per block of the launch (sparse launches only).
+// int2 per block of the launch (sparse launches only).  A sparse launch rebuilds its
+// uncertified tiles at rb_waves (8 or 16) waves per (tile, ko) item, with identical
+// results either way, and stores the number of items it found to *published (pinned
+// host memory, may be null) for the caller's next choice of width.
 int launch_conv_lse(const ConvJob *d_jobs, int njobs, int nblocks, const int32_t *d_block_job, int nt, int R_max,
-                    bool f64exp, bool sparse, int2 *rebuild, int *rebuild_count, int *next_count, hipStream_t s);
+                    bool f64exp, bool sparse, int2 *rebuild, int *rebuild_count, int *next_count, int rb_waves,
+                    int *published, hipStream_t s);
 bool conv_lse_sparse_fits(int nt, int R);
 
 // launchers (conv_linear.hip)

@@ -17,6 +17,7 @@
 #include "solver.h"
 
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstring>
 
@@ -340,6 +341,7 @@ Engine::~Engine() {
     if (h_jobs_) (void)hipHostFree(h_jobs_);
     if (h_map_) (void)hipHostFree(h_map_);
     if (h_err_) (void)hipHostFree(h_err_);
+    if (h_published_) (void)hipHostFree(h_published_);
     if (h_items_) (void)hipHostFree(h_items_);
     if (d_items_) (void)hipFree(d_items_);
     if (d_errs_) (void)hipFree(d_errs_);
@@ -419,18 +421,30 @@ int Engine::stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, in
             SE2_HIP(hipMalloc(&d_rebuild_count_, 2 * sizeof(int)));
             SE2_HIP(hipMemsetAsync(d_rebuild_count_, 0, 2 * sizeof(int), st));
         }
+        if (!h_published_) {
+            // rebuild item counts the kernels publish, one per ntheta class; until the first
+            // count arrives the narrow rebuild (suited to many items) is used
+            SE2_HIP(hipHostMalloc(reinterpret_cast<void **>(&h_published_), 3 * sizeof(int), hipHostMallocCoherent));
+            for (int c = 0; c < 3; ++c) h_published_[c] = INT_MAX;
+            SE2_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&d_published_), h_published_, 0));
+        }
         cap_rebuild_ = static_cast<size_t>(nblocks) * 2;
         SE2_HIP(hipMalloc(&d_rebuild_, cap_rebuild_ * sizeof(int2)));
     }
     int rc;
     if (!sparse) {
         rc = launch_conv_lse(t->d_jobs, static_cast<int>(nj), nblocks, t->d_map, nt, R_max, f64, false, nullptr, nullptr,
-                             nullptr, st);
+                             nullptr, 8, nullptr, st);
     } else {
         int *cnt = d_rebuild_count_ + rc_flip_, *next = d_rebuild_count_ + (1 - rc_flip_);
         rc_flip_ ^= 1;
+        // rebuild width from the last count this class published (written by the GPU
+        // asynchronously: a value some launches old; the results do not depend on it)
+        const int cls = nt == 8 ? 0 : (nt == 16 ? 1 : 2);
+        const int last = *reinterpret_cast<volatile int *>(h_published_ + cls);
+        const int rb_waves = (wide_rebuild_ && last <= kRebuildWideItems) ? 16 : 8;
         rc = launch_conv_lse(t->d_jobs, static_cast<int>(nj), nblocks, t->d_map, nt, R_max, f64, true, d_rebuild_, cnt,
-                             next, st);
+                             next, rb_waves, d_published_ + cls, st);
     }
     if (rc) return rc;
     SE2_HIP(hipEventRecord(t->used, st));

@@ -115,6 +115,11 @@ public:
     // the proximal step for JKO), half 1 the a-update (w-update) with the iteration count,
     // and the error sums when `check`.
     int step_half(const std::vector<Solve *> &solves, int half, bool check, hipStream_t st);
+    // Rebuilds of uncertified tiles at 16 waves per item while few are queued (the
+    // default), or always at 8.  Outputs are identical either way; a wide workgroup
+    // cannot share a CU with a sparse one, so engines whose streams run beside other
+    // engines' work keep the narrow form.
+    void set_wide_rebuild(bool on) { wide_rebuild_ = on; }
     // Copies err slots of the given solves to host (synchronises the stream).
     int read_errors(const std::vector<Solve *> &solves, std::vector<double> &max_err, hipStream_t st);
     // Optional event timing of every log-domain convolution launch.  With a reference event
@@ -150,6 +155,9 @@ private:
     uint64_t clock_ = 0;
     int2 *d_rebuild_ = nullptr;      // tiles left to the wide rebuild kernel, one slot per block
     int *d_rebuild_count_ = nullptr;  // two counters, used alternately
+    int *h_published_ = nullptr;      // pinned: rebuild items of the last launch per ntheta class
+    int *d_published_ = nullptr;      // the same memory as the kernels address it
+    bool wide_rebuild_ = true;
     int rc_flip_ = 0;
     size_t cap_rebuild_ = 0;
     ConvJob *h_jobs_ = nullptr;      // pinned staging (double-buffered)

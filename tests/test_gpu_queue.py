@@ -149,3 +149,28 @@ def test_kernel_time_accounts_every_convolution(nat):
     assert all(r["iters"] == it for r in reps)
     assert 2 * it <= kt["launches"] <= 2 * (it + 4)
     assert 0.0 < kt["seconds"] <= wall
+
+
+@pytest.mark.parametrize("n,nt,R,iters", [(64, 16, 5, 300), (32, 32, 3, 120), (40, 8, 4, 120)])
+def test_wide_and_narrow_rebuilds_are_bitwise_identical(nat, n, nt, R, iters):
+    """The blocking solver rebuilds few uncertified tiles at 16 waves per item, the queue's
+    lanes always at 8; the split of the window sums is the same for both widths, so the
+    potentials agree bit for bit (pruned engine, the workload's shapes and more)."""
+    torch = torch_dev()
+    g = synth.Grid(n, n, nt)
+    r = synth.rng_for(9200 + n, 0)
+    segs = synth.draw_segments(r, g, 6, 4.0, 16.0)
+    mu = synth.splat_segments(g, segs, 1.0, 1e-6)
+    nu = synth.splat_segments(g, synth.moved_segments(r, g, segs, 2.0, 0.2), 1.0, 1e-6)
+    k = nat.Kernel(n, n, nt, False, (1.0, 3.0, 1.0), 0.1, R)
+    o = nat.opts(tol=-1, max_iter=iters, check_every=20)
+    mud, nud = to_dev(mu), to_dev(nu)
+    f, gb = torch.empty_like(mud), torch.empty_like(mud)
+    rep_b = nat.se2_sinkhorn(k, mud, nud, o, f, gb)
+    q = nat.SolveQueue(hbm_budget_bytes=256 << 20, max_slots=2)
+    fq, gq = torch.empty_like(mud), torch.empty_like(mud)
+    rep_q = q.wait(q.submit_ot(k, mud, nud, o, fq, gq))
+    q.close()
+    assert rep_b["iters"] == rep_q["iters"] == iters
+    assert rep_b["terms_sparse"] > 0 and rep_b["terms_dense"] > 0
+    assert np.array_equal(to_host(f), to_host(fq)) and np.array_equal(to_host(gb), to_host(gq))
