@@ -41,12 +41,13 @@ SLOTS_SPARSE = 2 + 1 + EXP_SLOTS + 1
 # quoted as FP64-FMA equivalents (2 flops per slot): the published FP64 vector
 # peak of 78.6 TFLOP/s.
 PEAK_TFLOPS = 78.6
-# HBM bytes of one convolution launch (k_sparse + k_rebuild) on this workload, from
-# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (each scaled by what the counter reads for
-# a plain 256 MiB copy: x2.0 and x1.0), averaged over the 2004 launches of one bench
-# step; profiles/conv_lse_traffic_lines64x64x16_batch32.md.  Reported only while the
-# kernel's sources (the kernel file and its shared header) are the ones measured.
-TRAFFIC = {"sources_sha256": "bc70cb679cea288da2fe6c0808d5f50bcfb4cae615ec0f49707e9b09bb628af7", "bytes_per_launch": 148085105.6,
+# HBM bytes of one batched convolution half-step (k_sparse + k_rebuild of every lane) on
+# this workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (each scaled by what the
+# counter reads for a plain 256 MiB copy: x2.0 and x1.0), summed over the 3 x 2004
+# launch pairs of one bench step and divided by its 2004 half-steps;
+# profiles/conv_lse_traffic_lines64x64x16_batch32.md.  Reported only while the kernel's
+# sources (the kernel file and its shared header) are the ones measured.
+TRAFFIC = {"sources_sha256": "2d10804799e4366c9650178af1535d4c8e8f2b09577adf14d6f7b1cd8cf0cc1f", "bytes_per_launch": 151683658.6,
            "sources": ("paper_2402_15322_amd/csrc/conv_lse.hip", "paper_2402_15322_amd/csrc/conv_lse.h")}
 
 
