@@ -72,6 +72,10 @@ def parse():
     ap.add_argument("--plain", type=int, default=2, help="solves run one at a time beside the queue")
     ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations for the CPU baseline (0: auto)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="CPU only: the FP64 oracle timed per convolution, iteration and solve for every workload "
+                         "configuration, all threads and one thread (own JSON line)")
+    ap.add_argument("--oracle-timing-one-core", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-prune", action="store_true", help="dense convolutions only (no certified pruning)")
     ap.add_argument("--no-conv", action="store_true", help="skip the linear se2_conv measurements")
     ap.add_argument("--conv-only", action="store_true", help="only the linear se2_conv measurements")
@@ -287,18 +291,6 @@ def barycenter_workloads(native, torch, synth, c4_iters: int):
                      "sparse_terms": sum(r["terms_sparse"] for r in reps),
                      "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
                                   "frac": achieved / PEAK_TFLOPS}}
-        if name.startswith("curves"):
-            # the t = 1/2 problem again, blocking, 2 iterations, against the oracle's 2 iterations
-            import numpy as np
-            import oracle
-            inst = insts[2]
-            b = torch.empty_like(dev[2][0])
-            rep = native.se2_barycenter(k, dev[2], inst.lambdas, native.opts(tol=-1.0, max_iter=2, check_every=2), b)
-            logk, _ = oracle.kernel_table(g.nt, g.axial, inst.w, inst.eps, inst.radius)
-            bar_o, it_o, err_o, _ = oracle.ibp(logk, inst.mus, inst.lambdas, 2, -1.0)
-            out[name]["gpu_vs_oracle"] = {"t": 0.5, "iterations": it_o,
-                                          "barycenter_l1": float(np.sum(np.abs(b.cpu().numpy() - bar_o))),
-                                          "marg_l1_diff": abs(rep["marg_l1"] - err_o)}
         del dev, outs, k
     return out
 
@@ -310,6 +302,30 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU sharding is "
                                    "described in DESIGN.md and not implemented)"}))
         sys.exit(2)
+    if a.oracle_timing:
+        # CPU only (no GPU work in this process): all threads, then a one-thread child for the
+        # convolutions
+        import platform
+        import subprocess
+        import oracle
+        model = platform.processor()
+        try:
+            with open("/proc/cpuinfo") as fh:
+                model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), model)
+        except OSError:
+            pass
+        rec = {"mode": "oracle_timing", "kind": "oracle", "host": {"nproc": os.cpu_count(), "cpu_model": model},
+               "all_threads": dict(threads=oracle.num_threads(), **oracle_timing())}
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-timing-one-core"], env=env,
+                           capture_output=True, text=True, timeout=600)
+        rec["one_thread"] = json.loads(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else {"error": r.stderr[-500:]}
+        print(json.dumps(rec), flush=True)
+        return
+    if a.oracle_timing_one_core:
+        import oracle
+        print(json.dumps(dict(threads=oracle.num_threads(), **oracle_timing(one_conv_only=True))), flush=True)
+        return
     import numpy as np
     import torch
 
@@ -565,6 +581,7 @@ def cpu_baseline(inst, iters: int, native=None, torch=None, kernel=None):
     """FP64 oracle Sinkhorn on this host, a bounded sample of the same workload; with the
     library given, the same solve on the GPU at the same iteration count beside it, and the
     GPU result's errors against the oracle's (plan L1, marginal L1, relative cost)."""
+    import numpy as np
     import oracle
     logk, cost = oracle.kernel_table(NT, False, W_METRIC, EPS, R)
     if iters <= 0:
@@ -590,6 +607,93 @@ def cpu_baseline(inst, iters: int, native=None, torch=None, kernel=None):
             "marg_l1_gpu": rep["marg_l1"], "marg_l1_oracle": err_o,
             "marg_l1_diff": abs(rep["marg_l1"] - err_o), "rel_cost_diff": abs(rep["cost"] - c_o) / c_o,
             "engine": "FP32-exp log-domain engine with certified pruning"}
+        # the 128x128x16 interpolation at t = 1/2: 2 IBP iterations on the GPU (blocking call)
+        # against the oracle's 2 iterations
+        from paper_2402_15322_amd import synth
+        ci = synth.curves128(0, t=0.5)
+        g = ci.grid
+        kc = native.Kernel(g.nx, g.ny, g.nt, g.axial, ci.w, ci.eps, ci.radius)
+        dev = [torch.from_numpy(m).cuda() for m in ci.mus]
+        b = torch.empty_like(dev[0])
+        rep = native.se2_barycenter(kc, dev, ci.lambdas, native.opts(tol=-1.0, max_iter=2, check_every=2), b)
+        logk_c, _ = oracle.kernel_table(g.nt, g.axial, ci.w, ci.eps, ci.radius)
+        bar_o, it_o, err_o, _ = oracle.ibp(logk_c, ci.mus, ci.lambdas, 2, -1.0)
+        out["gpu_vs_oracle_curves128"] = {"t": 0.5, "iterations": it_o,
+                                          "barycenter_l1": float(np.abs(b.cpu().numpy() - bar_o).sum()),
+                                          "marg_l1_diff": abs(rep["marg_l1"] - err_o)}
+    return out
+
+
+def oracle_timing(one_conv_only: bool = False):
+    """The FP64 oracle timed on this host's cores for every configuration of the paper's
+    workloads, beside the GPU figures: seconds per log-domain convolution, per iteration
+    (Sinkhorn: 2 convolutions; IBP with n measures: 2n) and per 1000-iteration solve
+    (extrapolated from the iterations timed).  The serving trace is sampled by 8 requests of
+    each grid size (first ones of the trace), each timed over 2 iterations and extrapolated
+    to 1000 iterations; the trace total is the per-size mean times the requests of that size.
+    With one_conv_only (the one-core run) only the convolutions are timed."""
+    import numpy as np
+    import oracle
+    from paper_2402_15322_amd import synth
+
+    def t_conv(logk, x, reps):
+        lx = oracle.safe_log(x)
+        oracle.conv_log(logk, lx)
+        t = time.perf_counter()
+        for _ in range(reps):
+            oracle.conv_log(logk, lx)
+        return (time.perf_counter() - t) / reps
+
+    cfgs = []
+    c0 = synth.tiny_ot(0)
+    c1 = synth.lines64(0, paired=True)
+    c2 = synth.curves128(0, t=0.5)
+    c4 = synth.fields256(0, n=64, nt=8)
+    for name, inst, kind, iters, reps in (
+            ("16x16x8 OT (200 iterations)", c0, "ot", 200, 20),
+            ("64x64x16 OT, paired lines", c1, "ot", 3, 3),
+            ("128x128x16 interpolation, t = 1/2", c2, "ibp", 1, 1),
+            ("64x64x8 axial downsample of the 256x256x32 fields", c4, "ibp", 2, 3)):
+        g = inst.grid
+        logk, _ = oracle.kernel_table(g.nt, g.axial, inst.w, inst.eps, inst.radius)
+        x = inst.mu if kind == "ot" else inst.mus[0]
+        rec = {"config": name, "grid": f"{g.nx}x{g.ny}x{g.nt}", "window": f"{2 * inst.radius + 1}x{2 * inst.radius + 1}",
+               "s_per_conv": t_conv(logk, x, reps)}
+        convs = 2 if kind == "ot" else 2 * len(inst.mus)
+        if one_conv_only:
+            rec["s_per_iter_from_convs"] = convs * rec["s_per_conv"]
+        else:
+            t = time.perf_counter()
+            if kind == "ot":
+                oracle.sinkhorn(logk, inst.mu, inst.nu, iters, -1.0)
+            else:
+                oracle.ibp(logk, inst.mus, inst.lambdas, iters, -1.0)
+            rec["s_per_iter"] = (time.perf_counter() - t) / iters
+            rec["iters_timed"] = iters
+            rec["solve_iters"] = 200 if name.startswith("16x16x8") else 1000
+            rec["s_per_solve"] = rec["s_per_iter"] * rec["solve_iters"]
+        cfgs.append(rec)
+    out = {"configs": cfgs}
+    if not one_conv_only:
+        trace = synth.serving_trace(512, 200.0)
+        sizes = {}
+        for r in trace:
+            sizes.setdefault(r.inst.grid.nx, []).append(r)
+        per = {}
+        total = 0.0
+        for n, reqs in sorted(sizes.items()):
+            ts = []
+            for r in reqs[:8]:
+                g = r.inst.grid
+                logk, _ = oracle.kernel_table(g.nt, g.axial, r.inst.w, r.inst.eps, r.inst.radius)
+                t = time.perf_counter()
+                oracle.sinkhorn(logk, r.inst.mu, r.inst.nu, 2, -1.0)
+                ts.append((time.perf_counter() - t) / 2 * 1000)
+            per[f"{n}x{n}"] = {"requests_in_trace": len(reqs), "sampled": len(ts),
+                               "s_per_1000_iter_solve": float(np.mean(ts))}
+            total += len(reqs) * float(np.mean(ts))
+        out["serving_trace"] = {"per_grid": per, "s_for_all_512_requests": total,
+                                "solves_per_s": 512 / total, "note": "extrapolated from 2 timed iterations"}
     return out
 
 
