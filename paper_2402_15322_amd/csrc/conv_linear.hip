@@ -181,18 +181,47 @@ __global__ __launch_bounds__(256) void k_conv_bf16(const float *__restrict__ in,
         // halo row of (r, c): row0 + r - (dy0 + c) + R = hrow_t0 + t
         mfma_chunk<NT, DYC, RPW>(acc, bfr, lds16, row0 + R - dy0 - (DYC - 1), HWX, hx, kio);
     };
-    // the prefetch index is clamped (the last step reloads its own fragments) so the
-    // loop body has no branch and the loads' wait counts stay exact
-    load_b(b0, 0);
-    for (int step = 0; step < nsteps; ++step) {
-        load_b(b1, min(step + 1, nsteps - 1));
-        __builtin_amdgcn_sched_barrier(0);
-        run(b0, step);
-        __builtin_amdgcn_sched_barrier(0);
+    if constexpr (P::NB == 1) {
+        // three fragment buffers in rotation: the fragments of step s + 2 are requested while
+        // step s runs (a step is ~24 MFMAs per wave at two waves per SIMD, about one L2
+        // round trip), and no buffer is copied, so no wait falls on a load still in flight.
+        // Prefetch indices are clamped (the last steps reload fragments they do not use) so
+        // that the loads' wait counts stay exact; the last nsteps % 3 steps run after the loop.
+        bf16x8_t b2[DYC][P::NB];
+        load_b(b0, 0);
+        load_b(b1, min(1, nsteps - 1));
+        int step = 0;
+        for (; step + 3 <= nsteps; step += 3) {
+            load_b(b2, min(step + 2, nsteps - 1));
+            __builtin_amdgcn_sched_barrier(0);
+            run(b0, step);
+            __builtin_amdgcn_sched_barrier(0);
+            load_b(b0, min(step + 3, nsteps - 1));
+            __builtin_amdgcn_sched_barrier(0);
+            run(b1, step + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            load_b(b1, min(step + 4, nsteps - 1));
+            __builtin_amdgcn_sched_barrier(0);
+            run(b2, step + 2);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (step < nsteps) run(b0, step);
+        if (step + 1 < nsteps) run(b1, step + 1);
+    } else {
+        // two column blocks (nt = 32): the fragments of the next step are loaded while the
+        // current one runs (a third buffer would not fit the registers); the prefetch index is
+        // clamped (the last step reloads its own fragments) so the loop body has no branch
+        load_b(b0, 0);
+        for (int step = 0; step < nsteps; ++step) {
+            load_b(b1, min(step + 1, nsteps - 1));
+            __builtin_amdgcn_sched_barrier(0);
+            run(b0, step);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int c = 0; c < DYC; ++c)
+            for (int c = 0; c < DYC; ++c)
 #pragma unroll
-            for (int nb = 0; nb < P::NB; ++nb) b0[c][nb] = b1[c][nb];
+                for (int nb = 0; nb < P::NB; ++nb) b0[c][nb] = b1[c][nb];
+        }
     }
 
     // D: lane holds column j = lane % 16 (ko), rows 4*(lane/16) + q (pixels)
