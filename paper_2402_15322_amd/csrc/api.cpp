@@ -55,6 +55,7 @@ void kernel_free(Kernel *k) {
     (void)hipFree(k->d_Kbf16);
     (void)hipFree(k->d_K64);
     (void)hipFree(k->d_Bpack);
+    (void)hipFree(k->d_Fpack);
     delete k;
 }
 

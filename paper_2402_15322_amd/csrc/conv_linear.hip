@@ -13,7 +13,13 @@
 //         in LDS; kernel fragments are pre-packed on the host in operand order (one
 //         coalesced 16-byte load per lane) and zero-padded where a dx group
 //         overhangs the window or a dy chunk runs past it.
-//   F32 / F64: the same tiling on the vector ALUs with FP32 / FP64 FMAs.
+//   F32, nt = 16: the same implicit GEMM on the FP32 matrix cores
+//         (v_mfma_f32_16x16x4f32): per window offset (dy, dx), four 16 x 4 by 4 x 16
+//         products cover the 16 input orientations; a lane's four A operands are the
+//         four orientations it reads with one 16-byte LDS load, and the B operand is
+//         packed on the host to match.  The halo is staged in FP32, unrounded.
+//   F32 (nt = 8, 32) / F64: an 8 x 8 tile per workgroup on the vector ALUs with FP32 /
+//         FP64 FMAs.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -243,6 +249,138 @@ __global__ __launch_bounds__(256) void k_conv_bf16(const float *__restrict__ in,
     }
 }
 
+// FP32 convolution on the matrix cores, nt = 16: the tiling of k_conv_bf16 (kSeg output
+// pixels by kWaves * RPW output rows per workgroup, window rows in chunks of DYC), one
+// step per (dx, dy chunk).  For output row r and window row c of the chunk, the lane of
+// pixel i = lane % 16 and quad kq = lane / 16 reads input orientations 4 kq .. 4 kq + 3
+// of its input pixel as one float4; MFMA e (e = 0..3) multiplies element e by the packed
+// B value K[ko = lane % 16][ki = 4 kq + e], so the four MFMAs sum all 16 orientations.
+template <int DYC, int RPW>
+__global__ __launch_bounds__(256) void k_conv_f32m(const float *__restrict__ in, float *__restrict__ out,
+                                                   const f32x4_t *__restrict__ Fp, int nx, int ny, int R,
+                                                   int tiles_x, int tiles_y) {
+    constexpr int NT = 16;
+    extern __shared__ float lds32[];
+    const int W = 2 * R + 1;
+    const int HWX = kSeg + 2 * R;
+    constexpr int kRows = RPW * kWaves;
+    const int HWY = kRows + 2 * R;
+    const int tiles = tiles_x * tiles_y;
+    const int b = blockIdx.x / tiles;
+    const int t = blockIdx.x - b * tiles;
+    const int ty = t / tiles_x, tx = t - ty * tiles_x;
+    const int x0 = tx * kSeg, y0 = ty * kRows;
+    const float *img = in + static_cast<size_t>(b) * nx * ny * NT;
+    float *dst = out + static_cast<size_t>(b) * nx * ny * NT;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int i = lane & 15;      // output pixel within the segment (A row)
+    const int kq = lane >> 4;     // orientation quad of this lane
+    const int row0 = wave * RPW;  // first output row of this wave within the tile
+
+    f32x4_t acc[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) acc[r] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+    // (dx, dy chunk) steps; the fragments of a step are loaded one step ahead, those of
+    // the first step before the halo staging, so that their latency overlaps it
+    const int nchunks = (W + DYC - 1) / DYC;
+    const int nsteps = W * nchunks;
+    f32x4_t b0[DYC], b1[DYC];
+    auto load_b = [&](f32x4_t(&dstb)[DYC], int step) {
+        const int dxi = step / nchunks, ch = step - dxi * nchunks;
+        const f32x4_t *src = Fp + (static_cast<size_t>(ch * DYC) * W + dxi) * 64 + lane;
+#pragma unroll
+        for (int c = 0; c < DYC; ++c) dstb[c] = src[static_cast<size_t>(c) * W * 64];
+    };
+    load_b(b0, 0);
+
+    // stage the halo [hy][hx][ki] in FP32, zero outside the grid; loads go out in batches
+    // of 8 float4 per thread (clamped indices, no branches) before any is stored
+    const int xl = x0 - R;
+    {
+        constexpr int Q = NT / 4;
+        constexpr int NB8 = 8;
+        const int total = HWY * HWX * Q;
+        const float inv = 1.0f / static_cast<float>(HWX);
+        for (int e0 = 0; e0 < total; e0 += NB8 * 256) {
+            float4 v[NB8];
+            bool ok[NB8];
+#pragma unroll
+            for (int u = 0; u < NB8; ++u) {
+                const int e = min(e0 + u * 256 + static_cast<int>(threadIdx.x), total - 1);
+                const int p = e / Q, q = e - p * Q;
+                // p / HWX through a float reciprocal: exact for p < 2^20
+                const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv), hx = p - hy * HWX;
+                const int gy = y0 - R + hy, gx = xl + hx;
+                ok[u] = gy >= 0 && gy < ny && gx >= 0 && gx < nx;
+                const int cy = min(max(gy, 0), ny - 1), cx = min(max(gx, 0), nx - 1);
+                v[u] = *reinterpret_cast<const float4 *>(&img[(static_cast<size_t>(cy) * nx + cx) * NT + 4 * q]);
+            }
+#pragma unroll
+            for (int u = 0; u < NB8; ++u) {
+                const int e = e0 + u * 256 + static_cast<int>(threadIdx.x);
+                if (e < total)
+                    *reinterpret_cast<float4 *>(&lds32[4 * e]) = ok[u] ? v[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+    }
+    __syncthreads();
+
+    auto run = [&](const f32x4_t(&bfr)[DYC], int step) {
+        const int dxi = step / nchunks, ch = step - dxi * nchunks;
+        // input pixel x0 + i - dx (dx = dxi - R) sits at halo column i + 2R - dxi; output
+        // row r and window row c = r - t + DYC - 1 of the chunk meet halo row hrow0 + t
+        // (rows past the window carry zero fragments; their row index is clamped)
+        const float *base = lds32 + (i + 2 * R - dxi) * NT + 4 * kq;
+        const int rstride = HWX * NT;
+        const int hrow0 = row0 + 2 * R - ch * DYC - (DYC - 1);
+        constexpr int T = RPW + DYC - 1;
+        auto read_a = [&](int tt) { return *reinterpret_cast<const f32x4_t *>(base + max(hrow0 + tt, 0) * rstride); };
+        f32x4_t a = read_a(0);
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            f32x4_t an = a;
+            if (tt + 1 < T) an = read_a(tt + 1);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                const int c = r - tt + DYC - 1;
+                if (c < 0 || c >= DYC) continue;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], bfr[c][e], acc[r], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            a = an;
+        }
+    };
+    // a step is RPW * DYC * 4 MFMAs of 32 cycles per wave: one step of lookahead hides
+    // the fragment loads
+    for (int step = 0; step < nsteps; ++step) {
+        load_b(b1, min(step + 1, nsteps - 1));
+        __builtin_amdgcn_sched_barrier(0);
+        run(b0, step);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int c = 0; c < DYC; ++c) b0[c] = b1[c];
+    }
+
+    // D: lane holds column j = lane % 16 (ko), rows 4 * (lane / 16) + q (pixels)
+    const int j = lane & 15;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        const int gy = y0 + row0 + r;
+        if (gy >= ny) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int gx = x0 + 4 * (lane >> 4) + q;
+            if (gx < nx) dst[(static_cast<size_t>(gy) * nx + gx) * NT + j] = acc[r][q];
+        }
+    }
+}
+
 // Vector-ALU linear convolution (FP32 or FP64): one 8 x 8 tile per workgroup,
 // lane = pixel, wave w owns ko = w, w+4, ...; the halo of KC input orientations
 // at a time is staged in LDS theta-major.
@@ -338,6 +476,40 @@ int launch_bf16_nt(const Kernel &k, const float *in, float *out, int batch, hipS
     }
 }
 
+template <int DYC, int RPW>
+int launch_f32m_t(const Kernel &k, const float *in, float *out, int batch, hipStream_t s) {
+    const int nx = k.grid.nx, ny = k.grid.ny, R = k.metric.radius;
+    const int rows = RPW * kWaves;
+    const size_t lds = static_cast<size_t>(kSeg + 2 * R) * (rows + 2 * R) * 16 * sizeof(float);
+    const int tx = (nx + kSeg - 1) / kSeg, ty = (ny + rows - 1) / rows;
+    if (lds > 65536)
+        SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_conv_f32m<DYC, RPW>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+    hipLaunchKernelGGL((k_conv_f32m<DYC, RPW>), dim3(tx * ty * batch), dim3(256), lds, s, in, out,
+                       reinterpret_cast<const f32x4_t *>(k.d_Fpack), nx, ny, R, tx, ty);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+// 8 output rows per wave, or 4 when 8 would leave fewer than 4 workgroups per compute unit.
+template <int DYC>
+int launch_f32m_rpw(const Kernel &k, const float *in, float *out, int batch, hipStream_t s) {
+    const long tiles8 = static_cast<long>((k.grid.nx + kSeg - 1) / kSeg) * ((k.grid.ny + 8 * kWaves - 1) / (8 * kWaves));
+    if (tiles8 * batch >= 4L * kNumCUs) return launch_f32m_t<DYC, 8>(k, in, out, batch, s);
+    return launch_f32m_t<DYC, 4>(k, in, out, batch, s);
+}
+
+int launch_f32m(const Kernel &k, const float *in, float *out, int batch, hipStream_t s) {
+    switch (dy_chunk(2 * k.metric.radius + 1)) {
+        case 4: return launch_f32m_rpw<4>(k, in, out, batch, s);
+        case 5: return launch_f32m_rpw<5>(k, in, out, batch, s);
+        case 6: return launch_f32m_rpw<6>(k, in, out, batch, s);
+        case 7: return launch_f32m_rpw<7>(k, in, out, batch, s);
+        case 8: return launch_f32m_rpw<8>(k, in, out, batch, s);
+        default: return SE2_EINVAL;
+    }
+}
+
 template <typename T, int NT, int KC>
 int launch_valu_kc(const Kernel &k, const T *K, const T *in, T *out, int batch, hipStream_t s) {
     const int nx = k.grid.nx, ny = k.grid.ny, R = k.metric.radius;
@@ -401,6 +573,26 @@ std::vector<uint16_t> pack_bf16_operand(const std::vector<uint16_t> &Kb, int nt,
     return Bp;
 }
 
+// Host packing of the FP32 kernel (nt = 16) into the B operands of k_conv_f32m:
+// Fp[dyp][dx][lane][e] = K[dy = dyp - R][dx - R][ko = lane % 16][ki = 4 (lane / 16) + e],
+// zero for the dy rows that run past the window to a multiple of the dy chunk.
+std::vector<float> pack_f32_operand(const std::vector<float> &K32, int nt, int R) {
+    if (nt != 16) return {};
+    const int W = 2 * R + 1;
+    const int DYC = dy_chunk(W);
+    const int WP = (W + DYC - 1) / DYC * DYC;
+    std::vector<float> Fp(static_cast<size_t>(WP) * W * 64 * 4, 0.0f);
+    for (int dyi = 0; dyi < W; ++dyi)
+        for (int dxi = 0; dxi < W; ++dxi)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int e = 0; e < 4; ++e) {
+                    const int ko = lane & 15, ki = 4 * (lane >> 4) + e;
+                    Fp[((static_cast<size_t>(dyi) * W + dxi) * 64 + lane) * 4 + e] =
+                        K32[((static_cast<size_t>(dyi) * W + dxi) * nt + ko) * nt + ki];
+                }
+    return Fp;
+}
+
 int launch_conv_bf16(const Kernel &k, const float *in, float *out, int batch, hipStream_t s) {
     switch (k.grid.ntheta) {
         case 8: return launch_bf16_nt<8>(k, in, out, batch, s);
@@ -413,7 +605,8 @@ int launch_conv_bf16(const Kernel &k, const float *in, float *out, int batch, hi
 int launch_conv_f32(const Kernel &k, const float *in, float *out, int batch, hipStream_t s) {
     switch (k.grid.ntheta) {
         case 8: return launch_valu_t<float, 8>(k, k.d_K32, in, out, batch, s);
-        case 16: return launch_valu_t<float, 16>(k, k.d_K32, in, out, batch, s);
+        case 16: return k.d_Fpack ? launch_f32m(k, in, out, batch, s)
+                                  : launch_valu_t<float, 16>(k, k.d_K32, in, out, batch, s);
         case 32: return launch_valu_t<float, 32>(k, k.d_K32, in, out, batch, s);
         default: return SE2_EINVAL;
     }

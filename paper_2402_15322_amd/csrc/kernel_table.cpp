@@ -106,6 +106,11 @@ int build_tables(Kernel &k) {
     const std::vector<uint16_t> Bp = pack_bf16_operand(Kb, nt, R);
     SE2_HIP(hipMalloc(&k.d_Bpack, Bp.size() * sizeof(uint16_t)));
     SE2_HIP(hipMemcpy(k.d_Bpack, Bp.data(), Bp.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+    const std::vector<float> Fp = pack_f32_operand(K32, nt, R);
+    if (!Fp.empty()) {
+        SE2_HIP(hipMalloc(&k.d_Fpack, Fp.size() * sizeof(float)));
+        SE2_HIP(hipMemcpy(k.d_Fpack, Fp.data(), Fp.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
     SE2_HIP(hipMemcpy(k.d_L64, L2.data(), e * sizeof(double), hipMemcpyHostToDevice));
     SE2_HIP(hipMemcpy(k.d_L32, L32.data(), e * sizeof(float), hipMemcpyHostToDevice));
     SE2_HIP(hipMemcpy(k.d_cost, k.cost.data(), e * sizeof(double), hipMemcpyHostToDevice));

@@ -33,6 +33,12 @@ CONV_CASES = [
     (20, 7, 32, True, (1.0, 4.0, 1.0), 0.3, 2, 2),
     (33, 40, 32, True, (1.0, 4.0, 1.0), 0.03, 10, 1),
     (9, 30, 8, False, (1.5, 1.0, 2.0), 2.0, 0, 1),
+    # nt = 16 shapes of the FP32 matrix-core path: a single offset, a 15 x 15 window (dy
+    # chunks of 8), a 25 x 25 window (chunks of 7, three zero rows), 8 rows per wave
+    (16, 5, 16, False, (1.0, 2.0, 1.0), 1.0, 0, 3),
+    (23, 50, 16, False, (1.0, 3.0, 1.0), 0.05, 7, 1),
+    (30, 28, 16, False, (1.0, 3.0, 1.0), 0.5, 12, 1),
+    (40, 70, 16, False, (1.0, 2.0, 1.0), 0.3, 2, 120),
 ]
 
 
