@@ -11,8 +11,9 @@ Printed JSON line: the whole-job Sinkhorn iteration rate, solves/s (completed
 and converged), p50/p99 solve latency, the roofline of the dominant kernel (the
 log-domain convolution, timed with HIP events on the queue's stream), the same
 solves run one at a time beside it, the FP64 CPU oracle timed on a bounded
-sample on this host, and the linear se2_conv (BF16 on the matrix cores, and
-FP32) at the workloads' grid shapes against the MFMA peak.
+sample on this host, and the linear se2_conv (BF16 on the matrix cores; FP32 on
+the matrix cores at 16 orientations, on the vector ALUs at 32) at the workloads'
+grid shapes against the BF16 and FP32 peaks.
 """
 from __future__ import annotations
 
@@ -119,7 +120,7 @@ PEAK_F32_TFLOPS = 157.3
 
 
 def conv_measurements(native, torch, batch: int, reps: int):
-    """se2_conv (BF16 MFMA and FP32) timed with HIP events on the current stream."""
+    """se2_conv (BF16 and FP32) timed with HIP events on the current stream."""
     out = []
     for n, nt, R, axial, w, eps, b in CONV_SHAPES:
         b = b or batch
