@@ -249,17 +249,22 @@ __global__ __launch_bounds__(256) void k_conv_bf16(const float *__restrict__ in,
     }
 }
 
-// FP32 convolution on the matrix cores, nt = 16: the tiling of k_conv_bf16 (kSeg output
-// pixels by kWaves * RPW output rows per workgroup, window rows in chunks of DYC), one
-// step per (dx, dy chunk).  For output row r and window row c of the chunk, the lane of
-// pixel i = lane % 16 and quad kq = lane / 16 reads input orientations 4 kq .. 4 kq + 3
-// of its input pixel as one float4; MFMA e (e = 0..3) multiplies element e by the packed
-// B value K[ko = lane % 16][ki = 4 kq + e], so the four MFMAs sum all 16 orientations.
-template <int DYC, int RPW>
+// FP32 convolution on the matrix cores, nt = 16 or 32: the tiling of k_conv_bf16 (kSeg
+// output pixels by kWaves * RPW output rows per workgroup, window rows in chunks of
+// DYC), one step per (dx, dy chunk), in NT / 16 passes over 16 input orientations each
+// (the halo of one pass is staged in LDS in FP32).  For output row r and window row c of
+// the chunk, the lane of pixel i = lane % 16 and quad kq = lane / 16 reads the pass's
+// input orientations 4 kq .. 4 kq + 3 of its input pixel as one float4; MFMA e (e = 0..3)
+// of column block nb multiplies element e by the packed B value
+// K[ko = 16 nb + lane % 16][ki = 16 pass + 4 kq + e], so the four MFMAs sum the pass's 16
+// orientations into the 16 output orientations of the block.
+template <int NT, int DYC, int RPW>
 __global__ __launch_bounds__(256) void k_conv_f32m(const float *__restrict__ in, float *__restrict__ out,
                                                    const f32x4_t *__restrict__ Fp, int nx, int ny, int R,
                                                    int tiles_x, int tiles_y) {
-    constexpr int NT = 16;
+    static_assert(NT == 16 || NT == 32, "16 or 32 orientations");
+    constexpr int NB = NT / 16;  // output column blocks
+    constexpr int NP = NT / 16;  // passes over the input orientations
     extern __shared__ float lds32[];
     const int W = 2 * R + 1;
     const int HWX = kSeg + 2 * R;
@@ -279,62 +284,33 @@ __global__ __launch_bounds__(256) void k_conv_f32m(const float *__restrict__ in,
     const int kq = lane >> 4;     // orientation quad of this lane
     const int row0 = wave * RPW;  // first output row of this wave within the tile
 
-    f32x4_t acc[RPW];
+    f32x4_t acc[RPW][NB];
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) acc[r] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int r = 0; r < RPW; ++r)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[r][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
-    // (dx, dy chunk) steps; the fragments of a step are loaded one step ahead, those of
-    // the first step before the halo staging, so that their latency overlaps it
+    // (dx, dy chunk) steps of a pass; the fragments of a step are loaded one step ahead,
+    // those of a pass's first step before its halo staging, so that their latency overlaps it
     const int nchunks = (W + DYC - 1) / DYC;
     const int nsteps = W * nchunks;
-    f32x4_t b0[DYC], b1[DYC];
-    auto load_b = [&](f32x4_t(&dstb)[DYC], int step) {
+    f32x4_t b0[DYC][NB], b1[DYC][NB];
+    auto load_b = [&](f32x4_t(&dstb)[DYC][NB], int step, int pass) {
         const int dxi = step / nchunks, ch = step - dxi * nchunks;
-        const f32x4_t *src = Fp + (static_cast<size_t>(ch * DYC) * W + dxi) * 64 + lane;
 #pragma unroll
-        for (int c = 0; c < DYC; ++c) dstb[c] = src[static_cast<size_t>(c) * W * 64];
+        for (int c = 0; c < DYC; ++c)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                dstb[c][nb] = Fp[((((static_cast<size_t>(ch * DYC + c) * W + dxi) * NP + pass) * NB + nb) * 64) + lane];
     };
-    load_b(b0, 0);
-
-    // stage the halo [hy][hx][ki] in FP32, zero outside the grid; loads go out in batches
-    // of 8 float4 per thread (clamped indices, no branches) before any is stored
     const int xl = x0 - R;
-    {
-        constexpr int Q = NT / 4;
-        constexpr int NB8 = 8;
-        const int total = HWY * HWX * Q;
-        const float inv = 1.0f / static_cast<float>(HWX);
-        for (int e0 = 0; e0 < total; e0 += NB8 * 256) {
-            float4 v[NB8];
-            bool ok[NB8];
-#pragma unroll
-            for (int u = 0; u < NB8; ++u) {
-                const int e = min(e0 + u * 256 + static_cast<int>(threadIdx.x), total - 1);
-                const int p = e / Q, q = e - p * Q;
-                // p / HWX through a float reciprocal: exact for p < 2^20
-                const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv), hx = p - hy * HWX;
-                const int gy = y0 - R + hy, gx = xl + hx;
-                ok[u] = gy >= 0 && gy < ny && gx >= 0 && gx < nx;
-                const int cy = min(max(gy, 0), ny - 1), cx = min(max(gx, 0), nx - 1);
-                v[u] = *reinterpret_cast<const float4 *>(&img[(static_cast<size_t>(cy) * nx + cx) * NT + 4 * q]);
-            }
-#pragma unroll
-            for (int u = 0; u < NB8; ++u) {
-                const int e = e0 + u * 256 + static_cast<int>(threadIdx.x);
-                if (e < total)
-                    *reinterpret_cast<float4 *>(&lds32[4 * e]) = ok[u] ? v[u] : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-        }
-    }
-    __syncthreads();
-
-    auto run = [&](const f32x4_t(&bfr)[DYC], int step) {
+    auto run = [&](const f32x4_t(&bfr)[DYC][NB], int step) {
         const int dxi = step / nchunks, ch = step - dxi * nchunks;
         // input pixel x0 + i - dx (dx = dxi - R) sits at halo column i + 2R - dxi; output
         // row r and window row c = r - t + DYC - 1 of the chunk meet halo row hrow0 + t
         // (rows past the window carry zero fragments; their row index is clamped)
-        const float *base = lds32 + (i + 2 * R - dxi) * NT + 4 * kq;
-        const int rstride = HWX * NT;
+        const float *base = lds32 + (i + 2 * R - dxi) * 16 + 4 * kq;
+        const int rstride = HWX * 16;
         const int hrow0 = row0 + 2 * R - ch * DYC - (DYC - 1);
         constexpr int T = RPW + DYC - 1;
         auto read_a = [&](int tt) { return *reinterpret_cast<const f32x4_t *>(base + max(hrow0 + tt, 0) * rstride); };
@@ -344,40 +320,84 @@ __global__ __launch_bounds__(256) void k_conv_f32m(const float *__restrict__ in,
             f32x4_t an = a;
             if (tt + 1 < T) an = read_a(tt + 1);
             __builtin_amdgcn_sched_barrier(0);
+            // e outermost: consecutive MFMAs update different accumulators
 #pragma unroll
-            for (int r = 0; r < RPW; ++r) {
-                const int c = r - tt + DYC - 1;
-                if (c < 0 || c >= DYC) continue;
+            for (int e = 0; e < 4; ++e)
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], bfr[c][e], acc[r], 0, 0, 0);
-            }
+                for (int r = 0; r < RPW; ++r) {
+                    const int c = r - tt + DYC - 1;
+                    if (c < 0 || c >= DYC) continue;
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+                        acc[r][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], bfr[c][nb][e], acc[r][nb], 0, 0, 0);
+                }
             __builtin_amdgcn_sched_barrier(0);
             a = an;
         }
     };
-    // a step is RPW * DYC * 4 MFMAs of 32 cycles per wave: one step of lookahead hides
-    // the fragment loads
-    for (int step = 0; step < nsteps; ++step) {
-        load_b(b1, min(step + 1, nsteps - 1));
-        __builtin_amdgcn_sched_barrier(0);
-        run(b0, step);
-        __builtin_amdgcn_sched_barrier(0);
+
+    for (int pass = 0; pass < NP; ++pass) {
+        load_b(b0, 0, pass);
+        if (pass > 0) __syncthreads();  // every wave is done with the previous pass's halo
+        // stage the pass's halo [hy][hx][16 ki] in FP32, zero outside the grid; loads go
+        // out in batches of 8 float4 per thread (clamped indices, no branches) before any
+        // is stored
+        {
+            constexpr int Q = 4;
+            constexpr int NB8 = 8;
+            const int total = HWY * HWX * Q;
+            const float inv = 1.0f / static_cast<float>(HWX);
+            for (int e0 = 0; e0 < total; e0 += NB8 * 256) {
+                float4 v[NB8];
+                bool ok[NB8];
 #pragma unroll
-        for (int c = 0; c < DYC; ++c) b0[c] = b1[c];
+                for (int u = 0; u < NB8; ++u) {
+                    const int e = min(e0 + u * 256 + static_cast<int>(threadIdx.x), total - 1);
+                    const int p = e / Q, q = e - p * Q;
+                    // p / HWX through a float reciprocal: exact for p < 2^20
+                    const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv), hx = p - hy * HWX;
+                    const int gy = y0 - R + hy, gx = xl + hx;
+                    ok[u] = gy >= 0 && gy < ny && gx >= 0 && gx < nx;
+                    const int cy = min(max(gy, 0), ny - 1), cx = min(max(gx, 0), nx - 1);
+                    v[u] = *reinterpret_cast<const float4 *>(
+                        &img[(static_cast<size_t>(cy) * nx + cx) * NT + 16 * pass + 4 * q]);
+                }
+#pragma unroll
+                for (int u = 0; u < NB8; ++u) {
+                    const int e = e0 + u * 256 + static_cast<int>(threadIdx.x);
+                    if (e < total)
+                        *reinterpret_cast<float4 *>(&lds32[4 * e]) = ok[u] ? v[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
+        }
+        __syncthreads();
+        // a step is RPW * DYC * 4 * NB MFMAs of 32 cycles per wave: one step of lookahead
+        // hides the fragment loads
+        for (int step = 0; step < nsteps; ++step) {
+            load_b(b1, min(step + 1, nsteps - 1), pass);
+            __builtin_amdgcn_sched_barrier(0);
+            run(b0, step);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int c = 0; c < DYC; ++c)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) b0[c][nb] = b1[c][nb];
+        }
     }
 
-    // D: lane holds column j = lane % 16 (ko), rows 4 * (lane / 16) + q (pixels)
+    // D: lane holds column j = lane % 16 (ko within the block), rows 4 * (lane / 16) + q
     const int j = lane & 15;
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
         const int gy = y0 + row0 + r;
         if (gy >= ny) continue;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int gx = x0 + 4 * (lane >> 4) + q;
-            if (gx < nx) dst[(static_cast<size_t>(gy) * nx + gx) * NT + j] = acc[r][q];
-        }
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gx = x0 + 4 * (lane >> 4) + q;
+                if (gx < nx) dst[(static_cast<size_t>(gy) * nx + gx) * NT + 16 * nb + j] = acc[r][nb][q];
+            }
     }
 }
 
@@ -476,36 +496,44 @@ int launch_bf16_nt(const Kernel &k, const float *in, float *out, int batch, hipS
     }
 }
 
-template <int DYC, int RPW>
+template <int NT, int DYC, int RPW>
 int launch_f32m_t(const Kernel &k, const float *in, float *out, int batch, hipStream_t s) {
     const int nx = k.grid.nx, ny = k.grid.ny, R = k.metric.radius;
     const int rows = RPW * kWaves;
     const size_t lds = static_cast<size_t>(kSeg + 2 * R) * (rows + 2 * R) * 16 * sizeof(float);
     const int tx = (nx + kSeg - 1) / kSeg, ty = (ny + rows - 1) / rows;
     if (lds > 65536)
-        SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_conv_f32m<DYC, RPW>),
+        SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_conv_f32m<NT, DYC, RPW>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-    hipLaunchKernelGGL((k_conv_f32m<DYC, RPW>), dim3(tx * ty * batch), dim3(256), lds, s, in, out,
+    hipLaunchKernelGGL((k_conv_f32m<NT, DYC, RPW>), dim3(tx * ty * batch), dim3(256), lds, s, in, out,
                        reinterpret_cast<const f32x4_t *>(k.d_Fpack), nx, ny, R, tx, ty);
     SE2_HIP(hipGetLastError());
     return SE2_OK;
 }
 
-// 8 output rows per wave, or 4 when 8 would leave fewer than 4 workgroups per compute unit.
-template <int DYC>
+// nt = 16: 8 output rows per wave, or 4 when 8 would leave fewer than 4 workgroups per
+// compute unit.  nt = 32: 4 rows per wave (one 83 KB halo per CU at the 21 x 21 window;
+// measured at 256 x 256 x 32: 1852 us against 1995 us with 2 rows and two halos per CU).
+template <int NT, int DYC>
 int launch_f32m_rpw(const Kernel &k, const float *in, float *out, int batch, hipStream_t s) {
-    const long tiles8 = static_cast<long>((k.grid.nx + kSeg - 1) / kSeg) * ((k.grid.ny + 8 * kWaves - 1) / (8 * kWaves));
-    if (tiles8 * batch >= 4L * kNumCUs) return launch_f32m_t<DYC, 8>(k, in, out, batch, s);
-    return launch_f32m_t<DYC, 4>(k, in, out, batch, s);
+    if constexpr (NT == 32) {
+        return launch_f32m_t<NT, DYC, 4>(k, in, out, batch, s);
+    } else {
+        const long tiles8 =
+            static_cast<long>((k.grid.nx + kSeg - 1) / kSeg) * ((k.grid.ny + 8 * kWaves - 1) / (8 * kWaves));
+        if (tiles8 * batch >= 4L * kNumCUs) return launch_f32m_t<NT, DYC, 8>(k, in, out, batch, s);
+        return launch_f32m_t<NT, DYC, 4>(k, in, out, batch, s);
+    }
 }
 
-int launch_f32m(const Kernel &k, const float *in, float *out, int batch, hipStream_t s) {
+template <int NT>
+int launch_f32m_nt(const Kernel &k, const float *in, float *out, int batch, hipStream_t s) {
     switch (dy_chunk(2 * k.metric.radius + 1)) {
-        case 4: return launch_f32m_rpw<4>(k, in, out, batch, s);
-        case 5: return launch_f32m_rpw<5>(k, in, out, batch, s);
-        case 6: return launch_f32m_rpw<6>(k, in, out, batch, s);
-        case 7: return launch_f32m_rpw<7>(k, in, out, batch, s);
-        case 8: return launch_f32m_rpw<8>(k, in, out, batch, s);
+        case 4: return launch_f32m_rpw<NT, 4>(k, in, out, batch, s);
+        case 5: return launch_f32m_rpw<NT, 5>(k, in, out, batch, s);
+        case 6: return launch_f32m_rpw<NT, 6>(k, in, out, batch, s);
+        case 7: return launch_f32m_rpw<NT, 7>(k, in, out, batch, s);
+        case 8: return launch_f32m_rpw<NT, 8>(k, in, out, batch, s);
         default: return SE2_EINVAL;
     }
 }
@@ -573,23 +601,27 @@ std::vector<uint16_t> pack_bf16_operand(const std::vector<uint16_t> &Kb, int nt,
     return Bp;
 }
 
-// Host packing of the FP32 kernel (nt = 16) into the B operands of k_conv_f32m:
-// Fp[dyp][dx][lane][e] = K[dy = dyp - R][dx - R][ko = lane % 16][ki = 4 (lane / 16) + e],
-// zero for the dy rows that run past the window to a multiple of the dy chunk.
+// Host packing of the FP32 kernel (nt = 16 or 32) into the B operands of k_conv_f32m:
+// Fp[dyp][dx][pass][nb][lane][e] = K[dy = dyp - R][dx - R][ko = 16 nb + lane % 16]
+// [ki = 16 pass + 4 (lane / 16) + e], zero for the dy rows that run past the window to a
+// multiple of the dy chunk.
 std::vector<float> pack_f32_operand(const std::vector<float> &K32, int nt, int R) {
-    if (nt != 16) return {};
+    if (nt != 16 && nt != 32) return {};
     const int W = 2 * R + 1;
     const int DYC = dy_chunk(W);
     const int WP = (W + DYC - 1) / DYC * DYC;
-    std::vector<float> Fp(static_cast<size_t>(WP) * W * 64 * 4, 0.0f);
+    const int NB = nt / 16, NP = nt / 16;
+    std::vector<float> Fp(static_cast<size_t>(WP) * W * NP * NB * 64 * 4, 0.0f);
     for (int dyi = 0; dyi < W; ++dyi)
         for (int dxi = 0; dxi < W; ++dxi)
-            for (int lane = 0; lane < 64; ++lane)
-                for (int e = 0; e < 4; ++e) {
-                    const int ko = lane & 15, ki = 4 * (lane >> 4) + e;
-                    Fp[((static_cast<size_t>(dyi) * W + dxi) * 64 + lane) * 4 + e] =
-                        K32[((static_cast<size_t>(dyi) * W + dxi) * nt + ko) * nt + ki];
-                }
+            for (int pass = 0; pass < NP; ++pass)
+                for (int nb = 0; nb < NB; ++nb)
+                    for (int lane = 0; lane < 64; ++lane)
+                        for (int e = 0; e < 4; ++e) {
+                            const int ko = 16 * nb + (lane & 15), ki = 16 * pass + 4 * (lane >> 4) + e;
+                            Fp[(((((static_cast<size_t>(dyi) * W + dxi) * NP + pass) * NB + nb) * 64 + lane) * 4) + e] =
+                                K32[((static_cast<size_t>(dyi) * W + dxi) * nt + ko) * nt + ki];
+                        }
     return Fp;
 }
 
@@ -605,9 +637,10 @@ int launch_conv_bf16(const Kernel &k, const float *in, float *out, int batch, hi
 int launch_conv_f32(const Kernel &k, const float *in, float *out, int batch, hipStream_t s) {
     switch (k.grid.ntheta) {
         case 8: return launch_valu_t<float, 8>(k, k.d_K32, in, out, batch, s);
-        case 16: return k.d_Fpack ? launch_f32m(k, in, out, batch, s)
+        case 16: return k.d_Fpack ? launch_f32m_nt<16>(k, in, out, batch, s)
                                   : launch_valu_t<float, 16>(k, k.d_K32, in, out, batch, s);
-        case 32: return launch_valu_t<float, 32>(k, k.d_K32, in, out, batch, s);
+        case 32: return k.d_Fpack ? launch_f32m_nt<32>(k, in, out, batch, s)
+                                  : launch_valu_t<float, 32>(k, k.d_K32, in, out, batch, s);
         default: return SE2_EINVAL;
     }
 }

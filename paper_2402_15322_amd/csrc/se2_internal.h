@@ -53,7 +53,7 @@ struct Kernel {
     uint16_t *d_Kbf16 = nullptr; // exp(logk) in bfloat16 (RNE), table layout
     double *d_K64 = nullptr;    // exp(logk) in FP64
     uint16_t *d_Bpack = nullptr; // bfloat16 kernel packed in MFMA B-operand order
-    float *d_Fpack = nullptr;    // FP32 kernel packed in FP32-MFMA B-operand order (nt = 16 only)
+    float *d_Fpack = nullptr;    // FP32 kernel packed in FP32-MFMA B-operand order (nt = 16, 32)
     int nonzero_bf16 = 0;       // window offsets with any nonzero bfloat16 entry
     int device = 0;
     // eps-scaling: kernels of the same grid, weights and window at coarser eps, built on
@@ -83,7 +83,7 @@ bool conv_lse_sparse_fits(int nt, int R);
 
 // launchers (conv_linear.hip)
 std::vector<uint16_t> pack_bf16_operand(const std::vector<uint16_t> &Kb, int nt, int R);
-std::vector<float> pack_f32_operand(const std::vector<float> &K32, int nt, int R);  // empty unless nt = 16
+std::vector<float> pack_f32_operand(const std::vector<float> &K32, int nt, int R);  // empty unless nt = 16, 32
 size_t conv_bf16_lds_bytes(int nt, int R);
 int launch_conv_bf16(const Kernel &k, const float *in, float *out, int batch, hipStream_t s);
 int launch_conv_f32(const Kernel &k, const float *in, float *out, int batch, hipStream_t s);

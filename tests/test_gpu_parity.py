@@ -39,6 +39,7 @@ CONV_CASES = [
     (23, 50, 16, False, (1.0, 3.0, 1.0), 0.05, 7, 1),
     (30, 28, 16, False, (1.0, 3.0, 1.0), 0.5, 12, 1),
     (40, 70, 16, False, (1.0, 2.0, 1.0), 0.3, 2, 120),
+    (12, 20, 32, False, (1.0, 2.0, 1.0), 1.0, 0, 2),   # nt = 32, a single offset (two passes)
 ]
 
 
