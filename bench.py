@@ -11,9 +11,8 @@ Printed JSON line: the whole-job Sinkhorn iteration rate, solves/s (completed
 and converged), p50/p99 solve latency, the roofline of the dominant kernel (the
 log-domain convolution, timed with HIP events on the queue's stream), the same
 solves run one at a time beside it, the FP64 CPU oracle timed on a bounded
-sample on this host, and the linear se2_conv (BF16 on the matrix cores; FP32 on
-the matrix cores at 16 orientations, on the vector ALUs at 32) at the workloads'
-grid shapes against the BF16 and FP32 peaks.
+sample on this host, and the linear se2_conv (BF16 and FP32, both on the matrix
+cores) at the workloads' grid shapes against the BF16 and FP32 peaks.
 """
 from __future__ import annotations
 

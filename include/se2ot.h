@@ -73,7 +73,7 @@ typedef struct {
  *  SE2_BF16: se2_conv only -- input rounded to bfloat16 (RNE), kernel in bfloat16,
  *            products accumulated in FP32 on the matrix cores (MFMA); float in/out.
  *  SE2_F32 : FP32 kernel and accumulation (se2_conv: float in/out, on the matrix
- *            cores at ntheta = 16, on the vector ALUs otherwise); for the
+ *            cores at ntheta = 16 and 32, on the vector ALUs at 8); for the
  *            log-domain paths: exponent arguments formed in FP64, FP32 exp2 and
  *            FP32 partial sums combined in FP64.
  *  SE2_F64 : FP64 throughout (se2_conv: double in/out).                      */

@@ -13,13 +13,14 @@
 //         in LDS; kernel fragments are pre-packed on the host in operand order (one
 //         coalesced 16-byte load per lane) and zero-padded where a dx group
 //         overhangs the window or a dy chunk runs past it.
-//   F32, nt = 16: the same implicit GEMM on the FP32 matrix cores
-//         (v_mfma_f32_16x16x4f32): per window offset (dy, dx), four 16 x 4 by 4 x 16
-//         products cover the 16 input orientations; a lane's four A operands are the
-//         four orientations it reads with one 16-byte LDS load, and the B operand is
-//         packed on the host to match.  The halo is staged in FP32, unrounded.
-//   F32 (nt = 8, 32) / F64: an 8 x 8 tile per workgroup on the vector ALUs with FP32 /
-//         FP64 FMAs.
+//   F32, nt = 16 and 32: the same implicit GEMM on the FP32 matrix cores
+//         (v_mfma_f32_16x16x4f32): per window offset (dy, dx) and 16 input orientations,
+//         four 16 x 4 by 4 x 16 products per block of 16 output orientations; a lane's
+//         four A operands are the four orientations it reads with one 16-byte LDS load,
+//         and the B operand is packed on the host to match.  The halo is staged in FP32,
+//         unrounded, 16 input orientations at a time.
+//   F32 (nt = 8) / F64: an 8 x 8 tile per workgroup on the vector ALUs with FP32 / FP64
+//         FMAs.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
