@@ -299,8 +299,8 @@ def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU sharding is "
-                                   "described in DESIGN.md and not implemented)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (sharding a solve or the "
+                                   "request stream across GPUs is not implemented)"}))
         sys.exit(2)
     if a.oracle_timing:
         # CPU only (no GPU work in this process): all threads, then a one-thread child for the
