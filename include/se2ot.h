@@ -151,9 +151,9 @@ int se2_kernel_info(se2_kernel_t k, se2_grid_t *grid, se2_metric_t *metric, int3
 
 /*
  * se2_conv -- out[b] = K * in[b] for b < batch (Section 4.2), stream-ordered,
- * no host synchronisation.  SE2_BF16 and SE2_F32 read/write float arrays,
- * SE2_F64 double arrays; each is batch * nx * ny * ntheta elements.
- * in and out must not overlap.
+ * no host synchronisation.  SE2_BF16 and SE2_F32 read/write float arrays (in
+ * 16-byte aligned, else SE2_EINVAL), SE2_F64 double arrays; each is
+ * batch * nx * ny * ntheta elements.  in and out must not overlap.
  */
 int se2_conv(se2_kernel_t k, se2_prec_t prec, const void *in, void *out, int32_t batch, se2_stream_t stream);
 

@@ -298,6 +298,8 @@ int se2_kernel_info(se2_kernel_t h, se2_grid_t *grid, se2_metric_t *metric, int3
 int se2_conv(se2_kernel_t h, se2_prec_t prec, const void *in, void *out, int32_t batch, se2_stream_t stream) {
     const Kernel *k = reinterpret_cast<const Kernel *>(h);
     if (!k || !in || !out || batch < 0 || in == out) return SE2_EINVAL;
+    // the float paths stage the input with 16-byte loads
+    if (prec != SE2_F64 && (reinterpret_cast<uintptr_t>(in) & 15)) return SE2_EINVAL;
     if (batch == 0) return SE2_OK;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     switch (prec) {

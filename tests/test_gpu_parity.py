@@ -292,3 +292,19 @@ def test_invalid_inputs_rejected(nat):
     with pytest.raises(nat.SE2Error):
         nat.se2_barycenter(k, [to_dev(good), to_dev(good)], [0.7, 0.4], nat.opts(),
                            torch.empty((8, 8, 8), dtype=torch.float64, device="cuda"))
+
+
+def test_conv_rejects_misaligned_float_input(nat):
+    """The float paths stage their input with 16-byte loads: a misaligned input is refused on
+    the host, before any launch."""
+    torch = torch_dev()
+    k = _kernel(nat, 8, 8, 16, False, (1, 2, 1), 0.5, 2)
+    buf = torch.zeros(8 * 8 * 16 + 1, dtype=torch.float32, device="cuda")
+    x = buf[1:].view(8, 8, 16)
+    out = torch.empty((8, 8, 16), dtype=torch.float32, device="cuda")
+    for prec in (nat.SE2_BF16, nat.SE2_F32):
+        with pytest.raises(nat.SE2Error) as e:
+            nat.se2_conv(k, prec, x, out)
+        assert e.value.code == nat.SE2_EINVAL
+    nat.se2_conv(k, nat.SE2_F32, buf[:8 * 8 * 16].view(8, 8, 16), out)   # aligned: accepted
+    torch.cuda.synchronize()
