@@ -40,6 +40,7 @@ CONV_CASES = [
     (30, 28, 16, False, (1.0, 3.0, 1.0), 0.5, 12, 1),
     (40, 70, 16, False, (1.0, 2.0, 1.0), 0.3, 2, 120),
     (12, 20, 32, False, (1.0, 2.0, 1.0), 1.0, 0, 2),   # nt = 32, a single offset (two passes)
+    (20, 18, 32, True, (1.0, 4.0, 1.0), 0.4, 12, 1),   # nt = 32 at the largest window (25 x 25)
 ]
 
 
