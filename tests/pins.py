@@ -501,6 +501,59 @@ def pin_jko_step():
     assert np.max(np.abs(b - rot90(a))) <= 1e-12 * np.max(a)
 
 
+# --------------------------------------------------------------------------
+# The plan-difference checker: sum |pi_a - pi_b| over the window (plan of Section 4.1,
+# pi = exp(phi + log K + psi)) equals the same sum over the explicit dense plans of two
+# different iterates; a shift of phi by c scales the plan by e^c, so the L1 difference is
+# |1 - e^c| times the plan's mass; each of the four potentials enters
+# --------------------------------------------------------------------------
+
+def pin_plan_l1():
+    rng = np.random.default_rng(20)
+    nx, ny, nt, R, w, eps = 4, 5, 4, 2, (1.0, 2.0, 1.5), 0.4
+    LM = dense.dense_logk(nx, ny, nt, False, w, eps, R)
+    logk, _ = oracle.kernel_table(nt, False, w, eps, R)
+    mu = _rand_measure(rng, (ny, nx, nt))
+    nu = _rand_measure(rng, (ny, nx, nt))
+    a = oracle.sinkhorn(logk, mu, nu, 3, -1.0)[:2]
+    b = oracle.sinkhorn(logk, mu, nu, 25, -1.0)[:2]
+    want = np.abs(dense.plan(LM, *a) - dense.plan(LM, *b)).sum()
+    assert want >= 1e-3
+    got = oracle.plan_l1(logk, a[0], a[1], b[0], b[1])
+    assert abs(got - want) <= 1e-13 * want
+    assert abs(oracle.plan_l1(logk, b[0], b[1], a[0], a[1]) - want) <= 1e-13 * want
+    # each potential of the second pair enters: change only psi_b, then only phi_b
+    for pair in ((a[0], b[1]), (b[0], a[1])):
+        want2 = np.abs(dense.plan(LM, *a) - dense.plan(LM, *pair)).sum()
+        assert want2 >= 1e-3
+        assert abs(oracle.plan_l1(logk, a[0], a[1], *pair) - want2) <= 1e-13 * want2
+    # closed form: phi + c scales the plan by e^c
+    mass = dense.plan(LM, *b).sum()
+    for c in (0.3, -1.2):
+        got = oracle.plan_l1(logk, b[0], b[1], b[0] + c, b[1])
+        assert abs(got - abs(1.0 - math.exp(c)) * mass) <= 1e-13 * mass
+        got = oracle.plan_l1(logk, b[0], b[1], b[0], b[1] + c)
+        assert abs(got - abs(1.0 - math.exp(c)) * mass) <= 1e-13 * mass
+    assert oracle.plan_l1(logk, b[0], b[1], b[0], b[1]) == 0.0
+
+
+# --------------------------------------------------------------------------
+# The porous-medium energy F(nu) = ref/(m-1) sum (nu/ref)^m (Section 5.4, the energy of
+# eq. (pde_ndiff) on densities against the cell measure ref): hand-evaluated values
+# --------------------------------------------------------------------------
+
+def pin_porous_energy():
+    nu = np.array([0.5, 0.25, 0.25, 0.0])
+    # m = 2, ref = 1/4: densities (2, 1, 1, 0); F = 1/4 * (4 + 1 + 1) = 1.5
+    assert abs(oracle.porous_energy(nu, 2.0, 0.25) - 1.5) <= 1e-15
+    # m = 5, ref = 1/4: (32 + 1 + 1) / 4 / 4 = 2.125
+    assert abs(oracle.porous_energy(nu, 5.0, 0.25) - 2.125) <= 1e-15
+    # m = 3, ref = 1/2: densities (1, 1/2, 1/2, 0); F = 1/2 / 2 * (1 + 1/8 + 1/8) = 0.3125
+    assert abs(oracle.porous_energy(nu, 3.0, 0.5) - 0.3125) <= 1e-15
+    # grid shape does not matter, only the values
+    assert oracle.porous_energy(nu.reshape(2, 2), 5.0, 0.25) == oracle.porous_energy(nu, 5.0, 0.25)
+
+
 ALL_PINS = [
     pin_rho_closed_forms,
     pin_rho_inverse_symmetry,
@@ -520,4 +573,6 @@ ALL_PINS = [
     pin_eps_scaling,
     pin_lift_and_project,
     pin_jko_step,
+    pin_plan_l1,
+    pin_porous_energy,
 ]

@@ -67,6 +67,15 @@ MUTANTS = [
     # Section 2.2 / 4.1: cost sum pi rho^2 and the plan's marginals
     ("cost_with_log_kernel", "if (cost_tab) rc += p * cost_tab[kb + ki];", "if (cost_tab) rc += p * (-logk[kb + ki]);", 0),
     ("second_marginal_offset_sign", "int iy = jy + dy;", "int iy = jy - dy;", 0),
+    # the plan-difference checker: both plans from their own potentials
+    ("plan_l1_returns_zero", "    return tot;\n}", "    return 0.0 * tot;\n}", 0),
+    ("plan_l1_b_from_phi_a", "double pb = exp(phi_b[xo] + logk[kb + ki] + psi_b[yb + ki]);",
+     "double pb = exp(phi_a[xo] + logk[kb + ki] + psi_b[yb + ki]);", 0),
+    ("plan_l1_b_from_psi_a", "double pb = exp(phi_b[xo] + logk[kb + ki] + psi_b[yb + ki]);",
+     "double pb = exp(phi_b[xo] + logk[kb + ki] + psi_a[yb + ki]);", 0),
+    ("plan_l1_b_from_a", "double pb = exp(phi_b[xo] + logk[kb + ki] + psi_b[yb + ki]);",
+     "double pb = exp(phi_a[xo] + logk[kb + ki] + psi_a[yb + ki]);", 0),
+    ("plan_l1_signed", "tot += fabs(pa - pb);", "tot += pa - pb;", 0),
 ]
 
 
