@@ -37,10 +37,14 @@ EPS = 0.1
 EXP_SLOTS = 2  # v_exp_f32 issues at half rate on gfx950 (measured)
 SLOTS_DENSE = 2 + 2 + 1 + EXP_SLOTS + 1
 SLOTS_SPARSE = 2 + 1 + EXP_SLOTS + 1
-# One slot = one lane-operation; 256 CUs x 64 lanes x 2.4 GHz = 39.3 T slots/s,
-# quoted as FP64-FMA equivalents (2 flops per slot): the published FP64 vector
-# peak of 78.6 TFLOP/s.
-PEAK_TFLOPS = 78.6
+# One slot = one lane-instruction; 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T
+# lane-instructions/s is the vector-ALU issue peak.
+VALU_PEAK = 39.3216
+# Algorithmic HBM bytes per element of one log-domain half-step: the input potential,
+# the log-marginal, the previous output (for the marginal error) and the new output,
+# 4 bytes each in FP32.  The engine keeps those four arrays in FP64 (32 bytes).
+BYTES_PER_ELEMENT = 16
+FP64_STATE_BYTES_PER_ELEMENT = 32
 # HBM bytes of one batched convolution half-step (k_sparse + k_rebuild of every lane) on
 # this workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (each scaled by what the
 # counter reads for a plain 256 MiB copy: x2.0 and x1.0), summed over the 3 x 2004
@@ -58,6 +62,28 @@ def measured_traffic():
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return TRAFFIC["bytes_per_launch"] if h.hexdigest() == TRAFFIC["sources_sha256"] else None
+
+
+def log_conv_roofline(seconds, launches, outputs, terms_dense, terms_sparse, kernel, traffic=None):
+    """Roofline of the log-domain convolution: algorithmic HBM bytes (BYTES_PER_ELEMENT per
+    output element) per launch over the average launch time, against the HBM peak; beside it
+    the vector-ALU issue rate of the terms evaluated, against the issue peak."""
+    launches = max(1.0, launches)
+    avg = seconds / launches
+    elems = outputs / launches
+    alg = BYTES_PER_ELEMENT * elems
+    gbs = alg / avg / 1e9 if avg > 0 else 0.0
+    slots = (SLOTS_DENSE * terms_dense + SLOTS_SPARSE * terms_sparse) / launches
+    valu = slots / avg / 1e12 if avg > 0 else 0.0
+    return {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+            "traffic": traffic, "kernel": kernel, "avg_launch_us": avg * 1e6, "elements_per_launch": elems,
+            "bytes_per_element": BYTES_PER_ELEMENT, "algorithmic_bytes_per_launch": alg,
+            "fp64_state_bytes_per_element": FP64_STATE_BYTES_PER_ELEMENT,
+            "fp64_state_frac": FP64_STATE_BYTES_PER_ELEMENT * elems / avg / 1e9 / PEAK_HBM_GBS if avg > 0 else None,
+            "traffic_over_algorithmic": traffic / alg if traffic and alg > 0 else None,
+            "dense_terms_per_launch": terms_dense / launches, "sparse_terms_per_launch": terms_sparse / launches,
+            "valu_issue": {"lane_instr_per_s": valu * 1e12, "peak_lane_instr_per_s": VALU_PEAK * 1e12,
+                           "frac": valu / VALU_PEAK, "instr_per_term": {"dense": SLOTS_DENSE, "sparse": SLOTS_SPARSE}}}
 
 
 def parse():
@@ -215,7 +241,6 @@ def class_barycenter(native, torch, images, iters: int):
     per_iter = (w2 - w1) / iters
     conv_s = k2["seconds"] - k1["seconds"]
     terms = k2["terms"] - k1["terms"]
-    achieved = 2.0 * 8 * terms / conv_s / 1e12 if conv_s > 0 else 0.0
     return {"workload": f"{n} stroke images 28x28x16, w=(1,1.5,1), eps=0.5, 9x9 window, equal weights",
             "measures": n, "iters": [r1["iters"], r2["iters"]], "wall_s": [w1, w2],
             "steady_ms_per_iter": per_iter * 1e3, "steady_iters_per_s": 1.0 / per_iter if per_iter > 0 else None,
@@ -223,8 +248,8 @@ def class_barycenter(native, torch, images, iters: int):
             "conv_ms_per_iter": conv_s / iters * 1e3,
             "avg_conv_launch_us": conv_s / max(1.0, k2["launches"] - k1["launches"]) * 1e6,
             "lse_terms_per_s": terms / conv_s if conv_s > 0 else None,
-            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
-                         "frac": achieved / PEAK_TFLOPS, "kernel": "dense log-domain convolution (k_conv_lse)"},
+            "roofline": log_conv_roofline(conv_s, k2["launches"] - k1["launches"], k2["outputs"] - k1["outputs"],
+                                          terms, 0.0, "dense log-domain convolution (k_conv_lse)"),
             "marg_l1": r2["marg_l1"], "mass": r2["mass"]}
 
 
@@ -280,8 +305,6 @@ def barycenter_workloads(native, torch, synth, c4_iters: int):
         wall = time.perf_counter() - t0
         kt = q.kernel_time()
         q.close()
-        slots = SLOTS_DENSE * sum(r["terms_dense"] for r in reps) + SLOTS_SPARSE * sum(r["terms_sparse"] for r in reps)
-        achieved = 2.0 * slots / kt["seconds"] / 1e12 if kt["seconds"] > 0 else 0.0
         out[name] = {"requests": len(insts), "iters": [r["iters"] for r in reps],
                      "converged": sum(1 for r in reps if r["status"] == native.SE2_CONVERGED),
                      "wall_s": wall, "ibp_iters_per_s": sum(r["iters"] for r in reps) / wall,
@@ -289,8 +312,9 @@ def barycenter_workloads(native, torch, synth, c4_iters: int):
                      "conv_seconds": kt["seconds"], "half_steps": kt["launches"],
                      "dense_terms": sum(r["terms_dense"] for r in reps),
                      "sparse_terms": sum(r["terms_sparse"] for r in reps),
-                     "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
-                                  "frac": achieved / PEAK_TFLOPS}}
+                     "roofline": log_conv_roofline(kt["seconds"], kt["launches"], kt["outputs"],
+                                                   sum(r["terms_dense"] for r in reps),
+                                                   sum(r["terms_sparse"] for r in reps), "log-domain convolution")}
         del dev, outs, k
     return out
 
@@ -367,41 +391,45 @@ def main():
     # the budget admits the whole batch (each solve keeps its potentials and pruning state resident)
     q = native.SolveQueue(hbm_budget_bytes=native.ot_request_bytes(k, o) * a.batch + (64 << 20), max_slots=a.batch)
 
-    def one_step():
+    def one_step(lat):
         tickets = [q.submit_ot(k, mus[i], nus[i], o, fs[i], gs[i]) for i in range(a.batch)]
         reps = [q.wait(t) for t in tickets]
-        return tickets, reps
+        for t in tickets:
+            ts, _, td = q.times(t)
+            lat.append(td - ts)
+            q.release(t)
+        return reps
 
     for _ in range(a.warmup):
-        one_step()
+        one_step([])
     q.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    all_t, all_r = [], []
+    all_r, lat, step_ms = [], [], []
     for _ in range(a.steps):
-        t, r = one_step()
-        all_t += t
-        all_r += r
+        s0 = time.perf_counter()
+        all_r += one_step(lat)
+        step_ms.append((time.perf_counter() - s0) * 1e3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
     kt = q.kernel_time()
     q.profile(False)
-    lat = np.array([q.times(t)[2] - q.times(t)[0] for t in all_t])
+    lat = np.array(lat)
     q.close()
 
     iters = sum(r["iters"] for r in all_r)
     conv = sum(1 for r in all_r if r["status"] == native.SE2_CONVERGED)
     value = iters / wall
 
-    # roofline of the dominant kernel (log-domain convolution): the terms it evaluated
-    # (dense visits count every in-grid window entry, sparse visits their list entries)
-    launches = max(1.0, kt["launches"])
-    avg_launch = kt["seconds"] / launches
-    td = sum(r["terms_dense"] for r in all_r)
-    ts = sum(r["terms_sparse"] for r in all_r)
-    slots_per_launch = (SLOTS_DENSE * td + SLOTS_SPARSE * ts) / launches
-    achieved = 2.0 * slots_per_launch / avg_launch / 1e12 if avg_launch > 0 else 0.0
+    # roofline of the dominant kernel (log-domain convolution, one launch = one batched
+    # half-step of every resident solve): algorithmic HBM bytes per launch over its average
+    # duration (HIP events on the queue's streams, union over the lanes, timed region)
+    roof = log_conv_roofline(kt["seconds"], kt["launches"], kt["outputs"], sum(r["terms_dense"] for r in all_r),
+                             sum(r["terms_sparse"] for r in all_r),
+                             "log-domain convolution (k_sparse + k_rebuild), one batched half-step per launch",
+                             measured_traffic())
+    roof["window_terms_per_launch"] = kt["terms"] / max(1.0, kt["launches"])
 
     # the same solves one at a time (plain per-solve FP32 Sinkhorn on the same engine)
     plain_iters, plain_wall = 0, 0.0
@@ -485,12 +513,8 @@ def main():
         "marg_l1_f64_mean": float(np.mean([r["marg_l1_f64"] for r in all_r])),
         "plain_one_at_a_time_iters_per_s": plain_rate,
         "speedup_vs_plain": (value / plain_rate) if plain_rate else None,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS, "traffic": measured_traffic(),
-                     "kernel": "log-domain convolution (k_sparse + k_rebuild)", "avg_launch_us": avg_launch * 1e6,
-                     "dense_terms_per_launch": td / launches, "sparse_terms_per_launch": ts / launches,
-                     "window_terms_per_launch": kt["terms"] / launches,
-                     "slots_per_term": {"dense": SLOTS_DENSE, "sparse": SLOTS_SPARSE}},
+        "step_ms": step_ms,
+        "roofline": roof,
         "cpu_baseline": cpu,
         "kernel_build_ms": build_ms,
         "eps_scaling": eps_leg,

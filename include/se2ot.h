@@ -306,14 +306,22 @@ int se2_solve_queue_poll(se2_queue_t q, uint64_t ticket, se2_report_t *report);
 int se2_solve_queue_wait(se2_queue_t q, uint64_t ticket, se2_report_t *report);
 /* Timestamps (host steady clock, seconds) of submit, admission and completion. */
 int se2_solve_queue_times(se2_queue_t q, uint64_t ticket, double *t_submit, double *t_admit, double *t_done);
+/* Forget a finished ticket: its report and times are dropped and the ticket becomes invalid
+ * (SE2_EINVAL afterwards).  SE2_PENDING (nothing dropped) while the solve runs.  A queue keeps
+ * every finished ticket until it is released or the queue is destroyed, so a long-running
+ * serving loop releases each ticket once it has read the report and times; no other call
+ * on the same ticket may be in progress. */
+int se2_solve_queue_release(se2_queue_t q, uint64_t ticket);
 /* Counters: admitted, completed, rejected, peak slots in use, batched steps run. */
 int se2_solve_queue_stats(se2_queue_t q, int64_t *out5);
 /* Kernel timing of the queue's log-domain convolutions, measured with HIP events on
- * the queue's own streams (diagnostics for benchmarks).  enable = 1 starts
- * recording (and zeroes the totals); out4 receives [seconds during which any
- * convolution launch of the queue ran (the union of the launch intervals of its
- * streams), algorithmic LSE terms (window entries inside the grid), batched
- * half-steps issued (two per iteration of the resident solves), output elements]. */
+ * the queue's own streams (diagnostics for benchmarks; recording adds two event records
+ * per launch and event reads at every check).  enable = 1 starts recording (and zeroes
+ * the totals), enable = 0 stops it; out4 receives, for the launches recorded up to the
+ * last check of each lane, [seconds during which any convolution launch of the queue ran
+ * (the union of the launch intervals of its streams, formed by this call), algorithmic
+ * LSE terms (window entries inside the grid), batched half-steps issued (two per
+ * iteration of the resident solves), output elements]. */
 int se2_solve_queue_profile(se2_queue_t q, int32_t enable);
 int se2_solve_queue_kernel_time(se2_queue_t q, double *out4);
 /* Waits for all submitted work, then frees the queue. */

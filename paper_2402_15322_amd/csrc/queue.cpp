@@ -140,15 +140,16 @@ struct se2_queue_s {
     uint64_t gen = 0;  // bumped whenever a lane may find new work (submit, finish, profile, stop)
     bool stop = false;
     int64_t admitted = 0, completed = 0, rejected = 0, peak = 0, steps = 0;
-    // profiling: each lane resets its engine when it sees its flag; at checks it publishes
-    // its launch intervals (ms after prof_ref) and totals, and the snapshot is rebuilt
+    // profiling: each lane resets its engine when it sees its flag; at checks it appends the
+    // launch intervals (ms after prof_ref) that its engine collected since its last check and
+    // publishes its totals.  The union of the intervals is formed only when it is asked for
+    // (se2_solve_queue_kernel_time), so a check costs time in the new intervals only.
     int prof_request = 0;
     bool prof_reset[se2::kLanes] = {};
     hipEvent_t prof_ref = nullptr;
     std::vector<std::pair<double, double>> prof_iv[se2::kLanes];
     double prof_terms[se2::kLanes] = {}, prof_outputs[se2::kLanes] = {};
     int64_t prof_rounds[se2::kLanes] = {};
-    double prof_snapshot[4] = {0, 0, 0, 0};
     se2::Engine eng[se2::kLanes];
 };
 
@@ -251,7 +252,8 @@ void finish_group(se2_queue_s *Q, int l, const std::vector<Req *> &done) {
     Q->cv.notify_all();  // freed slots and memory may let the other lane admit
 }
 
-// The union of all lanes' published launch intervals, in seconds (under Q->mu).
+// The union of all lanes' published launch intervals, in seconds (under Q->mu).  Called by
+// se2_solve_queue_kernel_time only, never on a lane's iteration path.
 double union_seconds(const se2_queue_s *Q) {
     std::vector<std::pair<double, double>> iv;
     for (int l = 0; l < kLanes; ++l) iv.insert(iv.end(), Q->prof_iv[l].begin(), Q->prof_iv[l].end());
@@ -304,6 +306,8 @@ void lane_main(se2_queue_s *Q, int l) {
                     void *m = Q->arena.alloc(q->bytes);
                     if (!m) break;
                     q->mem = m;
+                    q->t_admit = now_seconds();
+                    q->state = ACTIVE;
                     Q->waiting[l].pop_front();
                     fresh.push_back(q);
                     Q->active[l].push_back(q);
@@ -320,8 +324,6 @@ void lane_main(se2_queue_s *Q, int l) {
         }
         std::vector<Solve *> init;
         for (Req *q : fresh) {
-            q->t_admit = now_seconds();
-            q->state = ACTIVE;
             q->rc = admit_one(Q, q);
             if (q->rc == SE2_OK) init.push_back(&q->s);
         }
@@ -407,21 +409,11 @@ void lane_main(se2_queue_s *Q, int l) {
             Q->steps += 1;
             if (Q->prof_request) Q->prof_rounds[l] += 2;
             if (check && Q->prof_request) {
-                // publish this lane's intervals; the convolution time is their union over all lanes
-                Q->prof_iv[l] = eng.prof_intervals;
+                // publish the intervals collected since this lane's last check, and its totals
+                Q->prof_iv[l].insert(Q->prof_iv[l].end(), eng.prof_intervals.begin(), eng.prof_intervals.end());
+                eng.prof_intervals.clear();
                 Q->prof_terms[l] = eng.prof_terms;
                 Q->prof_outputs[l] = eng.prof_outputs;
-                Q->prof_snapshot[0] = union_seconds(Q);
-                double terms = 0.0, outputs = 0.0;
-                int64_t rounds = 0;
-                for (int j = 0; j < kLanes; ++j) {
-                    terms += Q->prof_terms[j];
-                    outputs += Q->prof_outputs[j];
-                    rounds = std::max(rounds, Q->prof_rounds[j]);
-                }
-                Q->prof_snapshot[1] = terms;
-                Q->prof_snapshot[2] = static_cast<double>(rounds);
-                Q->prof_snapshot[3] = outputs;
             }
         }
         if (!finished.empty()) finish_group(Q, l, finished);
@@ -570,6 +562,16 @@ int se2_solve_queue_times(se2_queue_t Q, uint64_t ticket, double *t_submit, doub
     return q->state == DONE ? SE2_OK : SE2_PENDING;
 }
 
+int se2_solve_queue_release(se2_queue_t Q, uint64_t ticket) {
+    if (!Q) return SE2_EINVAL;
+    std::lock_guard<std::mutex> lk(Q->mu);
+    auto it = Q->all.find(ticket);
+    if (it == Q->all.end()) return SE2_EINVAL;
+    if (it->second->state != DONE) return SE2_PENDING;
+    Q->all.erase(it);
+    return SE2_OK;
+}
+
 int se2_solve_queue_stats(se2_queue_t Q, int64_t *out5) {
     if (!Q || !out5) return SE2_EINVAL;
     std::lock_guard<std::mutex> lk(Q->mu);
@@ -593,8 +595,11 @@ int se2_solve_queue_profile(se2_queue_t Q, int32_t enable) {
     }
     Q->prof_request = enable ? 1 : 0;
     for (bool &f : Q->prof_reset) f = true;
-    for (double &v : Q->prof_snapshot) v = 0.0;
     for (auto &v : Q->prof_iv) v.clear();
+    for (int l = 0; l < kLanes; ++l) {
+        Q->prof_terms[l] = Q->prof_outputs[l] = 0.0;
+        Q->prof_rounds[l] = 0;
+    }
     Q->gen += 1;
     Q->cv.notify_all();
     return SE2_OK;
@@ -603,10 +608,17 @@ int se2_solve_queue_profile(se2_queue_t Q, int32_t enable) {
 int se2_solve_queue_kernel_time(se2_queue_t Q, double *out4) {
     if (!Q || !out4) return SE2_EINVAL;
     std::lock_guard<std::mutex> lk(Q->mu);
-    out4[0] = Q->prof_snapshot[0];
-    out4[1] = Q->prof_snapshot[1];
-    out4[2] = Q->prof_snapshot[2];
-    out4[3] = Q->prof_snapshot[3];
+    double terms = 0.0, outputs = 0.0;
+    int64_t rounds = 0;
+    for (int j = 0; j < kLanes; ++j) {
+        terms += Q->prof_terms[j];
+        outputs += Q->prof_outputs[j];
+        rounds = std::max(rounds, Q->prof_rounds[j]);
+    }
+    out4[0] = union_seconds(Q);
+    out4[1] = terms;
+    out4[2] = static_cast<double>(rounds);
+    out4[3] = outputs;
     return SE2_OK;
 }
 

@@ -31,6 +31,7 @@ EXPORTED = [
     "se2_conv", "se2_conv_log", "se2_sinkhorn", "se2_barycenter", "se2_solve_queue_create",
     "se2_request_bytes", "se2_solve_queue_submit", "se2_solve_queue_poll", "se2_solve_queue_wait", "se2_solve_queue_times",
     "se2_solve_queue_stats", "se2_solve_queue_profile", "se2_solve_queue_kernel_time", "se2_solve_queue_destroy",
+    "se2_solve_queue_release",
     "se2_lift_field", "se2_project", "se2_split_signed", "se2_jko_step", "se2_gradient_flow",
 ]
 
@@ -117,6 +118,7 @@ def load() -> ctypes.CDLL:
             "se2_solve_queue_times": ([vp, u64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
             "se2_solve_queue_stats": ([vp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+            "se2_solve_queue_release": ([vp, u64], ctypes.c_int),
             "se2_solve_queue_profile": ([vp, i32], ctypes.c_int),
             "se2_solve_queue_kernel_time": ([vp, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
             "se2_solve_queue_destroy": ([vp], ctypes.c_int),
@@ -327,6 +329,14 @@ class SolveQueue:
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         load().se2_solve_queue_times(self.handle, ticket, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
         return a.value, b.value, c.value
+
+    def release(self, ticket: int) -> None:
+        """Forget a finished ticket (its report and times); raises while it still runs."""
+        rc = load().se2_solve_queue_release(self.handle, ticket)
+        if rc == SE2_PENDING:
+            raise SE2Error(rc, "release of a running ticket")
+        _check(rc, "release")
+        self._keep.pop(ticket, None)
 
     def stats(self) -> dict:
         out = (ctypes.c_int64 * 5)()

@@ -174,3 +174,28 @@ def test_wide_and_narrow_rebuilds_are_bitwise_identical(nat, n, nt, R, iters):
     assert rep_b["iters"] == rep_q["iters"] == iters
     assert rep_b["terms_sparse"] > 0 and rep_b["terms_dense"] > 0
     assert np.array_equal(to_host(f), to_host(fq)) and np.array_equal(to_host(gb), to_host(gq))
+
+
+def test_release_forgets_finished_tickets(nat):
+    """A finished ticket can be released once; afterwards it is unknown.  Released tickets do
+    not disturb the others' reports."""
+    torch = torch_dev()
+    g = synth.Grid(16, 16, 8)
+    mu = synth.splat_segments(g, synth.draw_segments(synth.rng_for(9500, 0), g, 3, 3.0, 8.0), 1.0, 1e-6)
+    k = nat.Kernel(16, 16, 8, False, (1.0, 2.0, 1.0), 0.5, 4)
+    md = to_dev(mu)
+    o = nat.opts(tol=-1, max_iter=20, check_every=10)
+    q = nat.SolveQueue(hbm_budget_bytes=64 << 20, max_slots=4)
+    ts = [q.submit_ot(k, md, md, o, torch.empty_like(md), torch.empty_like(md)) for _ in range(3)]
+    reps = [q.wait(t) for t in ts]
+    q.release(ts[0])
+    with pytest.raises(nat.SE2Error) as e:
+        q.release(ts[0])
+    assert e.value.code == nat.SE2_EINVAL
+    with pytest.raises(nat.SE2Error):
+        q.wait(ts[0])
+    assert q.wait(ts[1]) == reps[1] and q.times(ts[2])[2] > 0
+    q.release(ts[1])
+    q.release(ts[2])
+    assert q.stats()["completed"] == 3
+    q.close()
