@@ -271,6 +271,21 @@ int se2_project(const se2_grid_t *grid, const double *u, const double *u_minus, 
 int se2_split_signed(const double *u, size_t n, double *plus, double *minus, se2_stream_t stream);
 
 /*
+ * se2_split_signed_noalloc -- se2_split_signed without any allocation, for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight serving loops, and
+ * harnesses that forbid hipMalloc.  Same arguments, kernels and results (bitwise) as
+ * se2_split_signed; the partial sums go to a scratch array that the library holds on each
+ * GPU it runs on (64 KiB, kept until the process ends; its address is looked up once per
+ * device, by se2_init or by the first call on that device).  n is limited to
+ * 4096 * 16384 = 67,108,864 elements: larger n returns SE2_EINVAL before any device work.
+ * Every call on one GPU shares that GPU's scratch: calls that overlap on one GPU (on
+ * different streams, or from several threads without ordering) race and must not be
+ * issued.  Nothing in the scratch needs clearing: each call writes every value it reads.
+ * Stream-ordered, no host synchronisation.
+ */
+int se2_split_signed_noalloc(const double *u, size_t n, double *plus, double *minus, se2_stream_t stream);
+
+/*
  * Serving queue.  Three lanes, each a worker thread with its own stream on the current
  * device.  A request goes at submit to the lane with the least outstanding work and is
  * admitted, in arrival order within its lane, while the HBM budget and the slot count

@@ -240,7 +240,9 @@ int se2_init(void) {
         g_last_error = std::string("device is ") + prop.gcnArchName + ", library built for gfx950";
         return SE2_EINVAL;
     }
-    return SE2_OK;
+    // device address of the library's own scratch on this device (se2_split_signed_noalloc)
+    double *scr = nullptr;
+    return split_noalloc_scratch(&scr);
 }
 
 const char *se2_strerror(int code) {
@@ -393,6 +395,19 @@ int se2_split_signed(const double *u, size_t n, double *plus, double *minus, se2
     const int rc = launch_split_signed(u, n, plus, minus, scratch, st);
     SE2_HIP(hipFreeAsync(scratch, st));
     return rc;
+}
+
+int se2_split_signed_noalloc(const double *u, size_t n, double *plus, double *minus, se2_stream_t stream) {
+    if ((!u || !plus || !minus) && n > 0) return SE2_EINVAL;
+    if (split_blocks(n) > kSplitNoallocMaxBlocks) {
+        g_last_error = "se2_split_signed_noalloc: n = " + std::to_string(n) + " exceeds the maximum of " +
+                       std::to_string(static_cast<size_t>(kSplitNoallocMaxBlocks) * 16384) + " elements";
+        return SE2_EINVAL;
+    }
+    double *scr = nullptr;
+    const int rc = split_noalloc_scratch(&scr);
+    if (rc) return rc;
+    return launch_split_signed(u, n, plus, minus, scr, reinterpret_cast<hipStream_t>(stream));
 }
 
 int se2_sinkhorn(se2_kernel_t h, const double *mu, const double *nu, const se2_opts_t *opts, double *f_out,

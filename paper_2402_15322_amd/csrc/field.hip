@@ -12,10 +12,19 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
+#include <vector>
 
 #include "se2_internal.h"
 
 namespace se2 {
+
+// Scratch of se2_split_signed_noalloc: the per-block partial sums of the positive and
+// negative parts and their two totals, 2 * kSplitNoallocMaxBlocks + 2 doubles (64 KiB).
+// Every GPU the library runs on holds its own copy until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is a stand-in, not a device
+// address): it uses the address split_noalloc_scratch() obtained for the current device.
+static __device__ __align__(256) double scratch[2 * kSplitNoallocMaxBlocks + 2];
 
 namespace {
 
@@ -211,15 +220,32 @@ int split_blocks(size_t n) {
     return static_cast<int>(b > 0 ? b : 1);
 }
 
-int launch_split_signed(const double *u, size_t n, double *plus, double *minus, double *scratch, hipStream_t s) {
+int split_noalloc_scratch(double **out) {
+    static std::mutex mu;
+    static std::vector<double *> per_device;  // device address of `scratch` on each GPU, once known
+    int dev = 0;
+    SE2_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    if (static_cast<size_t>(dev) >= per_device.size()) per_device.resize(static_cast<size_t>(dev) + 1, nullptr);
+    if (per_device[dev] == nullptr) {
+        void *p = nullptr;
+        SE2_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (p == nullptr) return SE2_EHIP;
+        per_device[dev] = static_cast<double *>(p);
+    }
+    *out = per_device[dev];
+    return SE2_OK;
+}
+
+int launch_split_signed(const double *u, size_t n, double *plus, double *minus, double *part, hipStream_t s) {
     const int nb = split_blocks(n);
     const size_t chunk = 16384;
-    hipLaunchKernelGGL(k_signed_partials, dim3(nb), dim3(kThreads), 0, s, u, n, chunk, scratch);
+    hipLaunchKernelGGL(k_signed_partials, dim3(nb), dim3(kThreads), 0, s, u, n, chunk, part);
     SE2_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_signed_total, dim3(1), dim3(kThreads), 0, s, scratch, nb, scratch + 2 * nb);
+    hipLaunchKernelGGL(k_signed_total, dim3(1), dim3(kThreads), 0, s, part, nb, part + 2 * nb);
     SE2_HIP(hipGetLastError());
     if (n > 0) {
-        hipLaunchKernelGGL(k_signed_split, dim3(blocks_for(n)), dim3(kThreads), 0, s, u, n, scratch + 2 * nb, plus,
+        hipLaunchKernelGGL(k_signed_split, dim3(blocks_for(n)), dim3(kThreads), 0, s, u, n, part + 2 * nb, plus,
                            minus);
         SE2_HIP(hipGetLastError());
     }

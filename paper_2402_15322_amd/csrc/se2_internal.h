@@ -132,7 +132,11 @@ int launch_lift_field(const double *mag, const double *angle, double *out, size_
 int launch_project(const double *u, const double *um, size_t npix, int nt, double period, double *mass,
                    int32_t *argmax, double *ang, hipStream_t s);
 int split_blocks(size_t n);  // the scratch of launch_split_signed holds 2 * split_blocks(n) + 2 doubles
-int launch_split_signed(const double *u, size_t n, double *plus, double *minus, double *scratch, hipStream_t s);
+int launch_split_signed(const double *u, size_t n, double *plus, double *minus, double *part, hipStream_t s);
+// The library's own split scratch on the current device (2 * kSplitNoallocMaxBlocks + 2 doubles,
+// a file-scope device array of field.hip); its address is looked up once per device.
+constexpr int kSplitNoallocMaxBlocks = 4096;
+int split_noalloc_scratch(double **out);
 
 // Sums and bad-entry counts of m arrays of length n (pointers in a device table): d_stats
 // receives [m][2], d_part holds m * validate_many_blocks(n) * 2 doubles.

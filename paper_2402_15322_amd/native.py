@@ -33,6 +33,7 @@ EXPORTED = [
     "se2_solve_queue_stats", "se2_solve_queue_profile", "se2_solve_queue_kernel_time", "se2_solve_queue_destroy",
     "se2_solve_queue_release",
     "se2_lift_field", "se2_project", "se2_split_signed", "se2_jko_step", "se2_gradient_flow",
+    "se2_split_signed_noalloc",
 ]
 
 
@@ -103,6 +104,7 @@ def load() -> ctypes.CDLL:
             "se2_lift_field": ([ctypes.POINTER(Grid), vp, vp, vp, i32, vp], ctypes.c_int),
             "se2_project": ([ctypes.POINTER(Grid), vp, vp, vp, vp, vp, i32, vp], ctypes.c_int),
             "se2_split_signed": ([vp, sz, vp, vp, vp], ctypes.c_int),
+            "se2_split_signed_noalloc": ([vp, sz, vp, vp, vp], ctypes.c_int),
             "se2_jko_step": ([vp, vp, ctypes.POINTER(Flow), ctypes.POINTER(Opts), vp, vp, vp, ctypes.POINTER(Report),
                               vp], ctypes.c_int),
             "se2_gradient_flow": ([vp, vp, ctypes.POINTER(Flow), i32, ctypes.POINTER(Opts), vp, vp,
@@ -239,6 +241,11 @@ def se2_project(axial: bool, u, mass, u_minus=None, argmax=None, angle=None, str
 
 def se2_split_signed(u, plus, minus, stream=None) -> None:
     _check(load().se2_split_signed(_ptr(u), u.numel(), _ptr(plus), _ptr(minus), _stream(stream)), "se2_split_signed")
+
+
+def se2_split_signed_noalloc(u, plus, minus, stream=None) -> None:
+    _check(load().se2_split_signed_noalloc(_ptr(u), u.numel(), _ptr(plus), _ptr(minus), _stream(stream)),
+           "se2_split_signed_noalloc")
 
 
 def se2_sinkhorn(k: Kernel, mu, nu, o: Opts, f_out=None, g_out=None, stream=None) -> dict:

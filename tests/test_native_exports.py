@@ -58,3 +58,16 @@ def test_binding_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_noalloc_split_refuses_oversized_input_on_the_host():
+    """se2_split_signed_noalloc checks n against its scratch limit before any HIP call."""
+    lib = ctypes.CDLL(LIB)
+    lib.se2_split_signed_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p]
+    lib.se2_strerror.restype = ctypes.c_char_p
+    buf = (ctypes.c_double * 4)()
+    addr = ctypes.addressof(buf)  # never dereferenced: the size check fails first
+    rc = lib.se2_split_signed_noalloc(addr, 4096 * 16384 + 1, addr, addr, None)
+    assert rc == -1
+    assert b"exceeds the maximum" in lib.se2_strerror(rc)
