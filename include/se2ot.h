@@ -70,20 +70,34 @@ typedef struct {
 } se2_metric_t;
 
 /* Arithmetic of a convolution.
- *  SE2_BF16: se2_conv only -- input rounded to bfloat16 (RNE), kernel in bfloat16,
- *            products accumulated in FP32 on the matrix cores (MFMA); float in/out.
- *  SE2_F32 : FP32 kernel and accumulation (se2_conv: float in/out, on the matrix
- *            cores at ntheta = 16 and 32, on the vector ALUs at 8); for the
- *            log-domain paths: exponent arguments formed in FP64, FP32 exp2 and
- *            FP32 partial sums combined in FP64.
- *  SE2_F64 : FP64 throughout (se2_conv: double in/out).                      */
-typedef enum { SE2_BF16 = 0, SE2_F32 = 1, SE2_F64 = 2 } se2_prec_t;
+ *  SE2_BF16    : se2_conv -- input rounded to bfloat16 (RNE), kernel in bfloat16, products
+ *                accumulated in FP32 on the matrix cores (MFMA); float in/out.
+ *                Log-domain paths (se2_conv_log and the solvers) -- the certified linear-domain
+ *                engine on the matrix cores: per workgroup tile the input is shifted by its
+ *                maximum M over the tile's halo, 2^(in - M) is rounded to bfloat16 and
+ *                contracted with the bfloat16 kernel (FP32 accumulation), and the log is
+ *                M + log S.  An output whose sum S falls below 2^-87 in that frame (where
+ *                underflowed terms could matter) has its (8 x 8 tile, orientation) group
+ *                recomputed exactly in the log domain (counted in se2_report_t.fallbacks).
+ *                Relative error of K * exp(in) about 2^-8 (bfloat16 operands).
+ *  SE2_F32     : se2_conv -- FP32 kernel and accumulation (float in/out, on the matrix cores at
+ *                ntheta = 16 and 32, on the vector ALUs at 8).  Log-domain paths -- the exact
+ *                engine: exponent arguments formed in FP64, FP32 exp2 and FP32 partial sums
+ *                combined in FP64 (certified pruning of negligible terms, see prune).
+ *  SE2_F64     : FP64 throughout (se2_conv: double in/out).
+ *  SE2_F32_MFMA: log-domain paths only, ntheta = 16 or 32 -- the certified linear-domain engine
+ *                of SE2_BF16 with FP32 operands on the FP32 matrix cores, FP32 sums over one
+ *                step of the contraction (at most 128 products) added in FP64; relative error
+ *                of K * exp(in) about 1e-6 at most.                                          */
+typedef enum { SE2_BF16 = 0, SE2_F32 = 1, SE2_F64 = 2, SE2_F32_MFMA = 3 } se2_prec_t;
 
 typedef struct {
     double tol_marg_l1;   /* stop when the marginal L1 error <= tol; tol < 0 runs exactly max_iter */
     int32_t max_iter;     /* >= 1 */
     int32_t check_every;  /* iterations between convergence checks (>= 1) */
-    se2_prec_t prec;      /* SE2_F32 (default engine) or SE2_F64 (FP64 exp, slow) */
+    se2_prec_t prec;      /* engine of the solve (of its polish phase when polish = 1): SE2_F32 (exact,
+                             the default), SE2_F64 (FP64 exp, slow), SE2_BF16 or SE2_F32_MFMA (matrix
+                             cores, certified; see se2_prec_t) */
     int32_t final_check;  /* 1: recompute the final marginal error with an FP64 convolution */
     int32_t prune;        /* 1: certified pruning of negligible window entries (results equal the dense
                              sum to 2^-48 relative per skipped entry); 0: every entry, every time */
@@ -104,6 +118,15 @@ typedef struct {
     double eps_start;
     double eps_factor;    /* in (0, 1) */
     int32_t stage_iters;  /* >= 1 */
+    /* Phases.  polish = 0: the solve runs on `prec` throughout (bulk and switch_tol ignored).
+     * polish = 1: a bulk phase on the engine `bulk` (typically SE2_BF16) comes first -- over
+     * every coarse eps stage and at the final eps -- and at the final eps the solve moves to
+     * `prec` at the first check whose marginal L1 error is <= switch_tol or did not fall since
+     * the previous check of that stage (the bulk engine's precision floor); the final FP64
+     * check (final_check) follows as usual.  se2_report_t.phase_switch_iter records the move. */
+    se2_prec_t bulk;
+    int32_t polish;
+    double switch_tol;
 } se2_opts_t;
 
 typedef struct {
@@ -119,6 +142,10 @@ typedef struct {
     double terms_sparse; /* list entries evaluated by certified sparse visits (per output) */
     int32_t convs;      /* group convolutions applied */
     int32_t scaling_iters; /* iterations run at coarser eps (eps-scaling), included in iters */
+    int32_t fallbacks;  /* (8 x 8 tile, orientation) groups that the matrix-core engines recomputed in
+                           the log domain after a failed certificate */
+    int32_t phase_switch_iter; /* iteration at which the polish phase began (-1: never) */
+    double terms_linear; /* window terms evaluated on the matrix cores (SE2_BF16, SE2_F32_MFMA) */
 } se2_report_t;
 
 typedef struct se2_kernel_s *se2_kernel_t; /* library-owned, immutable, usable from any thread */
@@ -161,10 +188,15 @@ int se2_conv(se2_kernel_t k, se2_prec_t prec, const void *in, void *out, int32_t
  * se2_conv_log -- out[b] = log(K * exp(in[b])) in natural-log units, FP64 in and
  * out (-inf allowed: zero mass), the log form of the operator applied in every
  * Sinkhorn half-step.  prec SE2_F32: FP64 exponent arguments, FP32 exp2 and
- * partial sums, FP64 combination; SE2_F64: FP64 throughout.  Stream-ordered.
+ * partial sums, FP64 combination; SE2_F64: FP64 throughout; SE2_BF16 and
+ * SE2_F32_MFMA: the certified linear-domain engines on the matrix cores (see
+ * se2_prec_t; SE2_F32_MFMA needs ntheta = 16 or 32).  fallbacks (HOST, may be NULL)
+ * receives the number of (8 x 8 tile, orientation) groups recomputed in the log domain
+ * (0 for SE2_F32 and SE2_F64).  Takes a scratch with hipMallocAsync on `stream` and
+ * synchronises the stream before it returns (its job tables are staged from the host).
  */
 int se2_conv_log(se2_kernel_t k, se2_prec_t prec, const double *in, double *out, int32_t batch,
-                 se2_stream_t stream);
+                 int32_t *fallbacks, se2_stream_t stream);
 
 /*
  * se2_sinkhorn -- entropic OT between mu and nu (Section 4.1), log form:

@@ -35,13 +35,7 @@ bool valid_metric(const se2_metric_t *m) {
            m->w1 > 0 && m->w2 > 0 && m->w3 > 0 && m->eps > 0 && m->radius >= 0 && m->radius <= kMaxRadius;
 }
 
-bool valid_opts(const se2_opts_t *o, double eps) {
-    if (!(o && o->max_iter >= 1 && o->check_every >= 1 && (o->prec == SE2_F32 || o->prec == SE2_F64) &&
-          !std::isnan(o->tol_marg_l1) && !std::isnan(o->eps_start)))
-        return false;
-    std::vector<double> sched;
-    return eps_schedule(*o, eps, sched) == SE2_OK;
-}
+bool valid_opts(const se2_opts_t *o, const Kernel *k) { return o && k && valid_solver_opts(*o, *k); }
 
 }  // namespace
 
@@ -156,7 +150,7 @@ namespace se2 {
 namespace {
 
 bool valid_flow(const Kernel *k, const se2_flow_t *flow, const se2_opts_t *opts) {
-    return flow && valid_opts(opts, k->metric.eps) && std::isfinite(flow->tau) && flow->tau >= 0.0 &&
+    return flow && valid_opts(opts, k) && std::isfinite(flow->tau) && flow->tau >= 0.0 &&
            std::isfinite(flow->m) && flow->m > 1.0 && std::isfinite(flow->ref) && flow->ref > 0.0 &&
            !(opts->eps_start > k->metric.eps) &&
            std::isfinite((flow->tau / k->metric.eps) * flow->m / (flow->m - 1.0) * std::pow(flow->ref, 1.0 - flow->m));
@@ -210,6 +204,7 @@ int jko_run(const Kernel *k, const double *mu, const double *init, double init_s
                 s.status = SE2_MAX_ITER;
             } else {
                 s.cur ^= 1;
+                phase_after_check(s, errs[0]);
             }
         }
     }
@@ -316,20 +311,45 @@ int se2_conv(se2_kernel_t h, se2_prec_t prec, const void *in, void *out, int32_t
     }
 }
 
-int se2_conv_log(se2_kernel_t h, se2_prec_t prec, const double *in, double *out, int32_t batch,
+int se2_conv_log(se2_kernel_t h, se2_prec_t prec, const double *in, double *out, int32_t batch, int32_t *fallbacks,
                  se2_stream_t stream) {
     const Kernel *k = reinterpret_cast<const Kernel *>(h);
-    if (!k || !in || !out || batch < 0 || in == out || (prec != SE2_F32 && prec != SE2_F64)) return SE2_EINVAL;
-    if (batch == 0) return SE2_OK;
+    if (!k || !in || !out || batch < 0 || in == out) return SE2_EINVAL;
+    const bool lin = prec == SE2_BF16 || prec == SE2_F32_MFMA;
+    if (prec != SE2_F32 && prec != SE2_F64 && !lin) return SE2_EINVAL;
+    if (lin && !lin_supported(k->grid.ntheta, prec == SE2_BF16)) return SE2_EINVAL;
+    if (batch == 0) {
+        if (fallbacks) *fallbacks = 0;
+        return SE2_OK;
+    }
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const size_t E = static_cast<size_t>(k->grid.nx) * k->grid.ny * k->grid.ntheta;
+    const int nt = k->grid.ntheta, R = k->metric.radius;
+    const size_t E = static_cast<size_t>(k->grid.nx) * k->grid.ny * nt;
     const int tiles = tiles_of(k->grid.nx) * tiles_of(k->grid.ny);
-    // natural -> base-2 log units on a scratch copy; results scaled back in place
-    double *tmp = nullptr;
-    SE2_HIP(hipMallocAsync(reinterpret_cast<void **>(&tmp), E * batch * sizeof(double), st));
+    // the matrix-core engines' tiling (rows per wave from the grid, as in the solvers)
+    const int rpw = lin ? lin_rows_per_wave(nt, prec == SE2_BF16, k->grid.ny) : 0;
+    const int per = lin ? lin_blocks(k->grid.nx, k->grid.ny, rpw) : tiles;
+    // scratch: base-2 copy of the input, job table, block map; for the matrix-core engines also
+    // the list of tiles with rejected groups, two counters and the fallback counter
+    const size_t cap_tiles = static_cast<size_t>(tiles) * batch;  // capacity of the fallback list
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t o_jobs = al(E * batch * sizeof(double));
+    const size_t o_map = o_jobs + al(batch * sizeof(ConvJob));
+    const size_t o_fb = o_map + al(static_cast<size_t>(per) * batch * sizeof(int32_t));
+    const size_t o_cnt = o_fb + (lin ? al(cap_tiles * sizeof(int4)) : 0);
+    const size_t total = o_cnt + (lin ? al(3 * sizeof(int32_t)) : 0);
+    char *mem = nullptr;
+    SE2_HIP(hipMallocAsync(reinterpret_cast<void **>(&mem), total, st));
+    double *tmp = reinterpret_cast<double *>(mem);
+    ConvJob *dj = reinterpret_cast<ConvJob *>(mem + o_jobs);
+    int32_t *dm = reinterpret_cast<int32_t *>(mem + o_map);
+    int4 *fb = lin ? reinterpret_cast<int4 *>(mem + o_fb) : nullptr;
+    int32_t *cnt = lin ? reinterpret_cast<int32_t *>(mem + o_cnt) : nullptr;
+    // natural -> base-2 log units on the scratch copy; results scaled back in place
     int rc = launch_scale(in, tmp, E * batch, kLog2e, st);
     std::vector<ConvJob> jobs(batch);
-    for (int b = 0; b < batch && rc == SE2_OK; ++b) {
+    std::vector<int32_t> map(static_cast<size_t>(per) * batch);
+    for (int b = 0; b < batch; ++b) {
         ConvJob &j = jobs[b];
         j = ConvJob{};
         j.in = tmp + E * b;
@@ -338,31 +358,42 @@ int se2_conv_log(se2_kernel_t h, se2_prec_t prec, const double *in, double *out,
         j.L32 = k->d_L32;
         j.nx = k->grid.nx;
         j.ny = k->grid.ny;
-        j.R = k->metric.radius;
+        j.R = R;
         j.epi = EPI_RAW;
         j.tiles_x = tiles_of(k->grid.nx);
         j.tiles = tiles;
-        j.first_block = b * tiles;
+        j.first_block = b * per;
+        j.blocks = per;
+        if (lin) {
+            j.kop = prec == SE2_BF16 ? static_cast<const void *>(k->d_Bpack) : static_cast<const void *>(k->d_Fpack);
+            j.fallbacks = cnt + 2;
+        }
+        for (int t = 0; t < per; ++t) map[static_cast<size_t>(b) * per + t] = b;
     }
-    ConvJob *dj = nullptr;
-    int32_t *dm = nullptr;
-    std::vector<int32_t> map(static_cast<size_t>(tiles) * batch);
-    for (int b = 0; b < batch; ++b)
-        for (int t = 0; t < tiles; ++t) map[static_cast<size_t>(b) * tiles + t] = b;
+    if (rc == SE2_OK && hipMemcpyAsync(dj, jobs.data(), batch * sizeof(ConvJob), hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = SE2_EHIP;
+    if (rc == SE2_OK && hipMemcpyAsync(dm, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice, st) !=
+                            hipSuccess)
+        rc = SE2_EHIP;
+    if (rc == SE2_OK && lin) rc = launch_fill_i32(cnt, 3, 0, st);
     if (rc == SE2_OK) {
-        SE2_HIP(hipMallocAsync(reinterpret_cast<void **>(&dj), batch * sizeof(ConvJob), st));
-        SE2_HIP(hipMallocAsync(reinterpret_cast<void **>(&dm), map.size() * sizeof(int32_t), st));
-        SE2_HIP(hipMemcpyAsync(dj, jobs.data(), batch * sizeof(ConvJob), hipMemcpyHostToDevice, st));
-        SE2_HIP(hipMemcpyAsync(dm, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        rc = launch_conv_lse(dj, batch, tiles * batch, dm, k->grid.ntheta, k->metric.radius, prec == SE2_F64, false,
-                             nullptr, nullptr, nullptr, 8, nullptr, st);
+        if (lin) {
+            const int fb_grid = cap_tiles < 1024 ? static_cast<int>(cap_tiles) : 1024;
+            rc = launch_conv_lin_log(dj, per * batch, dm, nt, R, rpw, prec == SE2_BF16, fb, cnt, cnt + 1, fb_grid, st);
+        } else {
+            rc = launch_conv_lse(dj, batch, tiles * batch, dm, nt, R, prec == SE2_F64, false, nullptr, nullptr, nullptr,
+                                 8, nullptr, st);
+        }
     }
     if (rc == SE2_OK) rc = launch_scale(out, out, E * batch, kLn2, st);
+    int32_t h_fb = 0;
+    if (rc == SE2_OK && lin && fallbacks &&
+        hipMemcpyAsync(&h_fb, cnt + 2, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess)
+        rc = SE2_EHIP;
     // host vectors are read by the async copies: wait before they go out of scope
     SE2_HIP(hipStreamSynchronize(st));
-    if (dj) SE2_HIP(hipFreeAsync(dj, st));
-    if (dm) SE2_HIP(hipFreeAsync(dm, st));
-    SE2_HIP(hipFreeAsync(tmp, st));
+    SE2_HIP(hipFreeAsync(mem, st));
+    if (rc == SE2_OK && fallbacks) *fallbacks = lin ? h_fb : 0;
     return rc;
 }
 
@@ -413,7 +444,7 @@ int se2_split_signed_noalloc(const double *u, size_t n, double *plus, double *mi
 int se2_sinkhorn(se2_kernel_t h, const double *mu, const double *nu, const se2_opts_t *opts, double *f_out,
                  double *g_out, se2_report_t *report, se2_stream_t stream) {
     const Kernel *k = reinterpret_cast<const Kernel *>(h);
-    if (!k || !mu || !nu || !valid_opts(opts, k->metric.eps)) return SE2_EINVAL;
+    if (!k || !mu || !nu || !valid_opts(opts, k)) return SE2_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const double t0 = now_seconds();
     const size_t E = static_cast<size_t>(k->grid.nx) * k->grid.ny * k->grid.ntheta;
@@ -457,6 +488,7 @@ int se2_sinkhorn(se2_kernel_t h, const double *mu, const double *nu, const se2_o
                 s.status = SE2_MAX_ITER;
             } else {
                 s.cur ^= 1;
+                phase_after_check(s, errs[0]);
             }
         }
         if (!s.done && (rc = advance_stages(eng, one, st))) return rc;
@@ -520,7 +552,7 @@ int se2_gradient_flow(se2_kernel_t h, const double *mu0, const se2_flow_t *flow,
 int se2_barycenter(se2_kernel_t h, int32_t n, const double *const *mus, const double *lambdas,
                    const se2_opts_t *opts, double *bary_out, se2_report_t *report, se2_stream_t stream) {
     const Kernel *k = reinterpret_cast<const Kernel *>(h);
-    if (!k || n < 1 || n > kMaxMeasures || !mus || !lambdas || !bary_out || !valid_opts(opts, k->metric.eps))
+    if (!k || n < 1 || n > kMaxMeasures || !mus || !lambdas || !bary_out || !valid_opts(opts, k))
         return SE2_EINVAL;
     double lsum = 0.0;
     for (int i = 0; i < n; ++i) {
@@ -576,6 +608,8 @@ int se2_barycenter(se2_kernel_t h, int32_t n, const double *const *mus, const do
             } else if (last) {
                 s.done = true;
                 s.status = SE2_MAX_ITER;
+            } else {
+                phase_after_check(s, errs[0]);
             }
         }
         if (!s.done && (rc = advance_stages(eng, one, st))) return rc;

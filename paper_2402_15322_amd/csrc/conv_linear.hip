@@ -25,6 +25,7 @@
 
 #include <cstring>
 
+#include "conv_dev.h"
 #include "se2_internal.h"
 
 namespace se2 {
@@ -97,70 +98,22 @@ __device__ __forceinline__ void mfma_chunk(f32x4_t (&acc)[RPW][Pack<NT>::NB],
     }
 }
 
+// All (dx group, dy chunk) steps of the BF16 contraction of one workgroup tile: acc[r][nb]
+// receives output row row0 + r of the tile, column block nb.  lds16 holds the halo
+// [hy][hx][ki] in bfloat16 with hx = 0 at pixel xl.
 template <int NT, int DYC, int RPW>
-__global__ __launch_bounds__(256) void k_conv_bf16(const float *__restrict__ in, float *__restrict__ out,
-                                                   const bf16x8_t *__restrict__ Bp, int nx, int ny, int R,
-                                                   int tiles_x, int tiles_y) {
+__device__ __forceinline__ void bf16_contract(f32x4_t (&acc)[RPW][Pack<NT>::NB], const uint16_t *lds16,
+                                              const bf16x8_t *__restrict__ Bp, int R, int x0, int xl, int row0,
+                                              int lane) {
     using P = Pack<NT>;
-    extern __shared__ uint16_t lds16[];
     const int W = 2 * R + 1;
     const int G = (W + P::SPM - 1) / P::SPM;
-    const int HWX = kSeg + 2 * R + (G * P::SPM - W);  // halo width incl. overhang of the last dx group
-    constexpr int kRows = RPW * kWaves;
-    const int HWY = kRows + 2 * R;
-    const int tiles = tiles_x * tiles_y;
-    const int b = blockIdx.x / tiles;
-    const int t = blockIdx.x - b * tiles;
-    const int ty = t / tiles_x, tx = t - ty * tiles_x;
-    const int x0 = tx * kSeg, y0 = ty * kRows;
-    const float *img = in + static_cast<size_t>(b) * nx * ny * NT;
-    float *dst = out + static_cast<size_t>(b) * nx * ny * NT;
-
-    // stage halo [hy][hx][ki] as bfloat16, four orientations per thread and element;
-    // hx = 0 is pixel x0 - R - (overhang).  Loads go out in batches of 8 per thread
-    // (clamped indices, no branches) before any of them is converted and stored.
-    const int xl = x0 - R - (G * P::SPM - W);
-    {
-        constexpr int Q = NT / 4;
-        constexpr int NB8 = 8;
-        const int total = HWY * HWX * Q;
-        const float inv = 1.0f / static_cast<float>(HWX);
-        for (int e0 = 0; e0 < total; e0 += NB8 * 256) {
-            float4 v[NB8];
-            bool ok[NB8];
-#pragma unroll
-            for (int u = 0; u < NB8; ++u) {
-                const int e = min(e0 + u * 256 + static_cast<int>(threadIdx.x), total - 1);
-                const int p = e / Q, q = e - p * Q;
-                // p / HWX through a float reciprocal: exact for p < 2^20 (the +0.5 keeps
-                // the rounding error far from an integer boundary)
-                const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv), hx = p - hy * HWX;
-                const int gy = y0 - R + hy, gx = xl + hx;
-                ok[u] = gy >= 0 && gy < ny && gx >= 0 && gx < nx;
-                const int cy = min(max(gy, 0), ny - 1), cx = min(max(gx, 0), nx - 1);
-                v[u] = *reinterpret_cast<const float4 *>(&img[(static_cast<size_t>(cy) * nx + cx) * NT + 4 * q]);
-            }
-#pragma unroll
-            for (int u = 0; u < NB8; ++u) {
-                const int e = e0 + u * 256 + static_cast<int>(threadIdx.x);
-                if (e < total)
-                    *reinterpret_cast<uint2 *>(&lds16[4 * e]) =
-                        ok[u] ? make_uint2(f32x2_to_bf16x2_rne(v[u].x, v[u].y), f32x2_to_bf16x2_rne(v[u].z, v[u].w))
-                              : make_uint2(0u, 0u);
-            }
-        }
-    }
-    __syncthreads();
-
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int HWX = kSeg + 2 * R + (G * P::SPM - W);
     const int i = lane & 15;   // output pixel within the segment (A row)
     const int kb = lane >> 4;  // 8-wide K block of this lane
     const int slot = (kb * 8) / P::KI;
     const int kio = (kb * 8) % P::KI;
-    const int row0 = wave * RPW;  // first output row of this wave within the tile
 
-    f32x4_t acc[RPW][P::NB];
 #pragma unroll
     for (int r = 0; r < RPW; ++r)
 #pragma unroll
@@ -230,6 +183,68 @@ __global__ __launch_bounds__(256) void k_conv_bf16(const float *__restrict__ in,
                 for (int nb = 0; nb < P::NB; ++nb) b0[c][nb] = b1[c][nb];
         }
     }
+}
+
+template <int NT, int DYC, int RPW>
+__global__ __launch_bounds__(256) void k_conv_bf16(const float *__restrict__ in, float *__restrict__ out,
+                                                   const bf16x8_t *__restrict__ Bp, int nx, int ny, int R,
+                                                   int tiles_x, int tiles_y) {
+    using P = Pack<NT>;
+    extern __shared__ uint16_t lds16[];
+    const int W = 2 * R + 1;
+    const int G = (W + P::SPM - 1) / P::SPM;
+    const int HWX = kSeg + 2 * R + (G * P::SPM - W);  // halo width incl. overhang of the last dx group
+    constexpr int kRows = RPW * kWaves;
+    const int HWY = kRows + 2 * R;
+    const int tiles = tiles_x * tiles_y;
+    const int b = blockIdx.x / tiles;
+    const int t = blockIdx.x - b * tiles;
+    const int ty = t / tiles_x, tx = t - ty * tiles_x;
+    const int x0 = tx * kSeg, y0 = ty * kRows;
+    const float *img = in + static_cast<size_t>(b) * nx * ny * NT;
+    float *dst = out + static_cast<size_t>(b) * nx * ny * NT;
+
+    // stage halo [hy][hx][ki] as bfloat16, four orientations per thread and element;
+    // hx = 0 is pixel x0 - R - (overhang).  Loads go out in batches of 8 per thread
+    // (clamped indices, no branches) before any of them is converted and stored.
+    const int xl = x0 - R - (G * P::SPM - W);
+    {
+        constexpr int Q = NT / 4;
+        constexpr int NB8 = 8;
+        const int total = HWY * HWX * Q;
+        const float inv = 1.0f / static_cast<float>(HWX);
+        for (int e0 = 0; e0 < total; e0 += NB8 * 256) {
+            float4 v[NB8];
+            bool ok[NB8];
+#pragma unroll
+            for (int u = 0; u < NB8; ++u) {
+                const int e = min(e0 + u * 256 + static_cast<int>(threadIdx.x), total - 1);
+                const int p = e / Q, q = e - p * Q;
+                // p / HWX through a float reciprocal: exact for p < 2^20 (the +0.5 keeps
+                // the rounding error far from an integer boundary)
+                const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv), hx = p - hy * HWX;
+                const int gy = y0 - R + hy, gx = xl + hx;
+                ok[u] = gy >= 0 && gy < ny && gx >= 0 && gx < nx;
+                const int cy = min(max(gy, 0), ny - 1), cx = min(max(gx, 0), nx - 1);
+                v[u] = *reinterpret_cast<const float4 *>(&img[(static_cast<size_t>(cy) * nx + cx) * NT + 4 * q]);
+            }
+#pragma unroll
+            for (int u = 0; u < NB8; ++u) {
+                const int e = e0 + u * 256 + static_cast<int>(threadIdx.x);
+                if (e < total)
+                    *reinterpret_cast<uint2 *>(&lds16[4 * e]) =
+                        ok[u] ? make_uint2(f32x2_to_bf16x2_rne(v[u].x, v[u].y), f32x2_to_bf16x2_rne(v[u].z, v[u].w))
+                              : make_uint2(0u, 0u);
+            }
+        }
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int row0 = wave * RPW;  // first output row of this wave within the tile
+    f32x4_t acc[RPW][P::NB];
+    bf16_contract<NT, DYC, RPW>(acc, lds16, Bp, R, x0, xl, row0, lane);
 
     // D: lane holds column j = lane % 16 (ko), rows 4*(lane/16) + q (pixels)
     const int j = lane & 15;
@@ -250,61 +265,42 @@ __global__ __launch_bounds__(256) void k_conv_bf16(const float *__restrict__ in,
     }
 }
 
-// FP32 convolution on the matrix cores, nt = 16 or 32: the tiling of k_conv_bf16 (kSeg
-// output pixels by kWaves * RPW output rows per workgroup, window rows in chunks of
-// DYC), one step per (dx, dy chunk), in NT / 16 passes over 16 input orientations each
-// (the halo of one pass is staged in LDS in FP32).  For output row r and window row c of
-// the chunk, the lane of pixel i = lane % 16 and quad kq = lane / 16 reads the pass's
-// input orientations 4 kq .. 4 kq + 3 of its input pixel as one float4; MFMA e (e = 0..3)
-// of column block nb multiplies element e by the packed B value
+// FP32 matrix-core steps (nt = 16 or 32): the tiling of k_conv_bf16 (kSeg output pixels by
+// kWaves * RPW output rows per workgroup, window rows in chunks of DYC), one step per (dx, dy
+// chunk), in NT / 16 passes over 16 input orientations each (the halo of one pass is staged
+// in LDS in FP32, [hy][hx][16 ki], hx = 0 at pixel x0 - R).  For output row r and window row c
+// of the chunk, the lane of pixel i = lane % 16 and quad kq = lane / 16 reads the pass's
+// input orientations 4 kq .. 4 kq + 3 of its input pixel as one float4; MFMA e (e = 0..3) of
+// column block nb multiplies element e by the packed B value
 // K[ko = 16 nb + lane % 16][ki = 16 pass + 4 kq + e], so the four MFMAs sum the pass's 16
 // orientations into the 16 output orientations of the block.
-template <int NT, int DYC, int RPW>
-__global__ __launch_bounds__(256) void k_conv_f32m(const float *__restrict__ in, float *__restrict__ out,
-                                                   const f32x4_t *__restrict__ Fp, int nx, int ny, int R,
-                                                   int tiles_x, int tiles_y) {
-    static_assert(NT == 16 || NT == 32, "16 or 32 orientations");
-    constexpr int NB = NT / 16;  // output column blocks
-    constexpr int NP = NT / 16;  // passes over the input orientations
-    extern __shared__ float lds32[];
+template <int NT, int DYC>
+__device__ __forceinline__ void f32m_load_b(f32x4_t (&dstb)[DYC][NT / 16], const f32x4_t *__restrict__ Fp, int step,
+                                            int pass, int nchunks, int W, int lane) {
+    constexpr int NB = NT / 16, NP = NT / 16;
+    const int dxi = step / nchunks, ch = step - dxi * nchunks;
+#pragma unroll
+    for (int c = 0; c < DYC; ++c)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+            dstb[c][nb] = Fp[((((static_cast<size_t>(ch * DYC + c) * W + dxi) * NP + pass) * NB + nb) * 64) + lane];
+}
+
+// Every step of one pass, with the first step's fragments already in b0.  With FLUSH the
+// FP32 accumulators are added into FP64 ones after every step and cleared, so that no FP32
+// sum runs over more than one step (16 DYC products).
+template <int NT, int DYC, int RPW, bool FLUSH>
+__device__ __forceinline__ void f32m_steps(f32x4_t (&acc)[RPW][NT / 16], double (&acc64)[RPW][NT / 16][4],
+                                           f32x4_t (&b0)[DYC][NT / 16], const float *lds32,
+                                           const f32x4_t *__restrict__ Fp, int pass, int R, int row0, int lane) {
+    constexpr int NB = NT / 16;
     const int W = 2 * R + 1;
     const int HWX = kSeg + 2 * R;
-    constexpr int kRows = RPW * kWaves;
-    const int HWY = kRows + 2 * R;
-    const int tiles = tiles_x * tiles_y;
-    const int b = blockIdx.x / tiles;
-    const int t = blockIdx.x - b * tiles;
-    const int ty = t / tiles_x, tx = t - ty * tiles_x;
-    const int x0 = tx * kSeg, y0 = ty * kRows;
-    const float *img = in + static_cast<size_t>(b) * nx * ny * NT;
-    float *dst = out + static_cast<size_t>(b) * nx * ny * NT;
-
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
-    const int i = lane & 15;      // output pixel within the segment (A row)
-    const int kq = lane >> 4;     // orientation quad of this lane
-    const int row0 = wave * RPW;  // first output row of this wave within the tile
-
-    f32x4_t acc[RPW][NB];
-#pragma unroll
-    for (int r = 0; r < RPW; ++r)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[r][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-
-    // (dx, dy chunk) steps of a pass; the fragments of a step are loaded one step ahead,
-    // those of a pass's first step before its halo staging, so that their latency overlaps it
+    const int i = lane & 15;   // output pixel within the segment (A row)
+    const int kq = lane >> 4;  // orientation quad of this lane
     const int nchunks = (W + DYC - 1) / DYC;
     const int nsteps = W * nchunks;
-    f32x4_t b0[DYC][NB], b1[DYC][NB];
-    auto load_b = [&](f32x4_t(&dstb)[DYC][NB], int step, int pass) {
-        const int dxi = step / nchunks, ch = step - dxi * nchunks;
-#pragma unroll
-        for (int c = 0; c < DYC; ++c)
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-                dstb[c][nb] = Fp[((((static_cast<size_t>(ch * DYC + c) * W + dxi) * NP + pass) * NB + nb) * 64) + lane];
-    };
-    const int xl = x0 - R;
+    f32x4_t b1[DYC][NB];
     auto run = [&](const f32x4_t(&bfr)[DYC][NB], int step) {
         const int dxi = step / nchunks, ch = step - dxi * nchunks;
         // input pixel x0 + i - dx (dx = dxi - R) sits at halo column i + 2R - dxi; output
@@ -336,9 +332,69 @@ __global__ __launch_bounds__(256) void k_conv_f32m(const float *__restrict__ in,
             a = an;
         }
     };
+    // a step is RPW * DYC * 4 * NB MFMAs of 32 cycles per wave: one step of lookahead
+    // hides the fragment loads
+    for (int step = 0; step < nsteps; ++step) {
+        f32m_load_b<NT, DYC>(b1, Fp, min(step + 1, nsteps - 1), pass, nchunks, W, lane);
+        __builtin_amdgcn_sched_barrier(0);
+        run(b0, step);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (FLUSH) {
+#pragma unroll
+            for (int r = 0; r < RPW; ++r)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc64[r][nb][q] += static_cast<double>(acc[r][nb][q]);
+                    acc[r][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+                }
+        }
+#pragma unroll
+        for (int c = 0; c < DYC; ++c)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) b0[c][nb] = b1[c][nb];
+    }
+}
 
+// FP32 convolution on the matrix cores, nt = 16 or 32 (steps above).
+template <int NT, int DYC, int RPW>
+__global__ __launch_bounds__(256) void k_conv_f32m(const float *__restrict__ in, float *__restrict__ out,
+                                                   const f32x4_t *__restrict__ Fp, int nx, int ny, int R,
+                                                   int tiles_x, int tiles_y) {
+    static_assert(NT == 16 || NT == 32, "16 or 32 orientations");
+    constexpr int NB = NT / 16;  // output column blocks
+    constexpr int NP = NT / 16;  // passes over the input orientations
+    extern __shared__ float lds32[];
+    const int W = 2 * R + 1;
+    const int HWX = kSeg + 2 * R;
+    constexpr int kRows = RPW * kWaves;
+    const int HWY = kRows + 2 * R;
+    const int tiles = tiles_x * tiles_y;
+    const int b = blockIdx.x / tiles;
+    const int t = blockIdx.x - b * tiles;
+    const int ty = t / tiles_x, tx = t - ty * tiles_x;
+    const int x0 = tx * kSeg, y0 = ty * kRows;
+    const float *img = in + static_cast<size_t>(b) * nx * ny * NT;
+    float *dst = out + static_cast<size_t>(b) * nx * ny * NT;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int row0 = wave * RPW;  // first output row of this wave within the tile
+
+    f32x4_t acc[RPW][NB];
+    double unused[RPW][NB][4];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[r][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+    const int nchunks = (W + DYC - 1) / DYC;
+    f32x4_t b0[DYC][NB];
+    const int xl = x0 - R;
     for (int pass = 0; pass < NP; ++pass) {
-        load_b(b0, 0, pass);
+        // the fragments of a pass's first step are loaded before its halo staging, so that
+        // their latency overlaps it
+        f32m_load_b<NT, DYC>(b0, Fp, 0, pass, nchunks, W, lane);
         if (pass > 0) __syncthreads();  // every wave is done with the previous pass's halo
         // stage the pass's halo [hy][hx][16 ki] in FP32, zero outside the grid; loads go
         // out in batches of 8 float4 per thread (clamped indices, no branches) before any
@@ -372,18 +428,7 @@ __global__ __launch_bounds__(256) void k_conv_f32m(const float *__restrict__ in,
             }
         }
         __syncthreads();
-        // a step is RPW * DYC * 4 * NB MFMAs of 32 cycles per wave: one step of lookahead
-        // hides the fragment loads
-        for (int step = 0; step < nsteps; ++step) {
-            load_b(b1, min(step + 1, nsteps - 1), pass);
-            __builtin_amdgcn_sched_barrier(0);
-            run(b0, step);
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int c = 0; c < DYC; ++c)
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) b0[c][nb] = b1[c][nb];
-        }
+        f32m_steps<NT, DYC, RPW, false>(acc, unused, b0, lds32, Fp, pass, R, row0, lane);
     }
 
     // D: lane holds column j = lane % 16 (ko within the block), rows 4 * (lane / 16) + q
@@ -453,6 +498,347 @@ __global__ __launch_bounds__(256) void k_conv_valu(const T *__restrict__ in, T *
     if (gx < nx && gy < ny) {
 #pragma unroll
         for (int q = 0; q < NJ; ++q) dst[(static_cast<size_t>(gy) * nx + gx) * NT + wave + 4 * q] = acc[q];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Certified linear-domain evaluation of log-domain jobs (the solver's matrix-core engines)
+// ---------------------------------------------------------------------------------------
+//
+// For a job with log2 input g (FP64, -inf for zero mass) a workgroup computes, for every
+// output (x, ko) of its tile, LSE(x, ko) = log2 sum_{d, ki} K[d][ko][ki] 2^g(x - d, ki) as
+//     M = max of g over the tile's input halo,   V = 2^(g - M) (in (0, 1], 0 for zero mass),
+//     S = sum K V on the matrix cores,           LSE = M + log2 S.
+// The halo is read twice from global memory: once for M, once (from the L2) to form V,
+// which is rounded to bfloat16 (RNE) or kept in FP32 as it is staged in LDS.  The
+// contraction is that of the linear kernels.  The epilogue checks the certificate
+// S >= kLinCert per output; a group (8 x 8 tile, ko) all of whose outputs pass is written
+// with the job's scaling epilogue and error partial, slot [tile][ko]; a group with a
+// failing output is written nowhere here and appended to a list that k_lse_items then
+// recomputes exactly (so that in-place updates keep their previous values for it).
+
+// Maximum of the FP64 input over the halo rows [ylo, ylo + HWY) and columns [xl, xl + HWX)
+// (-inf outside the grid), over all NT orientations; the block maximum is returned to
+// every thread.  16-byte loads, BATCH items of 4 orientations per thread in flight.
+template <int NT>
+__device__ __forceinline__ double halo_max(const double *in_, int nx, int ny, int HWX, int HWY, int xl, int ylo,
+                                           double *s_m) {
+    constexpr int Q = NT / 4;
+    constexpr int BATCH = 4;
+    const gdptr in = (gdptr)in_;
+    const int total = HWY * HWX * Q;
+    const float inv = 1.0f / static_cast<float>(HWX);
+    double m = -INFINITY;
+    for (int e0 = 0; e0 < total; e0 += BATCH * 256) {
+        double v[BATCH][4];
+        bool ok[BATCH];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+            const int e = min(e0 + u * 256 + static_cast<int>(threadIdx.x), total - 1);
+            const int p = e / Q, q = e - p * Q;
+            const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv), hx = p - hy * HWX;
+            const int gy = ylo + hy, gx = xl + hx;
+            ok[u] = gy >= 0 && gy < ny && gx >= 0 && gx < nx;
+            const int cy = min(max(gy, 0), ny - 1), cx = min(max(gx, 0), nx - 1);
+            const gdptr src = in + (static_cast<size_t>(cy) * nx + cx) * NT + 4 * q;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[u][c] = src[c];
+        }
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u)
+            if (ok[u]) m = fmax(m, fmax(fmax(v[u][0], v[u][1]), fmax(v[u][2], v[u][3])));
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    __syncthreads();
+    return fmax(fmax(s_m[0], s_m[1]), fmax(s_m[2], s_m[3]));
+}
+
+// Stage V = 2^(g - M) of orientations [k0, k0 + KS) of the halo in LDS, [hy][hx][KS], as
+// bfloat16 (RNE) or FP32; zero outside the grid and for zero mass.
+template <int NT, int KS, bool BF16>
+__device__ __forceinline__ void stage_shifted(void *lds, const double *in_, double M, int k0, int nx, int ny, int HWX,
+                                              int HWY, int xl, int ylo) {
+    constexpr int Q = KS / 4;
+    constexpr int BATCH = 4;
+    const gdptr in = (gdptr)in_;
+    const int total = HWY * HWX * Q;
+    const float inv = 1.0f / static_cast<float>(HWX);
+    for (int e0 = 0; e0 < total; e0 += BATCH * 256) {
+        double v[BATCH][4];
+        bool ok[BATCH];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+            const int e = min(e0 + u * 256 + static_cast<int>(threadIdx.x), total - 1);
+            const int p = e / Q, q = e - p * Q;
+            const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv), hx = p - hy * HWX;
+            const int gy = ylo + hy, gx = xl + hx;
+            ok[u] = gy >= 0 && gy < ny && gx >= 0 && gx < nx;
+            const int cy = min(max(gy, 0), ny - 1), cx = min(max(gx, 0), nx - 1);
+            const gdptr src = in + (static_cast<size_t>(cy) * nx + cx) * NT + k0 + 4 * q;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[u][c] = src[c];
+        }
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+            const int e = e0 + u * 256 + static_cast<int>(threadIdx.x);
+            if (e < total) {
+                float f[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    // 2^d with d = g - M split as dh + dl (dh = FP32(d), |dl| <= 2^-24 |d|):
+                    // 2^dh (native exp2) times 1 + dl ln 2, so that the FP32 rounding of a
+                    // large |d| does not enter the result
+                    const double d = v[u][c] - M;
+                    const float dh = static_cast<float>(d);
+                    const float e = __builtin_amdgcn_exp2f(dh);
+                    if constexpr (BF16) {
+                        f[c] = ok[u] ? e : 0.0f;
+                    } else {
+                        const float dl = static_cast<float>(d - static_cast<double>(dh));
+                        f[c] = (ok[u] && v[u][c] != -INFINITY) ? fmaf(e, dl * 0.693147180559945309f, e) : 0.0f;
+                    }
+                }
+                if constexpr (BF16) {
+                    *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(lds) + 4 * e) =
+                        make_uint2(f32x2_to_bf16x2_rne(f[0], f[1]), f32x2_to_bf16x2_rne(f[2], f[3]));
+                } else {
+                    *reinterpret_cast<float4 *>(static_cast<float *>(lds) + 4 * e) = make_float4(f[0], f[1], f[2], f[3]);
+                }
+            }
+        }
+    }
+}
+
+// Certificate, epilogue, error partials and the fallback list of a matrix-core tile.
+// S[r][nb][q] is the shifted sum of the lane's output at pixel x0 + 4 (lane / 16) + q of row
+// y0 + row0 + r, orientation ko = 16 nb + lane % 16.  The group (8 x 8 tile, ko) of an output
+// is held by lanes ko + 16 {2h, 2h + 1} (h = 8-pixel half of the segment) over 8 rows: one
+// wave at 8 rows per wave, the wave pair (2m, 2m + 1) at 4 rows per wave.  Fixed-order sums:
+// within a lane over (r, q), then the even lane's sum plus the odd lane's, then the even
+// wave's plus the odd wave's.  An 8 x 8 tile with rejected groups is listed once, with the
+// mask of its rejected orientations.
+template <int NT, int RPW, int NB>
+__device__ __forceinline__ void lin_log_epilogue(const ConvJob &job, int jb, const double (&S)[RPW][NB][4], double M,
+                                                 int x0, int y0, int row0, int lane, int wave, int4 *__restrict__ fb,
+                                                 int *__restrict__ fb_count, int *s_xi, double *s_xd) {
+    const int nx = job.nx, ny = job.ny;
+    const int kb = lane >> 4, jj = lane & 15;
+    const int tx8 = (x0 >> 3) + (kb >> 1);
+    const int ty8 = (y0 + row0) >> 3;
+    const bool rep = ((kb & 1) == 0) && (RPW == 8 || (wave & 1) == 0);
+    const size_t slot = static_cast<size_t>(ty8 * job.tiles_x + tx8) * NT;
+    uint32_t rejected[2] = {0u, 0u};  // per 8-pixel half: orientations to recompute (wave-uniform)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int ko = 16 * nb + jj;
+        int any = 0, bad = 0;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gx = x0 + 4 * kb + q, gy = y0 + row0 + r;
+                if (ko < NT && gx < nx && gy < ny) {
+                    any = 1;
+                    if (!(S[r][nb][q] >= static_cast<double>(kLinCert))) bad = 1;
+                }
+            }
+        any |= __shfl_xor(any, 16);
+        bad |= __shfl_xor(bad, 16);
+        if constexpr (RPW == 4) {
+            __syncthreads();  // the previous round's reads of s_xi are done
+            s_xi[wave * 64 + lane] = any | (bad << 1);
+            __syncthreads();
+            const int o = s_xi[(wave ^ 1) * 64 + lane];
+            any |= o & 1;
+            bad |= o >> 1;
+        }
+        double err = 0.0;
+        if (any && !bad) {
+#pragma unroll
+            for (int r = 0; r < RPW; ++r)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int gx = x0 + 4 * kb + q, gy = y0 + row0 + r;
+                    if (ko < NT && gx < nx && gy < ny) {
+                        const double lse = M + log2(S[r][nb][q]);
+                        err += epilogue(job, (static_cast<size_t>(gy) * nx + gx) * NT + ko, lse);
+                    }
+                }
+        }
+        if (job.epi == EPI_SCALE && job.partial != nullptr) {
+            const double eo = __shfl_xor(err, 16);
+            double e = ((kb & 1) == 0) ? err + eo : eo + err;
+            if constexpr (RPW == 4) {
+                s_xd[wave * 64 + lane] = e;
+                __syncthreads();
+                const double ow = s_xd[(wave ^ 1) * 64 + lane];
+                e = ((wave & 1) == 0) ? e + ow : ow + e;
+            }
+            if (rep && any && !bad) job.partial[slot + ko] = e;
+        }
+        // rejected groups: lane 16 kb + jj with kb = 2h stands for (half h, ko)
+        const unsigned long long m = __ballot(rep && any && bad);
+        rejected[0] |= static_cast<uint32_t>(m & 0xffffull) << (16 * nb);
+        rejected[1] |= static_cast<uint32_t>((m >> 32) & 0xffffull) << (16 * nb);
+    }
+    const int np = (rejected[0] != 0u ? 1 : 0) + (rejected[1] != 0u ? 1 : 0);
+    if (np > 0 && lane == 0) {
+        int base = atomicAdd(fb_count, np);
+        const int row = ty8 * job.tiles_x + (x0 >> 3);
+        if (rejected[0] != 0u) fb[base++] = make_int4(jb, row, static_cast<int>(rejected[0]), 0);
+        if (rejected[1] != 0u) fb[base] = make_int4(jb, row + 1, static_cast<int>(rejected[1]), 0);
+    }
+}
+
+// BF16 operands: V rounded to bfloat16, the kernel's bfloat16 table, FP32 accumulation.
+template <int NT, int DYC, int RPW>
+__global__ __launch_bounds__(256) void k_lin_log_bf16(const ConvJob *__restrict__ jobs,
+                                                      const int32_t *__restrict__ block_job, int4 *__restrict__ fb,
+                                                      int *__restrict__ fb_count, int *__restrict__ fb_next) {
+    using P = Pack<NT>;
+    extern __shared__ uint16_t lds16[];
+    __shared__ double s_m[kWaves];
+    __shared__ int s_xi[kWaves * 64];
+    __shared__ double s_xd[kWaves * 64];
+    // the list counter of the following launch (its readers have finished: stream order)
+    if (blockIdx.x == 0 && threadIdx.x == 0) *fb_next = 0;
+    const int jb = block_job[blockIdx.x];
+    const ConvJob job = jobs[jb];
+    const int lt = static_cast<int>(blockIdx.x) - job.first_block;
+    const int nx = job.nx, ny = job.ny, R = job.R, W = 2 * R + 1;
+    const int G = (W + P::SPM - 1) / P::SPM;
+    const int HWX = kSeg + 2 * R + (G * P::SPM - W);
+    constexpr int kRows = RPW * kWaves;
+    const int HWY = kRows + 2 * R;
+    const int ltx = (nx + kSeg - 1) / kSeg;
+    const int ty = lt / ltx, tx = lt - ty * ltx;
+    const int x0 = tx * kSeg, y0 = ty * kRows;
+    const int xl = x0 - R - (G * P::SPM - W);
+    double M = halo_max<NT>(job.in, nx, ny, HWX, HWY, xl, y0 - R, s_m);
+    if (M == -INFINITY) M = 0.0;  // no mass in the halo: every V is 0, every group goes to the fallback
+    stage_shifted<NT, NT, true>(lds16, job.in, M, 0, nx, ny, HWX, HWY, xl, y0 - R);
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int row0 = wave * RPW;
+    f32x4_t acc[RPW][P::NB];
+    bf16_contract<NT, DYC, RPW>(acc, lds16, reinterpret_cast<const bf16x8_t *>(job.kop), R, x0, xl, row0, lane);
+    double S[RPW][P::NB][4];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r)
+#pragma unroll
+        for (int nb = 0; nb < P::NB; ++nb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) S[r][nb][q] = static_cast<double>(acc[r][nb][q]);
+    lin_log_epilogue<NT, RPW, P::NB>(job, jb, S, M, x0, y0, row0, lane, wave, fb, fb_count, s_xi, s_xd);
+}
+
+// FP32 operands on the FP32 matrix cores (nt = 16, 32): V and the kernel in FP32, FP32 sums
+// over one step added into FP64 accumulators.
+template <int NT, int DYC, int RPW>
+__global__ __launch_bounds__(256) void k_lin_log_f32(const ConvJob *__restrict__ jobs,
+                                                     const int32_t *__restrict__ block_job, int4 *__restrict__ fb,
+                                                     int *__restrict__ fb_count, int *__restrict__ fb_next) {
+    static_assert(NT == 16 || NT == 32, "16 or 32 orientations");
+    constexpr int NB = NT / 16, NP = NT / 16;
+    extern __shared__ float lds32[];
+    __shared__ double s_m[kWaves];
+    __shared__ int s_xi[kWaves * 64];
+    __shared__ double s_xd[kWaves * 64];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *fb_next = 0;
+    const int jb = block_job[blockIdx.x];
+    const ConvJob job = jobs[jb];
+    const int lt = static_cast<int>(blockIdx.x) - job.first_block;
+    const int nx = job.nx, ny = job.ny, R = job.R, W = 2 * R + 1;
+    const int HWX = kSeg + 2 * R;
+    constexpr int kRows = RPW * kWaves;
+    const int HWY = kRows + 2 * R;
+    const int ltx = (nx + kSeg - 1) / kSeg;
+    const int ty = lt / ltx, tx = lt - ty * ltx;
+    const int x0 = tx * kSeg, y0 = ty * kRows;
+    const int xl = x0 - R;
+    const f32x4_t *Fp = reinterpret_cast<const f32x4_t *>(job.kop);
+    double M = halo_max<NT>(job.in, nx, ny, HWX, HWY, xl, y0 - R, s_m);
+    if (M == -INFINITY) M = 0.0;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int row0 = wave * RPW;
+    f32x4_t acc[RPW][NB];
+    double acc64[RPW][NB][4];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            acc[r][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc64[r][nb][q] = 0.0;
+        }
+    const int nchunks = (W + DYC - 1) / DYC;
+    f32x4_t b0[DYC][NB];
+    for (int pass = 0; pass < NP; ++pass) {
+        f32m_load_b<NT, DYC>(b0, Fp, 0, pass, nchunks, W, lane);
+        if (pass > 0) __syncthreads();  // every wave is done with the previous pass's halo
+        stage_shifted<NT, 16, false>(lds32, job.in, M, 16 * pass, nx, ny, HWX, HWY, xl, y0 - R);
+        __syncthreads();
+        f32m_steps<NT, DYC, RPW, true>(acc, acc64, b0, lds32, Fp, pass, R, row0, lane);
+    }
+    lin_log_epilogue<NT, RPW, NB>(job, jb, acc64, M, x0, y0, row0, lane, wave, fb, fb_count, s_xi, s_xd);
+}
+
+template <int NT, int DYC, int RPW, bool BF16>
+int launch_lin_log_t(const ConvJob *d_jobs, int nblocks, const int32_t *d_map, int R, int4 *fb, int *fb_count,
+                     int *fb_next, hipStream_t s) {
+    const int rows = RPW * kWaves;
+    size_t lds;
+    const void *fn;
+    if constexpr (BF16) {
+        using P = Pack<NT>;
+        const int W = 2 * R + 1, G = (W + P::SPM - 1) / P::SPM;
+        lds = static_cast<size_t>(kSeg + 2 * R + (G * P::SPM - W)) * (rows + 2 * R) * NT * sizeof(uint16_t);
+        fn = reinterpret_cast<const void *>(&k_lin_log_bf16<NT, DYC, RPW>);
+    } else {
+        lds = static_cast<size_t>(kSeg + 2 * R) * (rows + 2 * R) * 16 * sizeof(float);
+        fn = reinterpret_cast<const void *>(&k_lin_log_f32<NT, DYC, RPW>);
+    }
+    if (lds > 65536) SE2_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+    if constexpr (BF16)
+        hipLaunchKernelGGL((k_lin_log_bf16<NT, DYC, RPW>), dim3(nblocks), dim3(256), lds, s, d_jobs, d_map, fb, fb_count,
+                           fb_next);
+    else
+        hipLaunchKernelGGL((k_lin_log_f32<NT, DYC, RPW>), dim3(nblocks), dim3(256), lds, s, d_jobs, d_map, fb, fb_count,
+                           fb_next);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+// nt = 32 has one row count per operand type (lin_rows_per_wave): 8 rows for bfloat16, 4 for
+// FP32 (its two FP64 accumulator blocks); nt <= 16 has both.
+template <int NT, int DYC, bool BF16>
+int launch_lin_log_rpw(const ConvJob *d_jobs, int nblocks, const int32_t *d_map, int R, int rpw, int4 *fb,
+                       int *fb_count, int *fb_next, hipStream_t s) {
+    if constexpr (NT == 32) {
+        constexpr int kR = BF16 ? 8 : 4;
+        if (rpw != kR) return SE2_EINVAL;
+        return launch_lin_log_t<NT, DYC, kR, BF16>(d_jobs, nblocks, d_map, R, fb, fb_count, fb_next, s);
+    } else {
+        if (rpw == 8) return launch_lin_log_t<NT, DYC, 8, BF16>(d_jobs, nblocks, d_map, R, fb, fb_count, fb_next, s);
+        return launch_lin_log_t<NT, DYC, 4, BF16>(d_jobs, nblocks, d_map, R, fb, fb_count, fb_next, s);
+    }
+}
+
+template <int NT, bool BF16>
+int launch_lin_log_nt(const ConvJob *d_jobs, int nblocks, const int32_t *d_map, int R, int rpw, int4 *fb,
+                      int *fb_count, int *fb_next, hipStream_t s) {
+    switch (dy_chunk(2 * R + 1)) {
+        case 4: return launch_lin_log_rpw<NT, 4, BF16>(d_jobs, nblocks, d_map, R, rpw, fb, fb_count, fb_next, s);
+        case 5: return launch_lin_log_rpw<NT, 5, BF16>(d_jobs, nblocks, d_map, R, rpw, fb, fb_count, fb_next, s);
+        case 6: return launch_lin_log_rpw<NT, 6, BF16>(d_jobs, nblocks, d_map, R, rpw, fb, fb_count, fb_next, s);
+        case 7: return launch_lin_log_rpw<NT, 7, BF16>(d_jobs, nblocks, d_map, R, rpw, fb, fb_count, fb_next, s);
+        case 8: return launch_lin_log_rpw<NT, 8, BF16>(d_jobs, nblocks, d_map, R, rpw, fb, fb_count, fb_next, s);
+        default: return SE2_EINVAL;
     }
 }
 
@@ -644,6 +1030,41 @@ int launch_conv_f32(const Kernel &k, const float *in, float *out, int batch, hip
                                   : launch_valu_t<float, 32>(k, k.d_K32, in, out, batch, s);
         default: return SE2_EINVAL;
     }
+}
+
+int lin_rows_per_wave(int nt, bool bf16, int ny) {
+    if (nt == 32) return bf16 ? 8 : 4;
+    return ny >= 128 ? 8 : 4;
+}
+
+int lin_blocks(int nx, int ny, int rpw) {
+    const int rows = rpw * kWaves;
+    return ((nx + kSeg - 1) / kSeg) * ((ny + rows - 1) / rows);
+}
+
+bool lin_supported(int nt, bool bf16) { return bf16 ? (nt == 8 || nt == 16 || nt == 32) : (nt == 16 || nt == 32); }
+
+int launch_conv_lin_log(const ConvJob *d_jobs, int nblocks, const int32_t *d_block_job, int nt, int R, int rpw,
+                        bool bf16, int4 *fb, int *fb_count, int *fb_next, int fb_grid, hipStream_t s) {
+    if (nblocks <= 0) return SE2_OK;
+    if (R < 0 || R > kMaxRadius || (rpw != 4 && rpw != 8) || !lin_supported(nt, bf16) || !fb || !fb_count ||
+        !fb_next || fb_count == fb_next)
+        return SE2_EINVAL;
+    int rc;
+    switch (nt) {
+        case 8: rc = launch_lin_log_nt<8, true>(d_jobs, nblocks, d_block_job, R, rpw, fb, fb_count, fb_next, s); break;
+        case 16:
+            rc = bf16 ? launch_lin_log_nt<16, true>(d_jobs, nblocks, d_block_job, R, rpw, fb, fb_count, fb_next, s)
+                      : launch_lin_log_nt<16, false>(d_jobs, nblocks, d_block_job, R, rpw, fb, fb_count, fb_next, s);
+            break;
+        case 32:
+            rc = bf16 ? launch_lin_log_nt<32, true>(d_jobs, nblocks, d_block_job, R, rpw, fb, fb_count, fb_next, s)
+                      : launch_lin_log_nt<32, false>(d_jobs, nblocks, d_block_job, R, rpw, fb, fb_count, fb_next, s);
+            break;
+        default: return SE2_EINVAL;
+    }
+    if (rc) return rc;
+    return launch_lse_tiles(d_jobs, fb_grid, nt, R, fb, fb_count, s);
 }
 
 int launch_conv_f64(const Kernel &k, const double *in, double *out, int batch, hipStream_t s) {

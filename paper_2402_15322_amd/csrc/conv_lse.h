@@ -74,8 +74,23 @@ struct ConvJob {
     float *mref;        // [E] per-output maximum exponent at build time
     int32_t *dense_flag; // [tiles] dense visits (diagnostics), may be null
     double *work;       // [tiles][2] in-grid LSE terms evaluated on the dense / sparse path, may be null
+    // certified linear-domain engines (matrix cores): the kernel in MFMA operand order and a
+    // counter of the (tile, ko) groups recomputed in the log domain (may be null)
+    const void *kop;
+    int32_t *fallbacks;
     int32_t nx, ny, R, epi;
     int32_t tiles_x, tiles, first_block, lmax;
+    int32_t blocks;     // workgroups of this job in its launch (8 x 8 tiles, or matrix-core tiles)
+    int32_t pad_;
 };
+
+// Certificate of the linear-domain engines.  A workgroup shifts its input halo by its
+// maximum M (so every exponential is <= 1) and sums S = sum K 2^(in - M) in FP32 on the
+// matrix cores.  Entries that underflow (an input, kernel value or product below 2^-126)
+// are lost, at most 2^-126 each, and a window holds fewer than 2^15 of them, so while
+// S >= kLinCert = 2^-87 the lost part is below 2^-24 of S: the output keeps the
+// precision of its arithmetic.  A group (8 x 8 tile, output orientation) with any output
+// below the bound (or with S = 0) is recomputed exactly in the log domain.
+constexpr float kLinCert = 0x1p-87f;
 
 }  // namespace se2

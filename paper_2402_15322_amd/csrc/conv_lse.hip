@@ -41,6 +41,7 @@
 
 #include <cmath>
 
+#include "conv_dev.h"
 #include "se2_internal.h"
 
 namespace se2 {
@@ -49,13 +50,6 @@ namespace {
 
 typedef const __attribute__((address_space(4))) double *cdptr;
 typedef const __attribute__((address_space(4))) float *cfptr;
-// Global-memory views of the job's pointers: global (not flat) loads wait on the
-// vector-memory counter only, so they do not serialise against LDS traffic.
-typedef const __attribute__((address_space(1))) double *gdptr;
-typedef const __attribute__((address_space(1))) float *gfptr;
-typedef const __attribute__((address_space(1))) int32_t *giptr;
-typedef __attribute__((address_space(1))) double *gdptr_w;
-typedef __attribute__((address_space(1))) float *gfptr_w;
 
 constexpr int kHaloBatch = 4;        // halo items each thread loads before storing any
 constexpr int kHaloBatchSparse = 2;  // the same in the sparse kernel (fewer registers)
@@ -120,34 +114,93 @@ __device__ __forceinline__ float wave_max(float v) {
     return v;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-    // butterfly in a fixed lane pattern: deterministic
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
-// Scaling epilogue of one output element; returns its contribution to the marginal error.
-__device__ __forceinline__ double epilogue(const ConvJob &job, size_t idx, double lse) {
-    double o, err = 0.0;
-    if (job.epi == EPI_RAW) {
-        o = lse;
-    } else if (job.epi == EPI_SCALE) {
-        const double lm = ((gdptr)job.aux)[idx];
-        o = (lm == -INFINITY) ? -INFINITY : lm - lse;
-        if (job.old != nullptr && lm != -INFINITY) err = exp2(lm) * fabs(expm1((((gdptr)job.old)[idx] - o) * kLn2));
-    } else {
-        const double bse = ((gdptr)job.aux)[idx];
-        o = (bse == -INFINITY || lse == -INFINITY) ? -INFINITY : bse + lse;
-    }
-    if (job.out != nullptr) ((gdptr_w)job.out)[idx] = o;  // checks keep only the error
-    return err;
-}
 
 // LDS offset of list term j relative to the output pixel: ki*npix + (R-dy)*HW + (R-dx).
 __device__ __forceinline__ int term_offset(uint32_t term, int nt, int R, int W, int HW, int npix) {
     const int kc = static_cast<int>(term) % nt, r = static_cast<int>(term) / nt;
     const int dyi = r / W, dxi = r - dyi * W;
     return kc * npix + (2 * R - dyi) * HW + (2 * R - dxi);
+}
+
+// Dense evaluation of one 8 x 8 tile of a job: lse[q] receives the LSE of the lane's pixel
+// at orientation ko = wave + 4 q (lane = pixel px + 8 py of the tile; rows and columns past
+// the grid compute clamped garbage that the caller does not store).  The input halo is
+// staged in LDS KC orientations at a time (twice when KC < NT: the max pass, then the sum).
+template <int NT, int KC, bool F64EXP>
+__device__ __forceinline__ void dense_tile(const ConvJob &job, double *lds, int x0, int y0, int px, int py, int wave,
+                                           double (&lse)[NT / 4]) {
+    constexpr int NJ = NT / 4;
+    const int R = job.R, W = 2 * R + 1, HW = kTile + 2 * R, npix = HW * HW;
+    const int nx = job.nx, ny = job.ny;
+    const cdptr L64 = (cdptr)(job.L64);
+    const cfptr L32 = (cfptr)(job.L32);
+    float mx[NJ];
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) mx[q] = -INFINITY;
+    for (int k0 = 0; k0 < NT; k0 += KC) {
+        if (k0 > 0) __syncthreads();
+        load_halo<KC>(lds, job.in, NT, k0, x0, y0, R, HW, nx, ny);
+        __syncthreads();
+        for (int dy = -R; dy <= R; ++dy) {
+            for (int dx = -R; dx <= R; ++dx) {
+                const int hb = (py + R - dy) * HW + (px + R - dx);
+                const cfptr Lr = L32 + (static_cast<size_t>((dy + R) * W + (dx + R)) * NT) * NT + k0;
+#pragma unroll
+                for (int kc = 0; kc < KC; ++kc) {
+                    const float v = static_cast<float>(lds[kc * npix + hb]);
+#pragma unroll
+                    for (int q = 0; q < NJ; ++q) mx[q] = fmaxf(mx[q], v + Lr[(wave + 4 * q) * NT + kc]);
+                }
+            }
+        }
+    }
+    double M[NJ], S[NJ];
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) {
+        M[q] = (mx[q] == -INFINITY) ? 0.0 : static_cast<double>(mx[q]);
+        S[q] = 0.0;
+    }
+    for (int k0 = 0; k0 < NT; k0 += KC) {
+        if (NT > KC) {
+            __syncthreads();
+            load_halo<KC>(lds, job.in, NT, k0, x0, y0, R, HW, nx, ny);
+            __syncthreads();
+        }
+        for (int dy = -R; dy <= R; ++dy) {
+            if constexpr (F64EXP) {
+                for (int dx = -R; dx <= R; ++dx) {
+                    const int hb = (py + R - dy) * HW + (px + R - dx);
+                    const cdptr Lr = L64 + (static_cast<size_t>((dy + R) * W + (dx + R)) * NT) * NT + k0;
+#pragma unroll
+                    for (int kc = 0; kc < KC; ++kc) {
+                        const double v = lds[kc * npix + hb];
+#pragma unroll
+                        for (int q = 0; q < NJ; ++q) S[q] += exp2((v + Lr[(wave + 4 * q) * NT + kc]) - M[q]);
+                    }
+                }
+            } else {
+                float srow[NJ];
+#pragma unroll
+                for (int q = 0; q < NJ; ++q) srow[q] = 0.0f;
+                for (int dx = -R; dx <= R; ++dx) {
+                    const int hb = (py + R - dy) * HW + (px + R - dx);
+                    const cdptr Lr = L64 + (static_cast<size_t>((dy + R) * W + (dx + R)) * NT) * NT + k0;
+#pragma unroll
+                    for (int kc = 0; kc < KC; ++kc) {
+                        const double v = lds[kc * npix + hb];
+#pragma unroll
+                        for (int q = 0; q < NJ; ++q)
+                            srow[q] += __builtin_amdgcn_exp2f(
+                                static_cast<float>((v + Lr[(wave + 4 * q) * NT + kc]) - M[q]));
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < NJ; ++q) S[q] += static_cast<double>(srow[q]);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) lse[q] = (S[q] > 0.0) ? M[q] + log2(S[q]) : -INFINITY;
 }
 
 template <int NT, int KC, bool F64EXP>
@@ -162,7 +215,7 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_lse(const ConvJob *__rest
     const int ty = tile / job.tiles_x;
     const int tx = tile - ty * job.tiles_x;
     const int x0 = tx * kTile, y0 = ty * kTile;
-    const int R = job.R, W = 2 * R + 1, HW = kTile + 2 * R, npix = HW * HW;
+    const int R = job.R;
     const int nx = job.nx, ny = job.ny;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
@@ -170,80 +223,9 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_lse(const ConvJob *__rest
     const int gx = x0 + px, gy = y0 + py;
     const bool valid = gx < nx && gy < ny;
     const size_t obase = (static_cast<size_t>(gy) * nx + gx) * NT;
-    const cdptr L64 = (cdptr)(job.L64);
-    const cfptr L32 = (cfptr)(job.L32);
 
     double lse[NJ];
-    {
-        // ---------------- dense evaluation ----------------
-        float mx[NJ];
-#pragma unroll
-        for (int q = 0; q < NJ; ++q) mx[q] = -INFINITY;
-        for (int k0 = 0; k0 < NT; k0 += KC) {
-            if (k0 > 0) __syncthreads();
-            load_halo<KC>(lds, job.in, NT, k0, x0, y0, R, HW, nx, ny);
-            __syncthreads();
-            for (int dy = -R; dy <= R; ++dy) {
-                for (int dx = -R; dx <= R; ++dx) {
-                    const int hb = (py + R - dy) * HW + (px + R - dx);
-                    const cfptr Lr = L32 + (static_cast<size_t>((dy + R) * W + (dx + R)) * NT) * NT + k0;
-#pragma unroll
-                    for (int kc = 0; kc < KC; ++kc) {
-                        const float v = static_cast<float>(lds[kc * npix + hb]);
-#pragma unroll
-                        for (int q = 0; q < NJ; ++q) mx[q] = fmaxf(mx[q], v + Lr[(wave + 4 * q) * NT + kc]);
-                    }
-                }
-            }
-        }
-        double M[NJ], S[NJ];
-#pragma unroll
-        for (int q = 0; q < NJ; ++q) {
-            M[q] = (mx[q] == -INFINITY) ? 0.0 : static_cast<double>(mx[q]);
-            S[q] = 0.0;
-        }
-        for (int k0 = 0; k0 < NT; k0 += KC) {
-            if (NT > KC) {
-                __syncthreads();
-                load_halo<KC>(lds, job.in, NT, k0, x0, y0, R, HW, nx, ny);
-                __syncthreads();
-            }
-            for (int dy = -R; dy <= R; ++dy) {
-                if constexpr (F64EXP) {
-                    for (int dx = -R; dx <= R; ++dx) {
-                        const int hb = (py + R - dy) * HW + (px + R - dx);
-                        const cdptr Lr = L64 + (static_cast<size_t>((dy + R) * W + (dx + R)) * NT) * NT + k0;
-#pragma unroll
-                        for (int kc = 0; kc < KC; ++kc) {
-                            const double v = lds[kc * npix + hb];
-#pragma unroll
-                            for (int q = 0; q < NJ; ++q) S[q] += exp2((v + Lr[(wave + 4 * q) * NT + kc]) - M[q]);
-                        }
-                    }
-                } else {
-                    float srow[NJ];
-#pragma unroll
-                    for (int q = 0; q < NJ; ++q) srow[q] = 0.0f;
-                    for (int dx = -R; dx <= R; ++dx) {
-                        const int hb = (py + R - dy) * HW + (px + R - dx);
-                        const cdptr Lr = L64 + (static_cast<size_t>((dy + R) * W + (dx + R)) * NT) * NT + k0;
-#pragma unroll
-                        for (int kc = 0; kc < KC; ++kc) {
-                            const double v = lds[kc * npix + hb];
-#pragma unroll
-                            for (int q = 0; q < NJ; ++q)
-                                srow[q] += __builtin_amdgcn_exp2f(
-                                    static_cast<float>((v + Lr[(wave + 4 * q) * NT + kc]) - M[q]));
-                        }
-                    }
-#pragma unroll
-                    for (int q = 0; q < NJ; ++q) S[q] += static_cast<double>(srow[q]);
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < NJ; ++q) lse[q] = (S[q] > 0.0) ? M[q] + log2(S[q]) : -INFINITY;
-    }
+    dense_tile<NT, KC, F64EXP>(job, lds, x0, y0, px, py, wave, lse);
 
     // ---------------- work counters (diagnostics) ----------------
     if (job.work != nullptr) {
@@ -744,6 +726,71 @@ __global__ __launch_bounds__(64 * RBW) void k_rebuild(const ConvJob *__restrict_
     }
 }
 
+// Exact log-domain recomputation of the (tile, ko) groups that the certificate of the
+// matrix-core engines rejected.  An item (job, tile, ko mask) is one 8 x 8 tile with the
+// orientations to recompute; a workgroup evaluates the whole tile as k_conv_lse does (the
+// halo is staged once for all orientations) and writes the outputs, error partial slots
+// [tile][ko] and counters of the masked orientations only: the others were written by the
+// matrix-core kernel, which for in-place updates has already replaced their previous values.
+template <int NT, int KC>
+__global__ __launch_bounds__(kConvThreads) void k_lse_tiles(const ConvJob *__restrict__ jobs,
+                                                            const int4 *__restrict__ items,
+                                                            const int *__restrict__ count) {
+    extern __shared__ double lds[];
+    constexpr int NJ = NT / 4;
+    const int n = *count;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int px = lane & 7, py = lane >> 3;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int4 v = items[it];
+        const ConvJob job = jobs[v.x];
+        const int tile = v.y;
+        const uint32_t mask = static_cast<uint32_t>(v.z);
+        const int ty = tile / job.tiles_x;
+        const int tx = tile - ty * job.tiles_x;
+        const int x0 = tx * kTile, y0 = ty * kTile;
+        const int R = job.R;
+        const int nx = job.nx, ny = job.ny;
+        const int gx = x0 + px, gy = y0 + py;
+        const bool valid = gx < nx && gy < ny;
+        const size_t obase = (static_cast<size_t>(min(gy, ny - 1)) * nx + min(gx, nx - 1)) * NT;
+        __syncthreads();  // the LDS of the previous item is free
+        double lse[NJ];
+        dense_tile<NT, KC, false>(job, lds, x0, y0, px, py, wave, lse);
+        double work = 0.0;
+        if (valid) {
+            const int cx = min(R, gx) + min(R, nx - 1 - gx) + 1;
+            const int cy = min(R, gy) + min(R, ny - 1 - gy) + 1;
+            work = static_cast<double>(cx) * cy * NT;
+        }
+#pragma unroll
+        for (int q = 0; q < NJ; ++q) {
+            const int ko = wave + 4 * q;
+            if (((mask >> ko) & 1u) == 0u) continue;  // wave-uniform
+            const double err = valid ? epilogue(job, obase + ko, lse[q]) : 0.0;
+            const double es = wave_sum(err);
+            if (job.epi == EPI_SCALE && job.partial != nullptr && lane == 0)
+                job.partial[static_cast<size_t>(tile) * NT + ko] = es;
+            const double ws = wave_sum(work);
+            if (job.work != nullptr && lane == 0) atomicAdd(&job.work[2 * tile], ws);
+        }
+        if (job.fallbacks != nullptr && threadIdx.x == 0) atomicAdd(job.fallbacks, __popc(mask));
+    }
+}
+
+template <int NT, int KC>
+int launch_tiles_t(const ConvJob *d_jobs, int grid, int R_max, const int4 *items, const int *count, hipStream_t s) {
+    const int HW = kTile + 2 * R_max;
+    const size_t lds = static_cast<size_t>(HW) * HW * KC * sizeof(double);
+    if (lds > 65536)
+        SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_lse_tiles<NT, KC>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+    hipLaunchKernelGGL((k_lse_tiles<NT, KC>), dim3(grid), dim3(kConvThreads), lds, s, d_jobs, items, count);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
 template <int NT, int KC, bool F64EXP>
 int launch_dense_t(const ConvJob *d_jobs, int nblocks, const int32_t *d_block_job, int R_max, hipStream_t s) {
     const int HW = kTile + 2 * R_max;
@@ -792,6 +839,24 @@ int launch_sparse_t(const ConvJob *d_jobs, int nblocks, const int32_t *d_block_j
 }
 
 }  // namespace
+
+int launch_lse_tiles(const ConvJob *d_jobs, int grid, int nt, int R_max, const int4 *items, const int *count,
+                     hipStream_t s) {
+    if (grid <= 0) return SE2_OK;
+    if (R_max < 0 || R_max > kMaxRadius || !items || !count) return SE2_EINVAL;
+    // the largest chunk of input orientations whose FP64 halo fits in 64 KiB (as k_conv_lse)
+    const bool kc16 = (kTile + 2 * R_max) * (kTile + 2 * R_max) * 16 * 8 <= 65536;
+    switch (nt) {
+        case 8: return launch_tiles_t<8, 8>(d_jobs, grid, R_max, items, count, s);
+        case 16:
+            return kc16 ? launch_tiles_t<16, 16>(d_jobs, grid, R_max, items, count, s)
+                        : launch_tiles_t<16, 8>(d_jobs, grid, R_max, items, count, s);
+        case 32:
+            return kc16 ? launch_tiles_t<32, 16>(d_jobs, grid, R_max, items, count, s)
+                        : launch_tiles_t<32, 8>(d_jobs, grid, R_max, items, count, s);
+        default: return SE2_EINVAL;
+    }
+}
 
 bool conv_lse_sparse_fits(int nt, int R) {
     const int HW = kTile + 2 * R;

@@ -384,8 +384,9 @@ void lane_main(se2_queue_s *Q, int l) {
             } else if (s.iter >= s.opts.max_iter) {
                 s.status = SE2_MAX_ITER;
                 finished.push_back(q);
-            } else if (s.kind == SE2_REQ_OT) {
-                s.cur ^= 1;
+            } else {
+                if (s.kind == SE2_REQ_OT) s.cur ^= 1;
+                phase_after_check(s, errs[i]);
             }
         }
         if (rc == SE2_OK) {
@@ -472,9 +473,7 @@ int se2_request_bytes(const se2_request_t *req, size_t *bytes) {
 int se2_solve_queue_submit(se2_queue_t Q, const se2_request_t *req, uint64_t *ticket) {
     if (!Q || !req || !ticket || !req->kernel) return SE2_EINVAL;
     const se2_opts_t &o = req->opts;
-    if (o.max_iter < 1 || o.check_every < 1 || std::isnan(o.tol_marg_l1) || std::isnan(o.eps_start) ||
-        (o.prec != SE2_F32 && o.prec != SE2_F64))
-        return SE2_EINVAL;
+    if (!valid_solver_opts(o, *reinterpret_cast<const Kernel *>(req->kernel))) return SE2_EINVAL;
     {
         // build the kernels of an eps-scaling schedule here, so admission only looks them up
         const Kernel &base = *reinterpret_cast<const Kernel *>(req->kernel);

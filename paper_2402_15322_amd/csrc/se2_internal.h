@@ -80,6 +80,11 @@ int launch_conv_lse(const ConvJob *d_jobs, int njobs, int nblocks, const int32_t
                     bool f64exp, bool sparse, int2 *rebuild, int *rebuild_count, int *next_count, int rb_waves,
                     int *published, hipStream_t s);
 bool conv_lse_sparse_fits(int nt, int R);
+// Exact log-domain recomputation of listed tiles (the fallback of the matrix-core engines):
+// item (job, 8 x 8 tile, mask of the orientations to recompute, unused); `count` (device)
+// holds the number of items, `grid` workgroups loop over them.
+int launch_lse_tiles(const ConvJob *d_jobs, int grid, int nt, int R_max, const int4 *items, const int *count,
+                     hipStream_t s);
 
 // launchers (conv_linear.hip)
 std::vector<uint16_t> pack_bf16_operand(const std::vector<uint16_t> &Kb, int nt, int R);
@@ -88,6 +93,18 @@ size_t conv_bf16_lds_bytes(int nt, int R);
 int launch_conv_bf16(const Kernel &k, const float *in, float *out, int batch, hipStream_t s);
 int launch_conv_f32(const Kernel &k, const float *in, float *out, int batch, hipStream_t s);
 int launch_conv_f64(const Kernel &k, const double *in, double *out, int batch, hipStream_t s);
+// Certified linear-domain log convolutions on the matrix cores (the solver's BF16 and FP32
+// engines): jobs of one ntheta and window radius R, `rpw` output rows per wave (4 or 8, a
+// function of the job's own grid, so that a job's tiles and results do not depend on what
+// else is in the launch), workgroups of lin_blocks() per job.  The 8 x 8 tiles with groups
+// (tile, ko) whose certificate fails are listed in fb (capacity: the jobs' tiles) with the
+// count in *fb_count and recomputed exactly by fb_grid workgroups right after; *fb_next (the
+// other of two counters) is zeroed for the following launch.  FP32 needs nt = 16 or 32.
+bool lin_supported(int nt, bool bf16);
+int lin_rows_per_wave(int nt, bool bf16, int ny);
+int lin_blocks(int nx, int ny, int rpw);
+int launch_conv_lin_log(const ConvJob *d_jobs, int nblocks, const int32_t *d_block_job, int nt, int R, int rpw,
+                        bool bf16, int4 *fb, int *fb_count, int *fb_next, int fb_grid, hipStream_t s);
 
 // elementwise.hip
 int launch_scale(const double *in, double *out, size_t n, double mul, hipStream_t s);

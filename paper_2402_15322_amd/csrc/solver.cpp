@@ -110,6 +110,7 @@ size_t carve(Solve &s, int kind, const Kernel &k, int n, bool prune, void *mem) 
     s.partial = c.take<double>(npart > ncost ? npart : ncost);
     s.err = c.take<double>(3 * static_cast<size_t>(nj) + 8);
     s.offsets = c.take<int32_t>(static_cast<size_t>(nj) + 1);
+    s.fb_count = c.take<int32_t>(static_cast<size_t>(nj));
     return c.used;
 }
 
@@ -154,6 +155,12 @@ int reset_list(const ListSet &l, const Solve &s, hipStream_t st) {
 
 int solve_reset_lists(Solve &s, hipStream_t st) {
     int rc = SE2_OK;
+    s.phase = 0;
+    s.phase_switch_iter = -1;
+    s.prev_err = -1.0;
+    s.terms_linear = 0.0;
+    if (s.fb_count && (rc = launch_fill_i32(s.fb_count, ot_like(s) ? 1 : static_cast<size_t>(s.n), 0, st)))
+        return rc;
     if (ot_like(s)) {
         if ((rc = reset_list(s.ls_phi, s, st))) return rc;
         return reset_list(s.ls_psi, s, st);
@@ -218,9 +225,47 @@ int advance_stages(Engine &eng, const std::vector<Solve *> &solves, hipStream_t 
         s->stage += 1;
         s->k = s->stage_k[s->stage];
         s->scaling_iters = s->iter;
+        s->prev_err = -1.0;
         moved.push_back(s);
     }
     return moved.empty() ? SE2_OK : eng.init_first_halfstep(moved, st);
+}
+
+namespace {
+bool valid_engine(int prec, const Kernel &k) {
+    switch (prec) {
+        case SE2_F32:
+        case SE2_F64:
+            return true;
+        case SE2_BF16:
+            return lin_supported(k.grid.ntheta, true);
+        case SE2_F32_MFMA:
+            return lin_supported(k.grid.ntheta, false) && k.d_Fpack != nullptr;
+        default:
+            return false;
+    }
+}
+}  // namespace
+
+bool valid_solver_opts(const se2_opts_t &o, const Kernel &k) {
+    if (!(o.max_iter >= 1 && o.check_every >= 1 && !std::isnan(o.tol_marg_l1) && !std::isnan(o.eps_start)))
+        return false;
+    if (!valid_engine(o.prec, k)) return false;
+    if (o.polish != 0 && o.polish != 1) return false;
+    if (o.polish && (!valid_engine(o.bulk, k) || std::isnan(o.switch_tol))) return false;
+    std::vector<double> sched;
+    return eps_schedule(o, k.metric.eps, sched) == SE2_OK;
+}
+
+void phase_after_check(Solve &s, double err) {
+    if (s.opts.polish && s.phase == 0 && final_stage(s)) {
+        const bool stalled = s.prev_err >= 0.0 && !(err < s.prev_err);
+        if (err <= s.opts.switch_tol || stalled) {
+            s.phase = 1;
+            s.phase_switch_iter = s.iter;
+        }
+    }
+    s.prev_err = err;
 }
 
 int solve_setup_ot(Solve &s, const double *mu, const double *nu, const double *init_g, hipStream_t st) {
@@ -326,6 +371,8 @@ int Engine::collect_profile() {
 }
 
 Engine::~Engine() {
+    if (d_fb_) (void)hipFree(d_fb_);
+    if (d_fb_count_) (void)hipFree(d_fb_count_);
     if (d_rebuild_) (void)hipFree(d_rebuild_);
     if (d_rebuild_count_) (void)hipFree(d_rebuild_count_);
     for (Pending &p : pending_) {
@@ -371,8 +418,10 @@ int Engine::ensure(size_t njobs, size_t nblocks) {
     return SE2_OK;
 }
 
-int Engine::stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, int R_max, bool sparse, bool f64,
+int Engine::stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, int R_max, LaunchKind kind, int rpw,
                              hipStream_t st) {
+    const bool sparse = kind == LK_SPARSE, f64 = kind == LK_F64;
+    const bool lin = kind == LK_LIN_BF16 || kind == LK_LIN_F32;
     const size_t nj = jobs.size();
     TableSlot *t = nullptr;
     for (TableSlot &c : tables_)
@@ -404,7 +453,7 @@ int Engine::stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, in
         int32_t *hm = h_map_ + h * cap_blocks_;
         std::memcpy(hj, jobs.data(), nj * sizeof(ConvJob));
         for (size_t q = 0; q < nj; ++q)
-            for (int b = 0; b < jobs[q].tiles; ++b) hm[jobs[q].first_block + b] = static_cast<int32_t>(q);
+            for (int b = 0; b < jobs[q].blocks; ++b) hm[jobs[q].first_block + b] = static_cast<int32_t>(q);
         SE2_HIP(hipMemcpyAsync(t->d_jobs, hj, nj * sizeof(ConvJob), hipMemcpyHostToDevice, st));
         SE2_HIP(hipMemcpyAsync(t->d_map, hm, static_cast<size_t>(nblocks) * sizeof(int32_t), hipMemcpyHostToDevice,
                                st));
@@ -431,8 +480,27 @@ int Engine::stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, in
         cap_rebuild_ = static_cast<size_t>(nblocks) * 2;
         SE2_HIP(hipMalloc(&d_rebuild_, cap_rebuild_ * sizeof(int2)));
     }
+    size_t cap_tiles = 0;  // 8 x 8 tiles of a matrix-core launch: the capacity of its fallback list
+    if (lin)
+        for (const ConvJob &j : jobs) cap_tiles += static_cast<size_t>(j.tiles);
+    if (lin && cap_tiles > cap_fb_) {
+        SE2_HIP(hipStreamSynchronize(st));  // earlier launches that used the old list are done
+        if (d_fb_) SE2_HIP(hipFree(d_fb_));
+        if (!d_fb_count_) {
+            SE2_HIP(hipMalloc(&d_fb_count_, 2 * sizeof(int)));
+            SE2_HIP(hipMemsetAsync(d_fb_count_, 0, 2 * sizeof(int), st));
+        }
+        cap_fb_ = cap_tiles * 2;
+        SE2_HIP(hipMalloc(&d_fb_, cap_fb_ * sizeof(int4)));
+    }
     int rc;
-    if (!sparse) {
+    if (lin) {
+        int *cnt = d_fb_count_ + fb_flip_, *next = d_fb_count_ + (1 - fb_flip_);
+        fb_flip_ ^= 1;
+        const int fb_grid = cap_tiles < 1024 ? static_cast<int>(cap_tiles) : 1024;
+        rc = launch_conv_lin_log(t->d_jobs, nblocks, t->d_map, nt, R_max, rpw, kind == LK_LIN_BF16, d_fb_, cnt, next,
+                                 fb_grid, st);
+    } else if (!sparse) {
         rc = launch_conv_lse(t->d_jobs, static_cast<int>(nj), nblocks, t->d_map, nt, R_max, f64, false, nullptr, nullptr,
                              nullptr, 8, nullptr, st);
     } else {
@@ -453,17 +521,21 @@ int Engine::stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, in
 
 int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool with_err, hipStream_t st) {
     // group jobs by ntheta (the kernels are specialised on it) and by engine: dense FP32,
-    // pruned (certified sparse kernel and its rebuild), dense FP64
+    // pruned (certified sparse kernel and its rebuild), dense FP64, and the matrix-core engines
+    // (bfloat16 or FP32 operands, per window radius)
     static const int kClasses[3] = {8, 16, 32};
     for (int nt : kClasses) {
         std::vector<ConvJob> jobs[3];
         int nblocks[3] = {0, 0, 0};
         int R_max = 0;
         bool present = false;
+        // matrix-core jobs, by (bfloat16?, rows per wave, window radius): their tiling is specialised on all three
+        std::vector<std::pair<std::pair<int, int>, std::vector<ConvJob>>> lin;
         for (Solve *s : solves) {
             if (s->k->grid.ntheta != nt) continue;
             present = true;
             const Kernel &k = *s->k;
+            const int ep = engine_prec(*s);
             ConvJob base{};
             base.L64 = k.d_L64;
             base.L32 = k.d_L32;
@@ -473,7 +545,6 @@ int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool wit
             base.tiles_x = tiles_of(k.grid.nx);
             base.tiles = s->tiles;
             base.lmax = kListMax;
-            if (base.R > R_max) R_max = base.R;
             auto attach = [&](ConvJob &j, const ListSet &l) {
                 j.lists = l.lists;
                 j.ref = l.ref;
@@ -482,15 +553,37 @@ int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool wit
                 j.dense_flag = l.dense_flag;
                 j.work = l.work;
             };
-            const bool f64 = s->opts.prec == SE2_F64;
+            const bool f64 = ep == SE2_F64;
+            const bool is_lin = linear_engine(ep);
             auto push = [&](ConvJob &j) {
+                if (is_lin) {
+                    // the whole window on the matrix cores: no lists; the exact recomputation of
+                    // rejected groups adds to the dense work counter and to the solve's fallbacks
+                    j.lists = nullptr;
+                    j.ref = nullptr;
+                    j.len = nullptr;
+                    j.mref = nullptr;
+                    j.kop = ep == SE2_BF16 ? static_cast<const void *>(k.d_Bpack) : static_cast<const void *>(k.d_Fpack);
+                    // key: (bfloat16?, radius, rows per wave)
+                    const int rpw = lin_rows_per_wave(nt, ep == SE2_BF16, k.grid.ny);
+                    const std::pair<int, int> key((ep == SE2_BF16 ? 1 : 0) + 2 * rpw, k.metric.radius);
+                    size_t g = 0;
+                    while (g < lin.size() && lin[g].first != key) ++g;
+                    if (g == lin.size()) lin.emplace_back(key, std::vector<ConvJob>());
+                    lin[g].second.push_back(j);
+                    s->terms_linear += conv_terms(k);
+                    return;
+                }
                 const int g = f64 ? 2 : (j.lists != nullptr ? 1 : 0);
+                if (j.R > R_max) R_max = j.R;
                 j.first_block = nblocks[g];
+                j.blocks = j.tiles;
                 nblocks[g] += j.tiles;
                 jobs[g].push_back(j);
             };
             if (ot_like(*s)) {
                 ConvJob j = base;
+                j.fallbacks = s->fb_count;
                 if (stage == 0 && s->kind == kKindJKO) {  // JKO: lsum = LSE(L + phi[cur]); the prox follows
                     j.in = s->phi[s->cur];
                     j.out = s->lsum;
@@ -517,6 +610,7 @@ int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool wit
             } else {
                 for (int i = 0; i < s->n; ++i) {
                     ConvJob j = base;
+                    j.fallbacks = s->fb_count + i;
                     if (stage == 0) {  // d-update: ld_i = lv_i + LSE(L + lw_i)
                         j.in = s->lw[i];
                         j.out = s->ld[i];
@@ -561,7 +655,22 @@ int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool wit
         }
         for (int g = 0; g < 3; ++g) {
             if (jobs[g].empty()) continue;
-            const int rc = stage_and_launch(jobs[g], nblocks[g], nt, R_max, g == 1, g == 2, st);
+            const LaunchKind kind = g == 1 ? LK_SPARSE : (g == 2 ? LK_F64 : LK_DENSE);
+            const int rc = stage_and_launch(jobs[g], nblocks[g], nt, R_max, kind, 0, st);
+            if (rc) return rc;
+        }
+        for (auto &grp : lin) {
+            const bool bf16 = (grp.first.first & 1) != 0;
+            const int rpw = grp.first.first >> 1;
+            const int R = grp.first.second;
+            std::vector<ConvJob> &js = grp.second;
+            int nb = 0;
+            for (ConvJob &j : js) {
+                j.first_block = nb;
+                j.blocks = lin_blocks(j.nx, j.ny, rpw);
+                nb += j.blocks;
+            }
+            const int rc = stage_and_launch(js, nb, nt, R, bf16 ? LK_LIN_BF16 : LK_LIN_F32, rpw, st);
             if (rc) return rc;
         }
         if (prof_) {
@@ -727,12 +836,13 @@ int Engine::launch_checks(const std::vector<ConvJob> &jobs, const std::vector<in
             if (nts[q] != nt) continue;
             ConvJob j = jobs[q];
             j.first_block = nblocks;
+            j.blocks = j.tiles;
             nblocks += j.tiles;
             if (j.R > R_max) R_max = j.R;
             group.push_back(j);
         }
         if (group.empty()) continue;
-        const int rc = stage_and_launch(group, nblocks, nt, R_max, false, true, st);
+        const int rc = stage_and_launch(group, nblocks, nt, R_max, LK_F64, 0, st);
         if (rc) return rc;
     }
     return SE2_OK;
@@ -835,6 +945,13 @@ int finish_solves(Engine &eng, std::vector<FinishReq> &reqs, hipStream_t st) {
         r.marg_l1_f64 = -1.0;
         r.convs = s.convs;
         r.scaling_iters = s.scaling_iters;
+        r.phase_switch_iter = s.phase_switch_iter;
+        r.terms_linear = s.terms_linear;
+        {
+            std::vector<int32_t> fb(static_cast<size_t>(nj));
+            SE2_HIP(hipMemcpy(fb.data(), s.fb_count, fb.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+            for (int32_t v : fb) r.fallbacks += v;
+        }
         if (s.kind == kKindJKO) {
             r.cost = e[2];
             r.mass = e[3];

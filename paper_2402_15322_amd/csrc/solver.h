@@ -64,6 +64,13 @@ struct Solve {
     std::vector<const Kernel *> stage_k;
     int stage = 0;
     int scaling_iters = 0;           // iterations run before the last stage began
+    // phases: a solve with opts.polish runs its bulk engine (opts.bulk) over the coarse eps
+    // stages and at the final eps until phase_after_check() moves it to opts.prec
+    int phase = 0;                   // 0: bulk, 1: polish
+    int phase_switch_iter = -1;      // iteration at which the polish phase began
+    double prev_err = -1.0;          // error of the previous check of the current stage
+    int32_t *fb_count = nullptr;     // per job (measure): groups recomputed after a failed certificate
+    double terms_linear = 0.0;       // window terms evaluated by the matrix-core engines
     // memory
     void *block = nullptr;           // single allocation holding every buffer
     size_t bytes = 0;
@@ -78,9 +85,19 @@ double conv_terms(const Kernel &k);
 
 // Bytes one solve needs on the device (for admission against a budget).
 size_t solve_bytes(int kind, const Kernel &k, int n_active, bool prune);
-// Pruning applies to the FP32 engine only (the FP64 engine always visits every term).
-inline bool prune_wanted(const se2_opts_t &o) { return o.prune != 0 && o.prec != SE2_F64; }
+// Pruning applies to the exact FP32 engine only (the FP64 engine always visits every term,
+// the matrix-core engines evaluate the whole window on the matrix cores).
+inline bool prune_wanted(const se2_opts_t &o) { return o.prune != 0 && o.prec == SE2_F32; }
 bool prune_enabled(const Solve &s);
+// The engine a solve runs now: its bulk engine during the bulk phase, else opts.prec.
+inline int engine_prec(const Solve &s) { return (s.opts.polish && s.phase == 0) ? s.opts.bulk : s.opts.prec; }
+inline bool linear_engine(int prec) { return prec == SE2_BF16 || prec == SE2_F32_MFMA; }
+// Options a solver accepts for this kernel (engines, phases, iteration limits, eps schedule).
+bool valid_solver_opts(const se2_opts_t &o, const Kernel &k);
+// Phase control after a check of a solve that goes on (error err): at its final eps stage a
+// solve in its bulk phase moves to the polish engine once err <= opts.switch_tol or the error
+// did not fall since the stage's previous check.
+void phase_after_check(Solve &s, double err);
 
 // Carve the buffers of `s` out of `mem` (size solve_bytes()).
 void solve_bind(Solve &s, void *mem);
@@ -102,8 +119,13 @@ int eps_schedule(const se2_opts_t &o, double eps, std::vector<double> &out);
 int plan_stages(Solve &s, const Kernel &base);
 inline bool final_stage(const Solve &s) { return s.stage + 1 >= static_cast<int>(s.stage_k.size()); }
 
+// Kinds of batched convolution launches: the exact log-domain engine (dense visits, or
+// certified sparse visits with their rebuilds), its FP64 form, and the certified linear-domain
+// engines on the matrix cores (bfloat16 or FP32 operands) with their exact recomputation.
+enum LaunchKind { LK_DENSE = 0, LK_SPARSE = 1, LK_F64 = 2, LK_LIN_BF16 = 3, LK_LIN_F32 = 4 };
+
 // Advances a set of solves (same ntheta or not) by one iteration each, with batched
-// launches: one launch per (stage, ntheta class).  If `check` is true, also reduces
+// launches: one launch per (stage, ntheta class, engine).  If `check` is true, also reduces
 // each solve's marginal error into its device `err` slot.
 class Engine {
 public:
@@ -136,7 +158,7 @@ public:
 
 private:
     int launch_stage(const std::vector<Solve *> &solves, int stage, bool with_err, hipStream_t st);
-    int stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, int R_max, bool sparse, bool f64,
+    int stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, int R_max, LaunchKind kind, int rpw,
                          hipStream_t st);
     int ensure(size_t njobs, size_t nblocks);
     // Device copies of job tables and block maps, kept while their content recurs (a
@@ -158,6 +180,10 @@ private:
     int *h_published_ = nullptr;      // pinned: rebuild items of the last launch per ntheta class
     int *d_published_ = nullptr;      // the same memory as the kernels address it
     bool wide_rebuild_ = true;
+    int4 *d_fb_ = nullptr;           // tiles left to the exact recomputation by matrix-core launches
+    size_t cap_fb_ = 0;
+    int *d_fb_count_ = nullptr;      // two counters used alternately (each launch zeroes the other)
+    int fb_flip_ = 0;
     int rc_flip_ = 0;
     size_t cap_rebuild_ = 0;
     ConvJob *h_jobs_ = nullptr;      // pinned staging (double-buffered)

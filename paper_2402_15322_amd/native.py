@@ -23,7 +23,7 @@ SE2_ENUMERIC = -4
 SE2_PENDING = 1
 SE2_CONVERGED = 0
 SE2_MAX_ITER = 1
-SE2_BF16, SE2_F32, SE2_F64 = 0, 1, 2
+SE2_BF16, SE2_F32, SE2_F64, SE2_F32_MFMA = 0, 1, 2, 3
 SE2_REQ_OT, SE2_REQ_BARYCENTER = 0, 1
 
 EXPORTED = [
@@ -51,14 +51,16 @@ class Opts(ctypes.Structure):
     _fields_ = [("tol_marg_l1", ctypes.c_double), ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("final_check", ctypes.c_int32), ("prune", ctypes.c_int32),
                 ("init_g", ctypes.c_void_p), ("eps_start", ctypes.c_double), ("eps_factor", ctypes.c_double),
-                ("stage_iters", ctypes.c_int32)]
+                ("stage_iters", ctypes.c_int32), ("bulk", ctypes.c_int32), ("polish", ctypes.c_int32),
+                ("switch_tol", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("marg_l1", ctypes.c_double),
                 ("marg_l1_f64", ctypes.c_double), ("cost", ctypes.c_double), ("mass", ctypes.c_double),
                 ("dual", ctypes.c_double), ("seconds", ctypes.c_double), ("terms_dense", ctypes.c_double),
-                ("terms_sparse", ctypes.c_double), ("convs", ctypes.c_int32), ("scaling_iters", ctypes.c_int32)]
+                ("terms_sparse", ctypes.c_double), ("convs", ctypes.c_int32), ("scaling_iters", ctypes.c_int32),
+                ("fallbacks", ctypes.c_int32), ("phase_switch_iter", ctypes.c_int32), ("terms_linear", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -100,7 +102,7 @@ def load() -> ctypes.CDLL:
             "se2_kernel_table": ([vp, vp, vp], ctypes.c_int),
             "se2_kernel_info": ([vp, ctypes.POINTER(Grid), ctypes.POINTER(Metric), ctypes.POINTER(i32)], ctypes.c_int),
             "se2_conv": ([vp, ctypes.c_int, vp, vp, i32, vp], ctypes.c_int),
-            "se2_conv_log": ([vp, ctypes.c_int, vp, vp, i32, vp], ctypes.c_int),
+            "se2_conv_log": ([vp, ctypes.c_int, vp, vp, i32, ctypes.POINTER(i32), vp], ctypes.c_int),
             "se2_lift_field": ([ctypes.POINTER(Grid), vp, vp, vp, i32, vp], ctypes.c_int),
             "se2_project": ([ctypes.POINTER(Grid), vp, vp, vp, vp, vp, i32, vp], ctypes.c_int),
             "se2_split_signed": ([vp, sz, vp, vp, vp], ctypes.c_int),
@@ -162,10 +164,13 @@ def _stream(stream) -> Optional[int]:
 
 def opts(tol: float = 1e-6, max_iter: int = 1000, check_every: int = 10, prec: int = SE2_F32,
          final_check: bool = True, prune: bool = True, init_g=None, eps_start: float = 0.0,
-         eps_factor: float = 0.5, stage_iters: int = 0) -> Opts:
-    """se2_opts_t; eps_start > eps turns on eps-scaling (stage_iters iterations per coarser eps)."""
+         eps_factor: float = 0.5, stage_iters: int = 0, bulk: Optional[int] = None,
+         switch_tol: float = 1e-3) -> Opts:
+    """se2_opts_t; eps_start > eps turns on eps-scaling (stage_iters iterations per coarser eps);
+    bulk (an engine) turns on a bulk phase on that engine before `prec` (switch at switch_tol)."""
     return Opts(tol, max_iter, check_every, prec, int(final_check), int(prune), _ptr(init_g), float(eps_start),
-                float(eps_factor), int(stage_iters))
+                float(eps_factor), int(stage_iters), int(bulk) if bulk is not None else 0,
+                1 if bulk is not None else 0, float(switch_tol))
 
 
 def se2_init() -> None:
@@ -212,9 +217,13 @@ def se2_conv(k: Kernel, prec: int, x, out, stream=None) -> None:
     _check(load().se2_conv(k.handle, prec, _ptr(x), _ptr(out), batch, _stream(stream)), "se2_conv")
 
 
-def se2_conv_log(k: Kernel, prec: int, x, out, stream=None) -> None:
+def se2_conv_log(k: Kernel, prec: int, x, out, stream=None) -> int:
+    """out = log(K * exp(x)); returns the groups recomputed in the log domain (matrix-core precisions)."""
     batch = x.numel() // (k.shape[0] * k.shape[1] * k.shape[2])
-    _check(load().se2_conv_log(k.handle, prec, _ptr(x), _ptr(out), batch, _stream(stream)), "se2_conv_log")
+    fb = ctypes.c_int32(0)
+    _check(load().se2_conv_log(k.handle, prec, _ptr(x), _ptr(out), batch, ctypes.byref(fb), _stream(stream)),
+           "se2_conv_log")
+    return fb.value
 
 
 def _grid(nx: int, ny: int, nt: int, axial: bool) -> Grid:

@@ -306,6 +306,34 @@ def lines64(instance: int = 0, paired: bool = True, n: int = 64) -> OTInstance:
     return OTInstance(g, (1.0, 3.0, 1.0), 0.1, 5, mu, nu, f"lines{n}x{n}x16-{tag}/{instance}")
 
 
+# The converging 64x64x16 instance.  With 1-px strokes the lines64 pairs (and even nu = mu)
+# keep a marginal error near 1.5e-6 for thousands of iterations: at eps = 0.1 a neighbouring
+# pixel is reached with weight e^-10 at best, so the mass balance between neighbours relaxes
+# on a time scale of ~10^4 iterations, with an amplitude set by the steepness of the strokes.
+# Strokes three times as wide (sigma_xy = 3 px) bring that plateau to 4e-7 (median; 6e-7 at
+# most over 32 instances after 3000 iterations).
+THETA_TURN = math.pi / 16
+THETA_SIGMA_XY = 3.0
+
+
+def lines64_theta(instance: int = 0, n: int = 64) -> OTInstance:
+    """n x n x 16, w=(1,3,1), eps=0.1, 11x11 window, 8 segments of 10-40 px splatted with
+    sigma_xy = 3 px, floor 1e-6.  nu has the same stroke points as mu, each segment's orientation
+    turned by a seeded angle in U[-pi/16, pi/16] (a motion along theta only, which the SE(2)
+    cost prices at w3^2 dtheta^2)."""
+    g = Grid(n, n, 16)
+    seed = 1 * 1000 + 500 + instance
+    scale = n / 64.0
+    segs = draw_segments(rng_for(seed, 0), g, 8, 10.0 * scale, 40.0 * scale, PAIRED_MARGIN)
+    px, py, ang, w = segment_points(segs)
+    mu = normalise(splat_points(g, px, py, np.mod(ang, g.period), w, THETA_SIGMA_XY), 1e-6)
+    r1 = rng_for(seed, 1)
+    turns = np.concatenate([np.full(max(1, int(math.floor(s.length / 0.25)) + 1), r1.uniform(-THETA_TURN, THETA_TURN))
+                            for s in segs])
+    nu = normalise(splat_points(g, px, py, np.mod(ang + turns, g.period), w, THETA_SIGMA_XY), 1e-6)
+    return OTInstance(g, (1.0, 3.0, 1.0), 0.1, 5, mu, nu, f"lines{n}x{n}x16-theta/{instance}")
+
+
 # Measures without a floor still get POSITIVE_FLOOR per element (about 2^-997, far
 # below any mass that matters): where one measure is exactly zero over a whole window,
 # the barycenter is zero there and mass of another measure has no partner inside the

@@ -1,0 +1,267 @@
+"""The certified matrix-core engines (SE2_BF16 and SE2_F32_MFMA) of the log-domain
+convolution and of the solvers, against the FP64 oracle.
+
+Each workgroup shifts its input halo by its maximum M, contracts 2^(in - M) with the kernel
+on the matrix cores and takes M + log S; an output whose S is below 2^-87 has its (8 x 8
+tile, orientation) group recomputed exactly.  Bounds on the natural log of K * exp(in), per
+output, derived from the arithmetic (-ln(1 - rel)):
+  * bfloat16 operands: rel = 2u + u^2 + 2^-21 + gamma_n + 2^-24, u = 2^-8 (RNE of V and of K),
+    2^-21 the exp2 of V before its rounding, gamma_n = n 2^-24 / (1 - n 2^-24) the FP32
+    accumulation over the n = (2R+1)^2 ntheta window terms, 2^-24 the underflowed terms that
+    the certificate admits;
+  * FP32 operands: rel = 2^-24 (K) + 2^-22 (exp2 of V) + 2^-23 (its FP32 correction) +
+    gamma_128 (an FP32 sum runs over one step, at most 128 products, the steps added in FP64)
+    + 2^-24;
+  * recomputed groups have the exact engine's error (2e-6), below both.
+Solvers: at equal iterations the FP32 engine meets the exact engine's bar (plan L1 <= 1e-5,
+marginal L1 within 1e-6, cost within 1e-6 relative).  A bfloat16 bulk phase followed by the
+FP32 polish, run to convergence, matches the oracle's converged solve (both at marginal
+L1 <= 8e-7): FP64 marginal check <= 1e-6, plan L1 <= 1e-5, relative cost <= 1e-3 (the stated
+targets).  The serving queue gives the same bits alone and mixed.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import to_dev, to_host, torch_dev
+from paper_2402_15322_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nat():
+    torch_dev()
+    from paper_2402_15322_amd import native
+    native.se2_init()
+    return native
+
+
+def _bound(nat, prec, W, nt):
+    if prec == nat.SE2_BF16:
+        u, n = 2.0 ** -8, W * W * nt
+        rel = 2 * u + u * u + 2.0 ** -21 + n * 2.0 ** -24 / (1 - n * 2.0 ** -24) + 2.0 ** -24
+    else:
+        rel = 2.0 ** -24 + 2.0 ** -22 + 2.0 ** -23 + 128 * 2.0 ** -24 / (1 - 128 * 2.0 ** -24) + 2.0 ** -24
+    return -math.log1p(-rel)
+
+
+CASES = [
+    # nx, ny, nt, axial, w, eps, R, batch
+    (16, 16, 8, False, (1.0, 2.0, 1.0), 0.5, 4, 2),
+    (13, 9, 16, False, (1.0, 3.0, 1.0), 0.8, 3, 2),
+    (37, 21, 16, False, (1.0, 3.0, 1.0), 0.1, 5, 1),
+    (20, 7, 32, True, (1.0, 4.0, 1.0), 0.3, 2, 2),
+    (33, 40, 32, True, (1.0, 4.0, 1.0), 0.03, 10, 1),
+    (23, 50, 16, False, (1.0, 3.0, 1.0), 0.05, 7, 1),
+    (40, 130, 16, False, (1.0, 2.0, 1.0), 0.3, 2, 3),   # 8 rows per wave (ny >= 128), ragged tiles
+    (30, 28, 16, False, (1.0, 3.0, 1.0), 0.5, 12, 1),   # the largest window
+]
+
+
+def _inputs(kind, shape, nt, rng):
+    B, ny, nx = shape
+    yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    base = (12 * np.sin(2 * np.pi * xx / 17.0)[..., None] + 10 * np.cos(2 * np.pi * yy / 23.0)[..., None]
+            + 3 * np.cos(np.arange(nt) * 2 * np.pi / nt)[None, None, :])
+    x = np.stack([base + rng.normal(0.0, 1.0, (ny, nx, nt)) for _ in range(B)])
+    if kind == "rough":      # the spread of converged potentials at small eps: every group falls back
+        x = rng.normal(0.0, 300.0, (B, ny, nx, nt))
+    if kind == "spike":      # one pixel far above the rest: only the tiles whose halo holds it fall back
+        x[:, ny // 3, nx // 2, :] += 150.0
+    x[:, :2, :3, 1] = -np.inf    # zero mass
+    return x
+
+
+@pytest.mark.parametrize("kind", ["smooth", "rough", "spike"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}{'a' if c[3] else ''}r{c[6]}b{c[7]}")
+def test_conv_log_matrix_cores(nat, case, kind):
+    torch = torch_dev()
+    nx, ny, nt, axial, w, eps, R, B = case
+    k = nat.Kernel(nx, ny, nt, axial, w, eps, R)
+    logk, _ = oracle.kernel_table(nt, axial, w, eps, R)
+    x = _inputs(kind, (B, ny, nx), nt, np.random.default_rng(31 * nx + ny))
+    ref = np.stack([oracle.conv_log(logk, x[b]) for b in range(B)])
+    fin = np.isfinite(ref)
+    groups = B * ((nx + 7) // 8) * ((ny + 7) // 8) * nt
+    xd = to_dev(x)
+    for prec in (nat.SE2_BF16, nat.SE2_F32_MFMA):
+        if prec == nat.SE2_F32_MFMA and nt == 8:
+            continue
+        out = torch.full_like(xd, float("nan"))
+        fb = nat.se2_conv_log(k, prec, xd, out)
+        got = to_host(out)
+        assert np.array_equal(fin, np.isfinite(got)), prec
+        err = float(np.max(np.abs(got[fin] - ref[fin])))
+        assert err <= _bound(nat, prec, 2 * R + 1, nt), (prec, err)
+        if kind == "smooth":
+            assert fb == 0, (prec, fb)
+        elif kind == "rough":
+            assert fb == groups, (prec, fb, groups)
+        else:
+            assert 0 < fb <= groups, (prec, fb, groups)
+            # a tile of 16 x 32 outputs or less whose halo (R + 1 wide) misses the spike keeps its groups
+            sy, sx, reach = ny // 3, nx // 2, 32 + 2 * R + 2
+            if max(sx, nx - sx, sy, ny - sy) > reach:
+                assert fb < groups, (prec, fb, groups)
+
+
+def test_matrix_core_options_are_checked(nat):
+    torch = torch_dev()
+    k8 = nat.Kernel(16, 16, 8, False, (1.0, 2.0, 1.0), 0.5, 4)
+    x = torch.zeros((16, 16, 8), dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    with pytest.raises(nat.SE2Error):         # FP32 matrix cores need 16 or 32 orientations
+        nat.se2_conv_log(k8, nat.SE2_F32_MFMA, x, y)
+    mu = torch.full_like(x, 1.0 / x.numel())
+    with pytest.raises(nat.SE2Error):
+        nat.se2_sinkhorn(k8, mu, mu, nat.opts(prec=nat.SE2_F32_MFMA), y, y.clone())
+    with pytest.raises(nat.SE2Error):         # a bulk engine that the grid does not support
+        nat.se2_sinkhorn(k8, mu, mu, nat.opts(prec=nat.SE2_F32, bulk=nat.SE2_F32_MFMA), y, y.clone())
+    bad = nat.opts(prec=nat.SE2_F32)
+    bad.polish = 2
+    with pytest.raises(nat.SE2Error):
+        nat.se2_sinkhorn(k8, mu, mu, bad, y, y.clone())
+
+
+def _solve(nat, k, inst, o):
+    torch = torch_dev()
+    mu, nu = to_dev(inst.mu), to_dev(inst.nu)
+    f, g = torch.empty_like(mu), torch.empty_like(mu)
+    rep = nat.se2_sinkhorn(k, mu, nu, o, f, g)
+    return rep, to_host(f) / inst.eps, to_host(g) / inst.eps
+
+
+def test_fp32_matrix_core_sinkhorn_equal_iterations(nat):
+    """The 64 x 64 x 16 theta-motion instance, 30 iterations: every group is certified, so the
+    whole solve runs on the matrix cores."""
+    inst = synth.lines64_theta(0)
+    g = inst.grid
+    k = nat.Kernel(g.nx, g.ny, g.nt, False, inst.w, inst.eps, inst.radius)
+    logk, cost = oracle.kernel_table(g.nt, False, inst.w, inst.eps, inst.radius)
+    phi_o, psi_o, it, err_o, _ = oracle.sinkhorn(logk, inst.mu, inst.nu, 30, -1.0)
+    c_o = oracle.plan_stats(logk, cost, phi_o, psi_o)[0]
+    rep, phi, psi = _solve(nat, k, inst, nat.opts(tol=-1, max_iter=30, check_every=10, prec=nat.SE2_F32_MFMA))
+    assert rep["iters"] == it == 30
+    assert oracle.plan_l1(logk, phi, psi, phi_o, psi_o) <= 1e-5
+    assert abs(rep["marg_l1"] - err_o) <= 1e-6
+    assert abs(rep["cost"] - c_o) <= 1e-6 * c_o
+    assert rep["fallbacks"] == 0 and rep["terms_linear"] > 0 and rep["phase_switch_iter"] == -1
+
+
+def test_bf16_bulk_then_fp32_polish_converges_to_the_oracle(nat):
+    """32 x 32 x 16 theta-motion instance at eps = 0.1: bfloat16 bulk phase, then the FP32
+    matrix-core polish, to marginal L1 8e-7; the oracle's plain FP64 Sinkhorn to the same
+    tolerance.  The converged plan is unique, so the two must agree."""
+    inst = synth.lines64_theta(1, n=32)
+    g = inst.grid
+    k = nat.Kernel(g.nx, g.ny, g.nt, False, inst.w, inst.eps, inst.radius)
+    logk, cost = oracle.kernel_table(g.nt, False, inst.w, inst.eps, inst.radius)
+    o = nat.opts(tol=8e-7, max_iter=3000, check_every=10, prec=nat.SE2_F32_MFMA, bulk=nat.SE2_BF16, switch_tol=1e-3)
+    rep, phi, psi = _solve(nat, k, inst, o)
+    assert rep["status"] == nat.SE2_CONVERGED
+    assert 0 < rep["phase_switch_iter"] < rep["iters"]
+    assert rep["marg_l1_f64"] <= 1e-6
+    phi_o, psi_o, it_o, err_o, _ = oracle.sinkhorn(logk, inst.mu, inst.nu, 3000, 8e-7)
+    assert err_o <= 8e-7
+    c_o = oracle.plan_stats(logk, cost, phi_o, psi_o)[0]
+    assert oracle.plan_l1(logk, phi, psi, phi_o, psi_o) <= 1e-5
+    assert abs(rep["cost"] - c_o) <= 1e-3 * c_o
+    # both marginals of the returned plan, in FP64 by the oracle (the second is exact up to the
+    # FP32 engine's rounding of the last b-update)
+    m1, m2, _, _ = oracle.marginal_errors(logk, cost, phi, psi, inst.mu, inst.nu)
+    assert m1 <= 1e-6 and m2 <= 1e-6
+
+
+def test_fp32_matrix_core_barycenter_equal_iterations(nat):
+    """8 stroke images on 28 x 28 x 16 (the class-barycenter metric, eps = 0.5), 10 IBP
+    iterations: some groups fall back to the exact engine, the rest run on the matrix cores."""
+    torch = torch_dev()
+    imgs = synth.stroke_images(8, seed=6200)
+    w, eps, R = (1.0, 1.5, 1.0), 0.5, 4
+    k = nat.Kernel(28, 28, 16, False, w, eps, R)
+    logk, _ = oracle.kernel_table(16, False, w, eps, R)
+    lam = [1.0 / 8] * 8
+    bar_o, it_o, err_o, _ = oracle.ibp(logk, list(imgs), lam, 10, -1.0)
+    out = torch.empty((28, 28, 16), dtype=torch.float64, device="cuda")
+    rep = nat.se2_barycenter(k, [to_dev(m) for m in imgs], lam,
+                             nat.opts(tol=-1, max_iter=10, check_every=10, prec=nat.SE2_F32_MFMA), out)
+    assert rep["iters"] == it_o == 10
+    assert float(np.sum(np.abs(to_host(out) - bar_o))) <= 1e-5
+    assert abs(rep["marg_l1"] - err_o) <= 1e-6
+    assert 0 < rep["fallbacks"] < 2 * 8 * 10 * 16 * 16
+
+
+def test_fp32_matrix_core_jko_step(nat):
+    """One JKO step of the porous-medium flow (m = 5) on a 32 x 32 x 16 grid, 20 iterations."""
+    torch = torch_dev()
+    inst = synth.lines64_theta(2, n=32)
+    w, eps, R = (1.0, math.sqrt(10.0), math.sqrt(2.0)), 0.5, 5
+    k = nat.Kernel(32, 32, 16, False, w, eps, R)
+    logk, _ = oracle.kernel_table(16, False, w, eps, R)
+    ref, tau = 1.0 / inst.mu.size, 1e-4
+    mu_d = to_dev(inst.mu)
+    nxt = torch.empty_like(mu_d)
+    rep = nat.se2_jko_step(k, mu_d, tau, 5.0, ref, nat.opts(tol=-1, max_iter=20, check_every=10,
+                                                            prec=nat.SE2_F32_MFMA), nxt)
+    _, _, nu_o, it_o, err_o = oracle.jko_step(logk, inst.mu, tau, 5.0, eps, ref, 20, -1.0)
+    assert rep["iters"] == it_o == 20
+    assert float(np.sum(np.abs(to_host(nxt) - nu_o))) <= 1e-5
+    assert abs(rep["marg_l1"] - err_o) <= 1e-6
+
+
+def test_eps_scaling_bulk_stages_then_exact_polish(nat):
+    """eps-scaling 0.4, 0.2, then 0.1 on the 32 x 32 x 16 theta-motion instance with the coarse
+    stages and the start of the last one on bfloat16, then the exact FP32 engine: the solve
+    converges to the oracle's converged solve.  (A schedule from 0.8 plateaus near 1.1e-6 in
+    exact arithmetic too: the slow mode of this kernel keeps a larger amplitude.)"""
+    inst = synth.lines64_theta(1, n=32)
+    g = inst.grid
+    k = nat.Kernel(g.nx, g.ny, g.nt, False, inst.w, inst.eps, inst.radius)
+    logk, cost = oracle.kernel_table(g.nt, False, inst.w, inst.eps, inst.radius)
+    o = nat.opts(tol=8e-7, max_iter=3000, check_every=10, prec=nat.SE2_F32, bulk=nat.SE2_BF16, switch_tol=1e-3,
+                 eps_start=0.4, eps_factor=0.5, stage_iters=50)
+    rep, phi, psi = _solve(nat, k, inst, o)
+    assert rep["status"] == nat.SE2_CONVERGED and rep["scaling_iters"] == 100
+    assert rep["phase_switch_iter"] > rep["scaling_iters"]
+    assert rep["marg_l1_f64"] <= 1e-6
+    phi_o, psi_o, _, err_o, _ = oracle.sinkhorn(logk, inst.mu, inst.nu, 3000, 8e-7)
+    c_o = oracle.plan_stats(logk, cost, phi_o, psi_o)[0]
+    assert oracle.plan_l1(logk, phi, psi, phi_o, psi_o) <= 1e-5
+    assert abs(rep["cost"] - c_o) <= 1e-3 * c_o
+
+
+def test_queue_matrix_core_solves_alone_and_mixed_are_bitwise_identical(nat):
+    """Engines and tiling of a solve depend on its own grid and phase only: submitted alone or
+    together with exact-engine and other matrix-core solves, its potentials are the same bits."""
+    torch = torch_dev()
+    insts = [synth.lines64_theta(i, n=32) for i in range(3)]
+    g = insts[0].grid
+    k = nat.Kernel(g.nx, g.ny, g.nt, False, insts[0].w, insts[0].eps, insts[0].radius)
+    opts = [nat.opts(tol=1e-6, max_iter=200, check_every=10, prec=nat.SE2_F32_MFMA, bulk=nat.SE2_BF16),
+            nat.opts(tol=1e-6, max_iter=200, check_every=10, prec=nat.SE2_F32_MFMA),
+            nat.opts(tol=1e-6, max_iter=200, check_every=10, prec=nat.SE2_F32)]
+
+    def run(which):
+        q = nat.SolveQueue(hbm_budget_bytes=256 << 20, max_slots=8)
+        outs, tickets = [], []
+        for i in which:
+            mu, nu = to_dev(insts[i].mu), to_dev(insts[i].nu)
+            f, gg = torch.empty_like(mu), torch.empty_like(mu)
+            tickets.append(q.submit_ot(k, mu, nu, opts[i], f, gg))
+            outs.append((f, gg))
+        reps = [q.wait(t) for t in tickets]
+        q.close()
+        return [(to_host(f), to_host(gg)) for f, gg in outs], reps
+
+    mixed, reps_m = run([0, 1, 2])
+    for i in range(3):
+        alone, reps_a = run([i])
+        assert reps_a[0]["iters"] == reps_m[i]["iters"]
+        assert reps_a[0]["phase_switch_iter"] == reps_m[i]["phase_switch_iter"]
+        for a, b in zip(alone[0], mixed[i]):
+            assert np.array_equal(a.view(np.uint64), b.view(np.uint64)), i
