@@ -51,7 +51,7 @@ FP64_STATE_BYTES_PER_ELEMENT = 32
 # launch pairs of one bench step and divided by its 2004 half-steps;
 # profiles/conv_lse_traffic_lines64x64x16_batch32.md.  Reported only while the kernel's
 # sources (the kernel file and its shared header) are the ones measured.
-TRAFFIC = {"sources_sha256": "2d10804799e4366c9650178af1535d4c8e8f2b09577adf14d6f7b1cd8cf0cc1f", "bytes_per_launch": 151683658.6,
+TRAFFIC = {"sources_sha256": "74c8802dc78de24f381cf6464c9a73c4598e85f2d6b1c8e7a66170f4372ba19f", "bytes_per_launch": 151627398.9,
            "sources": ("paper_2402_15322_amd/csrc/conv_lse.hip", "paper_2402_15322_amd/csrc/conv_lse.h")}
 
 
@@ -127,6 +127,15 @@ def parse():
                     help="eps-scaling leg: first eps of the schedule (<= 0.1 skips the leg)")
     ap.add_argument("--eps-factor", type=float, default=0.5)
     ap.add_argument("--stage-iters", type=int, default=100)
+    ap.add_argument("--conv-batch", type=int, default=32,
+                    help="converged leg: theta-motion solves submitted together (0 skips the leg)")
+    ap.add_argument("--conv-max-iter", type=int, default=3000)
+    ap.add_argument("--conv-engines", default="f32,bf16>f32,f32_mfma,bf16>f32_mfma",
+                    help="converged leg: engines, comma separated (prec, or bulk>prec)")
+    ap.add_argument("--converged-only", action="store_true", help="only the converged leg (for profiling)")
+    ap.add_argument("--halo-spread", action="store_true",
+                    help="only the spread of the log-potentials over a tile's halo and the matrix-core engines' "
+                         "fallback shares, per workload and eps")
     return ap.parse_args()
 
 
@@ -212,45 +221,61 @@ def field_measurements(native, torch, reps: int):
     return out
 
 
-def class_barycenter(native, torch, images, iters: int):
+def class_barycenter(native, torch, images, iters: int, engines=("f32_mfma", "bf16")):
     """Barycenter of a whole class of small images (the paper's MNIST/QuickDraw setting:
     28 x 28 images, 16 orientations, spatial anisotropy 1.5, ~6000 images per class), here
     seeded stroke images: w = (1, 1.5, 1), eps = 0.5, 9 x 9 window, equal weights, IBP on the
     dense engine, through the queue with convolution timing on.  Run at `iters` and at
     2 * `iters` iterations: the difference is the steady-state cost of `iters` iterations
-    (admission, validation and finishing cancel)."""
+    (admission, validation and finishing cancel).  The same on the matrix-core engines, with
+    the share of (tile, orientation) groups they recomputed exactly."""
     n = images.shape[0]
     k = native.Kernel(28, 28, 16, False, (1.0, 1.5, 1.0), 0.5, 4)
     dev = torch.from_numpy(images).cuda()
     mus = [dev[i] for i in range(n)]
     out = torch.empty(images.shape[1:], dtype=torch.float64, device="cuda")
-    runs = []
-    for it in (iters, 2 * iters):
-        o = native.opts(tol=-1.0, max_iter=it, check_every=it, final_check=False, prune=False)
-        q = native.SolveQueue(hbm_budget_bytes=int(n) * (1 << 20) + (1 << 30), max_slots=1)
-        q.profile(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ticket = q.submit_barycenter(k, mus, [1.0 / n] * n, o, out)
-        rep = q.wait(ticket)
-        wall = time.perf_counter() - t0
-        kt = q.kernel_time()
-        q.close()
-        runs.append((wall, kt, rep))
-    (w1, k1, r1), (w2, k2, r2) = runs
+
+    def two_runs(o_of):
+        runs = []
+        for it in (iters, 2 * iters):
+            o = o_of(it)
+            q = native.SolveQueue(hbm_budget_bytes=int(n) * (1 << 20) + (1 << 30), max_slots=1)
+            q.profile(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ticket = q.submit_barycenter(k, mus, [1.0 / n] * n, o, out)
+            rep = q.wait(ticket)
+            wall = time.perf_counter() - t0
+            kt = q.kernel_time()
+            q.close()
+            runs.append((wall, kt, rep))
+        return runs
+
+    (w1, k1, r1), (w2, k2, r2) = two_runs(
+        lambda it: native.opts(tol=-1.0, max_iter=it, check_every=it, final_check=False, prune=False))
     per_iter = (w2 - w1) / iters
     conv_s = k2["seconds"] - k1["seconds"]
     terms = k2["terms"] - k1["terms"]
-    return {"workload": f"{n} stroke images 28x28x16, w=(1,1.5,1), eps=0.5, 9x9 window, equal weights",
-            "measures": n, "iters": [r1["iters"], r2["iters"]], "wall_s": [w1, w2],
-            "steady_ms_per_iter": per_iter * 1e3, "steady_iters_per_s": 1.0 / per_iter if per_iter > 0 else None,
-            "convs_per_s": 2.0 * n / per_iter if per_iter > 0 else None,
-            "conv_ms_per_iter": conv_s / iters * 1e3,
-            "avg_conv_launch_us": conv_s / max(1.0, k2["launches"] - k1["launches"]) * 1e6,
-            "lse_terms_per_s": terms / conv_s if conv_s > 0 else None,
-            "roofline": log_conv_roofline(conv_s, k2["launches"] - k1["launches"], k2["outputs"] - k1["outputs"],
-                                          terms, 0.0, "dense log-domain convolution (k_conv_lse)"),
-            "marg_l1": r2["marg_l1"], "mass": r2["mass"]}
+    res = {"workload": f"{n} stroke images 28x28x16, w=(1,1.5,1), eps=0.5, 9x9 window, equal weights",
+           "measures": n, "iters": [r1["iters"], r2["iters"]], "wall_s": [w1, w2],
+           "steady_ms_per_iter": per_iter * 1e3, "steady_iters_per_s": 1.0 / per_iter if per_iter > 0 else None,
+           "convs_per_s": 2.0 * n / per_iter if per_iter > 0 else None,
+           "conv_ms_per_iter": conv_s / iters * 1e3,
+           "avg_conv_launch_us": conv_s / max(1.0, k2["launches"] - k1["launches"]) * 1e6,
+           "lse_terms_per_s": terms / conv_s if conv_s > 0 else None,
+           "roofline": log_conv_roofline(conv_s, k2["launches"] - k1["launches"], k2["outputs"] - k1["outputs"],
+                                         terms, 0.0, "dense log-domain convolution (k_conv_lse)"),
+           "marg_l1": r2["marg_l1"], "mass": r2["mass"], "matrix_core_engines": {}}
+    groups_per_iter = 2.0 * n * 16 * (28 // 8 + 1) ** 2
+    for name in engines:
+        (v1, q1, s1), (v2, q2, s2) = two_runs(
+            lambda it: engine_opts(native, name, tol=-1.0, max_iter=it, check_every=it, final_check=False))
+        pi = (v2 - v1) / iters
+        res["matrix_core_engines"][name] = {
+            "steady_ms_per_iter": pi * 1e3, "conv_ms_per_iter": (q2["seconds"] - q1["seconds"]) / iters * 1e3,
+            "fallback_group_share": (s2["fallbacks"] - s1["fallbacks"]) / (iters * groups_per_iter),
+            "marg_l1": s2["marg_l1"], "marg_l1_rel_diff_vs_exact": abs(s2["marg_l1"] - r2["marg_l1"]) / r2["marg_l1"]}
+    return res
 
 
 def gradient_flow(native, torch, synth, steps: int):
@@ -280,6 +305,7 @@ def gradient_flow(native, torch, synth, steps: int):
 
 
 def barycenter_workloads(native, torch, synth, c4_iters: int):
+    import numpy as np
     """The two barycenter workloads through the queue, convolution timing on.
     128x128x16 interpolation: two Bezier-stroke measures, w = (1,3,1), eps = 0.05, 15x15
     window, the five weights t in {0, 1/4, 1/2, 3/4, 1} as five resident requests, tol 1e-6,
@@ -305,6 +331,24 @@ def barycenter_workloads(native, torch, synth, c4_iters: int):
         wall = time.perf_counter() - t0
         kt = q.kernel_time()
         q.close()
+        engines = {}
+        if name.startswith("fields256"):
+            # the same IBP iterations on the matrix-core engines, each barycenter against the
+            # exact engine's (no oracle at this size; the 64x64x8 downsample is in cpu_baseline)
+            ref = outs[0].cpu().numpy()
+            for ename in ("bf16", "f32_mfma"):
+                oe = engine_opts(native, ename, tol=-1.0, max_iter=c4_iters, check_every=c4_iters, final_check=False)
+                be = torch.empty_like(outs[0])
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                re_ = native.se2_barycenter(k, dev[0], insts[0].lambdas, oe, be)
+                torch.cuda.synchronize()
+                we = time.perf_counter() - t1
+                E = float(ref.size)
+                engines[ename] = {"wall_s": we, "ibp_iters_per_s": re_["iters"] / we,
+                                  "fallback_group_share": re_["fallbacks"] / (2.0 * len(insts[0].mus) * re_["iters"]
+                                                                            * (E / (64.0 * g.nt)) * g.nt),
+                                  "barycenter_l1_vs_exact": float(np.abs(be.cpu().numpy() - ref).sum())}
         out[name] = {"requests": len(insts), "iters": [r["iters"] for r in reps],
                      "converged": sum(1 for r in reps if r["status"] == native.SE2_CONVERGED),
                      "wall_s": wall, "ibp_iters_per_s": sum(r["iters"] for r in reps) / wall,
@@ -314,9 +358,151 @@ def barycenter_workloads(native, torch, synth, c4_iters: int):
                      "sparse_terms": sum(r["terms_sparse"] for r in reps),
                      "roofline": log_conv_roofline(kt["seconds"], kt["launches"], kt["outputs"],
                                                    sum(r["terms_dense"] for r in reps),
-                                                   sum(r["terms_sparse"] for r in reps), "log-domain convolution")}
+                                                   sum(r["terms_sparse"] for r in reps), "log-domain convolution"),
+                     "matrix_core_engines": engines or None}
         del dev, outs, k
     return out
+
+
+ENGINES = {"f32": ("SE2_F32", None), "f64": ("SE2_F64", None), "bf16": ("SE2_BF16", None),
+           "f32_mfma": ("SE2_F32_MFMA", None), "bf16>f32": ("SE2_F32", "SE2_BF16"),
+           "bf16>f32_mfma": ("SE2_F32_MFMA", "SE2_BF16")}
+
+
+def engine_opts(native, name, **kw):
+    prec, bulk = ENGINES[name]
+    return native.opts(prec=getattr(native, prec), bulk=None if bulk is None else getattr(native, bulk), **kw)
+
+
+def converged_leg(native, torch, synth, a):
+    """The converging 64x64x16 instance: nu is mu's strokes with each segment's orientation
+    turned by a seeded angle in U[-pi/16, pi/16] (a motion along theta), strokes splatted with
+    sigma_xy = 3 px, floor 1e-6, w = (1,3,1), eps = 0.1, 11x11 window.  `conv_batch` solves are
+    submitted together to the serving queue and run to marginal L1 1e-6 (at most
+    `conv_max_iter` iterations), once per engine (warm-up run first, then the timed one), with
+    convolution timing on: exact FP32 with certified pruning, FP32 on the matrix cores, and a
+    bfloat16 bulk phase on the matrix cores before either.  The matrix-core engines' rate is
+    the dense-window flops (2 per in-grid window term) over the union of the launch intervals."""
+    import numpy as np
+    insts = [synth.lines64_theta(i) for i in range(a.conv_batch)]
+    g = insts[0].grid
+    k = native.Kernel(g.nx, g.ny, g.nt, False, insts[0].w, insts[0].eps, insts[0].radius)
+    mus = [torch.from_numpy(x.mu).cuda() for x in insts]
+    nus = [torch.from_numpy(x.nu).cuda() for x in insts]
+    res, pots, pick = {}, {}, 0
+    for name in [e for e in a.conv_engines.split(",") if e]:
+        o = engine_opts(native, name, tol=1e-6, max_iter=a.conv_max_iter, check_every=a.check_every,
+                        final_check=True, prune=True, switch_tol=1e-3)
+        fs = [torch.empty_like(m) for m in mus]
+        gs = [torch.empty_like(m) for m in mus]
+        q = native.SolveQueue(hbm_budget_bytes=native.ot_request_bytes(k, o) * a.conv_batch + (64 << 20),
+                              max_slots=a.conv_batch)
+        for timed in (False, True):
+            if timed:
+                q.profile(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ts = [q.submit_ot(k, mus[i], nus[i], o, fs[i], gs[i]) for i in range(a.conv_batch)]
+            reps = [q.wait(t) for t in ts]
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            lat = []
+            for t in ts:
+                t_s, _, t_d = q.times(t)
+                lat.append(t_d - t_s)
+                q.release(t)
+        kt = q.kernel_time()
+        q.close()
+        its = np.array([r["iters"] for r in reps])
+        conv = sum(1 for r in reps if r["status"] == native.SE2_CONVERGED)
+        lin = sum(r["terms_linear"] for r in reps)
+        rec = {"wall_s": wall, "converged": conv, "solves": len(reps), "converged_solves_per_s": conv / wall,
+               "iters_per_s": float(its.sum()) / wall, "iters_median": float(np.median(its)), "iters_max": int(its.max()),
+               "p50_latency_ms": float(np.percentile(lat, 50) * 1e3), "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+               "marg_l1_max": max(r["marg_l1"] for r in reps), "marg_l1_f64_max": max(r["marg_l1_f64"] for r in reps),
+               "phase_switch_iter_median": float(np.median([r["phase_switch_iter"] for r in reps])),
+               "fallback_groups": int(sum(r["fallbacks"] for r in reps)),
+               "conv_seconds": kt["seconds"], "half_steps": kt["launches"],
+               "avg_half_step_us": kt["seconds"] / max(1.0, kt["launches"]) * 1e6}
+        groups = 2.0 * float(its.sum()) * (g.nx // 8) * (g.ny // 8) * g.nt
+        if lin > 0:
+            # share of the window terms the matrix cores evaluated, and the rate of the whole
+            # convolution time in dense-window flops against the peak of the final engine
+            peak = PEAK_F32_TFLOPS if ENGINES[name][0] == "SE2_F32_MFMA" else PEAK_BF16_TFLOPS
+            tf = 2.0 * kt["terms"] / kt["seconds"] / 1e12 if kt["seconds"] > 0 else 0.0
+            rec["matrix_core"] = {"terms_share": lin / max(1.0, kt["terms"]), "dense_window_tflops": tf,
+                                  "peak_tflops": peak, "frac": tf / peak,
+                                  "fallback_groups_per_group_of_all_half_steps": rec["fallback_groups"] / groups}
+        res[name] = rec
+        if not pots:
+            # the instance the first engine solved in the fewest iterations: the one the oracle
+            # then runs to convergence beside them (its time stays bounded)
+            pick = int(np.argmin(its))
+        pots[name] = [(fs[pick].cpu().numpy(), gs[pick].cpu().numpy())]
+    out = {"workload": "lines64x64x16-theta OT: orientation turned by U[-pi/16, pi/16] per segment, sigma_xy = 3 px, "
+                       "floor 1e-6, w=(1,3,1), eps=0.1, 11x11 window, tol 1e-6, serving queue",
+           "batch": a.conv_batch, "max_iter": a.conv_max_iter, "engines": res}
+    return out, pots, insts[pick]
+
+
+def halo_spread(native, torch, synth):
+    """Why the matrix-core engines fall back: the spread of log2 b (the input of an a-update)
+    and of log2 a over the halo of each 16 x 16 output tile (radius 5), for the 64x64x16 paired
+    lines at eps 0.05, 0.1 and 0.5 after 50 and 1000 iterations (exact engine) and for the
+    theta-motion instance; raw (max - min: one shift per tile), after removing a per-orientation
+    offset, and after removing a least-squares plane in (x, y) plus a per-orientation offset.
+    A tile's shifted values must stay within 87 (the certificate) for its outputs to pass.
+    Beside it, the share of (tile, orientation) groups that the FP32 matrix-core engine
+    recomputes exactly over 300 iterations, and the same for the class barycenter."""
+    import numpy as np
+
+    def spreads(x2, R=5, T=16):
+        ny, nx, nt = x2.shape
+        out = []
+        for ty in range(0, ny, T):
+            for tx in range(0, nx, T):
+                h = x2[max(ty - R, 0):min(ty + T + R, ny), max(tx - R, 0):min(tx + T + R, nx), :]
+                fin = np.isfinite(h)
+                v = h[fin]
+                yy, xx, kk = np.nonzero(fin)
+                a2 = np.zeros((len(v), nt))
+                a2[np.arange(len(v)), kk] = 1.0
+                r2 = v - a2 @ np.linalg.lstsq(a2, v, rcond=None)[0]
+                a3 = np.concatenate([np.stack([xx, yy], 1).astype(float), a2], 1)
+                r3 = v - a3 @ np.linalg.lstsq(a3, v, rcond=None)[0]
+                out.append((v.max() - v.min(), r2.max() - r2.min(), r3.max() - r3.min()))
+        s_ = np.array(out)
+        return {name: {"median": float(np.median(s_[:, i])), "p90": float(np.percentile(s_[:, i], 90)),
+                       "share_within_87": float(np.mean(s_[:, i] <= 87.0))}
+                for i, name in enumerate(("one_shift", "per_orientation", "plane_and_per_orientation"))}
+
+    rec = {"tile": "16x16 outputs, halo radius 5, log2 units", "cases": []}
+    for label, make, epss in (("lines64x64x16-paired/0", lambda: synth.lines64(0), (0.05, 0.1, 0.5)),
+                              ("lines64x64x16-theta/0", lambda: synth.lines64_theta(0), (0.1,))):
+        inst = make()
+        g = inst.grid
+        mu, nu = torch.from_numpy(inst.mu).cuda(), torch.from_numpy(inst.nu).cuda()
+        for eps in epss:
+            k = native.Kernel(g.nx, g.ny, g.nt, False, inst.w, eps, inst.radius)
+            f, gg = torch.empty_like(mu), torch.empty_like(mu)
+            for iters in (50, 1000):
+                native.se2_sinkhorn(k, mu, nu, native.opts(tol=-1.0, max_iter=iters, check_every=50), f, gg)
+                rec["cases"].append({"instance": label, "eps": eps, "iters": iters,
+                                     "log2_b": spreads(gg.cpu().numpy() / eps / math.log(2.0)),
+                                     "log2_a": spreads(f.cpu().numpy() / eps / math.log(2.0))})
+            rep = native.se2_sinkhorn(k, mu, nu, native.opts(tol=-1.0, max_iter=300, prec=native.SE2_F32_MFMA), f, gg)
+            rec["cases"][-1]["f32_mfma_fallback_share_300_iters"] = rep["fallbacks"] / (300.0 * 2 * (g.nx // 8) ** 2 * g.nt)
+    imgs = synth.stroke_images(600, seed=6000)
+    kb = native.Kernel(28, 28, 16, False, (1.0, 1.5, 1.0), 0.5, 4)
+    dev = [torch.from_numpy(m).cuda() for m in imgs]
+    out = torch.empty_like(dev[0])
+    shares = {}
+    for name in ("bf16", "f32_mfma"):
+        rep = native.se2_barycenter(kb, dev, [1.0 / len(dev)] * len(dev),
+                                    engine_opts(native, name, tol=-1.0, max_iter=20, check_every=20, final_check=False), out)
+        shares[name] = rep["fallbacks"] / (20.0 * 2 * len(dev) * 16 * 16)
+    rec["class_barycenter_600_images_fallback_share_20_iters"] = shares
+    return rec
 
 
 def main():
@@ -378,6 +564,12 @@ def main():
         return
     if a.serving:
         print(json.dumps(serving(native, torch, synth, a, trace)), flush=True)
+        return
+    if a.converged_only:
+        print(json.dumps(converged_leg(native, torch, synth, a)[0]), flush=True)
+        return
+    if a.halo_spread:
+        print(json.dumps(halo_spread(native, torch, synth)), flush=True)
         return
     k = native.Kernel(NX, NX, NT, False, W_METRIC, EPS, R)
     insts = [synth.lines64(i, paired=True) for i in range(a.batch)]
@@ -476,6 +668,7 @@ def main():
         torch.cuda.synchronize()
         build_ms[f"{n}x{n}x{nt}{' axial' if axial else ''}, {2 * rad + 1}x{2 * rad + 1}"] = (time.perf_counter() - t0) * 1e3
         del kk
+    conv_leg, conv_pots, conv_inst = (None, None, None) if a.conv_batch <= 0 else converged_leg(native, torch, synth, a)
     class_meas = None if class_images is None else class_barycenter(native, torch, class_images, a.bary_iters)
     flow_meas = None if a.flow_steps <= 0 else gradient_flow(native, torch, synth, a.flow_steps)
     bary_meas = None if a.c4_iters <= 0 else barycenter_workloads(native, torch, synth, a.c4_iters)
@@ -485,7 +678,7 @@ def main():
 
     cpu = None
     if not a.no_cpu:
-        cpu = cpu_baseline(insts[0], a.cpu_iters, native, torch, k)
+        cpu = cpu_baseline(insts[0], a.cpu_iters, native, torch, k, conv_pots, conv_inst)
 
     out = {
         "metric": "Sinkhorn iters/sec & solves/sec at 64x64x16 (marg err<=1e-6); p50/p99 latency",
@@ -517,6 +710,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "kernel_build_ms": build_ms,
+        "converged_instance": conv_leg,
         "eps_scaling": eps_leg,
         "lift_project": field_meas,
         "class_barycenter": class_meas,
@@ -601,10 +795,13 @@ def serving(native, torch, synth, a, trace):
     }
 
 
-def cpu_baseline(inst, iters: int, native=None, torch=None, kernel=None):
+def cpu_baseline(inst, iters: int, native=None, torch=None, kernel=None, conv_pots=None, conv_inst=None):
     """FP64 oracle Sinkhorn on this host, a bounded sample of the same workload; with the
     library given, the same solve on the GPU at the same iteration count beside it, and the
-    GPU result's errors against the oracle's (plan L1, marginal L1, relative cost)."""
+    GPU result's errors against the oracle's (plan L1, marginal L1, relative cost).  With the
+    converged leg's potentials (the theta-motion instance its first engine solved in the fewest
+    iterations, per engine), the oracle runs that instance to marginal L1 1e-6 as well and the
+    converged plans are compared."""
     import numpy as np
     import oracle
     logk, cost = oracle.kernel_table(NT, False, W_METRIC, EPS, R)
@@ -645,6 +842,41 @@ def cpu_baseline(inst, iters: int, native=None, torch=None, kernel=None):
         out["gpu_vs_oracle_curves128"] = {"t": 0.5, "iterations": it_o,
                                           "barycenter_l1": float(np.abs(b.cpu().numpy() - bar_o).sum()),
                                           "marg_l1_diff": abs(rep["marg_l1"] - err_o)}
+        # the same 2 IBP iterations on bfloat16 operands (the configured precision of this workload)
+        rep = native.se2_barycenter(kc, dev, ci.lambdas, engine_opts(native, "bf16", tol=-1.0, max_iter=2,
+                                                                     check_every=2), b)
+        out["gpu_vs_oracle_curves128"]["bf16"] = {"barycenter_l1": float(np.abs(b.cpu().numpy() - bar_o).sum()),
+                                                  "fallbacks": rep["fallbacks"]}
+        # the 256x256x32 field barycenter's 64x64x8 downsample, 4 IBP iterations: exact engine and
+        # bfloat16 operands against the oracle (FP32 on the matrix cores needs 16 or 32 orientations)
+        fi = synth.fields256(0, n=64, nt=8)
+        g = fi.grid
+        kf = native.Kernel(g.nx, g.ny, g.nt, g.axial, fi.w, fi.eps, fi.radius)
+        devf = [torch.from_numpy(m).cuda() for m in fi.mus]
+        bf = torch.empty_like(devf[0])
+        logk_f, _ = oracle.kernel_table(g.nt, g.axial, fi.w, fi.eps, fi.radius)
+        bar_f, it_f, err_f, _ = oracle.ibp(logk_f, fi.mus, fi.lambdas, 4, -1.0)
+        rec = {"iterations": it_f}
+        for ename in ("f32", "bf16"):
+            rep = native.se2_barycenter(kf, devf, fi.lambdas, engine_opts(native, ename, tol=-1.0, max_iter=4,
+                                                                          check_every=4), bf)
+            rec[ename] = {"barycenter_l1": float(np.abs(bf.cpu().numpy() - bar_f).sum()),
+                          "marg_l1_diff": abs(rep["marg_l1"] - err_f), "fallbacks": rep["fallbacks"]}
+        out["gpu_vs_oracle_fields64x64x8"] = rec
+    if conv_pots:
+        gi = conv_inst.grid
+        logk_t, cost_t = oracle.kernel_table(gi.nt, False, conv_inst.w, conv_inst.eps, conv_inst.radius)
+        t = time.perf_counter()
+        phi_o, psi_o, it_o, err_o, _ = oracle.sinkhorn(logk_t, conv_inst.mu, conv_inst.nu, 3000, 1e-6)
+        c_o = oracle.plan_stats(logk_t, cost_t, phi_o, psi_o)[0]
+        rec = {"instance": conv_inst.name, "oracle_iters": it_o, "oracle_marg_l1": err_o,
+               "oracle_seconds": time.perf_counter() - t, "engines": {}}
+        for name, ((f, g),) in conv_pots.items():
+            phi, psi = f / conv_inst.eps, g / conv_inst.eps
+            m1, m2, c, _ = oracle.marginal_errors(logk_t, cost_t, phi, psi, conv_inst.mu, conv_inst.nu)
+            rec["engines"][name] = {"plan_l1": oracle.plan_l1(logk_t, phi, psi, phi_o, psi_o),
+                                    "marg_l1_first": m1, "marg_l1_second": m2, "rel_cost_diff": abs(c - c_o) / c_o}
+        out["gpu_vs_oracle_converged"] = rec
     return out
 
 

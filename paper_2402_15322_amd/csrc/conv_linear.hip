@@ -288,11 +288,13 @@ __device__ __forceinline__ void f32m_load_b(f32x4_t (&dstb)[DYC][NT / 16], const
 
 // Every step of one pass, with the first step's fragments already in b0.  With FLUSH the
 // FP32 accumulators are added into FP64 ones after every step and cleared, so that no FP32
-// sum runs over more than one step (16 DYC products).
-template <int NT, int DYC, int RPW, bool FLUSH>
+// sum runs over more than one step (16 DYC products).  With SCALE, fragment element e of
+// column block nb is multiplied by 2^kx[nb][e] (exact: an exponent change) before it is used.
+template <int NT, int DYC, int RPW, bool FLUSH, bool SCALE = false>
 __device__ __forceinline__ void f32m_steps(f32x4_t (&acc)[RPW][NT / 16], double (&acc64)[RPW][NT / 16][4],
                                            f32x4_t (&b0)[DYC][NT / 16], const float *lds32,
-                                           const f32x4_t *__restrict__ Fp, int pass, int R, int row0, int lane) {
+                                           const f32x4_t *__restrict__ Fp, int pass, int R, int row0, int lane,
+                                           const int (*kx)[4] = nullptr) {
     constexpr int NB = NT / 16;
     const int W = 2 * R + 1;
     const int HWX = kSeg + 2 * R;
@@ -335,6 +337,15 @@ __device__ __forceinline__ void f32m_steps(f32x4_t (&acc)[RPW][NT / 16], double 
     // a step is RPW * DYC * 4 * NB MFMAs of 32 cycles per wave: one step of lookahead
     // hides the fragment loads
     for (int step = 0; step < nsteps; ++step) {
+        if constexpr (SCALE) {
+            // b0 was requested a step ago: scale it now, before the next request goes out
+#pragma unroll
+            for (int c = 0; c < DYC; ++c)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) b0[c][nb][e] = __builtin_amdgcn_ldexpf(b0[c][nb][e], kx[nb][e]);
+        }
         f32m_load_b<NT, DYC>(b1, Fp, min(step + 1, nsteps - 1), pass, nchunks, W, lane);
         __builtin_amdgcn_sched_barrier(0);
         run(b0, step);
@@ -554,11 +565,64 @@ __device__ __forceinline__ double halo_max(const double *in_, int nx, int ny, in
     return fmax(fmax(s_m[0], s_m[1]), fmax(s_m[2], s_m[3]));
 }
 
+// Per-orientation maxima of the FP64 input over the halo (as halo_max), written to s_out[NT]
+// (-inf where an orientation has no mass in the halo); s_w holds kWaves * NT doubles.  Item
+// e = 4 orientations 4q .. 4q+3 of one pixel, q = e % (NT / 4); every thread keeps one q
+// (256 is a multiple of NT / 4), lanes with the same q are combined by butterflies over
+// multiples of NT / 4, then the waves in LDS.
+template <int NT>
+__device__ __forceinline__ void halo_max_per_k(const double *in_, int nx, int ny, int HWX, int HWY, int xl, int ylo,
+                                               double *s_w, double *s_out) {
+    constexpr int Q = NT / 4;
+    constexpr int BATCH = 4;
+    const gdptr in = (gdptr)in_;
+    const int total = HWY * HWX * Q;
+    const float inv = 1.0f / static_cast<float>(HWX);
+    double m[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int e0 = 0; e0 < total; e0 += BATCH * 256) {
+        double v[BATCH][4];
+        bool ok[BATCH];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+            const int eu = e0 + u * 256 + static_cast<int>(threadIdx.x);
+            const int e = min(eu, total - 1);
+            const int p = e / Q, q = e - p * Q;
+            const int hy = static_cast<int>((static_cast<float>(p) + 0.5f) * inv), hx = p - hy * HWX;
+            const int gy = ylo + hy, gx = xl + hx;
+            // a clamped item repeats the last one, whose quad may differ from this thread's
+            ok[u] = eu < total && gy >= 0 && gy < ny && gx >= 0 && gx < nx;
+            const int cy = min(max(gy, 0), ny - 1), cx = min(max(gx, 0), nx - 1);
+            const gdptr src = in + (static_cast<size_t>(cy) * nx + cx) * NT + 4 * q;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[u][c] = src[c];
+        }
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u)
+            if (ok[u])
+#pragma unroll
+                for (int c = 0; c < 4; ++c) m[c] = fmax(m[c], v[u][c]);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        for (int off = 32; off >= Q; off >>= 1) m[c] = fmax(m[c], __shfl_xor(m[c], off));
+    if (lane < Q)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s_w[wave * NT + 4 * lane + c] = m[c];
+    __syncthreads();
+    if (static_cast<int>(threadIdx.x) < NT) {
+        const int k = threadIdx.x;
+        s_out[k] = fmax(fmax(s_w[k], s_w[NT + k]), fmax(s_w[2 * NT + k], s_w[3 * NT + k]));
+    }
+    __syncthreads();
+}
+
 // Stage V = 2^(g - M) of orientations [k0, k0 + KS) of the halo in LDS, [hy][hx][KS], as
 // bfloat16 (RNE) or FP32; zero outside the grid and for zero mass.
+// With kshift (LDS, NT integers) the shift of orientation k is kshift[k] instead of M.
 template <int NT, int KS, bool BF16>
 __device__ __forceinline__ void stage_shifted(void *lds, const double *in_, double M, int k0, int nx, int ny, int HWX,
-                                              int HWY, int xl, int ylo) {
+                                              int HWY, int xl, int ylo, const int *kshift = nullptr) {
     constexpr int Q = KS / 4;
     constexpr int BATCH = 4;
     const gdptr in = (gdptr)in_;
@@ -589,7 +653,8 @@ __device__ __forceinline__ void stage_shifted(void *lds, const double *in_, doub
                     // 2^d with d = g - M split as dh + dl (dh = FP32(d), |dl| <= 2^-24 |d|):
                     // 2^dh (native exp2) times 1 + dl ln 2, so that the FP32 rounding of a
                     // large |d| does not enter the result
-                    const double d = v[u][c] - M;
+                    const int kk = k0 + 4 * ((e0 + u * 256 + static_cast<int>(threadIdx.x)) % Q) + c;
+                    const double d = v[u][c] - (kshift != nullptr ? static_cast<double>(kshift[kk]) : M);
                     const float dh = static_cast<float>(d);
                     const float e = __builtin_amdgcn_exp2f(dh);
                     if constexpr (BF16) {
@@ -612,14 +677,15 @@ __device__ __forceinline__ void stage_shifted(void *lds, const double *in_, doub
 
 // Certificate, epilogue, error partials and the fallback list of a matrix-core tile.
 // S[r][nb][q] is the shifted sum of the lane's output at pixel x0 + 4 (lane / 16) + q of row
-// y0 + row0 + r, orientation ko = 16 nb + lane % 16.  The group (8 x 8 tile, ko) of an output
+// y0 + row0 + r, orientation ko = 16 nb + lane % 16, and Mk[nb] the log2 of its frame.  The group (8 x 8 tile, ko) of an output
 // is held by lanes ko + 16 {2h, 2h + 1} (h = 8-pixel half of the segment) over 8 rows: one
 // wave at 8 rows per wave, the wave pair (2m, 2m + 1) at 4 rows per wave.  Fixed-order sums:
 // within a lane over (r, q), then the even lane's sum plus the odd lane's, then the even
 // wave's plus the odd wave's.  An 8 x 8 tile with rejected groups is listed once, with the
 // mask of its rejected orientations.
 template <int NT, int RPW, int NB>
-__device__ __forceinline__ void lin_log_epilogue(const ConvJob &job, int jb, const double (&S)[RPW][NB][4], double M,
+__device__ __forceinline__ void lin_log_epilogue(const ConvJob &job, int jb, const double (&S)[RPW][NB][4],
+                                                 const double (&Mk)[NB],
                                                  int x0, int y0, int row0, int lane, int wave, int4 *__restrict__ fb,
                                                  int *__restrict__ fb_count, int *s_xi, double *s_xd) {
     const int nx = job.nx, ny = job.ny;
@@ -661,7 +727,7 @@ __device__ __forceinline__ void lin_log_epilogue(const ConvJob &job, int jb, con
                 for (int q = 0; q < 4; ++q) {
                     const int gx = x0 + 4 * kb + q, gy = y0 + row0 + r;
                     if (ko < NT && gx < nx && gy < ny) {
-                        const double lse = M + log2(S[r][nb][q]);
+                        const double lse = Mk[nb] + log2(S[r][nb][q]);
                         err += epilogue(job, (static_cast<size_t>(gy) * nx + gx) * NT + ko, lse);
                     }
                 }
@@ -732,11 +798,21 @@ __global__ __launch_bounds__(256) void k_lin_log_bf16(const ConvJob *__restrict_
         for (int nb = 0; nb < P::NB; ++nb)
 #pragma unroll
             for (int q = 0; q < 4; ++q) S[r][nb][q] = static_cast<double>(acc[r][nb][q]);
-    lin_log_epilogue<NT, RPW, P::NB>(job, jb, S, M, x0, y0, row0, lane, wave, fb, fb_count, s_xi, s_xd);
+    double Mk[P::NB];
+#pragma unroll
+    for (int nb = 0; nb < P::NB; ++nb) Mk[nb] = M;
+    lin_log_epilogue<NT, RPW, P::NB>(job, jb, S, Mk, x0, y0, row0, lane, wave, fb, fb_count, s_xi, s_xd);
 }
 
 // FP32 operands on the FP32 matrix cores (nt = 16, 32): V and the kernel in FP32, FP32 sums
-// over one step added into FP64 accumulators.
+// over one step added into FP64 accumulators.  Frames per orientation: input orientation ki is
+// shifted by s_ki = ceil(max of g(., ki) over the halo), output orientation ko is reported in
+// the frame t_ko = ceil(max_ki (s_ki + L2[0][ko][ki])), and the kernel value K[d][ko][ki]
+// enters as K 2^(s_ki - t_ko) <= 1 (L2[d][ko][ki] <= L2[0][ko][ki]: the distance grows with the
+// offset), an exact exponent change.  Every term is <= 1 in the frame of its output, so the
+// certificate of kLinCert holds as for one shift per tile, while an orientation far from the
+// dominant ones (the tails of a peaked angular profile) keeps its own scale.
+constexpr int kNoMassShift = -(1 << 26);
 template <int NT, int DYC, int RPW>
 __global__ __launch_bounds__(256) void k_lin_log_f32(const ConvJob *__restrict__ jobs,
                                                      const int32_t *__restrict__ block_job, int4 *__restrict__ fb,
@@ -744,7 +820,9 @@ __global__ __launch_bounds__(256) void k_lin_log_f32(const ConvJob *__restrict__
     static_assert(NT == 16 || NT == 32, "16 or 32 orientations");
     constexpr int NB = NT / 16, NP = NT / 16;
     extern __shared__ float lds32[];
-    __shared__ double s_m[kWaves];
+    __shared__ double s_w[kWaves * NT];
+    __shared__ double s_max[NT];
+    __shared__ int s_sk[NT], s_tk[NT];
     __shared__ int s_xi[kWaves * 64];
     __shared__ double s_xd[kWaves * 64];
     if (blockIdx.x == 0 && threadIdx.x == 0) *fb_next = 0;
@@ -760,8 +838,21 @@ __global__ __launch_bounds__(256) void k_lin_log_f32(const ConvJob *__restrict__
     const int x0 = tx * kSeg, y0 = ty * kRows;
     const int xl = x0 - R;
     const f32x4_t *Fp = reinterpret_cast<const f32x4_t *>(job.kop);
-    double M = halo_max<NT>(job.in, nx, ny, HWX, HWY, xl, y0 - R, s_m);
-    if (M == -INFINITY) M = 0.0;
+    halo_max_per_k<NT>(job.in, nx, ny, HWX, HWY, xl, y0 - R, s_w, s_max);
+    if (static_cast<int>(threadIdx.x) < NT) {
+        const double m = s_max[threadIdx.x];
+        s_sk[threadIdx.x] = (m == -INFINITY) ? kNoMassShift
+                                             : static_cast<int>(ceil(fmin(fmax(m, -67108864.0), 67108864.0)));
+    }
+    __syncthreads();
+    if (static_cast<int>(threadIdx.x) < NT) {
+        const int ko = threadIdx.x;
+        const gdptr L0 = (gdptr)(job.L64) + (static_cast<size_t>(R * W + R) * NT + ko) * NT;  // offset d = 0
+        double t = -INFINITY;
+        for (int ki = 0; ki < NT; ++ki) t = fmax(t, static_cast<double>(s_sk[ki]) + L0[ki]);
+        s_tk[ko] = static_cast<int>(ceil(fmin(fmax(t, -67108864.0 * 2.0), 67108864.0)));
+    }
+    __syncthreads();
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
@@ -780,12 +871,23 @@ __global__ __launch_bounds__(256) void k_lin_log_f32(const ConvJob *__restrict__
     f32x4_t b0[DYC][NB];
     for (int pass = 0; pass < NP; ++pass) {
         f32m_load_b<NT, DYC>(b0, Fp, 0, pass, nchunks, W, lane);
+        // exponent of fragment element e of block nb: s(ki) - t(ko), ki = 16 pass + 4 (lane / 16) + e,
+        // ko = 16 nb + lane % 16 (clamped: K 2^x with x below -300 is zero either way)
+        int kx[NB][4];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                kx[nb][e] = max(s_sk[16 * pass + 4 * (lane >> 4) + e] - s_tk[16 * nb + (lane & 15)], -300);
         if (pass > 0) __syncthreads();  // every wave is done with the previous pass's halo
-        stage_shifted<NT, 16, false>(lds32, job.in, M, 16 * pass, nx, ny, HWX, HWY, xl, y0 - R);
+        stage_shifted<NT, 16, false>(lds32, job.in, 0.0, 16 * pass, nx, ny, HWX, HWY, xl, y0 - R, s_sk);
         __syncthreads();
-        f32m_steps<NT, DYC, RPW, true>(acc, acc64, b0, lds32, Fp, pass, R, row0, lane);
+        f32m_steps<NT, DYC, RPW, true, true>(acc, acc64, b0, lds32, Fp, pass, R, row0, lane, kx);
     }
-    lin_log_epilogue<NT, RPW, NB>(job, jb, acc64, M, x0, y0, row0, lane, wave, fb, fb_count, s_xi, s_xd);
+    double Mk[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) Mk[nb] = static_cast<double>(s_tk[16 * nb + (lane & 15)]);
+    lin_log_epilogue<NT, RPW, NB>(job, jb, acc64, Mk, x0, y0, row0, lane, wave, fb, fb_count, s_xi, s_xd);
 }
 
 template <int NT, int DYC, int RPW, bool BF16>

@@ -100,8 +100,8 @@ def test_conv_log_matrix_cores(nat, case, kind):
         assert err <= _bound(nat, prec, 2 * R + 1, nt), (prec, err)
         if kind == "smooth":
             assert fb == 0, (prec, fb)
-        elif kind == "rough":
-            assert fb == groups, (prec, fb, groups)
+        elif kind == "rough":   # independent values of spread 300: (nearly) every group is recomputed
+            assert fb >= 0.95 * groups, (prec, fb, groups)
         else:
             assert 0 < fb <= groups, (prec, fb, groups)
             # a tile of 16 x 32 outputs or less whose halo (R + 1 wide) misses the spike keeps its groups
@@ -265,3 +265,25 @@ def test_queue_matrix_core_solves_alone_and_mixed_are_bitwise_identical(nat):
         assert reps_a[0]["phase_switch_iter"] == reps_m[i]["phase_switch_iter"]
         for a, b in zip(alone[0], mixed[i]):
             assert np.array_equal(a.view(np.uint64), b.view(np.uint64)), i
+
+
+def test_eps_scaling_on_fp32_matrix_cores_equal_iterations(nat):
+    """Every eps stage (0.4, 0.2, then 0.1) on the FP32 matrix cores, 32 x 32 x 16 theta-motion
+    instance, against the oracle's stage loop at equal iterations per stage: the exact engine's
+    bars."""
+    inst = synth.lines64_theta(3, n=32)
+    g = inst.grid
+    k = nat.Kernel(g.nx, g.ny, g.nt, False, inst.w, inst.eps, inst.radius)
+    o = nat.opts(tol=-1, max_iter=60, check_every=10, prec=nat.SE2_F32_MFMA, eps_start=0.4, eps_factor=0.5,
+                 stage_iters=15)
+    rep, phi, psi = _solve(nat, k, inst, o)
+    kernel_at = lambda e: oracle.kernel_table(g.nt, False, inst.w, e, inst.radius)[0]
+    phi_o, psi_o, it_o, err_o, _ = oracle.sinkhorn_eps_scaling(kernel_at, inst.eps, inst.mu, inst.nu, 0.4, 0.5, 15,
+                                                               60, -1.0)
+    assert rep["iters"] == it_o == 60 and rep["scaling_iters"] == 30
+    logk, cost = oracle.kernel_table(g.nt, False, inst.w, inst.eps, inst.radius)
+    assert oracle.plan_l1(logk, phi, psi, phi_o, psi_o) <= 1e-5
+    assert abs(rep["marg_l1"] - err_o) <= 1e-6
+    c_o = oracle.plan_stats(logk, cost, phi_o, psi_o)[0]
+    assert abs(rep["cost"] - c_o) <= 1e-6 * c_o
+    assert rep["terms_linear"] > 0
