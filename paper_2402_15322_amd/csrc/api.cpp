@@ -16,6 +16,8 @@ namespace {
 thread_local std::string g_last_error;
 }
 
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
 void set_last_hip_error(hipError_t e, const char *what, const char *file, int line) {
     char buf[512];
     std::snprintf(buf, sizeof(buf), "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);

@@ -27,6 +27,7 @@
 
 #include "conv_dev.h"
 #include "se2_internal.h"
+#include "launch.h"
 
 namespace se2 {
 
@@ -98,13 +99,45 @@ __device__ __forceinline__ void mfma_chunk(f32x4_t (&acc)[RPW][Pack<NT>::NB],
     }
 }
 
+// Kernel fragments of step `step` ((dx group, dy chunk) = (step / nchunks, step % nchunks))
+// of the BF16 contraction, one 16-byte load per lane and fragment.
+template <int NT, int DYC>
+__device__ __forceinline__ void bf16_load_b(bf16x8_t (&dstb)[DYC][Pack<NT>::NB], const bf16x8_t *__restrict__ Bp,
+                                            int step, int R, int lane) {
+    using P = Pack<NT>;
+    const int W = 2 * R + 1;
+    const int G = (W + P::SPM - 1) / P::SPM;
+    const int nchunks = (W + DYC - 1) / DYC;
+    const int g = step / nchunks, ch = step - g * nchunks;
+    const bf16x8_t *src = Bp + (static_cast<size_t>(ch * DYC) * G + g) * P::NB * 64 + lane;
+#pragma unroll
+    for (int c = 0; c < DYC; ++c)
+#pragma unroll
+        for (int nb = 0; nb < P::NB; ++nb) dstb[c][nb] = src[(static_cast<size_t>(c) * G * P::NB + nb) * 64];
+}
+
+// The first two fragment sets of the contraction (steps 0 and 1, or 0 twice when there is
+// one step), requested by the caller right before bf16_contract.  (Requesting them before
+// the halo staging gains nothing: the staging loop waits for every load in flight.)
+template <int NT, int DYC>
+__device__ __forceinline__ void bf16_first_b(bf16x8_t (&b0)[DYC][Pack<NT>::NB], bf16x8_t (&b1)[DYC][Pack<NT>::NB],
+                                             const bf16x8_t *__restrict__ Bp, int R, int lane) {
+    using P = Pack<NT>;
+    const int W = 2 * R + 1;
+    const int nsteps = ((W + P::SPM - 1) / P::SPM) * ((W + DYC - 1) / DYC);
+    bf16_load_b<NT, DYC>(b0, Bp, 0, R, lane);
+    bf16_load_b<NT, DYC>(b1, Bp, min(1, nsteps - 1), R, lane);
+}
+
 // All (dx group, dy chunk) steps of the BF16 contraction of one workgroup tile: acc[r][nb]
 // receives output row row0 + r of the tile, column block nb.  lds16 holds the halo
-// [hy][hx][ki] in bfloat16 with hx = 0 at pixel xl.
+// [hy][hx][ki] in bfloat16 with hx = 0 at pixel xl; b0 and b1 hold the fragments of the
+// first two steps (bf16_first_b) and are used as buffers afterwards.
 template <int NT, int DYC, int RPW>
 __device__ __forceinline__ void bf16_contract(f32x4_t (&acc)[RPW][Pack<NT>::NB], const uint16_t *lds16,
                                               const bf16x8_t *__restrict__ Bp, int R, int x0, int xl, int row0,
-                                              int lane) {
+                                              int lane, bf16x8_t (&b0)[DYC][Pack<NT>::NB],
+                                              bf16x8_t (&b1)[DYC][Pack<NT>::NB]) {
     using P = Pack<NT>;
     const int W = 2 * R + 1;
     const int G = (W + P::SPM - 1) / P::SPM;
@@ -123,15 +156,7 @@ __device__ __forceinline__ void bf16_contract(f32x4_t (&acc)[RPW][Pack<NT>::NB],
     // current one runs on the matrix cores
     const int nchunks = (W + DYC - 1) / DYC;
     const int nsteps = G * nchunks;
-    bf16x8_t b0[DYC][P::NB], b1[DYC][P::NB];
-    auto load_b = [&](bf16x8_t(&dstb)[DYC][P::NB], int step) {
-        const int g = step / nchunks, ch = step - g * nchunks;
-        const bf16x8_t *src = Bp + (static_cast<size_t>(ch * DYC) * G + g) * P::NB * 64 + lane;
-#pragma unroll
-        for (int c = 0; c < DYC; ++c)
-#pragma unroll
-            for (int nb = 0; nb < P::NB; ++nb) dstb[c][nb] = src[(static_cast<size_t>(c) * G * P::NB + nb) * 64];
-    };
+    auto load_b = [&](bf16x8_t(&dstb)[DYC][P::NB], int step) { bf16_load_b<NT, DYC>(dstb, Bp, step, R, lane); };
     auto run = [&](const bf16x8_t(&bfr)[DYC][P::NB], int step) {
         const int g = step / nchunks, ch = step - g * nchunks;
         // this lane's dx: slots of group g run dx = -R + g*SPM + slot; input pixel
@@ -148,8 +173,6 @@ __device__ __forceinline__ void bf16_contract(f32x4_t (&acc)[RPW][Pack<NT>::NB],
         // Prefetch indices are clamped (the last steps reload fragments they do not use) so
         // that the loads' wait counts stay exact; the last nsteps % 3 steps run after the loop.
         bf16x8_t b2[DYC][P::NB];
-        load_b(b0, 0);
-        load_b(b1, min(1, nsteps - 1));
         int step = 0;
         for (; step + 3 <= nsteps; step += 3) {
             load_b(b2, min(step + 2, nsteps - 1));
@@ -170,8 +193,8 @@ __device__ __forceinline__ void bf16_contract(f32x4_t (&acc)[RPW][Pack<NT>::NB],
     } else {
         // two column blocks (nt = 32): the fragments of the next step are loaded while the
         // current one runs (a third buffer would not fit the registers); the prefetch index is
-        // clamped (the last step reloads its own fragments) so the loop body has no branch
-        load_b(b0, 0);
+        // clamped (the last step reloads its own fragments) so the loop body has no branch.
+        // b1 already holds step 1 (or step 0 again): it is overwritten before its first use.
         for (int step = 0; step < nsteps; ++step) {
             load_b(b1, min(step + 1, nsteps - 1));
             __builtin_amdgcn_sched_barrier(0);
@@ -244,7 +267,9 @@ __global__ __launch_bounds__(256) void k_conv_bf16(const float *__restrict__ in,
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
     const int row0 = wave * RPW;  // first output row of this wave within the tile
     f32x4_t acc[RPW][P::NB];
-    bf16_contract<NT, DYC, RPW>(acc, lds16, Bp, R, x0, xl, row0, lane);
+    bf16x8_t b0[DYC][P::NB], b1[DYC][P::NB];
+    bf16_first_b<NT, DYC>(b0, b1, Bp, R, lane);
+    bf16_contract<NT, DYC, RPW>(acc, lds16, Bp, R, x0, xl, row0, lane, b0, b1);
 
     // D: lane holds column j = lane % 16 (ko), rows 4*(lane/16) + q (pixels)
     const int j = lane & 15;
@@ -790,7 +815,10 @@ __global__ __launch_bounds__(256) void k_lin_log_bf16(const ConvJob *__restrict_
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
     const int row0 = wave * RPW;
     f32x4_t acc[RPW][P::NB];
-    bf16_contract<NT, DYC, RPW>(acc, lds16, reinterpret_cast<const bf16x8_t *>(job.kop), R, x0, xl, row0, lane);
+    bf16x8_t b0[DYC][Pack<NT>::NB], b1[DYC][Pack<NT>::NB];
+    bf16_first_b<NT, DYC>(b0, b1, reinterpret_cast<const bf16x8_t *>(job.kop), R, lane);
+    bf16_contract<NT, DYC, RPW>(acc, lds16, reinterpret_cast<const bf16x8_t *>(job.kop), R, x0, xl, row0, lane, b0,
+                                b1);
     double S[RPW][P::NB][4];
 #pragma unroll
     for (int r = 0; r < RPW; ++r)
@@ -906,14 +934,13 @@ int launch_lin_log_t(const ConvJob *d_jobs, int nblocks, const int32_t *d_map, i
         fn = reinterpret_cast<const void *>(&k_lin_log_f32<NT, DYC, RPW>);
     }
     if (lds > 65536) SE2_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+    // the exact recomputation of rejected groups follows: this is not the group's last kernel
     if constexpr (BF16)
-        hipLaunchKernelGGL((k_lin_log_bf16<NT, DYC, RPW>), dim3(nblocks), dim3(256), lds, s, d_jobs, d_map, fb, fb_count,
-                           fb_next);
+        return launch_kernel(&k_lin_log_bf16<NT, DYC, RPW>, dim3(nblocks), dim3(256), lds, s, false, d_jobs, d_map, fb,
+                             fb_count, fb_next);
     else
-        hipLaunchKernelGGL((k_lin_log_f32<NT, DYC, RPW>), dim3(nblocks), dim3(256), lds, s, d_jobs, d_map, fb, fb_count,
-                           fb_next);
-    SE2_HIP(hipGetLastError());
-    return SE2_OK;
+        return launch_kernel(&k_lin_log_f32<NT, DYC, RPW>, dim3(nblocks), dim3(256), lds, s, false, d_jobs, d_map, fb,
+                             fb_count, fb_next);
 }
 
 // nt = 32 has one row count per operand type (lin_rows_per_wave): 8 rows for bfloat16, 4 for

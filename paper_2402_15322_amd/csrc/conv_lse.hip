@@ -43,6 +43,7 @@
 
 #include "conv_dev.h"
 #include "se2_internal.h"
+#include "launch.h"
 
 namespace se2 {
 
@@ -786,9 +787,7 @@ int launch_tiles_t(const ConvJob *d_jobs, int grid, int R_max, const int4 *items
     if (lds > 65536)
         SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_lse_tiles<NT, KC>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-    hipLaunchKernelGGL((k_lse_tiles<NT, KC>), dim3(grid), dim3(kConvThreads), lds, s, d_jobs, items, count);
-    SE2_HIP(hipGetLastError());
-    return SE2_OK;
+    return launch_kernel(&k_lse_tiles<NT, KC>, dim3(grid), dim3(kConvThreads), lds, s, true, d_jobs, items, count);
 }
 
 template <int NT, int KC, bool F64EXP>
@@ -799,10 +798,8 @@ int launch_dense_t(const ConvJob *d_jobs, int nblocks, const int32_t *d_block_jo
     if (lds > 65536)
         SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_conv_lse<NT, KC, F64EXP>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-    hipLaunchKernelGGL((k_conv_lse<NT, KC, F64EXP>), dim3(nblocks), dim3(kConvThreads), lds, s, d_jobs,
-                       d_block_job);
-    SE2_HIP(hipGetLastError());
-    return SE2_OK;
+    return launch_kernel(&k_conv_lse<NT, KC, F64EXP>, dim3(nblocks), dim3(kConvThreads), lds, s, true, d_jobs,
+                         d_block_job);
 }
 
 template <int NT, int RBW>
@@ -816,10 +813,8 @@ int launch_rebuild_t(const ConvJob *d_jobs, int nblocks, int R_max, const int2 *
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lr)));
     const int cap = (RBW == 16) ? kRebuildGridWide : kRebuildGrid;
     const int grid = nblocks * NT < cap ? nblocks * NT : cap;
-    hipLaunchKernelGGL((k_rebuild<NT, RBW>), dim3(grid), dim3(64 * RBW), lr, s, d_jobs, rebuild, rebuild_count,
-                       published);
-    SE2_HIP(hipGetLastError());
-    return SE2_OK;
+    return launch_kernel(&k_rebuild<NT, RBW>, dim3(grid), dim3(64 * RBW), lr, s, true, d_jobs, rebuild,
+                         rebuild_count, published);
 }
 
 template <int NT>
@@ -831,9 +826,9 @@ int launch_sparse_t(const ConvJob *d_jobs, int nblocks, const int32_t *d_block_j
     if (lds > 65536)
         SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sparse<NT>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-    hipLaunchKernelGGL(k_sparse<NT>, dim3(xcd_grid(nblocks)), dim3(64 * NW), lds, s, d_jobs, d_block_job, nblocks,
-                       rebuild, rebuild_count, next_count);
-    SE2_HIP(hipGetLastError());
+    const int rc = launch_kernel(&k_sparse<NT>, dim3(xcd_grid(nblocks)), dim3(64 * NW), lds, s, false, d_jobs,
+                                 d_block_job, nblocks, rebuild, rebuild_count, next_count);
+    if (rc) return rc;
     return rb_waves == 16 ? launch_rebuild_t<NT, 16>(d_jobs, nblocks, R_max, rebuild, rebuild_count, published, s)
                           : launch_rebuild_t<NT, 8>(d_jobs, nblocks, R_max, rebuild, rebuild_count, published, s);
 }

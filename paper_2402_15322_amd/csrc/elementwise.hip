@@ -151,6 +151,20 @@ __global__ __launch_bounds__(kThreads) void k_sum_items(const SumItem *__restric
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
+// Hands the n error sums of a check to the host: copies them into pinned host memory, then
+// (after a system-scope fence) stores `seq` to the host's flag word, which the host polls.
+// One workgroup; it runs after k_sum_items in stream order, so the sums are complete.
+__global__ __launch_bounds__(kThreads) void k_publish(const double *__restrict__ errs, int n,
+                                                      double *__restrict__ host_errs, int *host_flag, int seq) {
+    for (int i = threadIdx.x; i < n; i += kThreads) host_errs[i] = errs[i];
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence_system();
+        *reinterpret_cast<volatile int *>(host_flag) = seq;
+    }
+}
+
 // IBP combine (Appendix A): log bar = sum_i lambda_i log d_i, then log v_i += log bar -
 // log d_i (log v_i = -inf where the barycenter is 0).  The sum runs in a fixed order: in
 // index order within chunks of kCombineChunk measures (one block row per chunk), then the
@@ -444,6 +458,13 @@ int launch_sum_partials(const double *partials, const int32_t *offsets, int njob
 int launch_sum_items(const SumItem *d_items, int n, double *out, hipStream_t s) {
     if (n <= 0) return SE2_OK;
     hipLaunchKernelGGL(k_sum_items, dim3(n), dim3(kThreads), 0, s, d_items, out);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
+int launch_publish(const double *errs, int n, double *host_errs, int *host_flag, int seq, hipStream_t s) {
+    if (n < 0 || !host_errs || !host_flag) return SE2_EINVAL;
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(kThreads), 0, s, errs, n, host_errs, host_flag, seq);
     SE2_HIP(hipGetLastError());
     return SE2_OK;
 }

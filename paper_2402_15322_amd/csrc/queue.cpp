@@ -405,6 +405,9 @@ void lane_main(se2_queue_s *Q, int l) {
                     finished.push_back(q);
                 }
         }
+        // a check folds the timing events of the interval before it; when solves finish here,
+        // fold the rest too, so that the intervals are published before their tickets complete
+        if (check && !finished.empty()) (void)eng.collect_profile();
         {
             std::lock_guard<std::mutex> lk(Q->mu);
             Q->steps += 1;

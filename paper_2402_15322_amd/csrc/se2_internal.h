@@ -28,6 +28,7 @@ constexpr int kMaxMeasures = 65535;  // measures of one barycenter (a launch gri
     } while (0)
 
 void set_last_hip_error(hipError_t e, const char *what, const char *file, int line);
+void set_last_error(const std::string &msg);  // the message se2_strerror() returns next
 
 // Pruning state of one convolution direction of one solve.
 struct ListSet {
@@ -118,6 +119,9 @@ struct SumItem {
     int32_t begin, end;
 };
 int launch_sum_items(const SumItem *d_items, int n, double *out, hipStream_t s);
+// Copies errs[0, n) to host_errs (pinned, device-addressable) and then stores seq to
+// *host_flag (the same memory kind) for a host that polls it.
+int launch_publish(const double *errs, int n, double *host_errs, int *host_flag, int seq, hipStream_t s);
 int launch_sum_partials(const double *partials, const int32_t *offsets, int njobs, double *out, hipStream_t s);
 // IBP combine over device tables of the measures' log v_i and log d_i pointers and weights;
 // `part` holds combine_chunks(n) * len doubles (unused when that is 1).

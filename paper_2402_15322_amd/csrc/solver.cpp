@@ -15,11 +15,17 @@
 // The w-update of iteration j+1 yields max_i sum mu_i |2^(lw_i^(j) - lw_i^(j+1)) - 1|,
 // the mu_i-side marginal error of iterate j (its barycenter side is exact).
 #include "solver.h"
+#include "launch.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
+#include <atomic>
 #include <chrono>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <thread>
 
 namespace se2 {
 
@@ -153,8 +159,18 @@ int reset_list(const ListSet &l, const Solve &s, hipStream_t st) {
 }
 }  // namespace
 
+// roctx ranges of a solve's phases, for tools that record them (rocprofv3 --marker-trace):
+// "se2 bulk" (the bulk engine of a solve with polish), "se2 solve" (a solve on one engine),
+// "se2 polish" (after the switch) and "se2 check" (the FP64 check and the report).  Each
+// solve has at most one range open; opening the next closes it.
+static void trace_phase(Solve &s, const char *name) {
+    if (s.trace_range != 0) roctxRangeStop(s.trace_range);
+    s.trace_range = name ? roctxRangeStartA(name) : 0;
+}
+
 int solve_reset_lists(Solve &s, hipStream_t st) {
     int rc = SE2_OK;
+    trace_phase(s, s.opts.polish ? "se2 bulk" : "se2 solve");
     s.phase = 0;
     s.phase_switch_iter = -1;
     s.prev_err = -1.0;
@@ -263,6 +279,7 @@ void phase_after_check(Solve &s, double err) {
         if (err <= s.opts.switch_tol || stalled) {
             s.phase = 1;
             s.phase_switch_iter = s.iter;
+            trace_phase(s, "se2 polish");
         }
     }
     s.prev_err = err;
@@ -348,25 +365,30 @@ void Engine::set_profiling(bool on, hipEvent_t ref) {
     prof_intervals.clear();
 }
 
-int Engine::collect_profile() {
-    for (Pending &p : pending_) {
-        float ms = 0.0f;
-        SE2_HIP(hipEventSynchronize(p.b));
-        SE2_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+int Engine::collect_profile() { return fold_profile(pending_.size(), true); }
+
+int Engine::fold_profile(size_t count, bool wait) {
+    if (count > pending_.size()) count = pending_.size();
+    for (size_t i = 0; i < count; ++i) {
+        Pending &p = pending_[i];
+        if (wait) SE2_HIP(hipEventSynchronize(p.b));
+        float t0 = 0.0f, t1 = 0.0f;
         if (prof_ref_) {
-            float t0 = 0.0f, t1 = 0.0f;
             SE2_HIP(hipEventElapsedTime(&t0, prof_ref_, p.a));
             SE2_HIP(hipEventElapsedTime(&t1, prof_ref_, p.b));
             prof_intervals.emplace_back(t0, t1);
+        } else {
+            SE2_HIP(hipEventElapsedTime(&t1, p.a, p.b));
         }
-        prof_seconds += 1e-3 * ms;
+        prof_seconds += 1e-3 * static_cast<double>(t1 - t0);
         prof_terms += p.terms;
         prof_outputs += p.outputs;
         prof_launches += 1;
         spare_.push_back(p.a);
         spare_.push_back(p.b);
     }
-    pending_.clear();
+    pending_.erase(pending_.begin(), pending_.begin() + static_cast<std::ptrdiff_t>(count));
+    prof_ready_ = prof_ready_ > count ? prof_ready_ - count : 0;
     return SE2_OK;
 }
 
@@ -383,16 +405,14 @@ Engine::~Engine() {
     for (TableSlot &t : tables_) {
         if (t.d_jobs) (void)hipFree(t.d_jobs);
         if (t.d_map) (void)hipFree(t.d_map);
-        if (t.used) (void)hipEventDestroy(t.used);
     }
     if (h_jobs_) (void)hipHostFree(h_jobs_);
     if (h_map_) (void)hipHostFree(h_map_);
-    if (h_err_) (void)hipHostFree(h_err_);
+    if (h_chk_) (void)hipHostFree(h_chk_);
     if (h_published_) (void)hipHostFree(h_published_);
     if (h_items_) (void)hipHostFree(h_items_);
     if (d_items_) (void)hipFree(d_items_);
     if (d_errs_) (void)hipFree(d_errs_);
-    if (items_used_) (void)hipEventDestroy(items_used_);
     for (auto &e : staged_)
         if (e) (void)hipEventDestroy(e);
 }
@@ -418,11 +438,63 @@ int Engine::ensure(size_t njobs, size_t nblocks) {
     return SE2_OK;
 }
 
+bool debug_checks() {
+    static const bool on = [] {
+        const char *v = std::getenv("SE2_DEBUG");
+        return v != nullptr && v[0] != '\0' && std::strcmp(v, "0") != 0;
+    }();
+    return on;
+}
+
+namespace {
+
+int job_error(size_t q, const char *what) {
+    set_last_error(std::string("debug check of a launch, job ") + std::to_string(q) + ": " + what);
+    return SE2_EINVAL;
+}
+
+}  // namespace
+
+int check_jobs(const std::vector<ConvJob> &jobs, int nblocks, int nt, int R_max, LaunchKind kind, int rpw) {
+    const bool sparse = kind == LK_SPARSE;
+    const bool lin = kind == LK_LIN_BF16 || kind == LK_LIN_F32;
+    if (nt != 8 && nt != 16 && nt != 32) return job_error(0, "ntheta of the launch");
+    if (R_max < 0 || R_max > kMaxRadius) return job_error(0, "window radius of the launch");
+    if (sparse && !conv_lse_sparse_fits(nt, R_max)) return job_error(0, "sparse halo does not fit the LDS");
+    int next = 0;
+    for (size_t q = 0; q < jobs.size(); ++q) {
+        const ConvJob &j = jobs[q];
+        if (!j.in || !j.L64) return job_error(q, "null input or kernel table");
+        // an FP64 check writes no output: only the error partials against `old`
+        if (!j.out && !(kind == LK_F64 && j.epi == EPI_SCALE && j.old && j.partial))
+            return job_error(q, "null output");
+        if (j.in == j.out) return job_error(q, "output aliases the input (other tiles read its halo)");
+        if (j.nx < 1 || j.ny < 1) return job_error(q, "empty grid");
+        if (j.R < 0 || j.R > R_max || (lin && j.R != R_max)) return job_error(q, "job radius outside the launch's");
+        const int tx = (j.nx + kTile - 1) / kTile, ty = (j.ny + kTile - 1) / kTile;
+        if (j.tiles_x != tx || j.tiles != tx * ty) return job_error(q, "tile counts do not match the grid");
+        const int want = lin ? lin_blocks(j.nx, j.ny, rpw) : j.tiles;
+        if (j.blocks != want || j.first_block != next) return job_error(q, "block range of the job");
+        next += j.blocks;
+        if (j.epi != EPI_RAW && j.epi != EPI_SCALE && j.epi != EPI_ADD) return job_error(q, "epilogue kind");
+        if (j.epi != EPI_RAW && !j.aux) return job_error(q, "epilogue operand missing");
+        if (sparse && (!j.lists || !j.ref || !j.len || !j.mref || !j.L32 || j.lmax != kListMax))
+            return job_error(q, "pruning state of a sparse job");
+        if (lin && !j.kop) return job_error(q, "packed kernel of a matrix-core job");
+    }
+    if (next != nblocks) return job_error(jobs.size(), "blocks of the launch");
+    return SE2_OK;
+}
+
 int Engine::stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, int R_max, LaunchKind kind, int rpw,
                              hipStream_t st) {
     const bool sparse = kind == LK_SPARSE, f64 = kind == LK_F64;
     const bool lin = kind == LK_LIN_BF16 || kind == LK_LIN_F32;
     const size_t nj = jobs.size();
+    if (debug_checks()) {
+        const int rc = check_jobs(jobs, nblocks, nt, R_max, kind, rpw);
+        if (rc) return rc;
+    }
     TableSlot *t = nullptr;
     for (TableSlot &c : tables_)
         if (c.key.size() == nj && std::memcmp(c.key.data(), jobs.data(), nj * sizeof(ConvJob)) == 0) {
@@ -434,8 +506,10 @@ int Engine::stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, in
         t = &tables_[0];
         for (TableSlot &c : tables_)
             if (c.last < t->last) t = &c;
-        if (!t->used) SE2_HIP(hipEventCreateWithFlags(&t->used, hipEventDisableTiming));
-        else SE2_HIP(hipEventSynchronize(t->used));
+        if (t->last > drained_) {
+            const int rc = sync(st);
+            if (rc) return rc;
+        }
         if (nj > t->cap_jobs || static_cast<size_t>(nblocks) > t->cap_blocks) {
             if (t->d_jobs) SE2_HIP(hipFree(t->d_jobs));
             if (t->d_map) SE2_HIP(hipFree(t->d_map));
@@ -463,7 +537,8 @@ int Engine::stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, in
     t->last = ++clock_;
     if (sparse && static_cast<size_t>(nblocks) > cap_rebuild_) {
         // stream order: earlier launches that used the old buffers finish before it is freed
-        SE2_HIP(hipStreamSynchronize(st));
+        const int rs = sync(st);
+        if (rs) return rs;
         if (d_rebuild_) SE2_HIP(hipFree(d_rebuild_));
         if (!d_rebuild_count_) {
             // two counters used alternately: each sparse launch zeroes the other one
@@ -484,7 +559,8 @@ int Engine::stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, in
     if (lin)
         for (const ConvJob &j : jobs) cap_tiles += static_cast<size_t>(j.tiles);
     if (lin && cap_tiles > cap_fb_) {
-        SE2_HIP(hipStreamSynchronize(st));  // earlier launches that used the old list are done
+        const int rs = sync(st);  // earlier launches that used the old list are done
+        if (rs) return rs;
         if (d_fb_) SE2_HIP(hipFree(d_fb_));
         if (!d_fb_count_) {
             SE2_HIP(hipMalloc(&d_fb_count_, 2 * sizeof(int)));
@@ -514,8 +590,57 @@ int Engine::stage_and_launch(std::vector<ConvJob> &jobs, int nblocks, int nt, in
         rc = launch_conv_lse(t->d_jobs, static_cast<int>(nj), nblocks, t->d_map, nt, R_max, f64, true, d_rebuild_, cnt,
                              next, rb_waves, d_published_ + cls, st);
     }
-    if (rc) return rc;
-    SE2_HIP(hipEventRecord(t->used, st));
+    if (rc == SE2_OK && debug_checks()) {
+        // debug: every launch completes (or reports its failure) before the next is issued
+        SE2_HIP(hipStreamSynchronize(st));
+        SE2_HIP(hipGetLastError());
+        drained_ = clock_;
+    }
+    return rc;
+}
+
+LaunchEvents *&launch_events() {
+    thread_local LaunchEvents *current = nullptr;
+    return current;
+}
+
+namespace {
+
+// Installs a LaunchEvents for the launches of one profiled group (no-op when `on` is false)
+// and restores the previous one on exit.
+class EventScope {
+public:
+    EventScope(bool on, hipEvent_t start) : on_(on), prev_(launch_events()) {
+        if (!on_) return;
+        ev_.start = start;
+        launch_events() = &ev_;
+    }
+    ~EventScope() {
+        if (on_) launch_events() = prev_;
+    }
+    EventScope(const EventScope &) = delete;
+    EventScope &operator=(const EventScope &) = delete;
+    void arm_stop(hipEvent_t stop) {
+        if (on_) ev_.stop = stop;
+    }
+    int finish(hipStream_t st) {
+        if (ev_.start) SE2_HIP(hipEventRecord(ev_.start, st));
+        if (ev_.stop) SE2_HIP(hipEventRecord(ev_.stop, st));
+        ev_.start = ev_.stop = nullptr;
+        return SE2_OK;
+    }
+
+private:
+    bool on_;
+    LaunchEvents *prev_;
+    LaunchEvents ev_;
+};
+
+}  // namespace
+
+int Engine::sync(hipStream_t st) {
+    SE2_HIP(hipStreamSynchronize(st));
+    drained_ = clock_;
     return SE2_OK;
 }
 
@@ -641,7 +766,8 @@ int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool wit
                     e = spare_.back();
                     spare_.pop_back();
                 } else {
-                    SE2_HIP(hipEventCreate(&e));
+                    // timing only: a device-scope release (no system-scope cache writeback)
+                    SE2_HIP(hipEventCreateWithFlags(&e, hipEventReleaseToDevice));
                 }
                 (q == 0 ? pe.a : pe.b) = e;
             }
@@ -651,11 +777,16 @@ int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool wit
                 pe.terms += c * conv_terms(*s->k);
                 pe.outputs += c * static_cast<double>(s->E);
             }
-            SE2_HIP(hipEventRecord(pe.a, st));
         }
+        // the first kernel of the group takes pe.a as its start time and the last kernel of
+        // the last launcher takes pe.b as its end time: no marker packets between half-steps
+        EventScope scope(prof_, pe.a);
+        int calls_left = static_cast<int>(lin.size());
+        for (int g = 0; g < 3; ++g) calls_left += jobs[g].empty() ? 0 : 1;
         for (int g = 0; g < 3; ++g) {
             if (jobs[g].empty()) continue;
             const LaunchKind kind = g == 1 ? LK_SPARSE : (g == 2 ? LK_F64 : LK_DENSE);
+            if (--calls_left == 0) scope.arm_stop(pe.b);
             const int rc = stage_and_launch(jobs[g], nblocks[g], nt, R_max, kind, 0, st);
             if (rc) return rc;
         }
@@ -670,11 +801,13 @@ int Engine::launch_stage(const std::vector<Solve *> &solves, int stage, bool wit
                 j.blocks = lin_blocks(j.nx, j.ny, rpw);
                 nb += j.blocks;
             }
+            if (--calls_left == 0) scope.arm_stop(pe.b);
             const int rc = stage_and_launch(js, nb, nt, R, bf16 ? LK_LIN_BF16 : LK_LIN_F32, rpw, st);
             if (rc) return rc;
         }
         if (prof_) {
-            SE2_HIP(hipEventRecord(pe.b, st));
+            const int rc = scope.finish(st);  // events no kernel took (nothing launched) as markers
+            if (rc) return rc;
             pending_.push_back(pe);
         }
         for (Solve *s : solves) s->convs += (s->k->grid.ntheta == nt) ? (ot_like(*s) ? 1 : s->n) : 0;
@@ -733,8 +866,10 @@ int Engine::sum_errors(const std::vector<Solve *> &solves, hipStream_t st) {
     const bool same = items_key_.size() == n &&
                       std::memcmp(items_key_.data(), items.data(), n * sizeof(SumItem)) == 0;
     if (!same) {
-        if (!items_used_) SE2_HIP(hipEventCreateWithFlags(&items_used_, hipEventDisableTiming));
-        else SE2_HIP(hipEventSynchronize(items_used_));  // no copy or sum in flight uses the table
+        if (items_last_ > drained_) {  // no copy or sum in flight may use the table
+            const int rs = sync(st);
+            if (rs) return rs;
+        }
         if (n > cap_items_) {
             if (h_items_) SE2_HIP(hipHostFree(h_items_));
             if (d_items_) SE2_HIP(hipFree(d_items_));
@@ -748,10 +883,8 @@ int Engine::sum_errors(const std::vector<Solve *> &solves, hipStream_t st) {
         SE2_HIP(hipMemcpyAsync(d_items_, h_items_, n * sizeof(SumItem), hipMemcpyHostToDevice, st));
         items_key_ = items;
     }
-    int rc = launch_sum_items(d_items_, static_cast<int>(n), d_errs_, st);
-    if (rc) return rc;
-    SE2_HIP(hipEventRecord(items_used_, st));
-    return SE2_OK;
+    items_last_ = ++clock_;
+    return launch_sum_items(d_items_, static_cast<int>(n), d_errs_, st);
 }
 
 int Engine::read_errors(const std::vector<Solve *> &solves, std::vector<double> &max_err, hipStream_t st) {
@@ -760,23 +893,56 @@ int Engine::read_errors(const std::vector<Solve *> &solves, std::vector<double> 
     for (Solve *s : solves) total += ot_like(*s) ? 1 : s->n;
     if (total != items_key_.size() || !d_errs_) return SE2_EINVAL;
     if (total > cap_err_) {
-        if (h_err_) SE2_HIP(hipHostFree(h_err_));
-        SE2_HIP(hipHostMalloc(&h_err_, total * 2 * sizeof(double), hipHostMallocDefault));
+        // coherent pinned memory the GPU writes directly: the flag word in its own 256 bytes,
+        // then the errors
+        if (h_chk_) {
+            const int rs = sync(st);
+            if (rs) return rs;
+            SE2_HIP(hipHostFree(h_chk_));
+            h_chk_ = nullptr;
+        }
+        const size_t bytes = kChkHeader + total * 2 * sizeof(double);
+        SE2_HIP(hipHostMalloc(reinterpret_cast<void **>(&h_chk_), bytes, hipHostMallocCoherent));
+        std::memset(h_chk_, 0, bytes);
+        SE2_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&d_chk_), h_chk_, 0));
         cap_err_ = total * 2;
     }
-    SE2_HIP(hipMemcpyAsync(h_err_, d_errs_, total * sizeof(double), hipMemcpyDeviceToHost, st));
-    SE2_HIP(hipStreamSynchronize(st));
-    if (prof_) {
-        int rc = collect_profile();
-        if (rc) return rc;
+    int *flag = reinterpret_cast<int *>(h_chk_);
+    const double *h_err = reinterpret_cast<const double *>(h_chk_ + kChkHeader);
+    const int seq = ++chk_seq_;
+    int rc = launch_publish(d_errs_, static_cast<int>(total), reinterpret_cast<double *>(d_chk_ + kChkHeader),
+                            reinterpret_cast<int *>(d_chk_), seq, st);
+    if (rc) return rc;
+    // while the queued iterations run: fold the timing events known to be complete (those
+    // recorded before the previous check's results arrived)
+    if (prof_ && (rc = fold_profile(prof_ready_, false))) return rc;
+    // Poll the flag (a lane waits here for the queued iterations to finish; polling answers
+    // within a microsecond where a blocking synchronisation takes tens).  After kCheckPollMs
+    // the wait blocks in hipStreamSynchronize, which also reports a failed launch.
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int spins = 0; *reinterpret_cast<volatile int *>(flag) != seq; ++spins) {
+        if ((spins & 255) == 255) {
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(kCheckPollMs)) {
+                const int rs = sync(st);
+                if (rs) return rs;
+                if (*reinterpret_cast<volatile int *>(flag) != seq) {
+                    set_last_error("the check results did not arrive although the stream drained");
+                    return SE2_EHIP;
+                }
+                break;
+            }
+            std::this_thread::yield();
+        }
     }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    prof_ready_ = pending_.size();  // everything recorded before the results is complete
     max_err.assign(solves.size(), 0.0);
     size_t off = 0;
     for (size_t q = 0; q < solves.size(); ++q) {
         const size_t c = ot_like(*solves[q]) ? 1 : solves[q]->n;
         double m = 0.0;
         for (size_t i = 0; i < c; ++i) {
-            const double e = h_err_[off + i];
+            const double e = h_err[off + i];
             if (!(e <= m)) m = e;  // NaN propagates
         }
         max_err[q] = m;
@@ -854,6 +1020,7 @@ int finish_solves(Engine &eng, std::vector<FinishReq> &reqs, hipStream_t st) {
     //    IBP: [2+2i] cost and [3+2i] mass of plan i, [2+2n] barycenter mass, [3+2n+i] FP64 check i
     std::vector<ConvJob> chk_a, chk_b;
     std::vector<int> nt_a, nt_b;
+    for (FinishReq &q : reqs) trace_phase(*q.s, "se2 check");
     for (FinishReq &q : reqs) {
         Solve &s = *q.s;
         const Kernel &k = *s.k;
@@ -932,6 +1099,7 @@ int finish_solves(Engine &eng, std::vector<FinishReq> &reqs, hipStream_t st) {
         }
     }
     SE2_HIP(hipStreamSynchronize(st));
+    eng.mark_drained();
     // 3. reports
     for (FinishReq &q : reqs) {
         Solve &s = *q.s;
@@ -988,6 +1156,7 @@ int finish_solves(Engine &eng, std::vector<FinishReq> &reqs, hipStream_t st) {
         r.seconds = now_seconds() - s.t_start;
         q.rc = (std::isfinite(r.cost) && std::isfinite(r.marg_l1)) ? SE2_OK : SE2_ENUMERIC;
         q.rep = r;
+        trace_phase(s, nullptr);
     }
     return SE2_OK;
 }

@@ -69,6 +69,7 @@ struct Solve {
     int phase = 0;                   // 0: bulk, 1: polish
     int phase_switch_iter = -1;      // iteration at which the polish phase began
     double prev_err = -1.0;          // error of the previous check of the current stage
+    uint64_t trace_range = 0;        // roctx range of the current phase (0: none open)
     int32_t *fb_count = nullptr;     // per job (measure): groups recomputed after a failed certificate
     double terms_linear = 0.0;       // window terms evaluated by the matrix-core engines
     // memory
@@ -124,6 +125,14 @@ inline bool final_stage(const Solve &s) { return s.stage + 1 >= static_cast<int>
 // engines on the matrix cores (bfloat16 or FP32 operands) with their exact recomputation.
 enum LaunchKind { LK_DENSE = 0, LK_SPARSE = 1, LK_F64 = 2, LK_LIN_BF16 = 3, LK_LIN_F32 = 4 };
 
+// Debug checks, on when the environment variable SE2_DEBUG is set (and not "0") at the
+// first launch: every job table is checked on the host against the invariants the kernels
+// assume (grid and tile counts, block ranges, radius within the launch's, no output aliasing
+// its input, the pruning state of sparse jobs), and every launch is synchronised, so that
+// a failing kernel is reported by the launch that issued it.  Results are unchanged.
+bool debug_checks();
+int check_jobs(const std::vector<ConvJob> &jobs, int nblocks, int nt, int R_max, LaunchKind kind, int rpw);
+
 // Advances a set of solves (same ntheta or not) by one iteration each, with batched
 // launches: one launch per (stage, ntheta class, engine).  If `check` is true, also reduces
 // each solve's marginal error into its device `err` slot.
@@ -152,7 +161,11 @@ public:
     std::vector<std::pair<double, double>> prof_intervals;
     // FP64 check convolutions (dense, FP64 exp): one launch per ntheta class.
     int launch_checks(const std::vector<ConvJob> &jobs, const std::vector<int> &nts, hipStream_t st);
-    int collect_profile();  // folds finished event pairs into the totals (after a sync)
+    // Folds the pending timing-event pairs into the totals, waiting for each; a check folds
+    // those already known complete by itself, so call this before reading the totals.
+    int collect_profile();
+    // The caller has synchronised the engine's stream: everything launched so far is done.
+    void mark_drained() { drained_ = clock_; }
     double prof_seconds = 0.0, prof_terms = 0.0, prof_outputs = 0.0;
     int64_t prof_launches = 0;
 
@@ -169,12 +182,16 @@ private:
         ConvJob *d_jobs = nullptr;
         int32_t *d_map = nullptr;
         size_t cap_jobs = 0, cap_blocks = 0;
-        hipEvent_t used = nullptr;  // recorded after each launch that reads the slot
-        uint64_t last = 0;
+        uint64_t last = 0;  // clock of the last launch that read the slot
     };
     static constexpr int kTableSlots = 16;
     TableSlot tables_[kTableSlots];
+    // Launch clock, and its value when the stream was last seen idle (after a host
+    // synchronisation).  An engine issues all its work on one stream, so a table slot or item
+    // table whose last use is not later than drained_ can be rewritten without waiting.
     uint64_t clock_ = 0;
+    uint64_t drained_ = 0;
+    int sync(hipStream_t st);  // hipStreamSynchronize, then drained_ = clock_
     int2 *d_rebuild_ = nullptr;      // tiles left to the wide rebuild kernel, one slot per block
     int *d_rebuild_count_ = nullptr;  // two counters, used alternately
     int *h_published_ = nullptr;      // pinned: rebuild items of the last launch per ntheta class
@@ -191,14 +208,18 @@ private:
     size_t cap_jobs_ = 0, cap_blocks_ = 0;
     int flip_ = 0;
     hipEvent_t staged_[2] = {nullptr, nullptr};
-    double *h_err_ = nullptr;
+    // check results: pinned coherent memory that k_publish writes (flag word, then errors)
+    static constexpr size_t kChkHeader = 256;
+    static constexpr int kCheckPollMs = 5;
+    char *h_chk_ = nullptr, *d_chk_ = nullptr;
     size_t cap_err_ = 0;
+    int chk_seq_ = 0;
     // batched error sums of a check: one item per (solve, job), results contiguous
     std::vector<SumItem> items_key_;   // the item table on the device
     SumItem *h_items_ = nullptr, *d_items_ = nullptr;
     double *d_errs_ = nullptr;
     size_t cap_items_ = 0;
-    hipEvent_t items_used_ = nullptr;
+    uint64_t items_last_ = 0;  // clock of the last error-sum launch that read the item table
     int sum_errors(const std::vector<Solve *> &solves, hipStream_t st);
     bool prof_ = false;
     hipEvent_t prof_ref_ = nullptr;
@@ -207,6 +228,8 @@ private:
         double terms, outputs;
     };
     std::vector<Pending> pending_;
+    size_t prof_ready_ = 0;  // leading entries of pending_ known to be complete
+    int fold_profile(size_t count, bool wait);
     std::vector<hipEvent_t> spare_;
 };
 
