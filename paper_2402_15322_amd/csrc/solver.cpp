@@ -909,7 +909,8 @@ int Engine::read_errors(const std::vector<Solve *> &solves, std::vector<double> 
     }
     int *flag = reinterpret_cast<int *>(h_chk_);
     const double *h_err = reinterpret_cast<const double *>(h_chk_ + kChkHeader);
-    const int seq = ++chk_seq_;
+    chk_seq_ = chk_seq_ == INT_MAX ? 1 : chk_seq_ + 1;  // never 0, the word's initial value
+    const int seq = chk_seq_;
     int rc = launch_publish(d_errs_, static_cast<int>(total), reinterpret_cast<double *>(d_chk_ + kChkHeader),
                             reinterpret_cast<int *>(d_chk_), seq, st);
     if (rc) return rc;
