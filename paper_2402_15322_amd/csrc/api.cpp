@@ -46,7 +46,7 @@ void kernel_free(Kernel *k) {
     for (auto &e : k->scaled) kernel_free(e.second);
     (void)hipFree(k->d_L64);
     (void)hipFree(k->d_L32);
-    (void)hipFree(k->d_cost);
+    (void)hipFree(k->d_cost32);
     (void)hipFree(k->d_K32);
     (void)hipFree(k->d_Kbf16);
     (void)hipFree(k->d_K64);

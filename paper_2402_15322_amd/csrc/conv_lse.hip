@@ -123,14 +123,17 @@ __device__ __forceinline__ int term_offset(uint32_t term, int nt, int R, int W, 
     return kc * npix + (2 * R - dyi) * HW + (2 * R - dxi);
 }
 
-// Dense evaluation of one 8 x 8 tile of a job: lse[q] receives the LSE of the lane's pixel
-// at orientation ko = wave + 4 q (lane = pixel px + 8 py of the tile; rows and columns past
-// the grid compute clamped garbage that the caller does not store).  The input halo is
-// staged in LDS KC orientations at a time (twice when KC < NT: the max pass, then the sum).
-template <int NT, int KC, bool F64EXP>
-__device__ __forceinline__ void dense_tile(const ConvJob &job, double *lds, int x0, int y0, int px, int py, int wave,
-                                           double (&lse)[NT / 4]) {
-    constexpr int NJ = NT / 4;
+// Dense evaluation of one 8 x 8 tile of a job at NQ output orientations per wave: lse[q]
+// receives the LSE of the lane's pixel at orientation ko[q] (wave-uniform; lane = pixel
+// px + 8 py of the tile; rows and columns past the grid compute clamped garbage that the
+// caller does not store).  The input halo is staged in LDS KC orientations at a time (twice
+// when KC < NT: the max pass, then the sum).  A wave with active == false takes part in the
+// staging only.  Each output's maximum and sum run over the same terms in the same order
+// whichever orientations share the wave, so the result of an output does not depend on NQ.
+template <int NT, int KC, bool F64EXP, int NQ>
+__device__ __forceinline__ void dense_tile_at(const ConvJob &job, double *lds, int x0, int y0, int px, int py,
+                                              const int (&ko)[NQ], bool active, double (&lse)[NQ]) {
+    constexpr int NJ = NQ;
     const int R = job.R, W = 2 * R + 1, HW = kTile + 2 * R, npix = HW * HW;
     const int nx = job.nx, ny = job.ny;
     const cdptr L64 = (cdptr)(job.L64);
@@ -142,6 +145,7 @@ __device__ __forceinline__ void dense_tile(const ConvJob &job, double *lds, int 
         if (k0 > 0) __syncthreads();
         load_halo<KC>(lds, job.in, NT, k0, x0, y0, R, HW, nx, ny);
         __syncthreads();
+        if (!active) continue;
         for (int dy = -R; dy <= R; ++dy) {
             for (int dx = -R; dx <= R; ++dx) {
                 const int hb = (py + R - dy) * HW + (px + R - dx);
@@ -150,7 +154,7 @@ __device__ __forceinline__ void dense_tile(const ConvJob &job, double *lds, int 
                 for (int kc = 0; kc < KC; ++kc) {
                     const float v = static_cast<float>(lds[kc * npix + hb]);
 #pragma unroll
-                    for (int q = 0; q < NJ; ++q) mx[q] = fmaxf(mx[q], v + Lr[(wave + 4 * q) * NT + kc]);
+                    for (int q = 0; q < NJ; ++q) mx[q] = fmaxf(mx[q], v + Lr[ko[q] * NT + kc]);
                 }
             }
         }
@@ -167,6 +171,7 @@ __device__ __forceinline__ void dense_tile(const ConvJob &job, double *lds, int 
             load_halo<KC>(lds, job.in, NT, k0, x0, y0, R, HW, nx, ny);
             __syncthreads();
         }
+        if (!active) continue;
         for (int dy = -R; dy <= R; ++dy) {
             if constexpr (F64EXP) {
                 for (int dx = -R; dx <= R; ++dx) {
@@ -176,7 +181,7 @@ __device__ __forceinline__ void dense_tile(const ConvJob &job, double *lds, int 
                     for (int kc = 0; kc < KC; ++kc) {
                         const double v = lds[kc * npix + hb];
 #pragma unroll
-                        for (int q = 0; q < NJ; ++q) S[q] += exp2((v + Lr[(wave + 4 * q) * NT + kc]) - M[q]);
+                        for (int q = 0; q < NJ; ++q) S[q] += exp2((v + Lr[ko[q] * NT + kc]) - M[q]);
                     }
                 }
             } else {
@@ -192,7 +197,7 @@ __device__ __forceinline__ void dense_tile(const ConvJob &job, double *lds, int 
 #pragma unroll
                         for (int q = 0; q < NJ; ++q)
                             srow[q] += __builtin_amdgcn_exp2f(
-                                static_cast<float>((v + Lr[(wave + 4 * q) * NT + kc]) - M[q]));
+                                static_cast<float>((v + Lr[ko[q] * NT + kc]) - M[q]));
                     }
                 }
 #pragma unroll
@@ -202,6 +207,16 @@ __device__ __forceinline__ void dense_tile(const ConvJob &job, double *lds, int 
     }
 #pragma unroll
     for (int q = 0; q < NJ; ++q) lse[q] = (S[q] > 0.0) ? M[q] + log2(S[q]) : -INFINITY;
+}
+
+// All NT orientations of the tile: wave w takes ko = w, w + 4, ... .
+template <int NT, int KC, bool F64EXP>
+__device__ __forceinline__ void dense_tile(const ConvJob &job, double *lds, int x0, int y0, int px, int py, int wave,
+                                           double (&lse)[NT / 4]) {
+    int ko[NT / 4];
+#pragma unroll
+    for (int q = 0; q < NT / 4; ++q) ko[q] = wave + 4 * q;
+    dense_tile_at<NT, KC, F64EXP, NT / 4>(job, lds, x0, y0, px, py, ko, true, lse);
 }
 
 template <int NT, int KC, bool F64EXP>
@@ -729,53 +744,82 @@ __global__ __launch_bounds__(64 * RBW) void k_rebuild(const ConvJob *__restrict_
 
 // Exact log-domain recomputation of the (tile, ko) groups that the certificate of the
 // matrix-core engines rejected.  An item (job, tile, ko mask) is one 8 x 8 tile with the
-// orientations to recompute; a workgroup evaluates the whole tile as k_conv_lse does (the
-// halo is staged once for all orientations) and writes the outputs, error partial slots
-// [tile][ko] and counters of the masked orientations only: the others were written by the
-// matrix-core kernel, which for in-place updates has already replaced their previous values.
+// orientations to recompute.  A workgroup stages the tile's halo as k_conv_lse does and
+// evaluates the masked orientations only, the j-th set bit of the mask on wave j mod 4
+// (NQ = ceil(popcount / 4) per wave; a wave's spare slot repeats the lowest masked
+// orientation and is not stored).  It writes the outputs, error partial slots [tile][ko] and
+// counters of the masked orientations only: the others were written by the matrix-core
+// kernel, which for in-place updates has already replaced their previous values.  The
+// outputs are the same bits as a dense visit of the whole tile.
+__device__ __forceinline__ int nth_set_bit(uint32_t m, int j) {
+    for (int i = 0; i < j; ++i) m &= m - 1u;
+    return __builtin_ctz(m);
+}
+
+template <int NT, int KC, int NQ>
+__device__ __forceinline__ void lse_tile_item(const ConvJob &job, double *lds, int tile, uint32_t mask, int wave,
+                                              int lane) {
+    const int p = __popc(mask);
+    const int px = lane & 7, py = lane >> 3;
+    const int ty = tile / job.tiles_x;
+    const int tx = tile - ty * job.tiles_x;
+    const int x0 = tx * kTile, y0 = ty * kTile;
+    const int R = job.R;
+    const int nx = job.nx, ny = job.ny;
+    const int gx = x0 + px, gy = y0 + py;
+    const bool valid = gx < nx && gy < ny;
+    const size_t obase = (static_cast<size_t>(min(gy, ny - 1)) * nx + min(gx, nx - 1)) * NT;
+    int ko[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int j = wave + 4 * q;
+        ko[q] = __builtin_amdgcn_readfirstlane(nth_set_bit(mask, j < p ? j : 0));
+    }
+    double lse[NQ];
+    dense_tile_at<NT, KC, false, NQ>(job, lds, x0, y0, px, py, ko, wave < p, lse);
+    double work = 0.0;
+    if (valid) {
+        const int cx = min(R, gx) + min(R, nx - 1 - gx) + 1;
+        const int cy = min(R, gy) + min(R, ny - 1 - gy) + 1;
+        work = static_cast<double>(cx) * cy * NT;
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        if (wave + 4 * q >= p) continue;  // wave-uniform
+        const double err = valid ? epilogue(job, obase + ko[q], lse[q]) : 0.0;
+        const double es = wave_sum(err);
+        if (job.epi == EPI_SCALE && job.partial != nullptr && lane == 0)
+            job.partial[static_cast<size_t>(tile) * NT + ko[q]] = es;
+        const double ws = wave_sum(work);
+        if (job.work != nullptr && lane == 0) atomicAdd(&job.work[2 * tile], ws);
+    }
+}
+
+template <int NT, int KC, int NQ = 1>
+__device__ __forceinline__ void lse_tile_item_nq(int nq, const ConvJob &job, double *lds, int tile, uint32_t mask,
+                                                 int wave, int lane) {
+    if constexpr (NQ <= NT / 4) {
+        if (nq <= NQ)
+            lse_tile_item<NT, KC, NQ>(job, lds, tile, mask, wave, lane);
+        else
+            lse_tile_item_nq<NT, KC, NQ + 1>(nq, job, lds, tile, mask, wave, lane);
+    }
+}
+
 template <int NT, int KC>
 __global__ __launch_bounds__(kConvThreads) void k_lse_tiles(const ConvJob *__restrict__ jobs,
                                                             const int4 *__restrict__ items,
                                                             const int *__restrict__ count) {
     extern __shared__ double lds[];
-    constexpr int NJ = NT / 4;
     const int n = *count;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
-    const int px = lane & 7, py = lane >> 3;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int4 v = items[it];
         const ConvJob job = jobs[v.x];
-        const int tile = v.y;
-        const uint32_t mask = static_cast<uint32_t>(v.z);
-        const int ty = tile / job.tiles_x;
-        const int tx = tile - ty * job.tiles_x;
-        const int x0 = tx * kTile, y0 = ty * kTile;
-        const int R = job.R;
-        const int nx = job.nx, ny = job.ny;
-        const int gx = x0 + px, gy = y0 + py;
-        const bool valid = gx < nx && gy < ny;
-        const size_t obase = (static_cast<size_t>(min(gy, ny - 1)) * nx + min(gx, nx - 1)) * NT;
+        const uint32_t mask = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(v.z));
         __syncthreads();  // the LDS of the previous item is free
-        double lse[NJ];
-        dense_tile<NT, KC, false>(job, lds, x0, y0, px, py, wave, lse);
-        double work = 0.0;
-        if (valid) {
-            const int cx = min(R, gx) + min(R, nx - 1 - gx) + 1;
-            const int cy = min(R, gy) + min(R, ny - 1 - gy) + 1;
-            work = static_cast<double>(cx) * cy * NT;
-        }
-#pragma unroll
-        for (int q = 0; q < NJ; ++q) {
-            const int ko = wave + 4 * q;
-            if (((mask >> ko) & 1u) == 0u) continue;  // wave-uniform
-            const double err = valid ? epilogue(job, obase + ko, lse[q]) : 0.0;
-            const double es = wave_sum(err);
-            if (job.epi == EPI_SCALE && job.partial != nullptr && lane == 0)
-                job.partial[static_cast<size_t>(tile) * NT + ko] = es;
-            const double ws = wave_sum(work);
-            if (job.work != nullptr && lane == 0) atomicAdd(&job.work[2 * tile], ws);
-        }
+        if (mask != 0u) lse_tile_item_nq<NT, KC>((__popc(mask) + 3) >> 2, job, lds, v.y, mask, wave, lane);
         if (job.fallbacks != nullptr && threadIdx.x == 0) atomicAdd(job.fallbacks, __popc(mask));
     }
 }
@@ -833,6 +877,97 @@ int launch_sparse_t(const ConvJob *d_jobs, int nblocks, const int32_t *d_block_j
                           : launch_rebuild_t<NT, 8>(d_jobs, nblocks, R_max, rebuild, rebuild_count, published, s);
 }
 
+// Plan statistics of pi(x, y) = 2^(phi2(x) + L2[x - y] + psi2(y)), the transport plan of the
+// scalings (Section 4.1), for the transport cost sum pi rho_b^2 and the plan mass sum pi
+// (Section 2.2).  Workgroup (tile, g) of plan j = blockIdx.y covers the outputs x of one 8 x 8
+// tile at orientations ko = 4 g + wave (lane = pixel) and their windows; the psi halo is staged
+// in LDS KC orientations at a time, kernel and cost values are wave-uniform (scalar loads).
+// After an a-update the rows of pi sum to the first marginal, so every term is at most 1 and
+// 2^u needs no shift.  Sums: FP32 over the KC orientations of one window offset, FP64 over the
+// offsets, then lanes (butterflies) and the four waves in order.  Partial b of plan j goes to
+// part[2 b], part[2 b + 1] (one plan, interleaved) or part[2 j nb + b], part[(2 j + 1) nb + b]
+// (plan tables, planar), nb = gridDim.x.
+template <int NT, int KC>
+__global__ __launch_bounds__(kConvThreads) void k_plan_tiles(const double *__restrict__ phi1,
+                                                             const double *__restrict__ psi1,
+                                                             const double *const *__restrict__ phi_tab,
+                                                             const double *const *__restrict__ psi_tab,
+                                                             const double *__restrict__ L64_,
+                                                             const float *__restrict__ cost_, int nx, int ny, int R,
+                                                             int tiles_x, double *__restrict__ part) {
+    extern __shared__ double lds[];
+    __shared__ double s_sum[8];
+    constexpr int NG = NT / 4;
+    const int j = blockIdx.y;
+    const double *phi = phi_tab != nullptr ? phi_tab[j] : phi1;
+    const double *psi = psi_tab != nullptr ? psi_tab[j] : psi1;
+    const int tile = static_cast<int>(blockIdx.x) / NG;
+    const int g = static_cast<int>(blockIdx.x) - tile * NG;
+    const int ty = tile / tiles_x;
+    const int tx = tile - ty * tiles_x;
+    const int x0 = tx * kTile, y0 = ty * kTile;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int ko = 4 * g + wave;
+    const int px = lane & 7, py = lane >> 3;
+    const int gx = x0 + px, gy = y0 + py;
+    const bool valid = gx < nx && gy < ny;
+    const double f = valid ? phi[(static_cast<size_t>(gy) * nx + gx) * NT + ko] : -INFINITY;
+    const int W = 2 * R + 1, HW = kTile + 2 * R, npix = HW * HW;
+    const cdptr L64 = (cdptr)L64_;
+    const cfptr cost = (cfptr)cost_;
+    double c = 0.0, m = 0.0;
+    for (int k0 = 0; k0 < NT; k0 += KC) {
+        if (k0 > 0) __syncthreads();
+        load_halo<KC>(lds, psi, NT, k0, x0, y0, R, HW, nx, ny);
+        __syncthreads();
+        if (f == -INFINITY) continue;
+        for (int dy = -R; dy <= R; ++dy) {
+            for (int dx = -R; dx <= R; ++dx) {
+                const int hb = (py + R - dy) * HW + (px + R - dx);
+                const size_t row = (static_cast<size_t>((dy + R) * W + (dx + R)) * NT + ko) * NT + k0;
+                float rs = 0.0f, rc = 0.0f;
+#pragma unroll
+                for (int kc = 0; kc < KC; ++kc) {
+                    const double u = (f + L64[row + kc]) + lds[kc * npix + hb];
+                    const float p = __builtin_amdgcn_exp2f(static_cast<float>(u));
+                    rs += p;
+                    rc += p * cost[row + kc];
+                }
+                m += static_cast<double>(rs);
+                c += static_cast<double>(rc);
+            }
+        }
+    }
+    c = block_sum_waves(c, s_sum);
+    m = block_sum_waves(m, s_sum + 4);
+    if (threadIdx.x == 0) {
+        const size_t nb = gridDim.x;
+        if (phi_tab != nullptr) {
+            part[(2 * static_cast<size_t>(j)) * nb + blockIdx.x] = c;
+            part[(2 * static_cast<size_t>(j) + 1) * nb + blockIdx.x] = m;
+        } else {
+            part[2 * static_cast<size_t>(blockIdx.x)] = c;
+            part[2 * static_cast<size_t>(blockIdx.x) + 1] = m;
+        }
+    }
+}
+
+template <int NT, int KC>
+int launch_plan_t(const Kernel &k, const double *phi, const double *psi, const double *const *phi_tab,
+                  const double *const *psi_tab, int nplans, double *part, hipStream_t s) {
+    const int R = k.metric.radius, HW = kTile + 2 * R;
+    const size_t lds = static_cast<size_t>(HW) * HW * KC * sizeof(double);
+    if (lds > 65536)
+        SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_plan_tiles<NT, KC>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+    const int tx = (k.grid.nx + kTile - 1) / kTile, ty = (k.grid.ny + kTile - 1) / kTile;
+    hipLaunchKernelGGL((k_plan_tiles<NT, KC>), dim3(tx * ty * (NT / 4), nplans), dim3(kConvThreads), lds, s, phi, psi,
+                       phi_tab, psi_tab, k.d_L64, k.d_cost32, k.grid.nx, k.grid.ny, R, tx, part);
+    SE2_HIP(hipGetLastError());
+    return SE2_OK;
+}
+
 }  // namespace
 
 int launch_lse_tiles(const ConvJob *d_jobs, int grid, int nt, int R_max, const int4 *items, const int *count,
@@ -849,6 +984,31 @@ int launch_lse_tiles(const ConvJob *d_jobs, int grid, int nt, int R_max, const i
         case 32:
             return kc16 ? launch_tiles_t<32, 16>(d_jobs, grid, R_max, items, count, s)
                         : launch_tiles_t<32, 8>(d_jobs, grid, R_max, items, count, s);
+        default: return SE2_EINVAL;
+    }
+}
+
+int plan_parts(const Kernel &k) {
+    const int tx = (k.grid.nx + kTile - 1) / kTile, ty = (k.grid.ny + kTile - 1) / kTile;
+    return tx * ty * (k.grid.ntheta / 4);
+}
+
+int launch_plan_tiles(const Kernel &k, const double *phi, const double *psi, const double *const *phi_tab,
+                      const double *const *psi_tab, int nplans, double *part, hipStream_t s) {
+    if (nplans < 1) return SE2_OK;
+    const int R = k.metric.radius;
+    if (R < 0 || R > kMaxRadius || !part || (phi_tab == nullptr) != (psi_tab == nullptr) ||
+        (phi_tab == nullptr && (!phi || !psi || nplans != 1)))
+        return SE2_EINVAL;
+    const bool kc16 = (kTile + 2 * R) * (kTile + 2 * R) * 16 * 8 <= 65536;
+    switch (k.grid.ntheta) {
+        case 8: return launch_plan_t<8, 8>(k, phi, psi, phi_tab, psi_tab, nplans, part, s);
+        case 16:
+            return kc16 ? launch_plan_t<16, 16>(k, phi, psi, phi_tab, psi_tab, nplans, part, s)
+                        : launch_plan_t<16, 8>(k, phi, psi, phi_tab, psi_tab, nplans, part, s);
+        case 32:
+            return kc16 ? launch_plan_t<32, 16>(k, phi, psi, phi_tab, psi_tab, nplans, part, s)
+                        : launch_plan_t<32, 8>(k, phi, psi, phi_tab, psi_tab, nplans, part, s);
         default: return SE2_EINVAL;
     }
 }

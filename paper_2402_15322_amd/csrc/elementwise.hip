@@ -214,81 +214,6 @@ __global__ __launch_bounds__(kThreads) void k_ibp_vupdate(double *const *__restr
     }
 }
 
-// Plan statistics of pi(x, y) = 2^(phi2(x) + L2(x - y) + psi2(y)) over the window of the
-// output element i = (x, ko): its terms of sum pi * rho^2 and sum pi.
-template <int NT>
-__device__ __forceinline__ void plan_terms(const double *__restrict__ phi2, const double *__restrict__ psi2,
-                                           const double *__restrict__ L64, const double *__restrict__ cost, int nx,
-                                           int ny, int R, size_t i, double &c, double &m) {
-    const int W = 2 * R + 1;
-    const int ko = static_cast<int>(i % NT);
-    const size_t pix = i / NT;
-    const int ix = static_cast<int>(pix % nx), iy = static_cast<int>(pix / nx);
-    const double f = phi2[i];
-    if (f == -INFINITY) return;
-    for (int dy = -R; dy <= R; ++dy) {
-        const int jy = iy - dy;
-        if (jy < 0 || jy >= ny) continue;
-        for (int dx = -R; dx <= R; ++dx) {
-            const int jx = ix - dx;
-            if (jx < 0 || jx >= nx) continue;
-            const size_t kb = (static_cast<size_t>((dy + R) * W + (dx + R)) * NT + ko) * NT;
-            const double *g = psi2 + (static_cast<size_t>(jy) * nx + jx) * NT;
-            float rs = 0.0f, rc = 0.0f;
-            for (int ki = 0; ki < NT; ++ki) {
-                const double u = (f + L64[kb + ki]) + g[ki];
-                const float p = __builtin_amdgcn_exp2f(static_cast<float>(u));
-                rs += p;
-                rc += p * static_cast<float>(cost[kb + ki]);
-            }
-            m += rs;
-            c += rc;
-        }
-    }
-}
-
-// Per block [sum pi * rho^2, sum pi].  One thread per output element (x, ko).
-template <int NT>
-__global__ __launch_bounds__(kThreads) void k_plan_cost(const double *__restrict__ phi2,
-                                                        const double *__restrict__ psi2,
-                                                        const double *__restrict__ L64,
-                                                        const double *__restrict__ cost, int nx, int ny, int R,
-                                                        double *__restrict__ part) {
-    __shared__ double sh[kThreads];
-    const size_t n = static_cast<size_t>(nx) * ny * NT;
-    const size_t i = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x;
-    double c = 0.0, m = 0.0;
-    if (i < n) plan_terms<NT>(phi2, psi2, L64, cost, nx, ny, R, i, c, m);
-    c = block_tree_sum(c, sh);
-    m = block_tree_sum(m, sh);
-    if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = c;
-        part[2 * blockIdx.x + 1] = m;
-    }
-}
-
-// The same for many plans of one grid (blockIdx.y = plan j, scalings from device tables):
-// part[(2 j) nb + block] = sum pi * rho^2, part[(2 j + 1) nb + block] = sum pi.
-template <int NT>
-__global__ __launch_bounds__(kThreads) void k_plan_cost_tab(const double *const *__restrict__ phi_tab,
-                                                            const double *const *__restrict__ psi_tab,
-                                                            const double *__restrict__ L64,
-                                                            const double *__restrict__ cost, int nx, int ny, int R,
-                                                            double *__restrict__ part) {
-    __shared__ double sh[kThreads];
-    const size_t n = static_cast<size_t>(nx) * ny * NT;
-    const size_t i = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x;
-    const int j = blockIdx.y;
-    double c = 0.0, m = 0.0;
-    if (i < n) plan_terms<NT>(phi_tab[j], psi_tab[j], L64, cost, nx, ny, R, i, c, m);
-    c = block_tree_sum(c, sh);
-    m = block_tree_sum(m, sh);
-    if (threadIdx.x == 0) {
-        part[(2 * static_cast<size_t>(j)) * gridDim.x + blockIdx.x] = c;
-        part[(2 * static_cast<size_t>(j) + 1) * gridDim.x + blockIdx.x] = m;
-    }
-}
-
 // Per block: sum over entries with m > 0 of f2 * m.
 __global__ __launch_bounds__(kThreads) void k_dot_pos(const double *__restrict__ f2, const double *__restrict__ m,
                                                       size_t n, size_t chunk, double *__restrict__ part) {
@@ -482,48 +407,6 @@ int launch_ibp_combine(double *const *d_lv, const double *const *d_ld, const dou
         SE2_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_ibp_vupdate, dim3(gx, nchunks), dim3(kThreads), 0, s, d_lv, d_ld, n, len, logbar);
-    SE2_HIP(hipGetLastError());
-    return SE2_OK;
-}
-
-// partials must hold 2 * ceil(E / 256) doubles; returns the block count through `tiles`-independent math.
-int launch_plan_cost(const Kernel &k, const double *phi2, const double *psi2, double *partials, int nblocks,
-                     hipStream_t s) {
-    const int nx = k.grid.nx, ny = k.grid.ny, R = k.metric.radius;
-    switch (k.grid.ntheta) {
-        case 8:
-            hipLaunchKernelGGL(k_plan_cost<8>, dim3(nblocks), dim3(kThreads), 0, s, phi2, psi2, k.d_L64, k.d_cost,
-                               nx, ny, R, partials);
-            break;
-        case 16:
-            hipLaunchKernelGGL(k_plan_cost<16>, dim3(nblocks), dim3(kThreads), 0, s, phi2, psi2, k.d_L64,
-                               k.d_cost, nx, ny, R, partials);
-            break;
-        case 32:
-            hipLaunchKernelGGL(k_plan_cost<32>, dim3(nblocks), dim3(kThreads), 0, s, phi2, psi2, k.d_L64,
-                               k.d_cost, nx, ny, R, partials);
-            break;
-        default:
-            return SE2_EINVAL;
-    }
-    SE2_HIP(hipGetLastError());
-    return SE2_OK;
-}
-
-int launch_plan_cost_tab(const Kernel &k, const double *const *phi_tab, const double *const *psi_tab, int njobs,
-                         double *partials, int nblocks, hipStream_t s) {
-    const int nx = k.grid.nx, ny = k.grid.ny, R = k.metric.radius;
-    if (njobs < 1) return SE2_OK;
-    const dim3 g(nblocks, njobs), b(kThreads);
-    switch (k.grid.ntheta) {
-        case 8: hipLaunchKernelGGL(k_plan_cost_tab<8>, g, b, 0, s, phi_tab, psi_tab, k.d_L64, k.d_cost, nx, ny, R,
-                                   partials); break;
-        case 16: hipLaunchKernelGGL(k_plan_cost_tab<16>, g, b, 0, s, phi_tab, psi_tab, k.d_L64, k.d_cost, nx, ny, R,
-                                    partials); break;
-        case 32: hipLaunchKernelGGL(k_plan_cost_tab<32>, g, b, 0, s, phi_tab, psi_tab, k.d_L64, k.d_cost, nx, ny, R,
-                                    partials); break;
-        default: return SE2_EINVAL;
-    }
     SE2_HIP(hipGetLastError());
     return SE2_OK;
 }

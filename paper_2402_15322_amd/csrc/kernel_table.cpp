@@ -99,7 +99,7 @@ int build_tables(Kernel &k) {
     const size_t e = k.entries;
     SE2_HIP(hipMalloc(&k.d_L64, e * sizeof(double)));
     SE2_HIP(hipMalloc(&k.d_L32, e * sizeof(float)));
-    SE2_HIP(hipMalloc(&k.d_cost, e * sizeof(double)));
+    SE2_HIP(hipMalloc(&k.d_cost32, e * sizeof(float)));
     SE2_HIP(hipMalloc(&k.d_K32, e * sizeof(float)));
     SE2_HIP(hipMalloc(&k.d_Kbf16, e * sizeof(uint16_t)));
     SE2_HIP(hipMalloc(&k.d_K64, e * sizeof(double)));
@@ -113,7 +113,8 @@ int build_tables(Kernel &k) {
     }
     SE2_HIP(hipMemcpy(k.d_L64, L2.data(), e * sizeof(double), hipMemcpyHostToDevice));
     SE2_HIP(hipMemcpy(k.d_L32, L32.data(), e * sizeof(float), hipMemcpyHostToDevice));
-    SE2_HIP(hipMemcpy(k.d_cost, k.cost.data(), e * sizeof(double), hipMemcpyHostToDevice));
+    const std::vector<float> C32(k.cost.begin(), k.cost.end());
+    SE2_HIP(hipMemcpy(k.d_cost32, C32.data(), e * sizeof(float), hipMemcpyHostToDevice));
     SE2_HIP(hipMemcpy(k.d_K32, K32.data(), e * sizeof(float), hipMemcpyHostToDevice));
     SE2_HIP(hipMemcpy(k.d_Kbf16, Kb.data(), e * sizeof(uint16_t), hipMemcpyHostToDevice));
     SE2_HIP(hipMemcpy(k.d_K64, K64.data(), e * sizeof(double), hipMemcpyHostToDevice));

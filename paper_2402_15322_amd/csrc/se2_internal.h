@@ -49,7 +49,7 @@ struct Kernel {
     std::vector<double> cost;   // rho^2 (host copy)
     double *d_L64 = nullptr;    // log2 kernel, FP64
     float *d_L32 = nullptr;     // log2 kernel, FP32
-    double *d_cost = nullptr;   // rho^2, FP64
+    float *d_cost32 = nullptr;  // rho^2, FP32 (plan statistics)
     float *d_K32 = nullptr;     // exp(logk) in FP32 (zero below the FP32 range)
     uint16_t *d_Kbf16 = nullptr; // exp(logk) in bfloat16 (RNE), table layout
     double *d_K64 = nullptr;    // exp(logk) in FP64
@@ -129,12 +129,12 @@ constexpr int kCombineChunk = 64;
 inline int combine_chunks(int n) { return (n + kCombineChunk - 1) / kCombineChunk; }
 int launch_ibp_combine(double *const *d_lv, const double *const *d_ld, const double *d_lam, int n, size_t len,
                        double *part, double *logbar, hipStream_t s);
-int launch_plan_cost(const Kernel &k, const double *phi2, const double *psi2, double *partials /* per tile x 3 */,
-                     int tiles, hipStream_t s);
-// Plan statistics of njobs plans of one grid in one launch (blockIdx.y = plan), partials
-// laid out [job][cost | mass][nblocks].
-int launch_plan_cost_tab(const Kernel &k, const double *const *phi_tab, const double *const *psi_tab, int njobs,
-                         double *partials, int nblocks, hipStream_t s);
+// Plan statistics (transport cost sum pi rho^2 and mass sum pi) of pi = 2^(phi2 + L2 + psi2):
+// one plan from phi/psi (tables null; partials [part][cost, mass]) or nplans plans from device
+// pointer tables (partials [plan][cost | mass][part]); plan_parts(k) partials per plan.
+int plan_parts(const Kernel &k);
+int launch_plan_tiles(const Kernel &k, const double *phi, const double *psi, const double *const *phi_tab,
+                      const double *const *psi_tab, int nplans, double *part, hipStream_t s);
 // JKO step of the porous-medium flow: psi = prox(lsum) - lsum (base 2), nu = 2^(psi + lsum),
 // and per-block partials of F(nu) = ref/(m-1) sum (nu/ref)^m.
 int launch_porous_prox(const double *lsum, double *psi, size_t n, double c, double m, hipStream_t s);

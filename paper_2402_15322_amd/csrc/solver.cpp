@@ -51,8 +51,6 @@ struct Carver {
     }
 };
 
-int cost_blocks(size_t E) { return static_cast<int>((E + 255) / 256); }
-
 ListSet carve_lists(Carver &c, const Kernel &k, size_t E, int tiles, bool prune, double *work = nullptr) {
     const int nt = k.grid.ntheta, HW = kTile + 2 * k.metric.radius;
     ListSet l;
@@ -74,7 +72,7 @@ size_t carve(Solve &s, int kind, const Kernel &k, int n, bool prune, void *mem) 
     prune = prune && conv_lse_sparse_fits(k.grid.ntheta, k.metric.radius);
     const int nj = kind != SE2_REQ_BARYCENTER ? 1 : n;
     const size_t npart = static_cast<size_t>(tiles) * k.grid.ntheta * nj;
-    const size_t ncost = 2 * static_cast<size_t>(cost_blocks(E)) * nj + 512;
+    const size_t ncost = 2 * static_cast<size_t>(plan_parts(k)) * nj + 512;
     Carver c{static_cast<char *>(mem)};
     if (kind != SE2_REQ_BARYCENTER) {
         s.lmu = c.take<double>(E);
@@ -340,7 +338,7 @@ int solve_setup_bary(Solve &s, const std::vector<const double *> &mus, hipStream
     SE2_HIP(hipMemcpyAsync(s.d_lv, s.lv.data(), s.n * sizeof(double *), hipMemcpyHostToDevice, st));
     SE2_HIP(hipMemcpyAsync(s.d_ld, s.ld.data(), s.n * sizeof(double *), hipMemcpyHostToDevice, st));
     SE2_HIP(hipMemcpyAsync(s.d_lw, s.lw.data(), s.n * sizeof(double *), hipMemcpyHostToDevice, st));
-    const int nb = cost_blocks(s.E);
+    const int nb = plan_parts(*s.k);
     std::vector<SumItem> items(2 * static_cast<size_t>(s.n));
     for (int j = 0; j < 2 * s.n; ++j) items[j] = SumItem{s.partial, j * nb, (j + 1) * nb};
     SE2_HIP(hipMemcpyAsync(s.d_cost_items, items.data(), items.size() * sizeof(SumItem), hipMemcpyHostToDevice, st));
@@ -1025,7 +1023,7 @@ int finish_solves(Engine &eng, std::vector<FinishReq> &reqs, hipStream_t st) {
     for (FinishReq &q : reqs) {
         Solve &s = *q.s;
         const Kernel &k = *s.k;
-        const int nb = cost_blocks(s.E);
+        const int nb = plan_parts(k);
         double *part = s.partial;  // scratch: >= 2 * nb + 512 doubles
         int rc = SE2_OK;
         if (ot_like(s)) {
@@ -1033,7 +1031,7 @@ int finish_solves(Engine &eng, std::vector<FinishReq> &reqs, hipStream_t st) {
             const double *phi = s.phi[s.cur];
             if (q.f_out && (rc = launch_scale(phi, q.f_out, s.E, scale, st))) return rc;
             if (q.g_out && (rc = launch_scale(s.psi, q.g_out, s.E, scale, st))) return rc;
-            if ((rc = launch_plan_cost(k, phi, s.psi, part, nb, st))) return rc;
+            if ((rc = launch_plan_tiles(k, phi, s.psi, nullptr, nullptr, 1, part, st))) return rc;
             if ((rc = launch_reduce_fixed(part, nb, 2, s.err + 2, st))) return rc;
             const int dnb = 256;
             if (s.kind == kKindJKO) {
@@ -1062,7 +1060,8 @@ int finish_solves(Engine &eng, std::vector<FinishReq> &reqs, hipStream_t st) {
             if ((rc = launch_exp2_out(s.logbar, q.bary_out, s.E, st))) return rc;
             // sum_i lambda_i <pi_i, rho^2> with pi_i = diag(w_i) K diag(v_i) (first marginal exact):
             // every plan in one launch, then the cost and mass sums of each in one launch
-            if ((rc = launch_plan_cost_tab(k, s.d_lw, const_cast<const double *const *>(s.d_lv), s.n, part, nb, st)))
+            if ((rc = launch_plan_tiles(k, nullptr, nullptr, s.d_lw, const_cast<const double *const *>(s.d_lv), s.n,
+                                        part, st)))
                 return rc;
             if ((rc = launch_sum_items(s.d_cost_items, 2 * s.n, s.err + 2, st))) return rc;
             // barycenter mass (FP64 fixed-order sum, the validation reduction)
