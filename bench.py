@@ -51,7 +51,7 @@ FP64_STATE_BYTES_PER_ELEMENT = 32
 # launch pairs of one bench step and divided by its 2004 half-steps;
 # profiles/conv_lse_traffic_lines64x64x16_batch32.md.  Reported only while the kernel's
 # sources (the kernel file and its shared header) are the ones measured.
-TRAFFIC = {"sources_sha256": "3e54558dabd2f1ded54b4c14d7d6364accbc1cb12223d97df3d69ea11482a424", "bytes_per_launch": 151702236.1,
+TRAFFIC = {"sources_sha256": "530dc52df664ba35fae3f7aab01937f412306ae8fbf098c64e0378c9de1225fe", "bytes_per_launch": 151610002.7,
            "sources": ("paper_2402_15322_amd/csrc/conv_lse.hip", "paper_2402_15322_amd/csrc/conv_lse.h")}
 
 
@@ -133,6 +133,8 @@ def parse():
     ap.add_argument("--conv-engines", default="f32,bf16>f32,f32_mfma,bf16>f32_mfma",
                     help="converged leg: engines, comma separated (prec, or bulk>prec)")
     ap.add_argument("--converged-only", action="store_true", help="only the converged leg (for profiling)")
+    ap.add_argument("--fields-only", action="store_true",
+                    help="only the 256x256x32 axial-field barycenter on every engine (for profiling)")
     ap.add_argument("--halo-spread", action="store_true",
                     help="only the spread of the log-potentials over a tile's halo and the matrix-core engines' "
                          "fallback shares, per workload and eps")
@@ -304,20 +306,22 @@ def gradient_flow(native, torch, synth, steps: int):
             "energy": [r["dual"] for r in reps], "transport_cost": [r["cost"] for r in reps]}
 
 
-def barycenter_workloads(native, torch, synth, c4_iters: int):
-    import numpy as np
+def barycenter_workloads(native, torch, synth, c4_iters: int, only=None):
     """The two barycenter workloads through the queue, convolution timing on.
     128x128x16 interpolation: two Bezier-stroke measures, w = (1,3,1), eps = 0.05, 15x15
     window, the five weights t in {0, 1/4, 1/2, 3/4, 1} as five resident requests, tol 1e-6,
     max 1000 IBP iterations, pruned engine.  256x256x32 axial fields: four measures, equal
     weights, w = (1,4,1), eps = 0.03, 21x21 window (the dense engine: the FP64 halo does not
-    fit the sparse kernel's LDS), `c4_iters` IBP iterations."""
+    fit the sparse kernel's LDS), `c4_iters` IBP iterations.  `only`: the names to run."""
+    import numpy as np
     out = {}
     for name, insts, o in (
             ("curves128x128x16_t5", [synth.curves128(0, t=t) for t in (0.0, 0.25, 0.5, 0.75, 1.0)],
              native.opts(tol=1e-6, max_iter=1000, check_every=10, final_check=True, prune=True)),
             ("fields256x256x32_axial_n4", [synth.fields256(0)],
              native.opts(tol=-1.0, max_iter=c4_iters, check_every=c4_iters, final_check=False, prune=True))):
+        if only is not None and name not in only:
+            continue
         g = insts[0].grid
         k = native.Kernel(g.nx, g.ny, g.nt, g.axial, insts[0].w, insts[0].eps, insts[0].radius)
         dev = [[torch.from_numpy(m).cuda() for m in inst.mus] for inst in insts]
@@ -333,22 +337,30 @@ def barycenter_workloads(native, torch, synth, c4_iters: int):
         q.close()
         engines = {}
         if name.startswith("fields256"):
-            # the same IBP iterations on the matrix-core engines, each barycenter against the
-            # exact engine's (no oracle at this size; the 64x64x8 downsample is in cpu_baseline)
+            # the same IBP iterations as blocking calls on the exact engine and the matrix-core
+            # engines, each barycenter against the queue's exact one (no oracle at this size; the
+            # 64x64x8 downsample is in cpu_baseline).  Runs of c4_iters and 2 c4_iters iterations
+            # are differenced: the cost per iteration without validation and finishing (later
+            # iterations recompute more groups on the matrix-core engines than the first ones).
             ref = outs[0].cpu().numpy()
-            for ename in ("bf16", "f32_mfma"):
-                oe = engine_opts(native, ename, tol=-1.0, max_iter=c4_iters, check_every=c4_iters, final_check=False)
-                be = torch.empty_like(outs[0])
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                re_ = native.se2_barycenter(k, dev[0], insts[0].lambdas, oe, be)
-                torch.cuda.synchronize()
-                we = time.perf_counter() - t1
-                E = float(ref.size)
-                engines[ename] = {"wall_s": we, "ibp_iters_per_s": re_["iters"] / we,
-                                  "fallback_group_share": re_["fallbacks"] / (2.0 * len(insts[0].mus) * re_["iters"]
-                                                                            * (E / (64.0 * g.nt)) * g.nt),
-                                  "barycenter_l1_vs_exact": float(np.abs(be.cpu().numpy() - ref).sum())}
+            E = float(ref.size)
+            groups_per_iter = 2.0 * len(insts[0].mus) * (E / (64.0 * g.nt)) * g.nt
+            for ename in ("f32", "bf16", "f32_mfma"):
+                runs = []
+                for it in (c4_iters, 2 * c4_iters):
+                    oe = engine_opts(native, ename, tol=-1.0, max_iter=it, check_every=it, final_check=False)
+                    be = torch.empty_like(outs[0])
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    re_ = native.se2_barycenter(k, dev[0], insts[0].lambdas, oe, be)
+                    torch.cuda.synchronize()
+                    runs.append((time.perf_counter() - t1, re_, be))
+                (w1, r1, b1), (w2, r2, _) = runs
+                per = (w2 - w1) / c4_iters
+                engines[ename] = {"wall_s": w1, "ibp_iters_per_s": r1["iters"] / w1,
+                                  "steady_ms_per_iter": per * 1e3,
+                                  "fallback_group_share": (r2["fallbacks"] - r1["fallbacks"]) / (c4_iters * groups_per_iter),
+                                  "barycenter_l1_vs_exact": float(np.abs(b1.cpu().numpy() - ref).sum())}
         out[name] = {"requests": len(insts), "iters": [r["iters"] for r in reps],
                      "converged": sum(1 for r in reps if r["status"] == native.SE2_CONVERGED),
                      "wall_s": wall, "ibp_iters_per_s": sum(r["iters"] for r in reps) / wall,
@@ -575,6 +587,10 @@ def main():
         return
     if a.converged_only:
         print(json.dumps(converged_leg(native, torch, synth, a)[0]), flush=True)
+        return
+    if a.fields_only:
+        print(json.dumps(barycenter_workloads(native, torch, synth, a.c4_iters, ("fields256x256x32_axial_n4",))),
+              flush=True)
         return
     if a.halo_spread:
         print(json.dumps(halo_spread(native, torch, synth)), flush=True)

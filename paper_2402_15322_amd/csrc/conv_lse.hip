@@ -124,15 +124,17 @@ __device__ __forceinline__ int term_offset(uint32_t term, int nt, int R, int W, 
 }
 
 // Dense evaluation of one 8 x 8 tile of a job at NQ output orientations per wave: lse[q]
-// receives the LSE of the lane's pixel at orientation ko[q] (wave-uniform; lane = pixel
+// receives the LSE of the lane's pixel at orientation ko(q) (wave-uniform; lane = pixel
 // px + 8 py of the tile; rows and columns past the grid compute clamped garbage that the
 // caller does not store).  The input halo is staged in LDS KC orientations at a time (twice
-// when KC < NT: the max pass, then the sum).  A wave with active == false takes part in the
-// staging only.  Each output's maximum and sum run over the same terms in the same order
-// whichever orientations share the wave, so the result of an output does not depend on NQ.
-template <int NT, int KC, bool F64EXP, int NQ>
+// when KC < NT: the max pass, then the sum).  With MAYIDLE, a wave with active == false takes
+// part in the staging only.  Each output's maximum and sum run over the same terms in the same
+// order whichever orientations share the wave, so the result of an output does not depend on
+// NQ.  (ko is a callable rather than an array so that the dense engine's ko = wave + 4 q stays
+// a compile-time stride: an array there cost the one-solve launches 1.5x.)
+template <int NT, int KC, bool F64EXP, int NQ, bool MAYIDLE, class KoF>
 __device__ __forceinline__ void dense_tile_at(const ConvJob &job, double *lds, int x0, int y0, int px, int py,
-                                              const int (&ko)[NQ], bool active, double (&lse)[NQ]) {
+                                              KoF ko, bool active, double (&lse)[NQ]) {
     constexpr int NJ = NQ;
     const int R = job.R, W = 2 * R + 1, HW = kTile + 2 * R, npix = HW * HW;
     const int nx = job.nx, ny = job.ny;
@@ -145,7 +147,7 @@ __device__ __forceinline__ void dense_tile_at(const ConvJob &job, double *lds, i
         if (k0 > 0) __syncthreads();
         load_halo<KC>(lds, job.in, NT, k0, x0, y0, R, HW, nx, ny);
         __syncthreads();
-        if (!active) continue;
+        if (MAYIDLE && !active) continue;
         for (int dy = -R; dy <= R; ++dy) {
             for (int dx = -R; dx <= R; ++dx) {
                 const int hb = (py + R - dy) * HW + (px + R - dx);
@@ -154,7 +156,7 @@ __device__ __forceinline__ void dense_tile_at(const ConvJob &job, double *lds, i
                 for (int kc = 0; kc < KC; ++kc) {
                     const float v = static_cast<float>(lds[kc * npix + hb]);
 #pragma unroll
-                    for (int q = 0; q < NJ; ++q) mx[q] = fmaxf(mx[q], v + Lr[ko[q] * NT + kc]);
+                    for (int q = 0; q < NJ; ++q) mx[q] = fmaxf(mx[q], v + Lr[ko(q) * NT + kc]);
                 }
             }
         }
@@ -171,7 +173,7 @@ __device__ __forceinline__ void dense_tile_at(const ConvJob &job, double *lds, i
             load_halo<KC>(lds, job.in, NT, k0, x0, y0, R, HW, nx, ny);
             __syncthreads();
         }
-        if (!active) continue;
+        if (MAYIDLE && !active) continue;
         for (int dy = -R; dy <= R; ++dy) {
             if constexpr (F64EXP) {
                 for (int dx = -R; dx <= R; ++dx) {
@@ -181,7 +183,7 @@ __device__ __forceinline__ void dense_tile_at(const ConvJob &job, double *lds, i
                     for (int kc = 0; kc < KC; ++kc) {
                         const double v = lds[kc * npix + hb];
 #pragma unroll
-                        for (int q = 0; q < NJ; ++q) S[q] += exp2((v + Lr[ko[q] * NT + kc]) - M[q]);
+                        for (int q = 0; q < NJ; ++q) S[q] += exp2((v + Lr[ko(q) * NT + kc]) - M[q]);
                     }
                 }
             } else {
@@ -197,7 +199,7 @@ __device__ __forceinline__ void dense_tile_at(const ConvJob &job, double *lds, i
 #pragma unroll
                         for (int q = 0; q < NJ; ++q)
                             srow[q] += __builtin_amdgcn_exp2f(
-                                static_cast<float>((v + Lr[ko[q] * NT + kc]) - M[q]));
+                                static_cast<float>((v + Lr[ko(q) * NT + kc]) - M[q]));
                     }
                 }
 #pragma unroll
@@ -213,10 +215,8 @@ __device__ __forceinline__ void dense_tile_at(const ConvJob &job, double *lds, i
 template <int NT, int KC, bool F64EXP>
 __device__ __forceinline__ void dense_tile(const ConvJob &job, double *lds, int x0, int y0, int px, int py, int wave,
                                            double (&lse)[NT / 4]) {
-    int ko[NT / 4];
-#pragma unroll
-    for (int q = 0; q < NT / 4; ++q) ko[q] = wave + 4 * q;
-    dense_tile_at<NT, KC, F64EXP, NT / 4>(job, lds, x0, y0, px, py, ko, true, lse);
+    dense_tile_at<NT, KC, F64EXP, NT / 4, false>(job, lds, x0, y0, px, py, [wave](int q) { return wave + 4 * q; },
+                                                 true, lse);
 }
 
 template <int NT, int KC, bool F64EXP>
@@ -776,7 +776,7 @@ __device__ __forceinline__ void lse_tile_item(const ConvJob &job, double *lds, i
         ko[q] = __builtin_amdgcn_readfirstlane(nth_set_bit(mask, j < p ? j : 0));
     }
     double lse[NQ];
-    dense_tile_at<NT, KC, false, NQ>(job, lds, x0, y0, px, py, ko, wave < p, lse);
+    dense_tile_at<NT, KC, false, NQ, true>(job, lds, x0, y0, px, py, [&ko](int q) { return ko[q]; }, wave < p, lse);
     double work = 0.0;
     if (valid) {
         const int cx = min(R, gx) + min(R, nx - 1 - gx) + 1;
