@@ -260,6 +260,37 @@ def test_barycenter_small(nat):
     assert abs(rep["mass"] - bar_o.sum()) <= 1e-6
 
 
+@pytest.mark.parametrize("shape", [(20, 13, 8, False), (21, 18, 16, False), (12, 10, 32, True)],
+                         ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}{'a' if c[3] else ''}")
+def test_barycenter_cost_matches_oracle(nat, shape):
+    """Transport cost and barycenter mass of an IBP solve (Appendix A): the cost is
+    sum_i lambda_i <pi_i, rho_b^2> with pi_i = diag(w_i) K diag(v_i) of the returned iterate,
+    whose w_i comes from the w-update that measured its error (so pi_i has marginal mu_i),
+    computed on the GPU from the measures' pointer tables; ragged tiles and all three
+    orientation counts."""
+    torch = torch_dev()
+    nx, ny, nt, axial = shape
+    g = synth.Grid(nx, ny, nt, axial)
+    mus = [synth.splat_segments(g, synth.draw_segments(synth.rng_for(79, s), g, 3, 3.0, 9.0), 1.0, 1e-6)
+           for s in range(3)]
+    lam = [0.25, 0.45, 0.3]
+    w, eps, R = (1.0, 2.0, 1.0), 0.4, 3
+    k = _kernel(nat, nx, ny, nt, axial, w, eps, R)
+    logk, cost = oracle.kernel_table(nt, axial, w, eps, R)
+    out = torch.empty((ny, nx, nt), dtype=torch.float64, device="cuda")
+    rep = nat.se2_barycenter(k, [to_dev(m) for m in mus], lam, nat.opts(tol=-1, max_iter=12, check_every=4), out)
+    bar_o, it_o, _, _, lv = oracle.ibp(logk, mus, lam, 12, -1.0, return_lv=True)
+    assert rep["iters"] == it_o == 12
+    c_o = 0.0
+    for i in range(3):
+        lw = oracle.safe_log(mus[i]) - oracle.conv_log(logk, lv[i])
+        c_i, m_i, _, _ = oracle.plan_stats(logk, cost, lw, lv[i])
+        assert abs(m_i - mus[i].sum()) <= 1e-9 * mus[i].sum()   # the mu_i side of pi_i is exact
+        c_o += lam[i] * c_i
+    assert abs(rep["cost"] - c_o) <= 1e-5 * c_o, (rep["cost"], c_o)
+    assert abs(rep["mass"] - bar_o.sum()) <= 1e-6
+
+
 def test_barycenter_weight_on_one_measure(nat):
     """lambda = e_1: the closed form bar = K*(mu_1 / K*1) (Appendix A with one active measure)."""
     torch = torch_dev()

@@ -100,17 +100,22 @@ def _gpu_bary(nat, inst, iters, prune=True, tol=-1.0, check_every=None):
 
 
 def test_barycenter_curves128_matches_oracle(nat):
-    """128x128x16 interpolation at t = 0.5 (two Bezier-stroke measures, no floor), 2 IBP iterations."""
+    """128x128x16 interpolation at t = 0.5 (two Bezier-stroke measures, no floor), 6 IBP
+    iterations (certified pruning on): barycenter, error, mass and the transport cost
+    sum_i lambda_i <pi_i, rho_b^2> of the returned iterate against the oracle."""
     inst = synth.curves128(0, t=0.5)
     g = inst.grid
-    logk, _ = oracle.kernel_table(g.nt, g.axial, inst.w, inst.eps, inst.radius)
-    bar_g, rep = _gpu_bary(nat, inst, 2)
-    bar_o, it_o, err_o, _ = oracle.ibp(logk, inst.mus, inst.lambdas, 2, -1.0)
-    assert rep["iters"] == it_o == 2
+    logk, cost = oracle.kernel_table(g.nt, g.axial, inst.w, inst.eps, inst.radius)
+    bar_g, rep = _gpu_bary(nat, inst, 6)
+    bar_o, it_o, err_o, _, lv = oracle.ibp(logk, inst.mus, inst.lambdas, 6, -1.0, return_lv=True)
+    assert rep["iters"] == it_o == 6
     l1 = float(np.sum(np.abs(bar_g - bar_o)))
     assert l1 <= 1e-5, l1
     assert abs(rep["marg_l1"] - err_o) <= 1e-6
     assert abs(rep["mass"] - bar_o.sum()) <= 1e-6
+    c_o = sum(lam * oracle.plan_stats(logk, cost, oracle.safe_log(m) - oracle.conv_log(logk, v), v)[0]
+              for lam, m, v in zip(inst.lambdas, inst.mus, lv))
+    assert abs(rep["cost"] - c_o) <= 1e-5 * c_o, (rep["cost"], c_o)
 
 
 def test_barycenter_curves128_pruned_equals_dense(nat):
