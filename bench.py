@@ -661,27 +661,34 @@ def main():
 
     # eps-scaling leg (outside the timed region): the same batch with the same iteration budget,
     # stage_iters iterations at each eps of eps_start * factor^s above 0.1, the rest at 0.1
+    # The coarse stages also run with a matrix-core bulk engine (switch_tol 1: the exact engine
+    # takes over at the first check of the final eps).
     eps_leg = None
     if a.eps_start > EPS:
-        o_s = native.opts(tol=a.tol, max_iter=a.max_iter, check_every=a.check_every, final_check=True,
-                          prune=not a.no_prune, eps_start=a.eps_start, eps_factor=a.eps_factor,
-                          stage_iters=a.stage_iters)
-        qs = native.SolveQueue(hbm_budget_bytes=native.ot_request_bytes(k, o_s) * a.batch + (64 << 20),
-                               max_slots=a.batch)
-        torch.cuda.synchronize()
-        s0 = time.perf_counter()
-        ts_ = [qs.submit_ot(k, mus[i], nus[i], o_s, fs[i], gs[i]) for i in range(a.batch)]
-        rs_ = [qs.wait(t) for t in ts_]
-        torch.cuda.synchronize()
-        w_s = time.perf_counter() - s0
-        qs.close()
+        def eps_run(bulk=None):
+            o_s = native.opts(tol=a.tol, max_iter=a.max_iter, check_every=a.check_every, final_check=True,
+                              prune=not a.no_prune, eps_start=a.eps_start, eps_factor=a.eps_factor,
+                              stage_iters=a.stage_iters, bulk=bulk, switch_tol=1.0)
+            qs = native.SolveQueue(hbm_budget_bytes=native.ot_request_bytes(k, o_s) * a.batch + (64 << 20),
+                                   max_slots=a.batch)
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            ts_ = [qs.submit_ot(k, mus[i], nus[i], o_s, fs[i], gs[i]) for i in range(a.batch)]
+            rs_ = [qs.wait(t) for t in ts_]
+            torch.cuda.synchronize()
+            w_s = time.perf_counter() - s0
+            qs.close()
+            return {"iters_per_s": sum(r["iters"] for r in rs_) / w_s, "wall_s": w_s,
+                    "coarse_iters_per_solve": rs_[0]["scaling_iters"],
+                    "converged": sum(1 for r in rs_ if r["status"] == native.SE2_CONVERGED),
+                    "marg_l1_mean": float(np.mean([r["marg_l1"] for r in rs_])),
+                    "marg_l1_f64_mean": float(np.mean([r["marg_l1_f64"] for r in rs_])),
+                    "fallback_groups": int(sum(r["fallbacks"] for r in rs_)),
+                    "phase_switch_iter_median": float(np.median([r["phase_switch_iter"] for r in rs_]))}
         eps_leg = {"schedule": {"eps_start": a.eps_start, "factor": a.eps_factor, "stage_iters": a.stage_iters},
-                   "iters_per_s": sum(r["iters"] for r in rs_) / w_s, "wall_s": w_s,
-                   "coarse_iters_per_solve": rs_[0]["scaling_iters"],
-                   "converged": sum(1 for r in rs_ if r["status"] == native.SE2_CONVERGED),
-                   "marg_l1_mean": float(np.mean([r["marg_l1"] for r in rs_])),
-                   "marg_l1_f64_mean": float(np.mean([r["marg_l1_f64"] for r in rs_])),
-                   "plain_marg_l1_mean": float(np.mean([r["marg_l1"] for r in all_r]))}
+                   **eps_run(), "plain_marg_l1_mean": float(np.mean([r["marg_l1"] for r in all_r])),
+                   "plain_step_wall_s": wall / a.steps,
+                   "matrix_core_bulk": {"f32_mfma": eps_run(native.SE2_F32_MFMA), "bf16": eps_run(native.SE2_BF16)}}
 
     # kernel tables (built once per grid and metric, host FP64 then uploaded)
     build_ms = {}
