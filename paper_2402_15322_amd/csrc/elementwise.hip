@@ -146,7 +146,12 @@ __global__ __launch_bounds__(kThreads) void k_sum_items(const SumItem *__restric
     __shared__ double sh[kThreads];
     const SumItem it = items[blockIdx.x];
     double s = 0.0;
-    for (int p = it.begin + threadIdx.x; p < it.end; p += kThreads) s += it.part[p];
+    if (it.ints) {
+        const int32_t *v = reinterpret_cast<const int32_t *>(it.part);
+        for (int p = it.begin + threadIdx.x; p < it.end; p += kThreads) s += static_cast<double>(v[p]);
+    } else {
+        for (int p = it.begin + threadIdx.x; p < it.end; p += kThreads) s += it.part[p];
+    }
     s = block_tree_sum(s, sh);
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }

@@ -115,8 +115,10 @@ int launch_fill(double *p, size_t n, double v, hipStream_t s);
 int launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t s);
 // One FP64 sum of part[begin, end): the marginal-error partials of one job.
 struct SumItem {
-    const double *part;
+    const double *part;  // with ints != 0: int32_t values at this address
     int32_t begin, end;
+    int32_t ints = 0;
+    int32_t pad = 0;
 };
 int launch_sum_items(const SumItem *d_items, int n, double *out, hipStream_t s);
 // Copies errs[0, n) to host_errs (pinned, device-addressable) and then stores seq to

@@ -172,6 +172,9 @@ int solve_reset_lists(Solve &s, hipStream_t st) {
     s.phase = 0;
     s.phase_switch_iter = -1;
     s.prev_err = -1.0;
+    s.fb_checked = -1.0;
+    s.fb_prev = 0.0;
+    s.fb_prev_iter = 0;
     s.terms_linear = 0.0;
     if (s.fb_count && (rc = launch_fill_i32(s.fb_count, ot_like(s) ? 1 : static_cast<size_t>(s.n), 0, st)))
         return rc;
@@ -272,9 +275,23 @@ bool valid_solver_opts(const se2_opts_t &o, const Kernel &k) {
 }
 
 void phase_after_check(Solve &s, double err) {
-    if (s.opts.polish && s.phase == 0 && final_stage(s)) {
-        const bool stalled = s.prev_err >= 0.0 && !(err < s.prev_err);
-        if (err <= s.opts.switch_tol || stalled) {
+    if (in_bulk_phase(s)) {
+        bool to_polish = false;
+        // (a) the share of the bulk engine's groups that fell back since the previous check:
+        // each iteration visits every (tile, orientation) group of every measure twice
+        const int its = s.iter - s.fb_prev_iter;
+        if (s.fb_checked >= 0.0 && its > 0) {
+            const double groups = 2.0 * its * s.tiles * s.k->grid.ntheta * (ot_like(s) ? 1 : s.n);
+            to_polish = (s.fb_checked - s.fb_prev) > kBulkFallbackMax * groups;
+            s.fb_prev = s.fb_checked;
+            s.fb_prev_iter = s.iter;
+        }
+        // (b) at the final eps: the tolerance or the bulk engine's noise floor
+        if (final_stage(s)) {
+            const bool stalled = s.prev_err >= 0.0 && !(err < s.prev_err);
+            to_polish = to_polish || err <= s.opts.switch_tol || stalled;
+        }
+        if (to_polish) {
             s.phase = 1;
             s.phase_switch_iter = s.iter;
             trace_phase(s, "se2 polish");
@@ -859,6 +876,9 @@ int Engine::sum_errors(const std::vector<Solve *> &solves, hipStream_t st) {
         const int nj = ot_like(*s) ? 1 : s->n;
         const int per = s->tiles * s->k->grid.ntheta;
         for (int i = 0; i < nj; ++i) items.push_back(SumItem{s->partial, i * per, (i + 1) * per});
+        // in the bulk phase also the solve's recomputed-group counters (for phase_after_check)
+        if (in_bulk_phase(*s) && s->fb_count)
+            items.push_back(SumItem{reinterpret_cast<const double *>(s->fb_count), 0, nj, 1});
     }
     const size_t n = items.size();
     const bool same = items_key_.size() == n &&
@@ -888,7 +908,7 @@ int Engine::sum_errors(const std::vector<Solve *> &solves, hipStream_t st) {
 int Engine::read_errors(const std::vector<Solve *> &solves, std::vector<double> &max_err, hipStream_t st) {
     // the errors of the last check, in the item order of sum_errors()
     size_t total = 0;
-    for (Solve *s : solves) total += ot_like(*s) ? 1 : s->n;
+    for (Solve *s : solves) total += (ot_like(*s) ? 1 : s->n) + ((in_bulk_phase(*s) && s->fb_count) ? 1 : 0);
     if (total != items_key_.size() || !d_errs_) return SE2_EINVAL;
     if (total > cap_err_) {
         // coherent pinned memory the GPU writes directly: the flag word in its own 256 bytes,
@@ -938,7 +958,8 @@ int Engine::read_errors(const std::vector<Solve *> &solves, std::vector<double> 
     max_err.assign(solves.size(), 0.0);
     size_t off = 0;
     for (size_t q = 0; q < solves.size(); ++q) {
-        const size_t c = ot_like(*solves[q]) ? 1 : solves[q]->n;
+        Solve &s = *solves[q];
+        const size_t c = ot_like(s) ? 1 : s.n;
         double m = 0.0;
         for (size_t i = 0; i < c; ++i) {
             const double e = h_err[off + i];
@@ -946,6 +967,7 @@ int Engine::read_errors(const std::vector<Solve *> &solves, std::vector<double> 
         }
         max_err[q] = m;
         off += c;
+        if (in_bulk_phase(s) && s.fb_count) s.fb_checked = h_err[off++];
     }
     return SE2_OK;
 }

@@ -19,6 +19,10 @@ struct DevBuf {
 
 // Solve kinds: the two public request kinds and the JKO step of a gradient flow.
 constexpr int kKindJKO = 2;
+// Largest share of recomputed groups a bulk phase on the matrix cores keeps running with:
+// above it the exact engine is faster (measured on the eps-scaling stages of the paired lines:
+// the matrix cores win at eps 1.6 and 0.8 and lose at 0.4 and 0.2).
+constexpr double kBulkFallbackMax = 0.25;
 
 // One solve, resident on the device.  All potentials are base-2 log-scalings.
 struct Solve {
@@ -69,6 +73,11 @@ struct Solve {
     int phase = 0;                   // 0: bulk, 1: polish
     int phase_switch_iter = -1;      // iteration at which the polish phase began
     double prev_err = -1.0;          // error of the previous check of the current stage
+    // bulk phase: recomputed groups (summed over the measures) at the last check, as read by
+    // read_errors (-1: not read), and the count and iteration of the check before
+    double fb_checked = -1.0;
+    double fb_prev = 0.0;
+    int fb_prev_iter = 0;
     uint64_t trace_range = 0;        // roctx range of the current phase (0: none open)
     int32_t *fb_count = nullptr;     // per job (measure): groups recomputed after a failed certificate
     double terms_linear = 0.0;       // window terms evaluated by the matrix-core engines
@@ -91,13 +100,16 @@ size_t solve_bytes(int kind, const Kernel &k, int n_active, bool prune);
 inline bool prune_wanted(const se2_opts_t &o) { return o.prune != 0 && o.prec == SE2_F32; }
 bool prune_enabled(const Solve &s);
 // The engine a solve runs now: its bulk engine during the bulk phase, else opts.prec.
-inline int engine_prec(const Solve &s) { return (s.opts.polish && s.phase == 0) ? s.opts.bulk : s.opts.prec; }
+inline bool in_bulk_phase(const Solve &s) { return s.opts.polish && s.phase == 0; }
+inline int engine_prec(const Solve &s) { return in_bulk_phase(s) ? s.opts.bulk : s.opts.prec; }
 inline bool linear_engine(int prec) { return prec == SE2_BF16 || prec == SE2_F32_MFMA; }
 // Options a solver accepts for this kernel (engines, phases, iteration limits, eps schedule).
 bool valid_solver_opts(const se2_opts_t &o, const Kernel &k);
-// Phase control after a check of a solve that goes on (error err): at its final eps stage a
-// solve in its bulk phase moves to the polish engine once err <= opts.switch_tol or the error
-// did not fall since the stage's previous check.
+// Phase control after a check of a solve that goes on (error err).  A solve in its bulk phase
+// moves to the polish engine (a) at any stage, once more than kBulkFallbackMax of the
+// (tile, orientation) groups its bulk engine visited since the previous check were recomputed
+// exactly (the matrix-core engine no longer pays there), or (b) at its final eps stage, once
+// err <= opts.switch_tol or the error did not fall since the stage's previous check.
 void phase_after_check(Solve &s, double err);
 
 // Carve the buffers of `s` out of `mem` (size solve_bytes()).

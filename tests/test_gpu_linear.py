@@ -193,6 +193,34 @@ def test_bf16_bulk_then_fp32_polish_converges_to_the_oracle(nat):
     assert m1 <= 1e-6 and m2 <= 1e-6
 
 
+def test_bulk_phase_ends_when_most_groups_fall_back(nat):
+    """32 x 32 x 16 paired lines at eps = 0.1: the potentials steepen over the first
+    iterations until the FP32 matrix-core bulk phase recomputes more than a quarter of its
+    groups exactly, and at the next check the solve moves to the exact engine (not on the error:
+    switch_tol 0, and the error still falls); the result meets the exact engine's bars against
+    the oracle at equal iterations.  On the theta-motion instance no group falls back and the
+    bulk phase continues."""
+    inst = synth.lines64(0, n=32)
+    g = inst.grid
+    k = nat.Kernel(g.nx, g.ny, g.nt, False, inst.w, inst.eps, inst.radius)
+    logk, cost = oracle.kernel_table(g.nt, False, inst.w, inst.eps, inst.radius)
+    o = nat.opts(tol=-1, max_iter=40, check_every=10, prec=nat.SE2_F32, bulk=nat.SE2_F32_MFMA, switch_tol=0.0)
+    rep, phi, psi = _solve(nat, k, inst, o)
+    assert rep["iters"] == 40
+    assert rep["phase_switch_iter"] in (10, 20, 30), rep["phase_switch_iter"]
+    assert rep["fallbacks"] > 0.25 * 2 * 10 * (32 // 8) ** 2 * 16
+    phi_o, psi_o, it_o, err_o, _ = oracle.sinkhorn(logk, inst.mu, inst.nu, 40, -1.0)
+    assert oracle.plan_l1(logk, phi, psi, phi_o, psi_o) <= 1e-5
+    assert abs(rep["marg_l1"] - err_o) <= 1e-6
+    c_o = oracle.plan_stats(logk, cost, phi_o, psi_o)[0]
+    assert abs(rep["cost"] - c_o) <= 1e-6 * c_o
+    th = synth.lines64_theta(1, n=32)
+    kt = nat.Kernel(th.grid.nx, th.grid.ny, th.grid.nt, False, th.w, th.eps, th.radius)
+    rt, _, _ = _solve(nat, kt, th, nat.opts(tol=-1, max_iter=40, check_every=10, prec=nat.SE2_F32,
+                                            bulk=nat.SE2_F32_MFMA, switch_tol=0.0))
+    assert rt["fallbacks"] == 0 and rt["phase_switch_iter"] == -1
+
+
 def test_fp32_matrix_core_barycenter_equal_iterations(nat):
     """8 stroke images on 28 x 28 x 16 (the class-barycenter metric, eps = 0.5), 10 IBP
     iterations: some groups fall back to the exact engine, the rest run on the matrix cores."""
