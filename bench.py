@@ -133,6 +133,8 @@ def parse():
     ap.add_argument("--conv-engines", default="f32,bf16>f32,f32_mfma,bf16>f32_mfma",
                     help="converged leg: engines, comma separated (prec, or bulk>prec)")
     ap.add_argument("--converged-only", action="store_true", help="only the converged leg (for profiling)")
+    ap.add_argument("--eps-only", action="store_true",
+                    help="only the eps-scaling leg of the headline batch on every engine (no timed steps)")
     ap.add_argument("--fields-only", action="store_true",
                     help="only the 256x256x32 axial-field barycenter on every engine (for profiling)")
     ap.add_argument("--halo-spread", action="store_true",
@@ -525,6 +527,49 @@ def halo_spread(native, torch, synth):
     return rec
 
 
+def eps_scaling_leg(native, torch, k, mus, nus, fs, gs, a, plain_curve=False):
+    """The headline batch with eps-scaling: stage_iters iterations at each eps of
+    eps_start * factor^s above the workload's eps, the rest of the same iteration budget at it;
+    on the exact engine, and with a matrix-core bulk engine over the coarse stages
+    (switch_tol 1: the exact engine takes over at the first check of the final eps, or earlier
+    when over a quarter of the bulk engine's groups fall back).  Each variant runs a warm-up
+    batch, then the timed one.  plain_curve: also the batch without eps-scaling at 2000, 3000
+    and 4000 iterations (time to a given error)."""
+    import numpy as np
+
+    def eps_run(bulk=None, scaled=True, max_iter=None):
+        o_s = native.opts(tol=a.tol, max_iter=max_iter or a.max_iter, check_every=a.check_every, final_check=True,
+                          prune=not a.no_prune, eps_start=a.eps_start if scaled else 0.0, eps_factor=a.eps_factor,
+                          stage_iters=a.stage_iters if scaled else 0, bulk=bulk, switch_tol=1.0)
+        qs = native.SolveQueue(hbm_budget_bytes=native.ot_request_bytes(k, o_s) * a.batch + (64 << 20),
+                               max_slots=a.batch)
+        for _ in range(2):  # a warm-up batch (stage kernels, tables), then the timed one
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            ts_ = [qs.submit_ot(k, mus[i], nus[i], o_s, fs[i], gs[i]) for i in range(a.batch)]
+            rs_ = [qs.wait(t) for t in ts_]
+            torch.cuda.synchronize()
+            w_s = time.perf_counter() - s0
+            for t in ts_:
+                qs.release(t)
+        qs.close()
+        return {"iters_per_s": sum(r["iters"] for r in rs_) / w_s, "wall_s": w_s,
+                "coarse_iters_per_solve": rs_[0]["scaling_iters"],
+                "converged": sum(1 for r in rs_ if r["status"] == native.SE2_CONVERGED),
+                "marg_l1_mean": float(np.mean([r["marg_l1"] for r in rs_])),
+                "marg_l1_f64_mean": float(np.mean([r["marg_l1_f64"] for r in rs_])),
+                "fallback_groups": int(sum(r["fallbacks"] for r in rs_)),
+                "phase_switch_iter_median": float(np.median([r["phase_switch_iter"] for r in rs_]))}
+
+    rec = {"schedule": {"eps_start": a.eps_start, "factor": a.eps_factor, "stage_iters": a.stage_iters},
+           **eps_run(),
+           "matrix_core_bulk": {"f32_mfma": eps_run(native.SE2_F32_MFMA), "bf16": eps_run(native.SE2_BF16)}}
+    if plain_curve:
+        rec["plain_curve"] = [{"iters": n, **{key: v for key, v in eps_run(scaled=False, max_iter=n).items()
+                                              if key in ("wall_s", "marg_l1_mean")}} for n in (2000, 3000, 4000)]
+    return rec
+
+
 def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -602,6 +647,10 @@ def main():
     fs = [torch.empty_like(m) for m in mus]
     gs = [torch.empty_like(m) for m in mus]
     torch.cuda.synchronize()
+    if a.eps_only:
+        print(json.dumps({"eps_scaling": eps_scaling_leg(native, torch, k, mus, nus, fs, gs, a, plain_curve=True)}),
+              flush=True)
+        return
     o = native.opts(tol=a.tol, max_iter=a.max_iter, check_every=a.check_every, final_check=True,
                     prune=not a.no_prune)
     # the budget admits the whole batch (each solve keeps its potentials and pruning state resident)
@@ -661,34 +710,11 @@ def main():
 
     # eps-scaling leg (outside the timed region): the same batch with the same iteration budget,
     # stage_iters iterations at each eps of eps_start * factor^s above 0.1, the rest at 0.1
-    # The coarse stages also run with a matrix-core bulk engine (switch_tol 1: the exact engine
-    # takes over at the first check of the final eps).
     eps_leg = None
     if a.eps_start > EPS:
-        def eps_run(bulk=None):
-            o_s = native.opts(tol=a.tol, max_iter=a.max_iter, check_every=a.check_every, final_check=True,
-                              prune=not a.no_prune, eps_start=a.eps_start, eps_factor=a.eps_factor,
-                              stage_iters=a.stage_iters, bulk=bulk, switch_tol=1.0)
-            qs = native.SolveQueue(hbm_budget_bytes=native.ot_request_bytes(k, o_s) * a.batch + (64 << 20),
-                                   max_slots=a.batch)
-            torch.cuda.synchronize()
-            s0 = time.perf_counter()
-            ts_ = [qs.submit_ot(k, mus[i], nus[i], o_s, fs[i], gs[i]) for i in range(a.batch)]
-            rs_ = [qs.wait(t) for t in ts_]
-            torch.cuda.synchronize()
-            w_s = time.perf_counter() - s0
-            qs.close()
-            return {"iters_per_s": sum(r["iters"] for r in rs_) / w_s, "wall_s": w_s,
-                    "coarse_iters_per_solve": rs_[0]["scaling_iters"],
-                    "converged": sum(1 for r in rs_ if r["status"] == native.SE2_CONVERGED),
-                    "marg_l1_mean": float(np.mean([r["marg_l1"] for r in rs_])),
-                    "marg_l1_f64_mean": float(np.mean([r["marg_l1_f64"] for r in rs_])),
-                    "fallback_groups": int(sum(r["fallbacks"] for r in rs_)),
-                    "phase_switch_iter_median": float(np.median([r["phase_switch_iter"] for r in rs_]))}
-        eps_leg = {"schedule": {"eps_start": a.eps_start, "factor": a.eps_factor, "stage_iters": a.stage_iters},
-                   **eps_run(), "plain_marg_l1_mean": float(np.mean([r["marg_l1"] for r in all_r])),
-                   "plain_step_wall_s": wall / a.steps,
-                   "matrix_core_bulk": {"f32_mfma": eps_run(native.SE2_F32_MFMA), "bf16": eps_run(native.SE2_BF16)}}
+        eps_leg = {**eps_scaling_leg(native, torch, k, mus, nus, fs, gs, a),
+                   "plain_marg_l1_mean": float(np.mean([r["marg_l1"] for r in all_r])),
+                   "plain_step_wall_s": wall / a.steps}
 
     # kernel tables (built once per grid and metric, host FP64 then uploaded)
     build_ms = {}
