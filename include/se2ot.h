@@ -121,11 +121,13 @@ typedef struct {
     /* Phases.  polish = 0: the solve runs on `prec` throughout (bulk and switch_tol ignored).
      * polish = 1: a bulk phase on the engine `bulk` (typically SE2_BF16) comes first -- over
      * the coarse eps stages and at the final eps.  The solve moves to `prec` at the first
-     * check after which more than a quarter of the (tile, orientation) groups the bulk engine
-     * visited since the previous check were recomputed exactly (any stage), or, at the final
-     * eps, whose marginal L1 error is <= switch_tol or did not fall since the previous check
-     * of that stage (the bulk engine's precision floor); the final FP64 check (final_check)
-     * follows as usual.  se2_report_t.phase_switch_iter records the move. */
+     * check after which more than a quarter (three quarters when `prec` visits whole
+     * windows: prune = 0, or a halo beyond the pruned kernel's LDS) of the (tile, orientation)
+     * groups the bulk engine visited since the previous check were recomputed exactly (any
+     * stage), or, at the final eps, whose marginal L1 error is <= switch_tol or did not fall
+     * since the previous check of that stage (the bulk engine's precision floor); the final
+     * FP64 check (final_check) follows as usual.  se2_report_t.phase_switch_iter records the
+     * move. */
     se2_prec_t bulk;
     int32_t polish;
     double switch_tol;

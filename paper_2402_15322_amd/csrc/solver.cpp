@@ -282,7 +282,9 @@ void phase_after_check(Solve &s, double err) {
         const int its = s.iter - s.fb_prev_iter;
         if (s.fb_checked >= 0.0 && its > 0) {
             const double groups = 2.0 * its * s.tiles * s.k->grid.ntheta * (ot_like(s) ? 1 : s.n);
-            to_polish = (s.fb_checked - s.fb_prev) > kBulkFallbackMax * groups;
+            const bool pruned = s.opts.prune && conv_lse_sparse_fits(s.k->grid.ntheta, s.k->metric.radius);
+            const double cap = pruned ? kBulkFallbackMaxPruned : kBulkFallbackMaxDense;
+            to_polish = (s.fb_checked - s.fb_prev) > cap * groups;
             s.fb_prev = s.fb_checked;
             s.fb_prev_iter = s.iter;
         }

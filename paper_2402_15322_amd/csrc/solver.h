@@ -20,9 +20,12 @@ struct DevBuf {
 // Solve kinds: the two public request kinds and the JKO step of a gradient flow.
 constexpr int kKindJKO = 2;
 // Largest share of recomputed groups a bulk phase on the matrix cores keeps running with:
-// above it the exact engine is faster (measured on the eps-scaling stages of the paired lines:
-// the matrix cores win at eps 1.6 and 0.8 and lose at 0.4 and 0.2).
-constexpr double kBulkFallbackMax = 0.25;
+// above it the exact engine is faster.  Against the pruned exact engine (measured on the
+// eps-scaling stages of the paired lines: the matrix cores win at eps 1.6 and 0.8 and lose at
+// 0.4 and 0.2) a quarter; against a dense exact visit, whose cost the recomputation of a
+// share s approaches as s (plus the contraction, a few percent of it), three quarters.
+constexpr double kBulkFallbackMaxPruned = 0.25;
+constexpr double kBulkFallbackMaxDense = 0.75;
 
 // One solve, resident on the device.  All potentials are base-2 log-scalings.
 struct Solve {
@@ -106,7 +109,7 @@ inline bool linear_engine(int prec) { return prec == SE2_BF16 || prec == SE2_F32
 // Options a solver accepts for this kernel (engines, phases, iteration limits, eps schedule).
 bool valid_solver_opts(const se2_opts_t &o, const Kernel &k);
 // Phase control after a check of a solve that goes on (error err).  A solve in its bulk phase
-// moves to the polish engine (a) at any stage, once more than kBulkFallbackMax of the
+// moves to the polish engine (a) at any stage, once more than kBulkFallbackMax* of the
 // (tile, orientation) groups its bulk engine visited since the previous check were recomputed
 // exactly (the matrix-core engine no longer pays there), or (b) at its final eps stage, once
 // err <= opts.switch_tol or the error did not fall since the stage's previous check.

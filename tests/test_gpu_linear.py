@@ -214,6 +214,12 @@ def test_bulk_phase_ends_when_most_groups_fall_back(nat):
     assert abs(rep["marg_l1"] - err_o) <= 1e-6
     c_o = oracle.plan_stats(logk, cost, phi_o, psi_o)[0]
     assert abs(rep["cost"] - c_o) <= 1e-6 * c_o
+    # against a dense exact engine (prune = 0) the bulk phase may keep three quarters of its
+    # groups recomputed: the same bulk iterations, so it switches at the same check or later
+    od = nat.opts(tol=-1, max_iter=40, check_every=10, prec=nat.SE2_F32, bulk=nat.SE2_F32_MFMA, switch_tol=0.0,
+                  prune=False)
+    rd, _, _ = _solve(nat, k, inst, od)
+    assert rd["phase_switch_iter"] == -1 or rd["phase_switch_iter"] >= rep["phase_switch_iter"]
     th = synth.lines64_theta(1, n=32)
     kt = nat.Kernel(th.grid.nx, th.grid.ny, th.grid.nt, False, th.w, th.eps, th.radius)
     rt, _, _ = _solve(nat, kt, th, nat.opts(tol=-1, max_iter=40, check_every=10, prec=nat.SE2_F32,
