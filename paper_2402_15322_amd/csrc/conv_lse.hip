@@ -880,14 +880,14 @@ int launch_sparse_t(const ConvJob *d_jobs, int nblocks, const int32_t *d_block_j
 // Plan statistics of pi(x, y) = 2^(phi2(x) + L2[x - y] + psi2(y)), the transport plan of the
 // scalings (Section 4.1), for the transport cost sum pi rho_b^2 and the plan mass sum pi
 // (Section 2.2).  Workgroup (tile, g) of plan j = blockIdx.y covers the outputs x of one 8 x 8
-// tile at orientations ko = 4 g + wave (lane = pixel) and their windows; the psi halo is staged
-// in LDS KC orientations at a time, kernel and cost values are wave-uniform (scalar loads).
-// After an a-update the rows of pi sum to the first marginal, so every term is at most 1 and
-// 2^u needs no shift.  Sums: FP32 over the KC orientations of one window offset, FP64 over the
-// offsets, then lanes (butterflies) and the four waves in order.  Partial b of plan j goes to
-// part[2 b], part[2 b + 1] (one plan, interleaved) or part[2 j nb + b], part[(2 j + 1) nb + b]
-// (plan tables, planar), nb = gridDim.x.
-template <int NT, int KC>
+// tile at the 4 NQ orientations ko = 4 NQ g + wave + 4 q (lane = pixel, q < NQ) and their
+// windows; the psi halo is staged in LDS KC orientations at a time, kernel and cost values are
+// wave-uniform (scalar loads).  After an a-update the rows of pi sum to the first marginal, so
+// every term is at most 1 and 2^u needs no shift.  Sums: FP32 over the KC orientations of one
+// window offset, FP64 over the offsets, then over q, lanes (butterflies) and the four waves in
+// order.  Partial b of plan j goes to part[2 b], part[2 b + 1] (one plan, interleaved) or
+// part[2 j nb + b], part[(2 j + 1) nb + b] (plan tables, planar), nb = gridDim.x.
+template <int NT, int KC, int NQ>
 __global__ __launch_bounds__(kConvThreads) void k_plan_tiles(const double *__restrict__ phi1,
                                                              const double *__restrict__ psi1,
                                                              const double *const *__restrict__ phi_tab,
@@ -897,7 +897,7 @@ __global__ __launch_bounds__(kConvThreads) void k_plan_tiles(const double *__res
                                                              int tiles_x, double *__restrict__ part) {
     extern __shared__ double lds[];
     __shared__ double s_sum[8];
-    constexpr int NG = NT / 4;
+    constexpr int NG = NT / (4 * NQ);
     const int j = blockIdx.y;
     const double *phi = phi_tab != nullptr ? phi_tab[j] : phi1;
     const double *psi = psi_tab != nullptr ? psi_tab[j] : psi1;
@@ -908,64 +908,106 @@ __global__ __launch_bounds__(kConvThreads) void k_plan_tiles(const double *__res
     const int x0 = tx * kTile, y0 = ty * kTile;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
-    const int ko = 4 * g + wave;
     const int px = lane & 7, py = lane >> 3;
     const int gx = x0 + px, gy = y0 + py;
     const bool valid = gx < nx && gy < ny;
-    const double f = valid ? phi[(static_cast<size_t>(gy) * nx + gx) * NT + ko] : -INFINITY;
+    double f[NQ];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int ko = 4 * NQ * g + wave + 4 * q;
+        f[q] = valid ? phi[(static_cast<size_t>(gy) * nx + gx) * NT + ko] : -INFINITY;
+        any = any || f[q] != -INFINITY;
+    }
     const int W = 2 * R + 1, HW = kTile + 2 * R, npix = HW * HW;
     const cdptr L64 = (cdptr)L64_;
     const cfptr cost = (cfptr)cost_;
-    double c = 0.0, m = 0.0;
+    double c[NQ], m[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) c[q] = m[q] = 0.0;
     for (int k0 = 0; k0 < NT; k0 += KC) {
         if (k0 > 0) __syncthreads();
         load_halo<KC>(lds, psi, NT, k0, x0, y0, R, HW, nx, ny);
         __syncthreads();
-        if (f == -INFINITY) continue;
+        if (!any) continue;
         for (int dy = -R; dy <= R; ++dy) {
             for (int dx = -R; dx <= R; ++dx) {
                 const int hb = (py + R - dy) * HW + (px + R - dx);
-                const size_t row = (static_cast<size_t>((dy + R) * W + (dx + R)) * NT + ko) * NT + k0;
-                float rs = 0.0f, rc = 0.0f;
+                const size_t row = (static_cast<size_t>((dy + R) * W + (dx + R)) * NT + 4 * NQ * g + wave) * NT + k0;
+                float rs[NQ], rc[NQ];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) rs[q] = rc[q] = 0.0f;
 #pragma unroll
                 for (int kc = 0; kc < KC; ++kc) {
-                    const double u = (f + L64[row + kc]) + lds[kc * npix + hb];
-                    const float p = __builtin_amdgcn_exp2f(static_cast<float>(u));
-                    rs += p;
-                    rc += p * cost[row + kc];
+                    const double v = lds[kc * npix + hb];
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) {
+                        const size_t e = row + static_cast<size_t>(4 * q) * NT + kc;
+                        const float p = __builtin_amdgcn_exp2f(static_cast<float>((f[q] + L64[e]) + v));
+                        rs[q] += p;
+                        rc[q] += p * cost[e];
+                    }
                 }
-                m += static_cast<double>(rs);
-                c += static_cast<double>(rc);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    m[q] += static_cast<double>(rs[q]);
+                    c[q] += static_cast<double>(rc[q]);
+                }
             }
         }
     }
-    c = block_sum_waves(c, s_sum);
-    m = block_sum_waves(m, s_sum + 4);
+    double ct = 0.0, mt = 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        ct += c[q];
+        mt += m[q];
+    }
+    ct = block_sum_waves(ct, s_sum);
+    mt = block_sum_waves(mt, s_sum + 4);
     if (threadIdx.x == 0) {
         const size_t nb = gridDim.x;
         if (phi_tab != nullptr) {
-            part[(2 * static_cast<size_t>(j)) * nb + blockIdx.x] = c;
-            part[(2 * static_cast<size_t>(j) + 1) * nb + blockIdx.x] = m;
+            part[(2 * static_cast<size_t>(j)) * nb + blockIdx.x] = ct;
+            part[(2 * static_cast<size_t>(j) + 1) * nb + blockIdx.x] = mt;
         } else {
-            part[2 * static_cast<size_t>(blockIdx.x)] = c;
-            part[2 * static_cast<size_t>(blockIdx.x) + 1] = m;
+            part[2 * static_cast<size_t>(blockIdx.x)] = ct;
+            part[2 * static_cast<size_t>(blockIdx.x) + 1] = mt;
         }
     }
 }
 
-template <int NT, int KC>
+// Orientations per lane of the plan statistics: four on grids whose one-per-lane launch would
+// already have 4096 workgroups per plan or more (the halo is then staged once per 16
+// orientations instead of once per 4, and a lane carries four independent sums), else one (a
+// small grid needs the workgroups to fill the compute units).
+int plan_nq(const Kernel &k) {
+    const int tiles = ((k.grid.nx + kTile - 1) / kTile) * ((k.grid.ny + kTile - 1) / kTile);
+    const int nt = k.grid.ntheta;
+    return (tiles * (nt / 4) >= 4096 && nt >= 16) ? 4 : 1;
+}
+
+template <int NT, int KC, int NQ>
 int launch_plan_t(const Kernel &k, const double *phi, const double *psi, const double *const *phi_tab,
                   const double *const *psi_tab, int nplans, double *part, hipStream_t s) {
     const int R = k.metric.radius, HW = kTile + 2 * R;
     const size_t lds = static_cast<size_t>(HW) * HW * KC * sizeof(double);
     if (lds > 65536)
-        SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_plan_tiles<NT, KC>),
+        SE2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_plan_tiles<NT, KC, NQ>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
     const int tx = (k.grid.nx + kTile - 1) / kTile, ty = (k.grid.ny + kTile - 1) / kTile;
-    hipLaunchKernelGGL((k_plan_tiles<NT, KC>), dim3(tx * ty * (NT / 4), nplans), dim3(kConvThreads), lds, s, phi, psi,
-                       phi_tab, psi_tab, k.d_L64, k.d_cost32, k.grid.nx, k.grid.ny, R, tx, part);
+    hipLaunchKernelGGL((k_plan_tiles<NT, KC, NQ>), dim3(tx * ty * (NT / (4 * NQ)), nplans), dim3(kConvThreads), lds,
+                       s, phi, psi, phi_tab, psi_tab, k.d_L64, k.d_cost32, k.grid.nx, k.grid.ny, R, tx, part);
     SE2_HIP(hipGetLastError());
     return SE2_OK;
+}
+
+template <int NT, int KC>
+int launch_plan_nq(const Kernel &k, const double *phi, const double *psi, const double *const *phi_tab,
+                   const double *const *psi_tab, int nplans, double *part, hipStream_t s) {
+    if constexpr (NT >= 16) {
+        if (plan_nq(k) == 4) return launch_plan_t<NT, KC, 4>(k, phi, psi, phi_tab, psi_tab, nplans, part, s);
+    }
+    return launch_plan_t<NT, KC, 1>(k, phi, psi, phi_tab, psi_tab, nplans, part, s);
 }
 
 }  // namespace
@@ -990,7 +1032,7 @@ int launch_lse_tiles(const ConvJob *d_jobs, int grid, int nt, int R_max, const i
 
 int plan_parts(const Kernel &k) {
     const int tx = (k.grid.nx + kTile - 1) / kTile, ty = (k.grid.ny + kTile - 1) / kTile;
-    return tx * ty * (k.grid.ntheta / 4);
+    return tx * ty * (k.grid.ntheta / (4 * plan_nq(k)));
 }
 
 int launch_plan_tiles(const Kernel &k, const double *phi, const double *psi, const double *const *phi_tab,
@@ -1002,13 +1044,13 @@ int launch_plan_tiles(const Kernel &k, const double *phi, const double *psi, con
         return SE2_EINVAL;
     const bool kc16 = (kTile + 2 * R) * (kTile + 2 * R) * 16 * 8 <= 65536;
     switch (k.grid.ntheta) {
-        case 8: return launch_plan_t<8, 8>(k, phi, psi, phi_tab, psi_tab, nplans, part, s);
+        case 8: return launch_plan_nq<8, 8>(k, phi, psi, phi_tab, psi_tab, nplans, part, s);
         case 16:
-            return kc16 ? launch_plan_t<16, 16>(k, phi, psi, phi_tab, psi_tab, nplans, part, s)
-                        : launch_plan_t<16, 8>(k, phi, psi, phi_tab, psi_tab, nplans, part, s);
+            return kc16 ? launch_plan_nq<16, 16>(k, phi, psi, phi_tab, psi_tab, nplans, part, s)
+                        : launch_plan_nq<16, 8>(k, phi, psi, phi_tab, psi_tab, nplans, part, s);
         case 32:
-            return kc16 ? launch_plan_t<32, 16>(k, phi, psi, phi_tab, psi_tab, nplans, part, s)
-                        : launch_plan_t<32, 8>(k, phi, psi, phi_tab, psi_tab, nplans, part, s);
+            return kc16 ? launch_plan_nq<32, 16>(k, phi, psi, phi_tab, psi_tab, nplans, part, s)
+                        : launch_plan_nq<32, 8>(k, phi, psi, phi_tab, psi_tab, nplans, part, s);
         default: return SE2_EINVAL;
     }
 }

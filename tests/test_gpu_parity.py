@@ -291,6 +291,23 @@ def test_barycenter_cost_matches_oracle(nat, shape):
     assert abs(rep["mass"] - bar_o.sum()) <= 1e-6
 
 
+def test_plan_statistics_on_a_large_grid(nat):
+    """Transport cost and plan mass on 256 x 256 x 16 (the plan statistics then take four
+    orientations per lane): from the GPU's own potentials after 6 iterations, against the
+    oracle's sums over the same plan."""
+    torch = torch_dev()
+    inst = synth.lines64(2, n=256)
+    g = inst.grid
+    k = _kernel(nat, g.nx, g.ny, g.nt, False, inst.w, inst.eps, inst.radius)
+    logk, cost = oracle.kernel_table(g.nt, False, inst.w, inst.eps, inst.radius)
+    mu, nu = to_dev(inst.mu), to_dev(inst.nu)
+    f, gg = torch.empty_like(mu), torch.empty_like(mu)
+    rep = nat.se2_sinkhorn(k, mu, nu, nat.opts(tol=-1, max_iter=6, check_every=3), f, gg)
+    c_o, m_o, _, _ = oracle.plan_stats(logk, cost, to_host(f) / inst.eps, to_host(gg) / inst.eps)
+    assert abs(rep["cost"] - c_o) <= 1e-6 * c_o, (rep["cost"], c_o)
+    assert abs(rep["mass"] - m_o) <= 1e-6 * m_o, (rep["mass"], m_o)
+
+
 def test_barycenter_weight_on_one_measure(nat):
     """lambda = e_1: the closed form bar = K*(mu_1 / K*1) (Appendix A with one active measure)."""
     torch = torch_dev()
