@@ -147,10 +147,11 @@ __global__ __launch_bounds__(kThreads) void k_sum_items(const SumItem *__restric
     const SumItem it = items[blockIdx.x];
     double s = 0.0;
     if (it.ints) {
-        const int32_t *v = reinterpret_cast<const int32_t *>(it.part);
+        const int32_t *v = static_cast<const int32_t *>(it.part);
         for (int p = it.begin + threadIdx.x; p < it.end; p += kThreads) s += static_cast<double>(v[p]);
     } else {
-        for (int p = it.begin + threadIdx.x; p < it.end; p += kThreads) s += it.part[p];
+        const double *v = static_cast<const double *>(it.part);
+        for (int p = it.begin + threadIdx.x; p < it.end; p += kThreads) s += v[p];
     }
     s = block_tree_sum(s, sh);
     if (threadIdx.x == 0) out[blockIdx.x] = s;

@@ -880,7 +880,7 @@ int Engine::sum_errors(const std::vector<Solve *> &solves, hipStream_t st) {
         for (int i = 0; i < nj; ++i) items.push_back(SumItem{s->partial, i * per, (i + 1) * per});
         // in the bulk phase also the solve's recomputed-group counters (for phase_after_check)
         if (in_bulk_phase(*s) && s->fb_count)
-            items.push_back(SumItem{reinterpret_cast<const double *>(s->fb_count), 0, nj, 1});
+            items.push_back(SumItem{s->fb_count, 0, nj, 1});
     }
     const size_t n = items.size();
     const bool same = items_key_.size() == n &&
