@@ -390,16 +390,35 @@ def _serve_request(seed: int, i: int, arrival: float, grids, paired: bool) -> Re
     return Request(float(arrival), OTInstance(g, (1.0, w2, 1.0), eps, rad, mu, nu, f"serve/{i}"))
 
 
+def _serve_theta_request(seed: int, i: int, arrival: float, grids) -> Request:
+    """A converging request: the theta-motion pair of lines64_theta on one of the serving
+    grids (segments scaled by n/64), eps = 0.1, w = (1,3,1)."""
+    r = rng_for(seed + 1 + i, 0)
+    n, nt, rad = grids[int(r.integers(len(grids)))]
+    g = Grid(n, n, nt)
+    scale = n / 64.0
+    segs = draw_segments(r, g, int(r.integers(4, 13)), 10.0 * scale, 40.0 * scale, PAIRED_MARGIN)
+    px, py, ang, w = segment_points(segs)
+    mu = normalise(splat_points(g, px, py, np.mod(ang, g.period), w, THETA_SIGMA_XY), 1e-6)
+    turns = np.concatenate([np.full(max(1, int(math.floor(s.length / 0.25)) + 1), r.uniform(-THETA_TURN, THETA_TURN))
+                            for s in segs])
+    nu = normalise(splat_points(g, px, py, np.mod(ang + turns, g.period), w, THETA_SIGMA_XY), 1e-6)
+    return Request(float(arrival), OTInstance(g, (1.0, 3.0, 1.0), 0.1, rad, mu, nu, f"serve-theta/{i}"))
+
+
 def _serve_chunk(args):
     seed, idx, arrivals, grids, paired = args
+    if paired == "theta":
+        return [_serve_theta_request(seed, i, a, grids) for i, a in zip(idx, arrivals)]
     return [_serve_request(seed, i, a, grids, paired) for i, a in zip(idx, arrivals)]
 
 
-def serving_trace(nreq: int = 512, rate: float = 200.0, seed: int = 3000, paired: bool = True,
+def serving_trace(nreq: int = 512, rate: float = 200.0, seed: int = 3000, paired=True,
                   grids: Optional[Sequence[Tuple[int, int, int]]] = None, workers: int = 1) -> List[Request]:
-    """Poisson stream of OT requests with mixed grid sizes, eps and w2.  Request i draws from
-    its own stream, so the trace is the same for any worker count (workers > 1 forks
-    processes: call it before any GPU work)."""
+    """Poisson stream of OT requests with mixed grid sizes, eps and w2 (paired = "theta":
+    theta-motion pairs that converge, eps 0.1, w2 = 3).  Request i draws from its own stream,
+    so the trace is the same for any worker count (workers > 1 forks processes: call it
+    before any GPU work)."""
     grids = list(grids or SERVE_GRIDS)
     arr = rng_for(seed, 0)
     gaps = arr.exponential(1.0 / rate, nreq)
