@@ -444,11 +444,6 @@ def converged_leg(native, torch, synth, a):
         rec = {"wall_s": wall, "converged": conv, "solves": len(reps), "converged_solves_per_s": conv / wall,
                "iters_per_s": float(its.sum()) / wall, "iters_median": float(np.median(its)), "iters_max": int(its.max()),
                "p50_latency_ms": float(np.percentile(lat, 50) * 1e3), "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
-        "converged_p50_p99_latency_ms": ([float(np.percentile(lat_conv, 50) * 1e3),
-                                          float(np.percentile(lat_conv, 99) * 1e3)] if lat_conv.size else None),
-        "marg_l1_max": float(max(r["marg_l1"] for r in reps)),
-        "converged_by_grid": {n: {"converged": c[0], "requests": c[1]} for n, c in sorted(by_grid.items())},
-        "iters_median": float(np.median([r["iters"] for r in reps])),
                "marg_l1_max": max(r["marg_l1"] for r in reps), "marg_l1_f64_max": max(r["marg_l1_f64"] for r in reps),
                "phase_switch_iter_median": float(np.median([r["phase_switch_iter"] for r in reps])),
                "fallback_groups": int(sum(r["fallbacks"] for r in reps)),
