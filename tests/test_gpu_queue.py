@@ -199,3 +199,33 @@ def test_release_forgets_finished_tickets(nat):
     q.release(ts[2])
     assert q.stats()["completed"] == 3
     q.close()
+
+
+def test_converging_serving_requests_reach_tolerance(nat):
+    """A burst of converging requests (theta-motion pairs of the converging serving trace on
+    64x64x16 and 128x128x16, eps 0.1) through the queue: every one reaches marginal L1 1e-6
+    with its FP64 check within 1.1e-6, and a sample equals the blocking call bit for bit."""
+    torch = torch_dev()
+    trace = synth.serving_trace(12, 1000.0, seed=3100, paired="theta", grids=synth.SERVE_GRIDS[1:])
+    kernels = {}
+    o = nat.opts(tol=1e-6, max_iter=3000, check_every=10, final_check=True)
+    q = nat.SolveQueue(hbm_budget_bytes=1 << 30, max_slots=12)
+    jobs = []
+    for r in trace:
+        x = r.inst
+        key = (x.grid.nx, x.radius)
+        if key not in kernels:
+            kernels[key] = nat.Kernel(x.grid.nx, x.grid.ny, x.grid.nt, False, x.w, x.eps, x.radius)
+        mu, nu = to_dev(x.mu), to_dev(x.nu)
+        f, g = torch.empty_like(mu), torch.empty_like(mu)
+        jobs.append((kernels[key], mu, nu, f, g, q.submit_ot(kernels[key], mu, nu, o, f, g)))
+    reps = [q.wait(j[5]) for j in jobs]
+    q.close()
+    assert {x.inst.grid.nx for x in trace} == {64, 128}
+    for rep in reps:
+        assert rep["status"] == nat.SE2_CONVERGED and rep["marg_l1"] <= 1e-6, rep
+        assert rep["marg_l1_f64"] <= 1.1e-6, rep
+    for k, mu, nu, f, g, _ in (jobs[0], jobs[-1]):
+        f2, g2 = torch.empty_like(mu), torch.empty_like(mu)
+        nat.se2_sinkhorn(k, mu, nu, o, f2, g2)
+        assert np.array_equal(to_host(f), to_host(f2)) and np.array_equal(to_host(g), to_host(g2))
