@@ -307,7 +307,7 @@ def pin_dense_sinkhorn_and_ibp():
     rng = np.random.default_rng(15)
     nx, ny, nt, R, w, eps = 4, 5, 4, 2, (1.0, 2.0, 1.5), 0.4
     LM = dense.dense_logk(nx, ny, nt, False, w, eps, R)
-    logk, _ = oracle.kernel_table(nt, False, w, eps, R)
+    logk, cost = oracle.kernel_table(nt, False, w, eps, R)
     mu = _rand_measure(rng, (ny, nx, nt), zero_frac=0.1)
     nu = _rand_measure(rng, (ny, nx, nt))
     phi, psi, it, err, _ = oracle.sinkhorn(logk, mu, nu, 25, -1.0)
@@ -317,6 +317,15 @@ def pin_dense_sinkhorn_and_ibp():
     assert np.sum(np.abs(pa - pb)) < 1e-12
     l1 = oracle.plan_l1(logk, phi, psi, dphi, dpsi)
     assert l1 < 1e-12
+    # plan statistics of arbitrary potentials (mass not 1) against the dense plan's sums, the
+    # cost from the dense matrix: rho^2 = -eps log K on the window
+    p2, s2 = phi + rng.normal(0.0, 0.3, phi.shape), psi + rng.normal(0.0, 0.3, psi.shape)
+    c_o, m_o, _, _ = oracle.plan_stats(logk, cost, p2, s2)
+    pd = dense.plan(LM, p2, s2)
+    fin = np.isfinite(LM)
+    cd, md = float(np.sum(pd[fin] * (-eps * LM[fin]))), float(pd.sum())
+    assert abs(md - 1.0) > 1e-3
+    assert abs(c_o - cd) <= 1e-11 * cd and abs(m_o - md) <= 1e-12 * md
     mus = [_rand_measure(rng, (ny, nx, nt)) for _ in range(3)]
     lam = [0.5, 0.25, 0.25]
     b, _, _, _ = oracle.ibp(logk, mus, lam, 15, -1.0)
