@@ -66,6 +66,9 @@ MUTANTS = [
      "ld[n * m + i] = (v == -INFINITY || c[i] == -INFINITY) ? -INFINITY : c[i];", 0),
     # Section 2.2 / 4.1: cost sum pi rho^2 and the plan's marginals
     ("cost_with_log_kernel", "if (cost_tab) rc += p * cost_tab[kb + ki];", "if (cost_tab) rc += p * (-logk[kb + ki]);", 0),
+    ("plan_without_psi", "double p = exp(phi[xo] + logk[kb + ki] + psi[yb + ki]);",
+     "double p = exp(phi[xo] + logk[kb + ki]);", 0),
+    ("cost_without_plan_weight", "if (cost_tab) rc += p * cost_tab[kb + ki];", "if (cost_tab) rc += cost_tab[kb + ki];", 0),
     ("second_marginal_offset_sign", "int iy = jy + dy;", "int iy = jy - dy;", 0),
     # the plan-difference checker: both plans from their own potentials
     ("plan_l1_returns_zero", "    return tot;\n}", "    return 0.0 * tot;\n}", 0),
