@@ -308,6 +308,28 @@ def test_plan_statistics_on_a_large_grid(nat):
     assert abs(rep["mass"] - m_o) <= 1e-6 * m_o, (rep["mass"], m_o)
 
 
+def test_barycenter_cost_on_a_large_grid(nat):
+    """The barycenter's plan statistics over the measures' pointer tables on 256 x 256 x 16
+    (four orientations per lane there), 3 IBP iterations of two measures with a 3 x 3 window:
+    cost and barycenter against the oracle."""
+    torch = torch_dev()
+    g = synth.Grid(256, 256, 16)
+    mus = [synth.splat_segments(g, synth.draw_segments(synth.rng_for(80, s), g, 6, 20.0, 60.0), 2.0, 1e-6)
+           for s in range(2)]
+    lam = [0.4, 0.6]
+    w, eps, R = (1.0, 2.0, 1.0), 0.5, 1
+    k = _kernel(nat, 256, 256, 16, False, w, eps, R)
+    logk, cost = oracle.kernel_table(16, False, w, eps, R)
+    out = torch.empty((256, 256, 16), dtype=torch.float64, device="cuda")
+    rep = nat.se2_barycenter(k, [to_dev(m) for m in mus], lam, nat.opts(tol=-1, max_iter=3, check_every=3), out)
+    bar_o, it_o, _, _, lv = oracle.ibp(logk, mus, lam, 3, -1.0, return_lv=True)
+    assert rep["iters"] == it_o == 3
+    assert float(np.sum(np.abs(to_host(out) - bar_o))) <= 1e-5
+    c_o = sum(l_ * oracle.plan_stats(logk, cost, oracle.safe_log(m) - oracle.conv_log(logk, v), v)[0]
+              for l_, m, v in zip(lam, mus, lv))
+    assert abs(rep["cost"] - c_o) <= 1e-5 * c_o, (rep["cost"], c_o)
+
+
 def test_barycenter_weight_on_one_measure(nat):
     """lambda = e_1: the closed form bar = K*(mu_1 / K*1) (Appendix A with one active measure)."""
     torch = torch_dev()
