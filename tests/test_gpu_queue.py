@@ -229,3 +229,28 @@ def test_converging_serving_requests_reach_tolerance(nat):
         f2, g2 = torch.empty_like(mu), torch.empty_like(mu)
         nat.se2_sinkhorn(k, mu, nu, o, f2, g2)
         assert np.array_equal(to_host(f), to_host(f2)) and np.array_equal(to_host(g), to_host(g2))
+
+
+def test_bulk_phase_switch_through_the_queue(nat):
+    """A matrix-core bulk phase that ends on its fallback share (32 x 32 x 16 paired lines) and
+    one that does not (theta motion), submitted together through the queue: the same switch
+    iterations and the same bits as the blocking calls."""
+    torch = torch_dev()
+    insts = [synth.lines64(0, n=32), synth.lines64_theta(1, n=32)]
+    o = nat.opts(tol=-1, max_iter=40, check_every=10, prec=nat.SE2_F32, bulk=nat.SE2_F32_MFMA, switch_tol=0.0)
+    ks = [nat.Kernel(x.grid.nx, x.grid.ny, x.grid.nt, False, x.w, x.eps, x.radius) for x in insts]
+    dev = [(to_dev(x.mu), to_dev(x.nu)) for x in insts]
+    q = nat.SolveQueue(hbm_budget_bytes=256 << 20, max_slots=4)
+    outs, tickets = [], []
+    for k, (mu, nu) in zip(ks, dev):
+        f, g = torch.empty_like(mu), torch.empty_like(mu)
+        tickets.append(q.submit_ot(k, mu, nu, o, f, g))
+        outs.append((f, g))
+    reps = [q.wait(t) for t in tickets]
+    q.close()
+    assert reps[0]["phase_switch_iter"] in (10, 20, 30) and reps[1]["phase_switch_iter"] == -1
+    for k, (mu, nu), (f, g), rq in zip(ks, dev, outs, reps):
+        f2, g2 = torch.empty_like(mu), torch.empty_like(mu)
+        rb = nat.se2_sinkhorn(k, mu, nu, o, f2, g2)
+        assert rb["phase_switch_iter"] == rq["phase_switch_iter"] and rb["fallbacks"] == rq["fallbacks"]
+        assert np.array_equal(to_host(f), to_host(f2)) and np.array_equal(to_host(g), to_host(g2))
