@@ -147,7 +147,8 @@ typedef struct {
     int32_t convs;      /* group convolutions applied */
     int32_t scaling_iters; /* iterations run at coarser eps (eps-scaling), included in iters */
     int32_t fallbacks;  /* (8 x 8 tile, orientation) groups that the matrix-core engines recomputed in
-                           the log domain after a failed certificate */
+                           the log domain after a failed certificate, summed over the measures;
+                           saturates at 2^31 - 1 (each measure's count is kept modulo 2^32) */
     int32_t phase_switch_iter; /* iteration at which the polish phase began (-1: never) */
     double terms_linear; /* window terms evaluated on the matrix cores (SE2_BF16, SE2_F32_MFMA) */
 } se2_report_t;

@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kThreads) void k_sum_items(const SumItem *__restric
     const SumItem it = items[blockIdx.x];
     double s = 0.0;
     if (it.ints) {
-        const int32_t *v = static_cast<const int32_t *>(it.part);
+        const uint32_t *v = static_cast<const uint32_t *>(it.part);  // counters that wrap at 2^32
         for (int p = it.begin + threadIdx.x; p < it.end; p += kThreads) s += static_cast<double>(v[p]);
     } else {
         const double *v = static_cast<const double *>(it.part);

@@ -115,7 +115,7 @@ int launch_fill(double *p, size_t n, double v, hipStream_t s);
 int launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t s);
 // One FP64 sum of part[begin, end): the marginal-error partials of one job.
 struct SumItem {
-    const void *part;  // double values, or int32_t values when ints != 0
+    const void *part;  // double values, or uint32_t counters when ints != 0
     int32_t begin, end;
     int32_t ints = 0;
     int32_t pad = 0;

@@ -19,6 +19,7 @@
 
 #include <rocprofiler-sdk-roctx/roctx.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <climits>
@@ -1140,9 +1141,12 @@ int finish_solves(Engine &eng, std::vector<FinishReq> &reqs, hipStream_t st) {
         r.phase_switch_iter = s.phase_switch_iter;
         r.terms_linear = s.terms_linear;
         {
-            std::vector<int32_t> fb(static_cast<size_t>(nj));
-            SE2_HIP(hipMemcpy(fb.data(), s.fb_count, fb.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-            for (int32_t v : fb) r.fallbacks += v;
+            // one unsigned 32-bit device counter per measure; the total saturates the int32 field
+            std::vector<uint32_t> fb(static_cast<size_t>(nj));
+            SE2_HIP(hipMemcpy(fb.data(), s.fb_count, fb.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+            uint64_t total = 0;
+            for (uint32_t v : fb) total += v;
+            r.fallbacks = static_cast<int32_t>(std::min<uint64_t>(total, INT32_MAX));
         }
         if (s.kind == kKindJKO) {
             r.cost = e[2];
