@@ -82,7 +82,7 @@ struct Solve {
     double fb_prev = 0.0;
     int fb_prev_iter = 0;
     uint64_t trace_range = 0;        // roctx range of the current phase (0: none open)
-    int32_t *fb_count = nullptr;     // per job (measure): groups recomputed after a failed certificate
+    int32_t *fb_count = nullptr;     // per job (measure): groups recomputed after a failed certificate (read as uint32)
     double terms_linear = 0.0;       // window terms evaluated by the matrix-core engines
     // memory
     void *block = nullptr;           // single allocation holding every buffer
