@@ -42,6 +42,28 @@ def test_noalloc_split_equals_allocating_split(nat):
         assert not np.any((a1 > 0) & (b1 > 0))
 
 
+def test_noalloc_split_at_its_maximum_and_empty(nat):
+    """n = 4096 * 16384, the largest input the scratch serves (every one of its 4096 block
+    partials used), bit for bit against the allocating split; then an empty input, which
+    both entry points accept and which writes nothing."""
+    torch = torch_dev()
+    n = 4096 * 16384
+    g = torch.Generator(device="cuda").manual_seed(77)
+    ud = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+    p0, m0 = torch.empty_like(ud), torch.empty_like(ud)
+    p1, m1 = torch.full_like(ud, float("nan")), torch.full_like(ud, float("nan"))
+    nat.se2_split_signed(ud, p0, m0)
+    nat.se2_split_signed_noalloc(ud, p1, m1)
+    assert torch.equal(p0.view(torch.int64), p1.view(torch.int64))
+    assert torch.equal(m0.view(torch.int64), m1.view(torch.int64))
+    assert abs(float(p1.sum()) - 1.0) <= 1e-9 and abs(float(m1.sum()) - 1.0) <= 1e-9
+    del ud, p0, m0, p1, m1
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    nat.se2_split_signed(e, e, e)
+    nat.se2_split_signed_noalloc(e, e, e)
+    torch.cuda.synchronize()
+
+
 def test_noalloc_split_rejects_oversized_input(nat):
     torch = torch_dev()
     x = torch.zeros(16, dtype=torch.float64, device="cuda")
