@@ -399,6 +399,16 @@ def pin_eps_scaling():
     b2, it2, e2, _ = oracle.ibp(kat(eps), mus, lam, 5000, 1e-12)
     assert e1 <= 1e-12 and e2 <= 1e-12 and 40 < it1 < 5000
     assert np.max(np.abs(b1 - b2)) < 1e-10 * np.max(b2)
+    # IBP carry-over: log v_i of a converged stage at 2 eps, rescaled by 2 (eps log v kept), starts
+    # the stage at eps closer than the same log v_i unscaled or a cold start (measured: 0.48 and
+    # 0.36 of their errors after one iteration)
+    eps = 0.2
+    _, itc, errc, _, lvc = oracle.ibp(kat(2 * eps), mus, lam, 20000, 1e-13, return_lv=True)
+    assert errc <= 1e-13
+    e_ok = oracle.ibp_eps_scaling(kat, eps, mus, lam, 2 * eps, 0.5, itc, itc + 1, -1.0)[2]
+    e_raw = oracle.ibp(kat(eps), mus, lam, 1, -1.0, lvc)[2]
+    e_cold = oracle.ibp(kat(eps), mus, lam, 1, -1.0)[2]
+    assert e_ok < 0.6 * e_raw and e_ok < 0.5 * e_cold, (e_ok, e_raw, e_cold)
 
 
 # --------------------------------------------------------------------------

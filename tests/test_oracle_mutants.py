@@ -10,6 +10,7 @@ is restored afterwards and still passes every pin (`test_oracle_pins.py`).
 from __future__ import annotations
 
 import contextlib
+import inspect
 import os
 import subprocess
 
@@ -127,3 +128,43 @@ def test_pins_catch_mutant(tmp_path, name, old, new, occ):
     with _oracle_build(str(so)):
         caught = _first_failing_pin()
     assert caught is not None, f"no pin fails for the mutant {name}"
+
+
+# Mistakes in the Python half of the oracle (the JKO step, the porous-medium energy, the
+# lift and projection, the split of a signed score, eps-scaling): (name, function of
+# `oracle`, text in its source, replacement).  The mutated function is compiled in the
+# oracle module's namespace and swapped in for the original while the pins run.
+PY_MUTANTS = [
+    # Section 5.4: the prox condition log q + c q^(m-1) = log p
+    ("prox_wrong_power", "porous_prox_log", "c * np.exp((m - 1.0) * mid)", "c * np.exp(m * mid)"),
+    ("prox_c_without_m_factor", "porous_c", "(tau / eps) * m / (m - 1.0) * ref ** (1.0 - m)",
+     "(tau / eps) * ref ** (1.0 - m)"),
+    # b = prox(K^T a) / K^T a, and the next measure is the prox itself
+    ("jko_b_is_prox_not_ratio", "jko_step", "psi = np.where(np.isfinite(sv), y - sv, -np.inf)",
+     "psi = np.where(np.isfinite(sv), y, -np.inf)"),
+    ("jko_next_measure_before_prox", "jko_step", "nu = np.exp(y)", "nu = np.exp(sv)"),
+    ("energy_without_reference_cell", "porous_energy", "np.sum((nu / ref) ** m)", "np.sum(nu ** m)"),
+    # Section 5.3: bins centred on theta_k, and b_t = P(U+) - P(U-)
+    ("lift_bins_not_centred", "lift_field", "take = (rel >= -step / 2) & (rel < step / 2)",
+     "take = (rel >= 0) & (rel < step)"),
+    ("project_adds_negative_part", "project", "mass = mass - u_minus.sum(axis=-1)",
+     "mass = mass + u_minus.sum(axis=-1)"),
+    ("split_not_normalised", "split_signed", "return (plus / sp if sp > 0 else plus), (minus / sn if sn > 0 else minus)",
+     "return plus, minus"),
+    # eps-scaling: the schedule ends at eps; g = eps log b carried over between stages
+    ("schedule_without_final_eps", "eps_schedule", "return out + [eps]", "return out"),
+    ("stage_potentials_not_rescaled", "sinkhorn_eps_scaling", "init = None if psi is None else psi * (sched[-2] / eps)",
+     "init = psi"),
+    ("ibp_stage_potentials_not_rescaled", "ibp_eps_scaling", "init = None if lv is None else lv * (sched[-2] / eps)",
+     "init = lv"),
+]
+
+
+@pytest.mark.parametrize("name,func,old,new", PY_MUTANTS, ids=[m[0] for m in PY_MUTANTS])
+def test_pins_catch_python_mutant(monkeypatch, name, func, old, new):
+    src = inspect.getsource(getattr(oracle, func))
+    assert src.count(old) == 1, name
+    ns = {}
+    exec(compile(src.replace(old, new), f"<mutant {name}>", "exec"), vars(oracle), ns)
+    monkeypatch.setattr(oracle, func, ns[func])
+    assert _first_failing_pin() is not None, f"no pin fails for the mutant {name}"
