@@ -489,6 +489,12 @@ def pin_jko_step():
     assert np.max(np.abs(nu.reshape(-1) - blur)) <= 1e-14
     # converged step: mass, stationarity of J(pi) = <C, pi> + eps sum pi (log pi - 1) + tau F(pi^T 1)
     ref = 1.0 / mu.size
+    # the flow moves probability measures: a step stopped after 3 iterations leaves its second
+    # marginal off mass one, and the flow scales it back before the next step
+    nu3 = oracle.jko_step(logk, mu, 0.05, 2.0, eps, ref, 3, -1.0)[2]
+    assert abs(nu3.sum() - 1.0) > 1e-9
+    traj, info = oracle.gradient_flow(logk, mu, 0.05, 2.0, eps, ref, 3, 3, -1.0)
+    assert all(abs(t.sum() - 1.0) <= 1e-12 for t in traj) and [it for it, _ in info] == [3, 3, 3]
     for tau, m in ((1e-3, 5.0), (0.05, 2.0)):
         phi, psi, nu, it, err = oracle.jko_step(logk, mu, tau, m, eps, ref, 5000, 1e-13)
         assert err <= 1e-13 and abs(nu.sum() - 1.0) <= 1e-12

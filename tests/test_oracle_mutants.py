@@ -147,6 +147,9 @@ PY_MUTANTS = [
     # Section 5.3: bins centred on theta_k, and b_t = P(U+) - P(U-)
     ("lift_bins_not_centred", "lift_field", "take = (rel >= -step / 2) & (rel < step / 2)",
      "take = (rel >= 0) & (rel < step)"),
+    ("lift_axial_ignored", "lift_field", "period = PI if axial else 2 * PI", "period = 2 * PI"),
+    ("project_argmax_of_last_axis_missed", "project", "np.argmax(u, axis=-1)", "np.argmax(u, axis=0)"),
+    ("flow_next_step_not_renormalised", "gradient_flow", "mu = nu / nu.sum()", "mu = nu"),
     ("project_adds_negative_part", "project", "mass = mass - u_minus.sum(axis=-1)",
      "mass = mass + u_minus.sum(axis=-1)"),
     ("split_not_normalised", "split_signed", "return (plus / sp if sp > 0 else plus), (minus / sn if sn > 0 else minus)",
